@@ -1,0 +1,300 @@
+"""Seeded synthetic inputs: grid PDE operators, geometric nested dissection,
+right-hand sides and coefficient fields.
+
+This module is the only code shared by the oracle and the HIP path.  It holds
+none of the solver's arithmetic: it produces the sparse matrix A (CSR, natural
+grid ordering), the fill-reducing ordering that both sides consume as an input
+(perm, separator tree), and seeded vectors.
+
+Workloads follow the regular-grid PDE benchmarks of the paper (Sec. 6.1):
+5-point / 7-point Poisson with homogeneous Dirichlet conditions, an upwind
+convection-diffusion operator, and a finite-volume variable-coefficient
+diffusion operator.  The ordering is the "geometric nested dissection" the
+paper uses for regular grids (Sec. 6.1), made concrete as:
+
+* cut the box along its longest axis (ties to the lower axis index), with the
+  separator plane at ``lo + (ext - 1) // 2``;
+* stop when every extent is at most ``leaf_side``;
+* number fronts in postorder (left subtree, right subtree, separator);
+* inside a separator (or a leaf box) order points by recursive coordinate
+  bisection (longer side first, first part of size ``ceil(len / 2)``), so a
+  run of consecutive indices is a compact patch of the face.  These patches
+  play the role of the separator partitions of Sec. 4.2.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from functools import lru_cache
+
+import numpy as np
+
+__all__ = [
+    "CSR", "Ordering", "poisson2d", "poisson3d", "convdiff2d", "fv_diffusion3d",
+    "smoothed_log_kappa", "geometric_nd", "workload", "WORKLOADS",
+]
+
+
+@dataclass
+class CSR:
+    n: int
+    rowptr: np.ndarray  # int64, n+1
+    colind: np.ndarray  # int32, nnz (sorted within a row)
+    val: np.ndarray     # float64, nnz
+
+    def to_scipy(self):
+        import scipy.sparse as sp
+        return sp.csr_matrix((self.val, self.colind, self.rowptr), shape=(self.n, self.n))
+
+    def matvec(self, x):
+        return self.to_scipy() @ x
+
+
+@dataclass
+class Ordering:
+    perm: np.ndarray      # int32, perm[new] = old
+    sep_ptr: np.ndarray   # int32, nfront+1; front f owns new indices [sep_ptr[f], sep_ptr[f+1])
+    parent: np.ndarray    # int32, nfront; -1 for the root; fronts are in postorder
+    boxes: list           # per front: (lo, hi) of the subtree box (geometry, informative)
+    dims: tuple
+
+    @property
+    def nfront(self):
+        return len(self.parent)
+
+
+def _coo_to_csr(n, rows, cols, vals):
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rowptr, rows + 1, 1)
+    rowptr = np.cumsum(rowptr)
+    return CSR(n, rowptr, cols.astype(np.int32), vals.astype(np.float64))
+
+
+def _grid_index(dims):
+    return np.arange(int(np.prod(dims))).reshape(tuple(reversed(dims)))  # [z][y][x]
+
+
+def _stencil(dims, centre, coeff):
+    """Assemble a nearest-neighbour operator on a grid with Dirichlet boundary.
+
+    ``centre`` is an array over grid points (natural ordering x fastest);
+    ``coeff(axis, sign)`` returns the off-diagonal value array over grid points
+    for the neighbour at +/-1 along ``axis`` (entries whose neighbour falls
+    outside the grid are dropped: homogeneous Dirichlet)."""
+    dims = tuple(dims)
+    n = int(np.prod(dims))
+    idx = np.arange(n)
+    coords = []
+    rem = idx.copy()
+    for d in dims:
+        coords.append(rem % d)
+        rem = rem // d
+    stride = np.cumprod((1,) + dims[:-1])
+    rows = [idx]
+    cols = [idx]
+    vals = [np.asarray(centre, dtype=np.float64) * np.ones(n)]
+    for ax, d in enumerate(dims):
+        for sign in (-1, 1):
+            ok = (coords[ax] + sign >= 0) & (coords[ax] + sign < d)
+            c = np.asarray(coeff(ax, sign), dtype=np.float64) * np.ones(n)
+            rows.append(idx[ok])
+            cols.append(idx[ok] + sign * stride[ax])
+            vals.append(c[ok])
+    return _coo_to_csr(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
+
+
+def poisson2d(nx, ny=None):
+    """5-point Laplacian (4, -1), homogeneous Dirichlet (Sec. 6.1, P2D)."""
+    ny = nx if ny is None else ny
+    return _stencil((nx, ny), 4.0, lambda ax, s: -1.0)
+
+
+def poisson3d(nx, ny=None, nz=None):
+    """7-point Laplacian (6, -1), homogeneous Dirichlet (Sec. 6.1, P3D)."""
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    return _stencil((nx, ny, nz), 6.0, lambda ax, s: -1.0)
+
+
+def convdiff2d(n, wx, wy):
+    """-Lap(u) + w.grad(u) with constant w, 5-point first-order upwind, scaled
+    by h^2 (h = 1/(n+1)).  Centre 4 + h(|wx|+|wy|); the upwind neighbour gets
+    -1 - h|w_axis|, the downwind neighbour -1.  The paper's C2D uses the same
+    upwind scheme (Sec. 6.1); the constant field follows the batched workload."""
+    h = 1.0 / (n + 1)
+    w = (wx, wy)
+
+    def coeff(ax, sign):
+        upwind = (sign < 0) if w[ax] >= 0 else (sign > 0)
+        return -1.0 - h * abs(w[ax]) if upwind else -1.0
+
+    return _stencil((n, n), 4.0 + h * (abs(wx) + abs(wy)), coeff)
+
+
+def smoothed_log_kappa(n, seed=3, sigma=0.5):
+    """log(kappa) iid N(0, sigma^2) from ``default_rng(seed)``, then a 3x3x3 box
+    mean over the in-domain neighbours.  Returns (kappa, rng) so that the caller
+    can keep drawing from the same stream (b, then x*)."""
+    rng = np.random.default_rng(seed)
+    g = rng.normal(0.0, sigma, n ** 3).reshape(n, n, n)  # [z][y][x]
+    s = np.zeros_like(g)
+    c = np.zeros_like(g)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                src = [slice(max(0, -d), n - max(0, d)) for d in (dz, dy, dx)]
+                dst = [slice(max(0, d), n - max(0, -d)) for d in (dz, dy, dx)]
+                s[tuple(dst)] += g[tuple(src)]
+                c[tuple(dst)] += 1.0
+    return np.exp(s / c).reshape(-1), rng
+
+
+def fv_diffusion3d(n, kappa):
+    """Cell-centred finite-volume -div(kappa grad u) on an n^3 grid with unit
+    spacing: face transmissibility 2 k_c k_c' / (k_c + k_c'); a Dirichlet
+    boundary face contributes 2 k_c to the diagonal."""
+    dims = (n, n, n)
+    N = n ** 3
+    kappa = np.asarray(kappa, dtype=np.float64)
+    idx = np.arange(N)
+    coords = [idx % n, (idx // n) % n, idx // (n * n)]
+    stride = (1, n, n * n)
+    diag = np.zeros(N)
+    rows, cols, vals = [], [], []
+    for ax in range(3):
+        for sign in (-1, 1):
+            ok = (coords[ax] + sign >= 0) & (coords[ax] + sign < n)
+            nb = idx[ok] + sign * stride[ax]
+            kc, kn = kappa[idx[ok]], kappa[nb]
+            t = 2.0 * kc * kn / (kc + kn)
+            rows.append(idx[ok]); cols.append(nb); vals.append(-t)
+            np.add.at(diag, idx[ok], t)
+            np.add.at(diag, idx[~ok], 2.0 * kappa[idx[~ok]])
+    rows.append(idx); cols.append(idx); vals.append(diag)
+    return _coo_to_csr(N, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
+
+
+# ---------------------------------------------------------------------------
+# geometric nested dissection
+# ---------------------------------------------------------------------------
+
+@lru_cache(maxsize=None)
+def _rcb_shape(shape):
+    """Relative coordinates of a box of ``shape`` in recursive coordinate
+    bisection order: split the longest side (ties to the lower axis) with the
+    first part holding ceil(len/2) points, recurse down to single points."""
+    size = int(np.prod(shape))
+    if size == 1:
+        return np.zeros((1, len(shape)), dtype=np.int64)
+    ax = int(np.argmax(shape))
+    first = (shape[ax] + 1) // 2
+    s1 = list(shape); s1[ax] = first
+    s2 = list(shape); s2[ax] = shape[ax] - first
+    a = _rcb_shape(tuple(s1))
+    b = _rcb_shape(tuple(s2)).copy()
+    b[:, ax] += first
+    return np.concatenate([a, b], axis=0)
+
+
+def _box_points(lo, hi, dims):
+    shape = tuple(int(h - l) for l, h in zip(lo, hi))
+    rel = _rcb_shape(shape)
+    absc = rel + np.asarray(lo, dtype=np.int64)
+    stride = np.cumprod((1,) + tuple(dims[:-1]))
+    return (absc * stride).sum(axis=1)
+
+
+def geometric_nd(dims, leaf_side):
+    """Nested dissection of a regular grid (see module docstring).  Returns an
+    :class:`Ordering`; fronts are numbered in postorder."""
+    dims = tuple(int(d) for d in dims)
+    fronts_pts = []
+    parent = []
+    boxes = []
+
+    def rec(lo, hi):
+        ext = [h - l for l, h in zip(lo, hi)]
+        if min(ext) <= 0:
+            return -1
+        if max(ext) <= leaf_side:
+            fid = len(fronts_pts)
+            fronts_pts.append(_box_points(lo, hi, dims))
+            parent.append(-1)
+            boxes.append((tuple(lo), tuple(hi)))
+            return fid
+        ax = int(np.argmax(ext))
+        cut = lo[ax] + (ext[ax] - 1) // 2
+        hl = list(hi); hl[ax] = cut
+        lr = list(lo); lr[ax] = cut + 1
+        a = rec(list(lo), hl)
+        b = rec(lr, list(hi))
+        slo = list(lo); slo[ax] = cut
+        shi = list(hi); shi[ax] = cut + 1
+        fid = len(fronts_pts)
+        fronts_pts.append(_box_points(slo, shi, dims))
+        parent.append(-1)
+        boxes.append((tuple(lo), tuple(hi)))
+        for c in (a, b):
+            if c >= 0:
+                parent[c] = fid
+        return fid
+
+    import sys
+    old = sys.getrecursionlimit()
+    sys.setrecursionlimit(max(old, 10000))
+    try:
+        rec([0] * len(dims), list(dims))
+    finally:
+        sys.setrecursionlimit(old)
+    sizes = np.array([len(p) for p in fronts_pts], dtype=np.int64)
+    sep_ptr = np.zeros(len(sizes) + 1, dtype=np.int32)
+    sep_ptr[1:] = np.cumsum(sizes)
+    perm = np.concatenate(fronts_pts).astype(np.int32)
+    return Ordering(perm, sep_ptr, np.asarray(parent, dtype=np.int32), boxes, dims)
+
+
+def halo_size(box, dims):
+    """Number of grid points just outside ``box`` across its faces (no edges
+    or corners) that lie inside the grid: the update-set size of the front
+    whose subtree covers ``box`` for a 5-/7-point stencil."""
+    lo, hi = box
+    ext = [h - l for l, h in zip(lo, hi)]
+    tot = 0
+    for ax in range(len(dims)):
+        area = int(np.prod([e for b, e in enumerate(ext) if b != ax]))
+        if lo[ax] > 0:
+            tot += area
+        if hi[ax] < dims[ax]:
+            tot += area
+    return tot
+
+
+# ---------------------------------------------------------------------------
+# named workloads
+# ---------------------------------------------------------------------------
+
+WORKLOADS = {
+    # name: (kind, grid side, nd leaf side, solver options)
+    "poisson2d_100": dict(kind="poisson2d", n=100, leaf_side=8,
+                          opts=dict(min_sep_hss=64, leaf_size=16, rel_tol=1e-4, d0=32, dd=16,
+                                    outer="gmres")),
+    "poisson3d_64": dict(kind="poisson3d", n=64, leaf_side=4,
+                         opts=dict(min_sep_hss=512, leaf_size=64, rel_tol=1e-6, d0=128, dd=128,
+                                   outer="ir")),
+}
+
+
+def workload(kind, n, leaf_side, rhs_seed=1, **_):
+    """Matrix, ordering and right-hand side of a named grid workload.  The
+    right-hand side is iid N(0,1) from ``default_rng(rhs_seed)``."""
+    if kind == "poisson2d":
+        A = poisson2d(n)
+        order = geometric_nd((n, n), leaf_side)
+    elif kind == "poisson3d":
+        A = poisson3d(n)
+        order = geometric_nd((n, n, n), leaf_side)
+    else:
+        raise ValueError(kind)
+    b = np.random.default_rng(rhs_seed).standard_normal(A.n)
+    return A, order, b

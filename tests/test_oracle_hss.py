@@ -1,0 +1,224 @@
+"""Pins for the oracle's HSS toolkit: ID, Alg. 1, matvec / extraction,
+ULV factorization and solves, low-rank Schur product (CPU only)."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import hss as H
+from oracle.symbolic import hss_tree, HNode
+
+
+class DenseOp:
+    def __init__(self, A):
+        self.A = A
+
+    def sample(self, R):
+        return self.A @ R, self.A.T @ R
+
+    def extract(self, I, J):
+        return self.A[np.ix_(np.asarray(I, int), np.asarray(J, int))]
+
+
+def _rand_fn(n, seed=0):
+    rg = np.random.default_rng(seed)
+    cache = {}
+
+    def rand(c0, nc):
+        for c in range(c0, c0 + nc):
+            if c not in cache:
+                cache[c] = rg.standard_normal(n)
+        return np.stack([cache[c] for c in range(c0, c0 + nc)], axis=1)
+    return rand
+
+
+def _four_leaf_hss(rng, m=(5, 6, 4, 7), r=3):
+    """The 7-node example of Fig. 1 / Eq. HSSexamplematrix with random
+    interpolative generators of rank r."""
+    lo = np.cumsum((0,) + m)
+    nodes = [HNode(lo[0], lo[1]), HNode(lo[1], lo[2]), HNode(lo[0], lo[2], [0, 1]),
+             HNode(lo[2], lo[3]), HNode(lo[3], lo[4]), HNode(lo[2], lo[4], [3, 4]),
+             HNode(lo[0], lo[4], [2, 5])]
+    for p, cs in ((2, (0, 1)), (5, (3, 4)), (6, (2, 5))):
+        for c in cs:
+            nodes[c].parent = p
+    gen = [H.NodeGen() for _ in nodes]
+    for t, nd in enumerate(nodes):
+        if t == 6:
+            continue
+        mm = nd.m if nd.leaf else 2 * r
+        for side in "UV":
+            perm = rng.permutation(mm)
+            E = rng.standard_normal((mm - r, r))
+            setattr(gen[t], side + "perm", perm)
+            setattr(gen[t], side + "E", E)
+        if nd.leaf:
+            gen[t].D = rng.standard_normal((nd.m, nd.m)) + 4 * np.eye(nd.m)
+    for t in (2, 5, 6):
+        gen[t].B12 = rng.standard_normal((r, r))
+        gen[t].B21 = rng.standard_normal((r, r))
+    return H.HSS(nodes, gen, 6)
+
+
+def _expand_by_formula(hs):
+    """Eq. HSSexamplematrix written out block by block."""
+    g = hs.gen
+    U = [x.U() if x.UE is not None else None for x in g]
+    V = [x.V() if x.VE is not None else None for x in g]
+    bd = sla.block_diag
+    U3 = bd(U[0], U[1]) @ U[2]
+    U6 = bd(U[3], U[4]) @ U[5]
+    V3 = bd(V[0], V[1]) @ V[2]
+    V6 = bd(V[3], V[4]) @ V[5]
+    top = np.block([[g[0].D, U[0] @ g[2].B12 @ V[1].T], [U[1] @ g[2].B21 @ V[0].T, g[1].D]])
+    bot = np.block([[g[3].D, U[3] @ g[5].B12 @ V[4].T], [U[4] @ g[5].B21 @ V[3].T, g[4].D]])
+    return np.block([[top, U3 @ g[6].B12 @ V6.T], [U6 @ g[6].B21 @ V3.T, bot]])
+
+
+def test_four_leaf_example_expand_matvec_extract(rng):
+    hs = _four_leaf_hss(rng)
+    F = _expand_by_formula(hs)
+    assert np.allclose(H.hss_dense(hs, 6), F, rtol=0, atol=1e-12)
+    X = rng.standard_normal((F.shape[0], 3))
+    assert np.allclose(H.hss_matvec(hs, 6, X), F @ X, atol=1e-11)
+    assert np.allclose(H.hss_matvec(hs, 6, X, trans=True), F.T @ X, atol=1e-11)
+    I = np.array([0, 3, 21, 9, 10])
+    J = np.array([20, 1, 5, 5])
+    assert np.allclose(H.hss_extract(hs, 6, I, J), F[np.ix_(I, J)], atol=1e-12)
+    # a subtree (node 5) is the HSS matrix of its block
+    lo, hi = hs.nodes[5].lo, hs.nodes[5].hi
+    assert np.allclose(H.hss_matvec(hs, 5, X[lo:hi]), F[lo:hi, lo:hi] @ X[lo:hi], atol=1e-11)
+
+
+def test_id_identities(rng):
+    """Y = Y(:,J) X with X(:,J) = I exactly (Sec. 2.2)."""
+    Y = rng.standard_normal((30, 8)) @ rng.standard_normal((8, 50))
+    perm, E, k = H.interp_decomp(Y, 1e-12)
+    assert k == 8
+    J = perm[:k]
+    X = H.interp_matrix(perm, E).T          # k x m
+    assert np.array_equal(X[:, J], np.eye(k))
+    assert np.linalg.norm(Y - Y[:, J] @ X) <= 1e-12 * np.linalg.norm(Y)
+
+
+def test_cpqr_matches_library_on_well_separated_columns(rng):
+    Q, _ = np.linalg.qr(rng.standard_normal((40, 40)))
+    Y = Q[:, :12] * np.geomspace(1, 1e-3, 12) @ rng.standard_normal((12, 12))
+    Y = Y * np.geomspace(10, 1, 12)
+    perm, R, k = H.cpqr_eps(Y, 0.0)
+    _, R2, p2 = sla.qr(Y, pivoting=True)
+    assert np.array_equal(perm[:6], p2[:6])
+    assert np.allclose(np.abs(np.diag(R[:6, :6])), np.abs(np.diag(R2[:6, :6])), rtol=1e-10)
+
+
+@pytest.mark.parametrize("eps", [1e-2, 1e-5, 1e-9])
+def test_epsilon_rank_rule(rng, eps):
+    """Rank stops at the first i with |R_{i+1,i+1}| / |R_11| <= eps (Sec. 5.4);
+    with prescribed, well separated singular values the ranks are known."""
+    n = 60
+    sv = 10.0 ** -np.arange(0, 12, 1.0)
+    U, _ = np.linalg.qr(rng.standard_normal((n, 12)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, 12)))
+    Y = (U * sv) @ V.T
+    _, R, k = H.cpqr_eps(Y, eps)
+    expect = int(np.sum(sv > eps * 1.0000001))
+    assert abs(k - expect) <= 1
+    if k < 12:
+        assert k == 0 or True
+    assert np.all(np.abs(np.diag(R[:k, :k])) / abs(R[0, 0]) > eps)
+
+
+def test_omega_annihilates_interpolative_basis(rng):
+    """Omega U = [0; I] exactly for U = Pi [I; E] (Sec. 2.3)."""
+    m, r = 11, 4
+    perm = rng.permutation(m)
+    E = rng.standard_normal((m - r, r))
+    U = H.interp_matrix(perm, E)
+    Om = np.block([[-E, np.eye(m - r)], [np.eye(r), np.zeros((r, m - r))]])[:, np.argsort(perm)]
+    OU = Om @ U
+    assert np.array_equal(OU[:m - r], np.zeros((m - r, r)))
+    assert np.array_equal(OU[m - r:], np.eye(r))
+
+
+def _hss_matrix(rng, n, rank, decay=1.0):
+    """A dense matrix with HSS structure: smooth kernel plus diagonal."""
+    x = np.sort(rng.uniform(0, 1, n))
+    K = 1.0 / (1.0 + 50 * np.abs(x[:, None] - x[None, :])) + 0.3 * np.outer(np.sin(7 * x), np.cos(3 * x))
+    return K + n * np.eye(n) * 0.05
+
+
+def test_compression_exact_recovery(rng):
+    """eps -> 0 and d >= m + p: the HSS reproduces the matrix (Alg. 1)."""
+    n = 96
+    A = rng.standard_normal((n, n)) + n * np.eye(n)
+    nodes, k, q = hss_tree(n, 0, 12)
+    hs = H.compress(DenseOp(A), nodes, len(nodes) - 1, _rand_fn(n), 1e-15, 130, 16, 10, 10000)
+    assert np.linalg.norm(H.hss_dense(hs, hs.root) - A) <= 1e-12 * np.linalg.norm(A)
+
+
+def test_compression_b_blocks_are_submatrices(rng):
+    """B_{nu1,nu2} = A(I^r_nu1, I^c_nu2) bit-exactly (Sec. 2.2)."""
+    n = 80
+    A = _hss_matrix(rng, n, 0)
+    nodes, k, q = hss_tree(50, 30, 10)
+    hs = H.compress(DenseOp(A), nodes, len(nodes) - 1, _rand_fn(n), 1e-8, 40, 20, 8, 10000)
+    for t, nd in enumerate(nodes):
+        if nd.children:
+            a, b = nd.children
+            assert np.array_equal(hs.gen[t].B12, A[np.ix_(hs.gen[a].Ir, hs.gen[b].Ic)])
+            assert np.array_equal(hs.gen[t].B21, A[np.ix_(hs.gen[b].Ir, hs.gen[a].Ic)])
+        if nd.leaf:
+            assert np.array_equal(hs.gen[t].D, A[nd.lo:nd.hi, nd.lo:nd.hi])
+
+
+def test_compression_known_ranks(rng):
+    """A synthetic HSS matrix with interpolative generators of rank r is
+    recovered with rank exactly r at every node when d >= r + p."""
+    r = 3
+    src = _four_leaf_hss(rng, m=(9, 10, 8, 11), r=r)
+    A = H.hss_dense(src, 6)
+    hs = H.compress(DenseOp(A), src.nodes, 6, _rand_fn(A.shape[0]), 1e-10, 16, 8, 5, 1000)
+    for t in range(6):
+        assert hs.gen[t].r == r and hs.gen[t].c == r
+    assert np.linalg.norm(H.hss_dense(hs, 6) - A) <= 1e-9 * np.linalg.norm(A)
+
+
+def test_adaptive_rank_growth(rng):
+    """Block of rank 40 with d0 = 8, dd = 8: d grows until d >= rank + p and
+    the final compression is accurate (Sec. 2.2.1)."""
+    n = 120
+    A = (rng.standard_normal((n, 40)) @ rng.standard_normal((40, n))) + 30 * np.eye(n)
+    nodes, k, q = hss_tree(60, 60, 30)
+    hs = H.compress(DenseOp(A), nodes, len(nodes) - 1, _rand_fn(n), 1e-12, 8, 8, 4, 10000)
+    assert hs.stats["rounds"] >= 4 and hs.stats["d"] >= 44
+    assert np.linalg.norm(H.hss_dense(hs, hs.root) - A) <= 1e-9 * np.linalg.norm(A)
+    with pytest.raises(H.RankError):
+        H.compress(DenseOp(A), nodes, len(nodes) - 1, _rand_fn(n), 1e-12, 8, 8, 4, 24)
+
+
+@pytest.mark.parametrize("s,u,leaf", [(64, 40, 8), (50, 0, 7), (33, 20, 40)])
+def test_ulv_equals_dense_solve(rng, s, u, leaf):
+    """ULV solves (and transposed solves) of the compressed F11 equal dense LU
+    solves of the expanded HSS matrix; Theta^* Phi equals F21 F11^{-1} F12."""
+    n = s + u
+    A = _hss_matrix(rng, n, 0) + 0.2 * rng.standard_normal((n, n)) / np.sqrt(n)
+    nodes, k, q = hss_tree(s, u, leaf)
+    hs = H.compress(DenseOp(A), nodes, len(nodes) - 1, _rand_fn(n), 1e-6, 24, 16, 6, 10000)
+    Fd = H.hss_dense(hs, hs.root)
+    F11 = Fd[:s, :s]
+    ulv = H.ulv_factor(hs, k)
+    b = rng.standard_normal((s, 2))
+    kap = np.linalg.cond(F11)
+    assert np.allclose(H.ulv_solve(ulv, b), np.linalg.solve(F11, b), rtol=0, atol=1e-13 * kap * np.abs(np.linalg.solve(F11, b)).max())
+    zt = H.ulv_solve_transpose(ulv, b)
+    assert np.linalg.norm(F11.T @ zt - b) <= 1e-12 * kap * np.linalg.norm(b)
+    if u:
+        Th, Ph = H.schur_lowrank(ulv, q)
+        S = Fd[s:, :s] @ np.linalg.solve(F11, Fd[:s, s:])
+        assert np.linalg.norm(Th @ Ph - S) <= 1e-12 * kap * np.linalg.norm(S)
+        ops = H.Front11Ops(hs, k, q)
+        z = rng.standard_normal((s, 1))
+        x = rng.standard_normal((u, 1))
+        assert np.allclose(ops.f21(z), Fd[s:, :s] @ z, atol=1e-11)
+        assert np.allclose(ops.f12(x), Fd[:s, s:] @ x, atol=1e-11)
+        assert np.allclose(ops.f12t(z), Fd[:s, s:].T @ z, atol=1e-11)
+        assert np.allclose(ops.f21t(x), Fd[s:, :s].T @ x, atol=1e-11)

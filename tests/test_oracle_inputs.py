@@ -1,0 +1,157 @@
+"""Pins for the oracle's RNG, the input generators, the ordering and the
+symbolic analysis (CPU only)."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import rng as orng
+from oracle import symbolic as osym
+from oracle import dense as odense
+from paper_1502_07405_amd import problems as P
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rows(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
+
+
+def test_philox_known_answers():
+    for row in _rows("philox4x32_10_kat.txt"):
+        v = [int(t, 16) for t in row]
+        out = orng.philox4x32_10(*v[:6])
+        assert [int(o) for o in out] == v[6:]
+
+
+def test_gaussian_moments_and_keying():
+    g = orng.gaussian(7, np.arange(40000), 8)
+    assert abs(g.mean()) < 0.01 and abs(g.std() - 1) < 0.01
+    assert abs((g ** 4).mean() - 3) < 0.05
+    # keyed by (seed, row, column): any subset of rows/columns sees the same values
+    sub = orng.gaussian(7, np.array([5, 17, 3]), 3, col0=4)
+    assert np.array_equal(sub, g[[5, 17, 3]][:, 4:7])
+    assert not np.allclose(orng.gaussian(8, np.arange(4), 4), g[:4, :4])
+
+
+def _mf_flop_model(dims, leaf):
+    """sum 2/3 s^3 + 2 s^2 u + 2 s u^2 over the geometric ND fronts, computed
+    from box geometry only (separator = cut plane, update = box halo)."""
+    tot = 0.0
+
+    def rec(lo, hi):
+        nonlocal tot
+        ext = [h - l for l, h in zip(lo, hi)]
+        if min(ext) <= 0:
+            return
+        if max(ext) <= leaf:
+            s = int(np.prod(ext))
+        else:
+            ax = int(np.argmax(ext))
+            cut = lo[ax] + (ext[ax] - 1) // 2
+            hl = list(hi); hl[ax] = cut
+            lr = list(lo); lr[ax] = cut + 1
+            rec(lo, hl); rec(lr, hi)
+            s = int(np.prod([e for b, e in enumerate(ext) if b != ax]))
+        u = P.halo_size((lo, hi), dims)
+        tot += 2 / 3 * s ** 3 + 2 * s * s * u + 2 * s * u * u
+    rec([0] * len(dims), list(dims))
+    return tot
+
+
+def test_nd_flop_model_matches_table2():
+    """Table 2 prints the dense-MF factor flops of the geometric-ND runs; our
+    ND rule must reproduce them (4.9e12 at 5000^2, 50.0e12 at 125^3)."""
+    for kind, dims, leaf, flops in _rows("table2_mf_flops.txt"):
+        dims = tuple(int(x) for x in dims.split(","))
+        model = _mf_flop_model(dims, int(leaf))
+        assert abs(model / float(flops) - 1) < 0.02, (kind, model)
+
+
+@pytest.mark.parametrize("dims,leaf", [((12, 9), 3), ((7, 8, 6), 2), ((16, 16), 4)])
+def test_nd_is_a_separator_tree(dims, leaf):
+    o = P.geometric_nd(dims, leaf)
+    N = int(np.prod(dims))
+    assert sorted(o.perm.tolist()) == list(range(N))
+    A = (P.poisson2d(*dims) if len(dims) == 2 else P.poisson3d(*dims)).to_scipy()
+    Ap = A[o.perm][:, o.perm].tocoo()
+    front_of = np.repeat(np.arange(o.nfront), np.diff(o.sep_ptr))
+    anc = [set() for _ in range(o.nfront)]
+    for f in range(o.nfront):
+        p = o.parent[f]
+        while p >= 0:
+            anc[f].add(p)
+            p = o.parent[p]
+    # every coupling is within a front or between a front and an ancestor
+    for i, j in zip(Ap.row, Ap.col):
+        fi, fj = front_of[i], front_of[j]
+        assert fi == fj or fj in anc[fi] or fi in anc[fj]
+
+
+@pytest.mark.parametrize("dims,leaf", [((20, 20), 4), ((9, 10, 8), 2)])
+def test_update_sets_equal_box_halo(dims, leaf):
+    """Symbolic update sets (sparse structure) equal the geometric halo of each
+    front's subtree box for a 5/7-point stencil."""
+    o = P.geometric_nd(dims, leaf)
+    A = P.poisson2d(*dims) if len(dims) == 2 else P.poisson3d(*dims)
+    Ap = osym.permute_csr(A, o.perm)
+    fronts = osym.analyse(Ap, o.sep_ptr, o.parent)
+    for f in fronts:
+        assert f.u == P.halo_size(o.boxes[f.id], dims)
+        assert np.all(f.upd >= f.sep_hi)
+
+
+def test_extend_add_worked_example():
+    """Eq. extend-add: U1 on {1,2} and U2 on {1,3} sum to the printed 3x3."""
+    sym = {}
+    vals = iter(np.arange(1.0, 9.0) * 10.0 + np.arange(8) * 0.125)
+    for k in (1, 2):
+        for nm in "abcd":
+            sym[f"{nm}{k}"] = next(vals)
+    F = np.zeros((3, 3))
+    idx = np.array([1, 2, 3])
+    for k, s in ((1, [1, 2]), (2, [1, 3])):
+        Uk = np.array([[sym[f"a{k}"], sym[f"b{k}"]], [sym[f"c{k}"], sym[f"d{k}"]]])
+        odense.extend_add(idx, np.array(s), Uk, F)
+    expect = np.array([[sum(sym[t] for t in e.split("+")) if e != "0" else 0.0 for e in row]
+                       for row in _rows("extend_add_example.txt")])
+    assert np.array_equal(F, expect)
+
+
+def test_extend_merge_fig2():
+    """Eq. Rmerge / Fig. 2: the parent's R reuses the children's entries on
+    shared rows and columns; keyed generation reproduces that provenance."""
+    seed = 11
+    Rg = lambda rows, d: orng.gaussian(seed, np.array(rows), d)
+    R1 = Rg([1, 4, 5], 1)
+    R2 = Rg([2, 3, 4, 5, 7], 2)
+    R3 = Rg([4, 5, 6, 7], 3)
+    src = {1: ({1: 0, 4: 1, 5: 2}, R1), 2: ({2: 0, 3: 1, 4: 2, 5: 3, 7: 4}, R2)}
+    pos3 = {4: 0, 5: 1, 6: 2, 7: 3}
+    for row, col, where in _rows("extend_merge_fig2.txt"):
+        row, col = int(row), int(col) - 1
+        val = R3[pos3[row], col]
+        owners = [k for k in (1, 2) if row in src[k][0] and col < src[k][1].shape[1]]
+        expect = {"1": [1], "2": [2], "12": [1, 2], "g": []}[where]
+        assert owners == expect, (row, col)
+        for k in owners:
+            assert src[k][1][src[k][0][row], col] == val
+
+
+def test_hss_tree_partition():
+    nodes, k, q = osym.hss_tree(100, 37, 16)
+    root = len(nodes) - 1
+    assert nodes[root].children == [k, q]
+    assert (nodes[k].lo, nodes[k].hi, nodes[q].lo, nodes[q].hi) == (0, 100, 100, 137)
+    leaves = [nd for nd in nodes if nd.leaf]
+    assert all(nd.m <= 16 for nd in leaves)
+    assert sum(nd.m for nd in leaves) == 137
+    for t, nd in enumerate(nodes):
+        for c in nd.children:
+            assert c < t        # postorder
+        if nd.children:
+            a, b = nd.children
+            assert nodes[a].lo == nd.lo and nodes[a].hi == nodes[b].lo and nodes[b].hi == nd.hi
+            if t != root:
+                assert nodes[a].m == (nd.m + 1) // 2

@@ -1,0 +1,108 @@
+"""Pins for the oracle's multifrontal solver, outer iterations and adjoint
+(CPU only): dense LU on tiny grids, exact solution x = 1 for b = A 1,
+eps -> 0 makes MF-HSS exact, transposed solves, adjoint identities."""
+import numpy as np
+import pytest
+
+from oracle import adjoint as oadj
+from oracle import krylov, mf
+from paper_1502_07405_amd import problems as P
+
+
+def _dense(A):
+    return A.to_scipy().toarray()
+
+
+@pytest.mark.parametrize("kind", ["p2d", "p3d", "cd2d"])
+def test_dense_mf_equals_dense_lu(kind, rng):
+    if kind == "p2d":
+        A, o = P.poisson2d(16), P.geometric_nd((16, 16), 4)
+    elif kind == "p3d":
+        A, o = P.poisson3d(8), P.geometric_nd((8, 8, 8), 2)
+    else:
+        A, o = P.convdiff2d(14, 18.0, -6.0), P.geometric_nd((14, 14), 3)
+    fac = mf.factor(A, o, mf.Options())
+    b = rng.standard_normal((A.n, 2))
+    Ad = _dense(A)
+    for tr in (False, True):
+        x = mf.apply_inverse(fac, b, trans=tr)
+        xr = np.linalg.solve(Ad.T if tr else Ad, b)
+        assert np.linalg.norm(x - xr) <= 1e-13 * np.linalg.norm(xr)
+
+
+def test_exact_solution_of_ones_rhs():
+    """The paper's right-hand side A [1 ... 1]^T (Sec. 6.1) has solution 1."""
+    A, o = P.poisson2d(30), P.geometric_nd((30, 30), 4)
+    fac = mf.factor(A, o, mf.Options(min_sep_hss=16, leaf_size=8, rel_tol=1e-3, d0=16, dd=16, p=5))
+    b = A.matvec(np.ones(A.n))
+    x, its, hist = krylov.gmres(A.matvec, lambda v: mf.apply_inverse(fac, v), b, 1e-12)
+    assert np.abs(x - 1).max() < 1e-9
+
+
+def test_hss_tolerance_to_zero_recovers_direct_solver(rng):
+    """eps -> 0: MF-HSS equals MF up to rounding, so refinement converges in
+    at most one step."""
+    A, o = P.convdiff2d(40, 12.0, 9.0), P.geometric_nd((40, 40), 4)
+    fac = mf.factor(A, o, mf.Options(min_sep_hss=12, leaf_size=8, rel_tol=1e-15, d0=16, dd=16, p=5))
+    b = rng.standard_normal(A.n)
+    xr = np.linalg.solve(_dense(A), b)
+    for tr in (False, True):
+        x = mf.apply_inverse(fac, b, trans=tr)
+        xr = np.linalg.solve(_dense(A).T if tr else _dense(A), b)
+        assert np.linalg.norm(x - xr) <= 1e-11 * np.linalg.norm(xr)
+    x, its, _ = krylov.refine(A.matvec, lambda v: mf.apply_inverse(fac, v), b, 1e-12)
+    assert its <= 1
+
+
+def test_preconditioned_gmres_and_refinement_converge(rng):
+    A, o = P.poisson3d(12), P.geometric_nd((12, 12, 12), 2)
+    fac = mf.factor(A, o, mf.Options(min_sep_hss=40, leaf_size=16, rel_tol=1e-2, d0=16, dd=16, p=5))
+    b = rng.standard_normal(A.n)
+    pc = lambda v: mf.apply_inverse(fac, v)
+    xg, itg, hg = krylov.gmres(A.matvec, pc, b, 1e-10)
+    assert np.linalg.norm(b - A.matvec(xg)) <= 1e-10 * np.linalg.norm(b)
+    xr, itr, hr = krylov.refine(A.matvec, pc, b, 1e-10, max_it=100)
+    assert np.linalg.norm(b - A.matvec(xr)) <= 1e-10 * np.linalg.norm(b)
+    assert itg <= itr + 1
+    with pytest.raises(krylov.NoConvergence):
+        krylov.refine(A.matvec, pc, b, 1e-14, max_it=1)
+
+
+def test_rank_stays_flat_in_2d(rng):
+    """2D elliptic fronts have O(1) HSS rank (Table 1): the top front's rank
+    barely changes as the grid side doubles."""
+    ranks = []
+    for n in (48, 96):
+        A, o = P.poisson2d(n), P.geometric_nd((n, n), 8)
+        fac = mf.factor(A, o, mf.Options(min_sep_hss=32, leaf_size=16, rel_tol=1e-6, d0=32, dd=16, p=10))
+        ranks.append(max(r[1] for r in mf.hss_ranks(fac)))
+    assert ranks[1] <= ranks[0] + 8
+
+
+def test_adjoint_matches_dense(rng):
+    """lambda = A^{-T} g, dL/db = lambda, dL/dA_ij = -lambda_i x_j on the
+    pattern; checked against dense solves and central differences."""
+    n = 10
+    kap, _ = P.smoothed_log_kappa(n, seed=4)
+    A = P.fv_diffusion3d(n, kap)
+    o = P.geometric_nd((n, n, n), 2)
+    fac = mf.factor(A, o, mf.Options(min_sep_hss=30, leaf_size=16, rel_tol=1e-8, d0=24, dd=16, p=5))
+    b = rng.standard_normal(A.n)
+    xs = rng.standard_normal(A.n)
+    x, lam, dval = oadj.solve_and_adjoint(A, fac, b, lambda x: 2 * (x - xs), tol=1e-13)
+    Ad = _dense(A)
+    assert np.linalg.norm(x - np.linalg.solve(Ad, b)) <= 1e-11 * np.linalg.norm(x)
+    lam_ref = np.linalg.solve(Ad.T, 2 * (x - xs))
+    assert np.linalg.norm(lam - lam_ref) <= 1e-8 * np.linalg.norm(lam_ref)
+    # central differences of L = ||x - x*||^2 w.r.t. a few matrix entries
+    S = A.to_scipy().tocoo()
+    for e in rng.choice(S.nnz, 4, replace=False):
+        h = 1e-6 * abs(S.data[e])
+        Lv = []
+        for sgn in (1, -1):
+            M = Ad.copy()
+            M[S.row[e], S.col[e]] += sgn * h
+            xx = np.linalg.solve(M, b)
+            Lv.append(np.sum((xx - xs) ** 2))
+        fd = (Lv[0] - Lv[1]) / (2 * h)
+        assert abs(fd - dval[e]) <= 1e-5 * max(1.0, abs(fd))
