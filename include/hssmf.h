@@ -1,0 +1,163 @@
+/*
+ * hssmf.h -- C ABI of an MI355X (gfx950) HSS-structured multifrontal sparse
+ * solver with randomized sampling.
+ *
+ * Method: Ghysels, Li, Rouet, Williams, Napov, "An efficient multi-core
+ * implementation of a novel HSS-structured multifrontal solver using
+ * randomized sampling" (arXiv 1502.07405).  The solver computes an (exact or
+ * HSS-approximate) multifrontal LU factorization of a general sparse
+ * non-singular matrix (Sec. 3, Sec. 4) and uses it inside iterative
+ * refinement or restarted GMRES (Sec. 4.5, Sec. 6.1) to solve A x = b.
+ *
+ * Conventions
+ *  - Every function returns HSSMF_OK (0) or a negative status code; no C++
+ *    exception crosses this boundary.  hssmf_strerror() names a code.
+ *  - Matrix and ordering arrays are HOST arrays owned by the caller; they are
+ *    read during the call only (copied / uploaded).
+ *  - Vector arguments of the solve functions are DEVICE pointers (HIP global
+ *    memory on the current device), owned by the caller.
+ *  - A handle owns all device memory of a factorization until
+ *    hssmf_destroy().  A handle is not thread-safe; calls on one handle must
+ *    not overlap.  All device work is enqueued on the stream given to
+ *    hssmf_factor (0 = the null stream); functions return after that stream
+ *    has drained (they synchronize when they need host-visible results).
+ *  - Indices are 0-based.
+ */
+#ifndef HSSMF_H
+#define HSSMF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define HSSMF_OK 0
+#define HSSMF_EINVAL (-1)    /* malformed CSR, ordering, options or arguments */
+#define HSSMF_ENOMEM (-2)    /* device or host allocation failed */
+#define HSSMF_ESINGULAR (-3) /* zero pivot in an F11 block or at an ULV top node */
+#define HSSMF_ERANK (-4)     /* adaptive sampling reached d_max (Sec. 2.2.1) */
+#define HSSMF_ENOCONV (-5)   /* outer solver did not reach tol within max_it */
+#define HSSMF_EDEVICE (-6)   /* HIP runtime error / no device */
+
+/* precision of the sampling and ULV products (pivoted QR / ID, the LU of
+ * F11 blocks and the refinement residual always stay FP64) */
+#define HSSMF_PREC_FP64 0
+#define HSSMF_PREC_FP32 1
+#define HSSMF_PREC_BF16 2
+
+#define HSSMF_OUTER_IR 0
+#define HSSMF_OUTER_GMRES 1
+
+/* Sparse matrix A (n x n) in CSR form, host memory.  rowptr has n+1 entries
+ * (rowptr[0] = 0, non-decreasing), colind/val have rowptr[n] entries; column
+ * indices lie in [0, n) and are unique within a row. */
+typedef struct {
+  int32_t n;
+  const int64_t* rowptr;
+  const int32_t* colind;
+  const double* val;
+} hssmf_csr;
+
+/* Fill-reducing nested-dissection ordering (Sec. 3.1) with its separator
+ * tree, host memory.  perm[new] = old (a permutation of 0..n-1).  Fronts are
+ * numbered in postorder (children before parents, parent[f] > f, -1 for a
+ * root); front f eliminates the new indices [sep_ptr[f], sep_ptr[f+1]);
+ * sep_ptr[0] = 0, sep_ptr[nfront] = n, non-decreasing.  Every off-diagonal
+ * coupling of P A P^T must join a front with itself or with an ancestor
+ * (the separator property); violations give HSSMF_EINVAL. */
+typedef struct {
+  const int32_t* perm;
+  int32_t nfront;
+  const int32_t* sep_ptr;
+  const int32_t* parent;
+} hssmf_ordering;
+
+/* Options.  Use hssmf_default_opts() and override fields. */
+typedef struct {
+  double rel_tol;      /* HSS compression tolerance eps: rank stops at
+                          |R_{i+1,i+1}| <= eps |R_11| (Sec. 5.4) */
+  int32_t leaf_size;   /* max HSS leaf size (Sec. 4.2, b) */
+  int32_t min_sep_hss; /* a front is HSS iff its separator has at least this
+                          many indices; large value = pure multifrontal */
+  int32_t d0;          /* initial number of random vectors (Sec. 2.2) */
+  int32_t dd;          /* growth step Delta d of the adaptive scheme (Sec. 4.3) */
+  int32_t p;           /* oversampling: an ID of rank k succeeds iff k <= d - p
+                          or k equals the node's row count */
+  int32_t d_max;       /* cap on d; reaching it gives HSSMF_ERANK */
+  uint64_t seed;       /* key of the counter-based Gaussian generator of R */
+  int32_t gemm_prec;   /* HSSMF_PREC_*: sampling / ULV product precision */
+  int32_t outer;       /* HSSMF_OUTER_IR or HSSMF_OUTER_GMRES */
+  int32_t restart;     /* GMRES restart length (30 in Sec. 6.1) */
+  double tol;          /* stop when ||b - A x||_2 / ||b||_2 <= tol */
+  int32_t max_it;      /* max refinement steps / GMRES iterations */
+} hssmf_opts;
+
+typedef struct {
+  int32_t iterations;    /* refinement steps or GMRES iterations */
+  double rel_residual;   /* final ||b - A x|| / ||b|| (FP64) */
+  int32_t failed_front;  /* front id for HSSMF_ESINGULAR, else -1 */
+} hssmf_info;
+
+typedef struct {
+  int32_t n, nfront, n_hss_fronts, max_rank, max_d, growth_rounds;
+  int64_t factor_bytes;     /* device bytes held by the factors */
+  double t_plan_ms, t_factor_ms;     /* host planning + upload, numeric factor */
+  double flops_factor;      /* algorithmic flops of the numeric factorization */
+} hssmf_stats;
+
+/* Fill *o with defaults: rel_tol 1e-6, leaf_size 64, min_sep_hss INT32_MAX
+ * (pure multifrontal), d0 128, dd 128, p 10, d_max 4096, seed 0, FP64,
+ * iterative refinement, restart 30, tol 1e-10, max_it 50. */
+int hssmf_default_opts(hssmf_opts* o);
+
+/* Symbolic analysis, upload and numeric factorization (Sec. 3.2, Sec. 4).
+ * stream: a hipStream_t (may be 0).  On success *out receives a new handle.
+ * Errors: EINVAL (bad CSR / ordering / options), ENOMEM, ESINGULAR (zero
+ * pivot; the front is reported by hssmf_last_failed_front), ERANK, EDEVICE. */
+int hssmf_factor(const hssmf_csr* A, const hssmf_ordering* ord, const hssmf_opts* opts,
+                 void* stream, void** out);
+
+/* Re-run the numeric factorization with new values (same pattern as the
+ * matrix given to hssmf_factor; val has rowptr[n] entries, host memory). */
+int hssmf_refactor(void* h, const double* val);
+
+/* One application of the factorization, y = M^{-1} x (trans = 0) or
+ * y = M^{-T} x (trans = 1): the multifrontal forward sweep bottom-up and the
+ * backward sweep top-down (Sec. 3.3), with ULV solves on HSS fronts.  x, y:
+ * device arrays of n doubles (may alias). */
+int hssmf_apply(void* h, int32_t trans, const double* x, double* y);
+
+/* Solve A x = b with the outer solver of the options (Sec. 4.5): b, x are
+ * device arrays of n doubles.  ENOCONV still writes the best x and fills
+ * info. */
+int hssmf_solve(void* h, const double* b, double* x, hssmf_info* info);
+
+/* Solve A^T lambda = g with the same factors (transposed sweeps). */
+int hssmf_solve_transpose(void* h, const double* g, double* lambda, hssmf_info* info);
+
+/* Adjoint of x = A^{-1} b for a scalar loss L with gradient g = dL/dx:
+ * lambda = A^{-T} g, dl_db = lambda, dl_dval[e] = -lambda[row(e)] x[col(e)]
+ * for every CSR entry e.  x, g, dl_db: device arrays of n doubles; dl_dval:
+ * device array of nnz doubles. */
+int hssmf_adjoint(void* h, const double* x, const double* g, double* dl_db, double* dl_dval,
+                  hssmf_info* info);
+
+int hssmf_stats_get(void* h, hssmf_stats* s);
+
+/* Per HSS front (in front order) write up to cap records of 5 int32:
+ * front id, max row rank, max column rank, final d, growth rounds.  Returns
+ * the number of HSS fronts (>= 0) or a status code. */
+int hssmf_hss_ranks(void* h, int32_t* out, int32_t cap);
+
+int hssmf_last_failed_front(void* h);
+
+void hssmf_destroy(void* h);
+
+const char* hssmf_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HSSMF_H */

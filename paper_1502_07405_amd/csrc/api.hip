@@ -1,0 +1,501 @@
+// C ABI (include/hssmf.h): setup of a factorization (plan, uploads, maps,
+// HSS trees), numeric refactorization, preconditioner application, the
+// outer solvers (iterative refinement, restarted GMRES with modified
+// Gram-Schmidt, Sec. 4.5 / Sec. 6.1), transpose solve and adjoint.
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <functional>
+
+#include "solver.hpp"
+#include "vec.hpp"
+
+using namespace hssmf;
+
+namespace {
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+template <class T>
+T* upload_big(Handle& h, const T* src, size_t n) {
+  T* d = h.cur->get<T>(n);
+  if (n) HIP_CHECK(hipMemcpy(d, src, n * sizeof(T), hipMemcpyHostToDevice));
+  return d;
+}
+template <class T>
+T* upload_big(Handle& h, const std::vector<T>& v) {
+  return upload_big(h, v.data(), v.size());
+}
+
+int split(std::vector<HNode>& nd, int lo, int hi, int leaf) {
+  if (hi - lo <= leaf) {
+    HNode x;
+    x.lo = lo; x.hi = hi; x.height = 0;
+    nd.push_back(x);
+    return (int)nd.size() - 1;
+  }
+  int mid = lo + (hi - lo + 1) / 2;
+  int a = split(nd, lo, mid, leaf);
+  int b = split(nd, mid, hi, leaf);
+  HNode x;
+  x.lo = lo; x.hi = hi;
+  x.kid[0] = a; x.kid[1] = b;
+  x.height = 1 + std::max(nd[a].height, nd[b].height);
+  nd.push_back(x);
+  int id = (int)nd.size() - 1;
+  nd[a].parent = nd[b].parent = id;
+  return id;
+}
+
+void setup(Handle& h, const hssmf_csr* A) {
+  Plan& P = h.P;
+  h.cur = &h.arena;
+  h.stager.init(size_t(64) << 20);
+  const int n = P.n;
+  const int64_t nnz = P.nnz;
+  h.d_rowptr = upload_big(h, A->rowptr, (size_t)n + 1);
+  h.d_colind = upload_big(h, A->colind, (size_t)nnz);
+  h.d_val = upload_big(h, A->val, (size_t)nnz);
+  // A^T in CSR over the caller's ordering, values through an index
+  {
+    std::vector<int64_t> tr(n + 1, 0), tv(nnz);
+    std::vector<int> tc(nnz), row(nnz);
+    for (int i = 0; i < n; ++i)
+      for (int64_t e = A->rowptr[i]; e < A->rowptr[i + 1]; ++e) { tr[A->colind[e] + 1]++; row[e] = i; }
+    for (int i = 0; i < n; ++i) tr[i + 1] += tr[i];
+    std::vector<int64_t> fill(tr.begin(), tr.end() - 1);
+    for (int i = 0; i < n; ++i)
+      for (int64_t e = A->rowptr[i]; e < A->rowptr[i + 1]; ++e) {
+        int64_t p = fill[A->colind[e]]++;
+        tc[p] = i;
+        tv[p] = e;
+      }
+    h.d_trowptr = upload_big(h, tr);
+    h.d_tcolind = upload_big(h, tc);
+    h.d_tvidx = upload_big(h, tv);
+    h.d_row = upload_big(h, row);
+    h.d_col = h.d_colind;
+  }
+  h.d_perm = upload_big(h, P.perm);
+  h.d_iperm = upload_big(h, P.iperm);
+  h.yws = h.arena.get<double>(n);
+  h.d_scal = h.arena.get<double>(1024);
+  h.d_part = h.arena.get<double>(kDotParts);
+  h.d_info = h.arena.get<int>(2);
+  h.fr.assign(P.nfront, FrontRT());
+  // per-front maps
+  for (int f = 0; f < P.nfront; ++f) {
+    const FrontPlan& fp = P.fr[f];
+    FrontRT& R = h.fr[f];
+    R.d_upd = upload_big(h, fp.upd);
+    R.w = h.arena.get<double>(std::max(fp.u, 1));
+    for (size_t k = 0; k < fp.kids.size(); ++k) {
+      R.d_kidmap[k] = upload_big(h, fp.kidmap[k]);
+      std::vector<int> inv(fp.n, -1);
+      for (size_t t = 0; t < fp.kidmap[k].size(); ++t) inv[fp.kidmap[k][t]] = (int)t;
+      R.d_inv[k] = upload_big(h, inv);
+    }
+  }
+  // dense fronts: one buffer per level, assembly maps in level order
+  std::vector<int64_t> adst, asrc;
+  h.level_buf.assign(P.levels.size(), nullptr);
+  for (size_t lev = 0; lev < P.levels.size(); ++lev) {
+    int64_t total = 0;
+    for (int f : P.levels[lev])
+      if (!P.fr[f].hss) total += (int64_t)P.fr[f].n * P.fr[f].n;
+    if (total == 0) continue;
+    double* buf = h.arena.get<double>(total);
+    h.level_buf[lev] = buf;
+    int64_t off = 0;
+    for (int f : P.levels[lev]) {
+      const FrontPlan& fp = P.fr[f];
+      if (fp.hss) continue;
+      FrontRT& R = h.fr[f];
+      R.F = buf + off;
+      R.ipiv = h.arena.get<int>(std::max(fp.s, 1));
+      R.U = R.F + (int64_t)fp.s * (fp.n + 1);
+      R.ldu = fp.n;
+      LocalCSR L;
+      front_local_csr(P, fp, false, L);
+      R.asm_off = (int64_t)adst.size();
+      for (int r = 0; r < fp.n; ++r)
+        for (int e = L.rowptr[r]; e < L.rowptr[r + 1]; ++e) {
+          adst.push_back(off + r + (int64_t)L.col[e] * fp.n);
+          asrc.push_back(L.vidx[e]);
+        }
+      R.asm_cnt = (int64_t)adst.size() - R.asm_off;
+      off += (int64_t)fp.n * fp.n;
+    }
+  }
+  h.d_asm_dst = upload_big(h, adst);
+  h.d_asm_src = upload_big(h, asrc);
+  // HSS fronts
+  for (int f = 0; f < P.nfront; ++f) {
+    const FrontPlan& fp = P.fr[f];
+    if (!fp.hss) continue;
+    h.fr[f].hidx = (int)h.hf.size();
+    h.hf.emplace_back();
+    HFront& F = h.hf.back();
+    F.f = f; F.n = fp.n; F.s = fp.s; F.u = fp.u;
+    const int leaf = std::max(1, h.o.leaf_size);
+    F.k = split(F.nd, 0, fp.s, leaf);
+    if (fp.u > 0) {
+      F.q = split(F.nd, fp.s, fp.n, leaf);
+      HNode rt;
+      rt.lo = 0; rt.hi = fp.n;
+      rt.kid[0] = F.k; rt.kid[1] = F.q;
+      rt.height = 1 + std::max(F.nd[F.k].height, F.nd[F.q].height);
+      F.nd.push_back(rt);
+      F.root = (int)F.nd.size() - 1;
+      F.nd[F.k].parent = F.nd[F.q].parent = F.root;
+    } else {
+      F.root = F.k;
+      F.q = -1;
+    }
+    F.maxh = F.nd[F.root].height;
+    std::vector<int> orig(fp.n);
+    for (int i = 0; i < fp.s; ++i) orig[i] = P.perm[fp.lo + i];
+    for (int i = 0; i < fp.u; ++i) orig[fp.s + i] = P.perm[fp.upd[i]];
+    F.orig = upload_big(h, orig);
+    LocalCSR L, T;
+    front_local_csr(P, fp, false, L);
+    front_local_csr(P, fp, true, T);
+    F.a_row = upload_big(h, L.rowptr);
+    F.a_col = upload_big(h, L.col);
+    F.a_vidx = upload_big(h, L.vidx);
+    F.at_row = upload_big(h, T.rowptr);
+    F.at_col = upload_big(h, T.col);
+    F.at_vidx = upload_big(h, T.vidx);
+  }
+  HIP_CHECK(hipDeviceSynchronize());
+}
+
+void numeric(Handle& h) {
+  HIP_CHECK(hipStreamSynchronize(h.st));
+  h.stager.sync();
+  h.narena.release();
+  h.cur = &h.narena;
+  double t0 = now_ms();
+  numeric_factor(h);
+  build_solve_ops(h);
+  HIP_CHECK(hipStreamSynchronize(h.st));
+  h.stager.sync();
+  h.stats.t_factor_ms = now_ms() - t0;
+  h.cur = &h.arena;
+  // statistics
+  int maxr = 0, maxd = 0, rounds = 0;
+  for (auto& F : h.hf) {
+    for (auto& nd : F.nd) maxr = std::max(maxr, std::max(nd.r, nd.c));
+    maxd = std::max(maxd, F.d);
+    rounds += F.rounds;
+  }
+  h.stats.max_rank = maxr;
+  h.stats.max_d = maxd;
+  h.stats.growth_rounds = rounds;
+  h.stats.factor_bytes = (int64_t)(h.arena.used() + h.narena.used());
+}
+
+}  // namespace
+
+namespace {
+thread_local int g_failed_front = -1;
+
+int guard_impl(Handle* h, const std::function<void()>& fn) {
+  try {
+    fn();
+    return HSSMF_OK;
+  } catch (const Error& e) {
+    if (e.front >= 0) {
+      g_failed_front = e.front;
+      if (h) h->failed_front = e.front;
+    }
+    if (std::getenv("HSSMF_VERBOSE")) std::fprintf(stderr, "hssmf: %s\n", e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    return HSSMF_ENOMEM;
+  } catch (const std::exception& e) {
+    if (std::getenv("HSSMF_VERBOSE")) std::fprintf(stderr, "hssmf: %s\n", e.what());
+    return HSSMF_EDEVICE;
+  }
+}
+
+// restarted, left-preconditioned GMRES(m) with modified Gram-Schmidt on the
+// device and Givens rotations on the host; x0 = 0; stops on the true
+// relative residual
+int gmres(Handle& h, int trans, const double* b, double* x, hssmf_info* info) {
+  const int n = h.P.n, m = std::max(1, std::min(h.o.restart, 200));
+  Arena::Mark mk = h.arena.mark();
+  double* V = h.arena.get<double>((size_t)n * (m + 1));
+  double* w = h.arena.get<double>(n);
+  double* r = h.arena.get<double>(n);
+  double* hcol = h.d_scal;  // m+2 device scalars
+  const double nb = dnrm2(h, b, n);
+  HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * n, h.st));
+  if (nb == 0.0) {
+    if (info) { info->iterations = 0; info->rel_residual = 0; }
+    h.arena.reset(mk);
+    return HSSMF_OK;
+  }
+  int its = 0;
+  double rel = 1.0, beta0 = -1.0;
+  std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  auto true_res = [&](const double* xx) {
+    spmv(h, trans, xx, r, -1.0, 0.0);
+    launch_axpy(r, b, n, nullptr, 1.0, 0, h.st);
+    return dnrm2(h, r, n) / nb;
+  };
+  while (its < h.o.max_it) {
+    // r = M^{-1} (b - A x)
+    spmv(h, trans, x, r, -1.0, 0.0);
+    launch_axpy(r, b, n, nullptr, 1.0, 0, h.st);
+    apply_inverse(h, trans, r, w);
+    double beta = dnrm2(h, w, n);
+    if (beta0 < 0) beta0 = beta;
+    if (beta == 0.0) break;
+    HIP_CHECK(hipMemcpyAsync(hcol, &beta, sizeof(double), hipMemcpyHostToDevice, h.st));
+    launch_axpy(V, w, n, hcol, 1.0, 1, h.st);  // v0 = w / beta
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jd = 0;
+    bool done = false;
+    for (int j = 0; j < m && its < h.o.max_it; ++j) {
+      double* vj = V + (size_t)j * n;
+      spmv(h, trans, vj, r, 1.0, 0.0);
+      apply_inverse(h, trans, r, w);
+      for (int i = 0; i <= j; ++i) {
+        launch_dot(w, V + (size_t)i * n, n, h.d_part, hcol + i, 0, h.st);
+        launch_axpy(w, V + (size_t)i * n, n, hcol + i, -1.0, 0, h.st);
+      }
+      launch_dot(w, w, n, h.d_part, hcol + j + 1, 1, h.st);
+      launch_axpy(V + (size_t)(j + 1) * n, w, n, hcol + j + 1, 1.0, 1, h.st);
+      std::vector<double> hc(j + 2);
+      HIP_CHECK(hipMemcpyAsync(hc.data(), hcol, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, h.st));
+      HIP_CHECK(hipStreamSynchronize(h.st));
+      h.stager.sync();
+      for (int i = 0; i < j; ++i) {
+        double t = cs[i] * hc[i] + sn[i] * hc[i + 1];
+        hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
+        hc[i] = t;
+      }
+      double den = std::hypot(hc[j], hc[j + 1]);
+      cs[j] = hc[j] / den;
+      sn[j] = hc[j + 1] / den;
+      hc[j] = den;
+      hc[j + 1] = 0.0;
+      for (int i = 0; i <= j; ++i) H[i + (size_t)j * (m + 1)] = hc[i];
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++its;
+      jd = j + 1;
+      bool est = std::fabs(g[j + 1]) <= h.o.tol * beta0;
+      if (est || its >= h.o.max_it || j == m - 1) {
+        // x_t = x + V y
+        for (int i = jd - 1; i >= 0; --i) {
+          double s = g[i];
+          for (int l = i + 1; l < jd; ++l) s -= H[i + (size_t)l * (m + 1)] * y[l];
+          y[i] = s / H[i + (size_t)i * (m + 1)];
+        }
+        HIP_CHECK(hipMemcpyAsync(w, x, sizeof(double) * n, hipMemcpyDeviceToDevice, h.st));
+        HIP_CHECK(hipMemcpyAsync(hcol + m + 2, y.data(), sizeof(double) * jd, hipMemcpyHostToDevice, h.st));
+        for (int i = 0; i < jd; ++i) launch_axpy(w, V + (size_t)i * n, n, hcol + m + 2 + i, 1.0, 0, h.st);
+        rel = true_res(w);
+        if (rel <= h.o.tol || j == m - 1 || its >= h.o.max_it) {
+          HIP_CHECK(hipMemcpyAsync(x, w, sizeof(double) * n, hipMemcpyDeviceToDevice, h.st));
+          if (rel <= h.o.tol) done = true;
+          break;
+        }
+      }
+    }
+    (void)jd;
+    if (done) break;
+  }
+  HIP_CHECK(hipStreamSynchronize(h.st));
+  h.arena.reset(mk);
+  if (info) { info->iterations = its; info->rel_residual = rel; }
+  return rel <= h.o.tol ? HSSMF_OK : HSSMF_ENOCONV;
+}
+
+int refine(Handle& h, int trans, const double* b, double* x, hssmf_info* info) {
+  const int n = h.P.n;
+  Arena::Mark mk = h.arena.mark();
+  double* r = h.arena.get<double>(n);
+  double* z = h.arena.get<double>(n);
+  const double nb = dnrm2(h, b, n);
+  apply_inverse(h, trans, b, x);
+  double rel = 0.0;
+  int it = 0;
+  for (;; ++it) {
+    spmv(h, trans, x, r, -1.0, 0.0);
+    launch_axpy(r, b, n, nullptr, 1.0, 0, h.st);
+    rel = nb > 0 ? dnrm2(h, r, n) / nb : 0.0;
+    if (rel <= h.o.tol || it >= h.o.max_it) break;
+    apply_inverse(h, trans, r, z);
+    launch_axpy(x, z, n, nullptr, 1.0, 0, h.st);
+  }
+  HIP_CHECK(hipStreamSynchronize(h.st));
+  h.arena.reset(mk);
+  if (info) { info->iterations = it; info->rel_residual = rel; info->failed_front = -1; }
+  return rel <= h.o.tol ? HSSMF_OK : HSSMF_ENOCONV;
+}
+
+int outer(Handle& h, int trans, const double* b, double* x, hssmf_info* info) {
+  if (info) { info->iterations = 0; info->rel_residual = 0; info->failed_front = -1; }
+  return h.o.outer == HSSMF_OUTER_GMRES ? gmres(h, trans, b, x, info) : refine(h, trans, b, x, info);
+}
+
+}  // namespace
+
+extern "C" {
+
+int hssmf_default_opts(hssmf_opts* o) {
+  if (!o) return HSSMF_EINVAL;
+  std::memset(o, 0, sizeof(*o));
+  o->rel_tol = 1e-6;
+  o->leaf_size = 64;
+  o->min_sep_hss = INT32_MAX;
+  o->d0 = 128;
+  o->dd = 128;
+  o->p = 10;
+  o->d_max = 4096;
+  o->seed = 0;
+  o->gemm_prec = HSSMF_PREC_FP64;
+  o->outer = HSSMF_OUTER_IR;
+  o->restart = 30;
+  o->tol = 1e-10;
+  o->max_it = 50;
+  return HSSMF_OK;
+}
+
+int hssmf_factor(const hssmf_csr* A, const hssmf_ordering* ord, const hssmf_opts* opts, void* stream, void** out) {
+  if (!out || !A || !ord || !opts) return HSSMF_EINVAL;
+  *out = nullptr;
+  if (opts->leaf_size < 1 || opts->d0 < 1 || opts->dd < 1 || opts->p < 0 || opts->d_max < opts->d0 ||
+      !(opts->rel_tol >= 0.0) || opts->restart < 1 || opts->max_it < 0 || opts->gemm_prec < 0 ||
+      opts->gemm_prec > 2)
+    return HSSMF_EINVAL;
+  Handle* h = new (std::nothrow) Handle();
+  if (!h) return HSSMF_ENOMEM;
+  int rc = guard_impl(h, [&]() {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) throw Error(HSSMF_EDEVICE, "no HIP device");
+    HIP_CHECK(hipGetDevice(&h->device));
+    h->o = *opts;
+    h->st = static_cast<hipStream_t>(stream);
+    double t0 = now_ms();
+    build_plan(A, ord, opts, h->P);
+    setup(*h, A);
+    h->stats.t_plan_ms = now_ms() - t0;
+    h->stats.n = h->P.n;
+    h->stats.nfront = h->P.nfront;
+    h->stats.n_hss_fronts = (int)h->hf.size();
+    numeric(*h);
+  });
+  if (rc != HSSMF_OK) {
+    delete h;
+    return rc;
+  }
+  g_failed_front = -1;
+  *out = h;
+  return HSSMF_OK;
+}
+
+int hssmf_refactor(void* hv, const double* val) {
+  Handle* h = static_cast<Handle*>(hv);
+  if (!h || !val) return HSSMF_EINVAL;
+  return guard_impl(h, [&]() {
+    HIP_CHECK(hipMemcpyAsync(h->d_val, val, sizeof(double) * h->P.nnz, hipMemcpyHostToDevice, h->st));
+    numeric(*h);
+  });
+}
+
+int hssmf_apply(void* hv, int32_t trans, const double* x, double* y) {
+  Handle* h = static_cast<Handle*>(hv);
+  if (!h || !x || !y || (trans != 0 && trans != 1)) return HSSMF_EINVAL;
+  return guard_impl(h, [&]() {
+    apply_inverse(*h, trans, x, y);
+    HIP_CHECK(hipStreamSynchronize(h->st));
+    h->stager.sync();
+  });
+}
+
+int hssmf_solve(void* hv, const double* b, double* x, hssmf_info* info) {
+  Handle* h = static_cast<Handle*>(hv);
+  if (!h || !b || !x) return HSSMF_EINVAL;
+  int out = HSSMF_OK;
+  int rc = guard_impl(h, [&]() { out = outer(*h, 0, b, x, info); });
+  return rc != HSSMF_OK ? rc : out;
+}
+
+int hssmf_solve_transpose(void* hv, const double* g, double* lam, hssmf_info* info) {
+  Handle* h = static_cast<Handle*>(hv);
+  if (!h || !g || !lam) return HSSMF_EINVAL;
+  int out = HSSMF_OK;
+  int rc = guard_impl(h, [&]() { out = outer(*h, 1, g, lam, info); });
+  return rc != HSSMF_OK ? rc : out;
+}
+
+int hssmf_adjoint(void* hv, const double* x, const double* g, double* dl_db, double* dl_dval, hssmf_info* info) {
+  Handle* h = static_cast<Handle*>(hv);
+  if (!h || !x || !g || !dl_db || !dl_dval) return HSSMF_EINVAL;
+  int out = HSSMF_OK;
+  int rc = guard_impl(h, [&]() {
+    out = outer(*h, 1, g, dl_db, info);
+    launch_adjoint_grad(h->d_row, h->d_col, dl_db, x, dl_dval, h->P.nnz, h->st);
+    HIP_CHECK(hipStreamSynchronize(h->st));
+  });
+  return rc != HSSMF_OK ? rc : out;
+}
+
+int hssmf_stats_get(void* hv, hssmf_stats* s) {
+  Handle* h = static_cast<Handle*>(hv);
+  if (!h || !s) return HSSMF_EINVAL;
+  *s = h->stats;
+  return HSSMF_OK;
+}
+
+int hssmf_hss_ranks(void* hv, int32_t* out, int32_t cap) {
+  Handle* h = static_cast<Handle*>(hv);
+  if (!h || (cap > 0 && !out)) return HSSMF_EINVAL;
+  int i = 0;
+  for (auto& F : h->hf) {
+    if (i < cap) {
+      int mr = 0, mc = 0;
+      for (auto& nd : F.nd) { mr = std::max(mr, nd.r); mc = std::max(mc, nd.c); }
+      int32_t* o = out + 5 * i;
+      o[0] = F.f; o[1] = mr; o[2] = mc; o[3] = F.d; o[4] = F.rounds;
+    }
+    ++i;
+  }
+  return i;
+}
+
+int hssmf_last_failed_front(void* hv) {
+  Handle* h = static_cast<Handle*>(hv);
+  return h ? h->failed_front : g_failed_front;
+}
+
+void hssmf_destroy(void* hv) {
+  Handle* h = static_cast<Handle*>(hv);
+  if (!h) return;
+  (void)hipStreamSynchronize(h->st);
+  delete h;
+}
+
+const char* hssmf_strerror(int code) {
+  switch (code) {
+    case HSSMF_OK: return "ok";
+    case HSSMF_EINVAL: return "invalid argument";
+    case HSSMF_ENOMEM: return "out of memory";
+    case HSSMF_ESINGULAR: return "zero pivot";
+    case HSSMF_ERANK: return "HSS rank exceeds d_max";
+    case HSSMF_ENOCONV: return "no convergence";
+    case HSSMF_EDEVICE: return "device error";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,117 @@
+// Shared host/device definitions of the HIP library: status handling,
+// device memory arena, launch descriptors.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/hssmf.h"
+
+namespace hssmf {
+
+struct Error : std::runtime_error {
+  int code;
+  int front;
+  Error(int c, const std::string& m, int f = -1) : std::runtime_error(m), code(c), front(f) {}
+};
+
+#define HIP_CHECK(expr)                                                                  \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      throw ::hssmf::Error(HSSMF_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+#define REQUIRE(cond, code, msg)                  \
+  do {                                            \
+    if (!(cond)) throw ::hssmf::Error(code, msg); \
+  } while (0)
+
+// Bump allocator over large device chunks.  Everything a factorization
+// holds lives here and is released at once.  Chunks go back to a process
+// wide cache so repeated factorizations do not pay hipMalloc again.
+class Arena {
+ public:
+  ~Arena() { release(); }
+  void* alloc(size_t bytes, size_t align = 256);
+  template <class T>
+  T* get(size_t n) {
+    return static_cast<T*>(alloc(sizeof(T) * (n ? n : 1)));
+  }
+  void release();
+  size_t used() const { return used_; }
+  // scoped marks: everything allocated after mark() is reclaimed by reset()
+  struct Mark {
+    size_t chunk, off, used;
+  };
+  Mark mark() const { return {chunks_.empty() ? 0 : chunks_.size() - 1, off_, used_}; }
+  void reset(const Mark& m);
+
+ private:
+  struct Chunk {
+    char* p;
+    size_t size;
+  };
+  std::vector<Chunk> chunks_;
+  size_t off_ = 0;
+  size_t used_ = 0;
+};
+
+// --- batched GEMM descriptor ------------------------------------------------
+// C(m x n) = alpha * op(A) op(B) + beta * C, column major.  Optional row maps:
+// op(A) row i reads A row amap[i] (transA == 0 only), op(B) row kk reads B
+// row bmap[kk] (transB == 0 only), C row i is C row cmap[i].
+struct GemmDesc {
+  const void* A;
+  const void* B;
+  void* C;
+  const int* amap;
+  const int* bmap;
+  const int* cmap;
+  int m, n, k;
+  int lda, ldb, ldc;
+  int transA, transB;
+  double alpha, beta;
+  int tiles_m, tiles_n;
+  int64_t tile_base;
+};
+
+// input precision of A and B / storage of C
+enum GemmType {
+  GEMM_F64 = 0,     // double x double -> double (FP64 MFMA)
+  GEMM_F32 = 1,     // float x float -> float (FP32 MFMA)
+  GEMM_F32_D = 2,   // float x float -> double C
+  GEMM_BF16 = 3,    // bf16 x bf16 -> float (FP32 accumulation)
+  GEMM_BF16_D = 4,  // bf16 x bf16 -> double C
+};
+
+// launch a batch of GEMMs (descriptors in host memory; staged to the device)
+class Stager;
+void gemm_batched(const std::vector<GemmDesc>& d, GemmType t, Stager& st, hipStream_t s);
+
+// Pinned host ring + device mirror for per-launch descriptor arrays.
+class Stager {
+ public:
+  Stager() = default;
+  ~Stager();
+  void init(size_t bytes);
+  // copy host bytes to device memory valid until the next sync()
+  void* put(const void* src, size_t bytes, hipStream_t s);
+  template <class T>
+  T* put_vec(const std::vector<T>& v, hipStream_t s) {
+    return static_cast<T*>(put(v.data(), v.size() * sizeof(T), s));
+  }
+  // caller guarantees the stream has drained
+  void sync() { off_ = 0; }
+
+ private:
+  char* host_ = nullptr;
+  char* dev_ = nullptr;
+  size_t cap_ = 0, off_ = 0;
+};
+
+}  // namespace hssmf

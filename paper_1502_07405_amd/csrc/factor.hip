@@ -1,0 +1,816 @@
+// Numeric multifrontal factorization on the GPU (Sec. 3.2 and Sec. 4).
+//
+// Fronts are processed by elimination-tree height, all fronts of one height
+// together.  Dense fronts: zero fill, assembly of original entries,
+// extend-add of the children's update matrices (one launch per child slot),
+// batched blocked partial LU.  HSS fronts: keyed random matrix, samples
+// F R and F^T R by skinny extend-add (sparse product plus GEMMs with the
+// children's update matrices through row maps), Alg. 1 bottom-up over the
+// HSS levels with the adaptive-rank loop, ULV-like factorization of F11,
+// the low-rank Schur product Theta^* Phi and the update matrix
+// F22 - Theta^* Phi for the parent.  Only ranks and pivot orders of the IDs
+// come back to the host (one synchronization per HSS level).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "solver.hpp"
+
+namespace hssmf {
+
+GemmType Handle::gt() const { return GEMM_F64; }
+
+namespace {
+
+GemmDesc G(const void* A, int lda, int tA, const void* B, int ldb, int tB, void* C, int ldc, int m, int n, int k,
+           double al, double be, const int* bmap = nullptr, const int* cmap = nullptr, const int* amap = nullptr) {
+  GemmDesc g{};
+  g.A = A; g.B = B; g.C = C;
+  g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+  g.transA = tA; g.transB = tB;
+  g.m = m; g.n = n; g.k = k;
+  g.alpha = al; g.beta = be;
+  g.amap = amap; g.bmap = bmap; g.cmap = cmap;
+  return g;
+}
+
+CopyDesc Cp(const void* src, int lds, const int* rmap, void* dst, int ldd, int m, int n, int acc = 0,
+            double alpha = 1.0, const int* cmap = nullptr, int trans = 0) {
+  CopyDesc c{};
+  c.src = src; c.dst = dst; c.rmap = rmap; c.cmap = cmap;
+  c.m = m; c.n = n; c.lds = lds; c.ldd = ldd;
+  c.accumulate = acc; c.trans = trans; c.alpha = alpha;
+  return c;
+}
+
+void run_gemm(Handle& h, const std::vector<GemmDesc>& v, GemmType t = GEMM_F64) {
+  if (!v.empty()) gemm_batched(v, t, h.stager, h.st);
+}
+
+void run_copy(Handle& h, const std::vector<CopyDesc>& v) {
+  std::vector<CopyDesc> w;
+  int64_t mx = 0;
+  for (auto& c : v)
+    if (c.m > 0 && c.n > 0) { w.push_back(c); mx = std::max<int64_t>(mx, (int64_t)c.m * c.n); }
+  if (w.empty()) return;
+  launch_copy(h.stager.put_vec(w, h.st), (int)w.size(), mx, 0, h.st);
+}
+
+void run_extract(Handle& h, const std::vector<ExtractDesc>& v, const FrontOpDev* fops) {
+  std::vector<ExtractDesc> w;
+  int64_t mx = 0;
+  for (auto& c : v)
+    if (c.m > 0 && c.n > 0) { w.push_back(c); mx = std::max<int64_t>(mx, (int64_t)c.m * c.n); }
+  if (w.empty()) return;
+  launch_extract(h.stager.put_vec(w, h.st), (int)w.size(), fops, mx, h.st);
+}
+
+void run_interp(Handle& h, const std::vector<InterpDesc>& v) {
+  std::vector<InterpDesc> w;
+  int64_t mx = 0;
+  for (auto& c : v)
+    if (c.m > 0 && c.k > 0) { w.push_back(c); mx = std::max<int64_t>(mx, (int64_t)c.m * c.k); }
+  if (w.empty()) return;
+  launch_interp_dense(h.stager.put_vec(w, h.st), (int)w.size(), mx, h.st);
+}
+
+}  // namespace
+
+// ------------------------------------------------------- blocked LU -------
+constexpr int NB = 32;
+
+void blocked_lu(Handle& h, const std::vector<LUFront>& fronts) {
+  if (fronts.empty()) return;
+  LUFront* d = upload(h, fronts);
+  int maxs = 0, maxn = 0;
+  for (auto& f : fronts) { maxs = std::max(maxs, f.s); maxn = std::max(maxn, f.n); }
+  const int nf = (int)fronts.size();
+  for (int jb = 0; jb < maxs; jb += NB) {
+    launch_lu_panel(d, nf, jb, NB, h.d_info, h.st);
+    launch_laswp(d, nf, jb, NB, maxn, h.st);
+    launch_trsm_u12(d, nf, jb, NB, maxn, h.st);
+    std::vector<GemmDesc> g;
+    for (auto& f : fronts) {
+      if (jb >= f.s) continue;
+      int w = std::min(NB, f.s - jb);
+      int m2 = f.n - jb - w;
+      if (m2 <= 0) continue;
+      const int64_t ld = f.ld;
+      g.push_back(G(f.F + (jb + w) + jb * ld, f.ld, 0, f.F + jb + (jb + w) * ld, f.ld, 0,
+                    f.F + (jb + w) + (jb + w) * ld, f.ld, m2, m2, w, -1.0, 1.0));
+    }
+    run_gemm(h, g);
+  }
+}
+
+// X := op(T)^{-1} X for a triangular T (n x n), X n x ncols; blocks of 64
+// solved by trsm_block, off-diagonal blocks applied with GEMMs
+void tri_solve_many(Handle& h, const double* T, int ldt, int n, double* X, int ldx, int ncols, bool lower,
+                    bool unit, bool trans) {
+  if (n <= 0 || ncols <= 0) return;
+  auto run_block = [&](int b0, int bs) {
+    TrsmDesc td{T, X, n, ncols, ldt, ldx, b0, bs};
+    TrsmDesc* dd = static_cast<TrsmDesc*>(h.stager.put(&td, sizeof(td), h.st));
+    launch_trsm_block(dd, 1, lower, unit, trans, ncols, h.st);
+  };
+  // logical T(i,j) = trans ? T[j,i] : T[i,j]; the block (rows R, cols C)
+  // of the logical matrix as a GEMM operand
+  auto blk = [&](int r0, int c0) -> const double* {
+    return trans ? T + c0 + (int64_t)r0 * ldt : T + r0 + (int64_t)c0 * ldt;
+  };
+  if (lower) {
+    for (int b0 = 0; b0 < n; b0 += 64) {
+      int bs = std::min(64, n - b0);
+      run_block(b0, bs);
+      int rest = n - b0 - bs;
+      if (rest > 0)
+        run_gemm(h, {G(blk(b0 + bs, b0), ldt, trans, X + b0, ldx, 0, X + b0 + bs, ldx, rest, ncols, bs, -1.0, 1.0)});
+    }
+  } else {
+    for (int b1 = n; b1 > 0; b1 -= 64) {
+      int b0 = std::max(0, b1 - 64), bs = b1 - b0;
+      run_block(b0, bs);
+      if (b0 > 0) run_gemm(h, {G(blk(0, b0), ldt, trans, X + b0, ldx, 0, X, ldx, b0, ncols, bs, -1.0, 1.0)});
+    }
+  }
+}
+
+// ------------------------------------------------------------ HSS ---------
+namespace {
+
+struct NRef {
+  HFront* F;
+  int t;
+  HNode& n() const { return F->nd[t]; }
+};
+
+double* dalloc(Handle& h, int64_t n) { return h.cur->get<double>((size_t)std::max<int64_t>(n, 1)); }
+int* ialloc(Handle& h, int64_t n) { return h.cur->get<int>((size_t)std::max<int64_t>(n, 1)); }
+
+// allocate / grow R, S^r, S^c of a front to hold dnew columns
+void grow_samples(Handle& h, HFront& F, int dnew) {
+  if (dnew <= F.dcap) return;
+  int cap = dnew;
+  double* R = dalloc(h, (int64_t)F.n * cap);
+  double* Sr = dalloc(h, (int64_t)F.n * cap);
+  double* Sc = dalloc(h, (int64_t)F.n * cap);
+  if (F.R && F.d > 0) {
+    size_t bytes = sizeof(double) * (size_t)F.n * F.d;
+    HIP_CHECK(hipMemcpyAsync(R, F.R, bytes, hipMemcpyDeviceToDevice, h.st));
+    HIP_CHECK(hipMemcpyAsync(Sr, F.Sr, bytes, hipMemcpyDeviceToDevice, h.st));
+    HIP_CHECK(hipMemcpyAsync(Sc, F.Sc, bytes, hipMemcpyDeviceToDevice, h.st));
+  }
+  F.R = R; F.Sr = Sr; F.Sc = Sc;
+  F.dcap = cap;
+}
+
+// columns [c0, c0+nc) of S^r = F R and S^c = F^T R (Eq. FtimesR): the
+// original entries by a sparse product, each child's update matrix by one
+// GEMM whose B rows and C rows go through the child-to-parent map
+void sample(Handle& h, const std::vector<HFront*>& fs, const std::vector<int>& c0, int nc) {
+  std::vector<SpmmDesc> sp;
+  int maxr = 0;
+  for (size_t i = 0; i < fs.size(); ++i) {
+    HFront& F = *fs[i];
+    const int64_t off = (int64_t)c0[i] * F.n;
+    sp.push_back({{F.a_row, F.a_col, F.a_vidx}, h.d_val, F.R + off, F.Sr + off, F.n, nc, F.n, F.n});
+    sp.push_back({{F.at_row, F.at_col, F.at_vidx}, h.d_val, F.R + off, F.Sc + off, F.n, nc, F.n, F.n});
+    maxr = std::max(maxr, F.n);
+  }
+  launch_spmm(h.stager.put_vec(sp, h.st), (int)sp.size(), maxr, nc, h.st);
+  for (int slot = 0; slot < 2; ++slot) {
+    std::vector<GemmDesc> g;
+    for (size_t i = 0; i < fs.size(); ++i) {
+      HFront& F = *fs[i];
+      const FrontPlan& fp = h.P.fr[F.f];
+      if ((int)fp.kids.size() <= slot) continue;
+      int c = fp.kids[slot];
+      const FrontRT& K = h.fr[c];
+      int u = h.P.fr[c].u;
+      if (u == 0) continue;
+      const int* map = h.fr[F.f].d_kidmap[slot];
+      const int64_t off = (int64_t)c0[i] * F.n;
+      g.push_back(G(K.U, K.ldu, 0, F.R + off, F.n, 0, F.Sr + off, F.n, u, nc, u, 1.0, 1.0, map, map));
+      g.push_back(G(K.U, K.ldu, 1, F.R + off, F.n, 0, F.Sc + off, F.n, u, nc, u, 1.0, 1.0, map, map));
+    }
+    run_gemm(h, g);
+  }
+}
+
+// unreduced node samples S^r_tau, S^c_tau on all current columns (Alg. 1:
+// leaf S - D R, non-leaf stacked reduced children samples minus B R)
+void node_samples(Handle& h, const std::vector<NRef>& nodes) {
+  std::vector<CopyDesc> cp;
+  std::vector<GemmDesc> g;
+  for (auto& x : nodes) {
+    HFront& F = *x.F;
+    HNode& nd = x.n();
+    const int d = F.d;
+    nd.Sr = dalloc(h, (int64_t)nd.mr * d);
+    nd.Sc = dalloc(h, (int64_t)nd.mc * d);
+    if (nd.leaf()) {
+      const int m = nd.m();
+      cp.push_back(Cp(F.Sr + nd.lo, F.n, nullptr, nd.Sr, m, m, d));
+      cp.push_back(Cp(F.Sc + nd.lo, F.n, nullptr, nd.Sc, m, m, d));
+      g.push_back(G(nd.D, m, 0, F.R + nd.lo, F.n, 0, nd.Sr, m, m, d, m, -1.0, 1.0));
+      g.push_back(G(nd.D, m, 1, F.R + nd.lo, F.n, 0, nd.Sc, m, m, d, m, -1.0, 1.0));
+    } else {
+      HNode& a = F.nd[nd.kid[0]];
+      HNode& b = F.nd[nd.kid[1]];
+      cp.push_back(Cp(a.Srr, a.r, nullptr, nd.Sr, nd.mr, a.r, d));
+      cp.push_back(Cp(b.Srr, b.r, nullptr, nd.Sr + a.r, nd.mr, b.r, d));
+      cp.push_back(Cp(a.Scr, a.c, nullptr, nd.Sc, nd.mc, a.c, d));
+      cp.push_back(Cp(b.Scr, b.c, nullptr, nd.Sc + a.c, nd.mc, b.c, d));
+      // S^r: [S_a - B12 R^r_b ; S_b - B21 R^r_a]
+      g.push_back(G(nd.B12, a.r, 0, b.Rrr, b.c, 0, nd.Sr, nd.mr, a.r, d, b.c, -1.0, 1.0));
+      g.push_back(G(nd.B21, b.r, 0, a.Rrr, a.c, 0, nd.Sr + a.r, nd.mr, b.r, d, a.c, -1.0, 1.0));
+      // S^c: [S_a - B21^T R^c_b ; S_b - B12^T R^c_a]
+      g.push_back(G(nd.B21, b.r, 1, b.Rcr, b.r, 0, nd.Sc, nd.mc, a.c, d, b.r, -1.0, 1.0));
+      g.push_back(G(nd.B12, a.r, 1, a.Rcr, a.r, 0, nd.Sc + a.c, nd.mc, b.c, d, a.r, -1.0, 1.0));
+    }
+  }
+  run_copy(h, cp);
+  run_gemm(h, g);
+}
+
+// reduced samples and random matrices after the ID: S(J,:), R^r = V^T R,
+// R^c = U^T R with U = Pi [I; E] applied as a row gather plus one GEMM
+void reduce_nodes(Handle& h, const std::vector<NRef>& nodes) {
+  std::vector<CopyDesc> stack, sel;
+  std::vector<GemmDesc> g;
+  for (auto& x : nodes) {
+    HFront& F = *x.F;
+    HNode& nd = x.n();
+    const int d = F.d;
+    nd.Srr = dalloc(h, (int64_t)nd.r * d);
+    nd.Scr = dalloc(h, (int64_t)nd.c * d);
+    nd.Rrr = dalloc(h, (int64_t)nd.c * d);
+    nd.Rcr = dalloc(h, (int64_t)nd.r * d);
+    const double *Rin_r, *Rin_c;
+    int ld_r, ld_c;
+    if (nd.leaf()) {
+      Rin_r = Rin_c = F.R + nd.lo;
+      ld_r = ld_c = F.n;
+    } else {
+      HNode& a = F.nd[nd.kid[0]];
+      HNode& b = F.nd[nd.kid[1]];
+      double* tr = dalloc(h, (int64_t)nd.mc * d);
+      double* tc = dalloc(h, (int64_t)nd.mr * d);
+      stack.push_back(Cp(a.Rrr, a.c, nullptr, tr, nd.mc, a.c, d));
+      stack.push_back(Cp(b.Rrr, b.c, nullptr, tr + a.c, nd.mc, b.c, d));
+      stack.push_back(Cp(a.Rcr, a.r, nullptr, tc, nd.mr, a.r, d));
+      stack.push_back(Cp(b.Rcr, b.r, nullptr, tc + a.r, nd.mr, b.r, d));
+      Rin_r = tr; ld_r = nd.mc;
+      Rin_c = tc; ld_c = nd.mr;
+    }
+    sel.push_back(Cp(nd.Sr, nd.mr, nd.dpermr, nd.Srr, nd.r, nd.r, d));
+    sel.push_back(Cp(nd.Sc, nd.mc, nd.dpermc, nd.Scr, nd.c, nd.c, d));
+    sel.push_back(Cp(Rin_r, ld_r, nd.dpermc, nd.Rrr, nd.c, nd.c, d));
+    sel.push_back(Cp(Rin_c, ld_c, nd.dpermr, nd.Rcr, nd.r, nd.r, d));
+    if (nd.mc > nd.c)
+      g.push_back(G(nd.Ec, nd.mc - nd.c, 1, Rin_r, ld_r, 0, nd.Rrr, nd.c, nd.c, d, nd.mc - nd.c, 1.0, 1.0,
+                    nd.dpermc + nd.c));
+    if (nd.mr > nd.r)
+      g.push_back(G(nd.Er, nd.mr - nd.r, 1, Rin_c, ld_c, 0, nd.Rcr, nd.r, nd.r, d, nd.mr - nd.r, 1.0, 1.0,
+                    nd.dpermr + nd.r));
+  }
+  run_copy(h, stack);
+  run_copy(h, sel);
+  run_gemm(h, g);
+}
+
+// FrontOpDev table for the fronts of one level (element extraction)
+FrontOpDev* front_ops(Handle& h, const std::vector<HFront*>& fs) {
+  std::vector<FrontOpDev> v;
+  for (HFront* F : fs) {
+    F->fop = (int)v.size();
+    FrontOpDev o{};
+    o.A = {F->a_row, F->a_col, F->a_vidx};
+    o.val = h.d_val;
+    o.n = F->n;
+    const FrontPlan& fp = h.P.fr[F->f];
+    o.nkids = 0;
+    for (size_t k = 0; k < fp.kids.size(); ++k) {
+      int c = fp.kids[k];
+      if (h.P.fr[c].u == 0) continue;
+      o.U[o.nkids] = h.fr[c].U;
+      o.ldu[o.nkids] = h.fr[c].ldu;
+      o.inv[o.nkids] = h.fr[F->f].d_inv[k];
+      o.nkids++;
+    }
+    v.push_back(o);
+  }
+  return upload(h, v);
+}
+
+void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops, const int* iota) {
+  const hssmf_opts& o = h.o;
+  // initial samples
+  {
+    std::vector<int> c0;
+    for (HFront* F : fs) {
+      F->d = 0;
+      F->dcap = 0;
+      F->R = F->Sr = F->Sc = nullptr;
+      grow_samples(h, *F, o.d0);
+      F->d = o.d0;
+      F->rounds = 0;
+      F->finished = false;
+      F->refresh = false;
+      for (auto& nd : F->nd) { nd.done = false; nd.D = nullptr; }
+      launch_rng(F->R, F->n, F->orig, F->n, 0, F->d, o.seed, h.st);
+      c0.push_back(0);
+    }
+    sample(h, fs, c0, o.d0);
+  }
+  int maxh = 0;
+  for (HFront* F : fs) maxh = std::max(maxh, F->maxh);
+  while (true) {
+    for (int hh = 0; hh <= maxh; ++hh) {
+      std::vector<NRef> refresh, cand;
+      for (HFront* F : fs) {
+        if (F->finished) continue;
+        for (int t = 0; t < (int)F->nd.size(); ++t) {
+          HNode& nd = F->nd[t];
+          if (nd.height != hh || t == F->root) continue;
+          if (nd.done) {
+            if (F->refresh) refresh.push_back({F, t});
+          } else if (nd.leaf() || (F->nd[nd.kid[0]].done && F->nd[nd.kid[1]].done)) {
+            cand.push_back({F, t});
+          }
+        }
+      }
+      if (refresh.empty() && cand.empty()) continue;
+      // element extraction for the candidates (D at leaves, B at parents)
+      std::vector<ExtractDesc> ex;
+      for (auto& x : cand) {
+        HNode& nd = x.n();
+        HFront& F = *x.F;
+        if (nd.leaf()) {
+          nd.mr = nd.mc = nd.m();
+          if (!nd.D) {
+            nd.D = dalloc(h, (int64_t)nd.m() * nd.m());
+            ex.push_back({nd.D, iota + nd.lo, iota + nd.lo, nd.m(), nd.m(), nd.m(), F.fop});
+          }
+        } else {
+          HNode& a = F.nd[nd.kid[0]];
+          HNode& b = F.nd[nd.kid[1]];
+          nd.mr = a.r + b.r;
+          nd.mc = a.c + b.c;
+          nd.B12 = dalloc(h, (int64_t)a.r * b.c);
+          nd.B21 = dalloc(h, (int64_t)b.r * a.c);
+          ex.push_back({nd.B12, a.dIr, b.dIc, a.r, b.c, a.r, F.fop});
+          ex.push_back({nd.B21, b.dIr, a.dIc, b.r, a.c, b.r, F.fop});
+        }
+      }
+      run_extract(h, ex, fops);
+      std::vector<NRef> all = refresh;
+      all.insert(all.end(), cand.begin(), cand.end());
+      node_samples(h, all);
+      // interpolative decompositions of the candidates (both sides)
+      std::vector<int> off(cand.size() + 1, 0);
+      for (size_t i = 0; i < cand.size(); ++i) off[i + 1] = off[i] + 2 + cand[i].n().mr + cand[i].n().mc;
+      int* ibuf = ialloc(h, off.back());
+      std::vector<QRDesc> q;
+      int maxm = 0;
+      for (size_t i = 0; i < cand.size(); ++i) {
+        HNode& nd = cand[i].n();
+        const int d = cand[i].F->d;
+        nd.drank = ibuf + off[i];
+        nd.dpermr = nd.drank + 2;
+        nd.dpermc = nd.dpermr + nd.mr;
+        nd.Er = dalloc(h, (int64_t)nd.mr * std::min(nd.mr, d));
+        nd.Ec = dalloc(h, (int64_t)nd.mc * std::min(nd.mc, d));
+        QRDesc a{nd.Sr, dalloc(h, (int64_t)nd.mr * d), nd.dpermr, nd.drank, nd.Er, nullptr, nullptr, nd.mr, d,
+                 nd.mr, o.rel_tol};
+        QRDesc b{nd.Sc, dalloc(h, (int64_t)nd.mc * d), nd.dpermc, nd.drank + 1, nd.Ec, nullptr, nullptr, nd.mc,
+                 d, nd.mc, o.rel_tol};
+        q.push_back(a);
+        q.push_back(b);
+        maxm = std::max(maxm, std::max(nd.mr, nd.mc));
+      }
+      if (!q.empty()) launch_qr(upload(h, q), (int)q.size(), 1, maxm, h.st);
+      std::vector<int> hbuf(off.back());
+      if (!hbuf.empty())
+        HIP_CHECK(hipMemcpyAsync(hbuf.data(), ibuf, hbuf.size() * sizeof(int), hipMemcpyDeviceToHost, h.st));
+      HIP_CHECK(hipStreamSynchronize(h.st));
+      h.stager.sync();
+      std::vector<NRef> ok = refresh;
+      std::vector<int> ivec;
+      std::vector<std::pair<HNode*, int>> ipos;
+      for (size_t i = 0; i < cand.size(); ++i) {
+        HFront& F = *cand[i].F;
+        HNode& nd = cand[i].n();
+        const int* b = hbuf.data() + off[i];
+        int r = b[0], c = b[1];
+        bool okr = r <= F.d - o.p || r == nd.mr;
+        bool okc = c <= F.d - o.p || c == nd.mc;
+        if (!(okr && okc)) continue;
+        nd.r = r;
+        nd.c = c;
+        nd.permr.assign(b + 2, b + 2 + nd.mr);
+        nd.permc.assign(b + 2 + nd.mr, b + 2 + nd.mr + nd.mc);
+        std::vector<int> base_r, base_c;
+        if (nd.leaf()) {
+          for (int j = nd.lo; j < nd.hi; ++j) { base_r.push_back(j); base_c.push_back(j); }
+        } else {
+          HNode& a = F.nd[nd.kid[0]];
+          HNode& bb = F.nd[nd.kid[1]];
+          base_r = a.Ir; base_r.insert(base_r.end(), bb.Ir.begin(), bb.Ir.end());
+          base_c = a.Ic; base_c.insert(base_c.end(), bb.Ic.begin(), bb.Ic.end());
+        }
+        nd.Ir.resize(r);
+        nd.Ic.resize(c);
+        for (int j = 0; j < r; ++j) nd.Ir[j] = base_r[nd.permr[j]];
+        for (int j = 0; j < c; ++j) nd.Ic[j] = base_c[nd.permc[j]];
+        ipos.push_back({&nd, (int)ivec.size()});
+        ivec.insert(ivec.end(), nd.Ir.begin(), nd.Ir.end());
+        ivec.insert(ivec.end(), nd.Ic.begin(), nd.Ic.end());
+        nd.done = true;
+        ok.push_back(cand[i]);
+      }
+      if (!ivec.empty()) {
+        int* dI = upload(h, ivec);
+        for (auto& pr : ipos) {
+          pr.first->dIr = dI + pr.second;
+          pr.first->dIc = dI + pr.second + pr.first->r;
+        }
+      }
+      reduce_nodes(h, ok);
+    }
+    // front roots: extract B between k and q (or the separator root's children)
+    std::vector<ExtractDesc> ex;
+    for (HFront* F : fs) {
+      if (F->finished) continue;
+      HNode& rt = F->nd[F->root];
+      if (rt.leaf()) {
+        if (!rt.D) {
+          rt.D = dalloc(h, (int64_t)rt.m() * rt.m());
+          ex.push_back({rt.D, iota + rt.lo, iota + rt.lo, rt.m(), rt.m(), rt.m(), F->fop});
+        }
+        F->finished = true;
+        continue;
+      }
+      HNode& a = F->nd[rt.kid[0]];
+      HNode& b = F->nd[rt.kid[1]];
+      if (!(a.done && b.done)) continue;
+      rt.B12 = dalloc(h, (int64_t)a.r * b.c);
+      rt.B21 = dalloc(h, (int64_t)b.r * a.c);
+      ex.push_back({rt.B12, a.dIr, b.dIc, a.r, b.c, a.r, F->fop});
+      ex.push_back({rt.B21, b.dIr, a.dIc, b.r, a.c, b.r, F->fop});
+      F->finished = true;
+    }
+    run_extract(h, ex, fops);
+    bool all = true;
+    for (HFront* F : fs) all = all && F->finished;
+    if (all) break;
+    // adaptive rank: more random vectors for the fronts that are not done
+    std::vector<HFront*> grow;
+    std::vector<int> c0;
+    for (HFront* F : fs) {
+      F->refresh = false;
+      if (F->finished) continue;
+      if (F->d + o.dd > o.d_max) throw Error(HSSMF_ERANK, "HSS compression reached d_max", F->f);
+      grow_samples(h, *F, F->d + o.dd);
+      launch_rng(F->R, F->n, F->orig, F->n, F->d, o.dd, o.seed, h.st);
+      c0.push_back(F->d);
+      grow.push_back(F);
+      F->d += o.dd;
+      F->rounds++;
+      F->refresh = true;
+    }
+    sample(h, grow, c0, o.dd);
+  }
+}
+
+// ULV-like factorization of every k-subtree (Sec. 2.3), bottom-up by
+// height, then the LU of the merged top block
+void ulv_level(Handle& h, std::vector<HFront*>& fs) {
+  int maxh = 0;
+  for (HFront* F : fs) maxh = std::max(maxh, F->nd[F->k].height);
+  auto in_k = [](HFront* F, int t) {
+    while (t >= 0 && t != F->k) t = F->nd[t].parent;
+    return t == F->k;
+  };
+  for (int hh = 0; hh <= maxh; ++hh) {
+    std::vector<NRef> L;
+    for (HFront* F : fs)
+      for (int t = 0; t < (int)F->nd.size(); ++t)
+        if (F->nd[t].height == hh && t != F->k && in_k(F, t)) L.push_back({F, t});
+    if (L.empty()) continue;
+    // dense generators, merged blocks Dbar and Vbar
+    std::vector<InterpDesc> ip;
+    std::vector<CopyDesc> cp;
+    std::vector<GemmDesc> g1, g2;
+    for (auto& x : L) {
+      HNode& nd = x.n();
+      HFront& F = *x.F;
+      nd.Ud = dalloc(h, (int64_t)nd.mr * nd.r);
+      nd.Vd = dalloc(h, (int64_t)nd.mc * nd.c);
+      ip.push_back({nd.Ud, nd.dpermr, nd.Er, nd.mr, nd.r, nd.mr, 0});
+      ip.push_back({nd.Vd, nd.dpermc, nd.Ec, nd.mc, nd.c, nd.mc, 0});
+      const int m = nd.mr;
+      if (nd.leaf()) {
+        nd.Dbar = nd.D;
+      } else {
+        HNode& a = F.nd[nd.kid[0]];
+        HNode& b = F.nd[nd.kid[1]];
+        nd.Dbar = dalloc(h, (int64_t)m * m);
+        nd.Vbar = dalloc(h, (int64_t)m * nd.c);
+        // diagonal blocks: D^ of the children (last r columns of WQ)
+        cp.push_back(Cp(a.WQ + (int64_t)a.nl * a.r, a.r, nullptr, nd.Dbar, m, a.r, a.r));
+        cp.push_back(Cp(b.WQ + (int64_t)b.nl * b.r, b.r, nullptr, nd.Dbar + a.r + (int64_t)a.r * m, m, b.r, b.r));
+        // off-diagonal blocks: B12 V^_b^T and B21 V^_a^T (V^ = last r rows of QV)
+        g1.push_back(G(nd.B12, a.r, 0, b.QV + b.nl, b.mr, 1, nd.Dbar + (int64_t)a.r * m, m, a.r, b.r, b.c, 1.0,
+                       0.0));
+        g1.push_back(G(nd.B21, b.r, 0, a.QV + a.nl, a.mr, 1, nd.Dbar + a.r, m, b.r, a.r, a.c, 1.0, 0.0));
+      }
+    }
+    run_interp(h, ip);
+    run_copy(h, cp);
+    run_gemm(h, g1);
+    for (auto& x : L) {
+      HNode& nd = x.n();
+      HFront& F = *x.F;
+      if (nd.leaf()) {
+        nd.Vbar = nd.Vd;
+      } else {
+        HNode& a = F.nd[nd.kid[0]];
+        HNode& b = F.nd[nd.kid[1]];
+        // Vbar = diag(V^_a, V^_b) V_tau
+        g2.push_back(G(a.QV + a.nl, a.mr, 0, nd.Vd, nd.mc, 0, nd.Vbar, nd.mr, a.r, nd.c, a.c, 1.0, 0.0));
+        g2.push_back(G(b.QV + b.nl, b.mr, 0, nd.Vd + a.c, nd.mc, 0, nd.Vbar + a.r, nd.mr, b.r, nd.c, b.c,
+                       1.0, 0.0));
+      }
+    }
+    run_gemm(h, g2);
+    // W = Omega Dbar: top rows Dbar[perm[r:]] - E Dbar[perm[:r]], bottom Dbar[perm[:r]]
+    std::vector<CopyDesc> wc;
+    std::vector<GemmDesc> wg;
+    std::vector<QRDesc> q;
+    int maxm = 0;
+    std::vector<double*> Wt(L.size()), Wb(L.size());
+    for (size_t i = 0; i < L.size(); ++i) {
+      HNode& nd = L[i].n();
+      const int m = nd.mr, r = nd.r, nl = m - r;
+      nd.nl = nl;
+      Wt[i] = dalloc(h, (int64_t)std::max(nl, 1) * m);
+      Wb[i] = dalloc(h, (int64_t)std::max(r, 1) * m);
+      wc.push_back(Cp(nd.Dbar, m, nd.dpermr + r, Wt[i], std::max(nl, 1), nl, m));
+      wc.push_back(Cp(nd.Dbar, m, nd.dpermr, Wb[i], std::max(r, 1), r, m));
+      if (nl > 0 && r > 0)
+        wg.push_back(G(nd.Er, nl, 0, nd.Dbar, m, 0, Wt[i], nl, nl, m, r, -1.0, 1.0, nd.dpermr));
+      nd.Q = dalloc(h, (int64_t)m * m);
+      nd.L = dalloc(h, (int64_t)std::max(nl, 1) * std::max(nl, 1));
+      // LQ of Wt: QR of Wt^T (columns = rows of Wt, length m)
+      q.push_back({Wt[i], dalloc(h, (int64_t)m * std::max(nl, 1)), ialloc(h, std::max(nl, 1)), ialloc(h, 1),
+                   nullptr, nd.Q, nd.L, nl, m, std::max(nl, 1), 0.0});
+      maxm = std::max(maxm, std::max(nl, 1));
+    }
+    run_copy(h, wc);
+    run_gemm(h, wg);
+    launch_qr(upload(h, q), (int)q.size(), 0, maxm, h.st);
+    // [D^21 D^] = Wb Q ;  [V^1; V^] = Q^T Vbar
+    std::vector<GemmDesc> g3;
+    for (size_t i = 0; i < L.size(); ++i) {
+      HNode& nd = L[i].n();
+      const int m = nd.mr, r = nd.r;
+      nd.WQ = dalloc(h, (int64_t)std::max(r, 1) * m);
+      nd.QV = dalloc(h, (int64_t)m * std::max(nd.c, 1));
+      if (r > 0) g3.push_back(G(Wb[i], r, 0, nd.Q, m, 0, nd.WQ, r, r, m, m, 1.0, 0.0));
+      if (nd.c > 0) g3.push_back(G(nd.Q, m, 1, nd.Vbar, m, 0, nd.QV, m, m, nd.c, m, 1.0, 0.0));
+    }
+    run_gemm(h, g3);
+  }
+  // top node k: merged block and its LU
+  std::vector<CopyDesc> cp;
+  std::vector<GemmDesc> g1, g2;
+  std::vector<InterpDesc> ip;
+  for (HFront* F : fs) {
+    HNode& k = F->nd[F->k];
+    const bool has_gen = F->q >= 0;
+    if (has_gen) {
+      k.Ud = dalloc(h, (int64_t)k.mr * k.r);
+      k.Vd = dalloc(h, (int64_t)k.mc * k.c);
+      ip.push_back({k.Ud, k.dpermr, k.Er, k.mr, k.r, k.mr, 0});
+      ip.push_back({k.Vd, k.dpermc, k.Ec, k.mc, k.c, k.mc, 0});
+    }
+    if (k.leaf()) {
+      F->mk = k.m();
+      F->Dk = dalloc(h, (int64_t)F->mk * F->mk);
+      cp.push_back(Cp(k.D, F->mk, nullptr, F->Dk, F->mk, F->mk, F->mk));
+    } else {
+      HNode& a = F->nd[k.kid[0]];
+      HNode& b = F->nd[k.kid[1]];
+      const int m = a.r + b.r;
+      F->mk = m;
+      F->Dk = dalloc(h, (int64_t)m * m);
+      cp.push_back(Cp(a.WQ + (int64_t)a.nl * a.r, a.r, nullptr, F->Dk, m, a.r, a.r));
+      cp.push_back(Cp(b.WQ + (int64_t)b.nl * b.r, b.r, nullptr, F->Dk + a.r + (int64_t)a.r * m, m, b.r, b.r));
+      g1.push_back(G(k.B12, a.r, 0, b.QV + b.nl, b.mr, 1, F->Dk + (int64_t)a.r * m, m, a.r, b.r, b.c, 1.0, 0.0));
+      g1.push_back(G(k.B21, b.r, 0, a.QV + a.nl, a.mr, 1, F->Dk + a.r, m, b.r, a.r, a.c, 1.0, 0.0));
+    }
+    F->ipivk = ialloc(h, F->mk);
+  }
+  run_interp(h, ip);
+  run_copy(h, cp);
+  run_gemm(h, g1);
+  for (HFront* F : fs) {
+    HNode& k = F->nd[F->k];
+    if (F->q < 0) continue;
+    if (k.leaf()) {
+      F->Vbark = k.Vd;
+    } else {
+      HNode& a = F->nd[k.kid[0]];
+      HNode& b = F->nd[k.kid[1]];
+      F->Vbark = dalloc(h, (int64_t)F->mk * k.c);
+      g2.push_back(G(a.QV + a.nl, a.mr, 0, k.Vd, k.mc, 0, F->Vbark, F->mk, a.r, k.c, a.c, 1.0, 0.0));
+      g2.push_back(G(b.QV + b.nl, b.mr, 0, k.Vd + a.c, k.mc, 0, F->Vbark + a.r, F->mk, b.r, k.c, b.c, 1.0, 0.0));
+    }
+  }
+  run_gemm(h, g2);
+  std::vector<LUFront> lu;
+  for (HFront* F : fs) lu.push_back({F->Dk, F->ipivk, F->mk, F->mk, F->mk, F->f});
+  blocked_lu(h, lu);
+}
+
+// nested bases U^big, V^big (Eq. nestedUV) of every non-root node, the
+// low-rank Schur product and the dense update matrix of each front
+void schur_level(Handle& h, std::vector<HFront*>& fs) {
+  int maxh = 0;
+  std::vector<HFront*> wu;
+  for (HFront* F : fs)
+    if (F->q >= 0) { wu.push_back(F); maxh = std::max(maxh, F->nd[F->root].height); }
+  if (wu.empty()) return;
+  for (int hh = 0; hh < maxh; ++hh) {
+    std::vector<InterpDesc> ip;
+    std::vector<GemmDesc> g;
+    for (HFront* F : wu)
+      for (int t = 0; t < (int)F->nd.size(); ++t) {
+        HNode& nd = F->nd[t];
+        if (nd.height != hh || t == F->root) continue;
+        if (!nd.Ud) {
+          nd.Ud = dalloc(h, (int64_t)nd.mr * nd.r);
+          nd.Vd = dalloc(h, (int64_t)nd.mc * nd.c);
+          ip.push_back({nd.Ud, nd.dpermr, nd.Er, nd.mr, nd.r, nd.mr, 0});
+          ip.push_back({nd.Vd, nd.dpermc, nd.Ec, nd.mc, nd.c, nd.mc, 0});
+        }
+        if (nd.leaf()) {
+          nd.Ubig = nd.Ud;
+          nd.Vbig = nd.Vd;
+        } else {
+          HNode& a = F->nd[nd.kid[0]];
+          HNode& b = F->nd[nd.kid[1]];
+          const int m = nd.m();
+          nd.Ubig = dalloc(h, (int64_t)m * nd.r);
+          nd.Vbig = dalloc(h, (int64_t)m * nd.c);
+          g.push_back(G(a.Ubig, a.m(), 0, nd.Ud, nd.mr, 0, nd.Ubig, m, a.m(), nd.r, a.r, 1.0, 0.0));
+          g.push_back(G(b.Ubig, b.m(), 0, nd.Ud + a.r, nd.mr, 0, nd.Ubig + a.m(), m, b.m(), nd.r, b.r, 1.0, 0.0));
+          g.push_back(G(a.Vbig, a.m(), 0, nd.Vd, nd.mc, 0, nd.Vbig, m, a.m(), nd.c, a.c, 1.0, 0.0));
+          g.push_back(G(b.Vbig, b.m(), 0, nd.Vd + a.c, nd.mc, 0, nd.Vbig + a.m(), m, b.m(), nd.c, b.c, 1.0, 0.0));
+        }
+      }
+    run_interp(h, ip);
+    run_gemm(h, g);
+  }
+  // Theta^T = U_LU^{-T} (Vbar_k B_qk^T) Ubig_q^T ; Phi = L_LU^{-1} P U_k B_kq Vbig_q^T
+  std::vector<GemmDesc> g1, g2, g3;
+  std::vector<double*> T1(wu.size()), T3(wu.size());
+  for (size_t i = 0; i < wu.size(); ++i) {
+    HFront& F = *wu[i];
+    HNode& rt = F.nd[F.root];
+    HNode& k = F.nd[F.k];
+    HNode& q = F.nd[F.q];
+    const int mk = F.mk, u = F.u;
+    // root children are (k, q): B12 = B_kq (r_k x c_q), B21 = B_qk (r_q x c_k)
+    T1[i] = dalloc(h, (int64_t)mk * std::max(q.r, 1));  // Vbar_k B_qk^T : mk x r_q
+    g1.push_back(G(F.Vbark, mk, 0, rt.B21, q.r, 1, T1[i], mk, mk, q.r, k.c, 1.0, 0.0));
+    T3[i] = dalloc(h, (int64_t)std::max(k.r, 1) * u);   // B_kq Vbig_q^T : r_k x u
+    g1.push_back(G(rt.B12, k.r, 0, q.Vbig, u, 1, T3[i], std::max(k.r, 1), k.r, u, q.c, 1.0, 0.0));
+    F.ThT = dalloc(h, (int64_t)mk * u);
+    F.Phi = dalloc(h, (int64_t)mk * u);
+    g2.push_back(G(T1[i], mk, 0, q.Ubig, u, 1, F.ThT, mk, mk, u, q.r, 1.0, 0.0));
+    g2.push_back(G(k.Ud, mk, 0, T3[i], std::max(k.r, 1), 0, F.Phi, mk, mk, u, k.r, 1.0, 0.0));
+  }
+  run_gemm(h, g1);
+  run_gemm(h, g2);
+  for (HFront* F : wu) {
+    // Theta^T := U^{-T} Theta^T  (logical lower, non-unit, transposed access)
+    tri_solve_many(h, F->Dk, F->mk, F->mk, F->ThT, F->mk, F->u, true, false, true);
+    launch_pivots(F->Phi, F->mk, F->u, F->ipivk, F->mk, 0, h.st);
+    tri_solve_many(h, F->Dk, F->mk, F->mk, F->Phi, F->mk, F->u, true, true, false);
+  }
+  // dense update matrix: expand F22 of the q-subtree, subtract Theta^* Phi
+  for (HFront* F : wu) {
+    F->Upd = dalloc(h, (int64_t)F->u * F->u);
+    h.fr[F->f].U = F->Upd;
+    h.fr[F->f].ldu = F->u;
+  }
+  std::vector<CopyDesc> cp;
+  for (HFront* F : wu)
+    for (int t = 0; t < (int)F->nd.size(); ++t) {
+      HNode& nd = F->nd[t];
+      if (!nd.leaf() || nd.lo < F->s) continue;
+      const int o = nd.lo - F->s;
+      cp.push_back(Cp(nd.D, nd.m(), nullptr, F->Upd + o + (int64_t)o * F->u, F->u, nd.m(), nd.m()));
+    }
+  run_copy(h, cp);
+  std::vector<GemmDesc> e1, e2;
+  std::vector<std::pair<double*, int>> tmp;
+  for (HFront* F : wu)
+    for (int t = 0; t < (int)F->nd.size(); ++t) {
+      HNode& nd = F->nd[t];
+      if (nd.leaf() || nd.lo < F->s) continue;
+      HNode& a = F->nd[nd.kid[0]];
+      HNode& b = F->nd[nd.kid[1]];
+      // block (a, b) = Ubig_a B12 Vbig_b^T ; block (b, a) = Ubig_b B21 Vbig_a^T
+      double* ta = dalloc(h, (int64_t)std::max(a.r, 1) * b.m());
+      double* tb = dalloc(h, (int64_t)std::max(b.r, 1) * a.m());
+      e1.push_back(G(nd.B12, a.r, 0, b.Vbig, b.m(), 1, ta, std::max(a.r, 1), a.r, b.m(), b.c, 1.0, 0.0));
+      e1.push_back(G(nd.B21, b.r, 0, a.Vbig, a.m(), 1, tb, std::max(b.r, 1), b.r, a.m(), a.c, 1.0, 0.0));
+      const int oa = a.lo - F->s, ob = b.lo - F->s;
+      e2.push_back(G(a.Ubig, a.m(), 0, ta, std::max(a.r, 1), 0, F->Upd + oa + (int64_t)ob * F->u, F->u, a.m(),
+                     b.m(), a.r, 1.0, 0.0));
+      e2.push_back(G(b.Ubig, b.m(), 0, tb, std::max(b.r, 1), 0, F->Upd + ob + (int64_t)oa * F->u, F->u, b.m(),
+                     a.m(), b.r, 1.0, 0.0));
+    }
+  run_gemm(h, e1);
+  run_gemm(h, e2);
+  std::vector<GemmDesc> s;
+  for (HFront* F : wu)
+    s.push_back(G(F->ThT, F->mk, 1, F->Phi, F->mk, 0, F->Upd, F->u, F->u, F->u, F->mk, -1.0, 1.0));
+  run_gemm(h, s);
+}
+
+}  // namespace
+
+// -------------------------------------------------------- numeric ---------
+void numeric_factor(Handle& h) {
+  const Plan& P = h.P;
+  HIP_CHECK(hipMemsetAsync(h.d_info, 0, sizeof(int), h.st));
+  for (size_t lev = 0; lev < P.levels.size(); ++lev) {
+    const std::vector<int>& ids = P.levels[lev];
+    // dense fronts
+    std::vector<LUFront> lu;
+    int64_t total = 0;
+    for (int f : ids)
+      if (!P.fr[f].hss) total += (int64_t)P.fr[f].n * P.fr[f].n;
+    if (total > 0) {
+      launch_fill(h.level_buf[lev], total, 0.0, h.st);
+      int64_t a0 = -1, a1 = 0;
+      for (int f : ids) {
+        const FrontRT& R = h.fr[f];
+        if (P.fr[f].hss) continue;
+        if (a0 < 0) a0 = R.asm_off;
+        a1 = R.asm_off + R.asm_cnt;
+      }
+      if (a0 >= 0) launch_assemble(h.level_buf[lev], h.d_asm_dst + a0, h.d_asm_src + a0, h.d_val, a1 - a0, h.st);
+      for (int slot = 0; slot < 2; ++slot) {
+        std::vector<EADesc> ea;
+        int maxu = 0;
+        for (int f : ids) {
+          const FrontPlan& fp = P.fr[f];
+          if (fp.hss || (int)fp.kids.size() <= slot) continue;
+          int c = fp.kids[slot];
+          int u = P.fr[c].u;
+          if (u == 0) continue;
+          ea.push_back({h.fr[c].U, h.fr[f].F, h.fr[f].d_kidmap[slot], u, h.fr[c].ldu, fp.n, 0});
+          maxu = std::max(maxu, u);
+        }
+        if (!ea.empty()) launch_extend_add(h.stager.put_vec(ea, h.st), (int)ea.size(), maxu, h.st);
+      }
+      for (int f : ids) {
+        const FrontPlan& fp = P.fr[f];
+        if (fp.hss) continue;
+        lu.push_back({h.fr[f].F, h.fr[f].ipiv, fp.s, fp.n, fp.n, f});
+      }
+      blocked_lu(h, lu);
+    }
+    // HSS fronts
+    std::vector<HFront*> fs;
+    for (int f : ids)
+      if (P.fr[f].hss) fs.push_back(&h.hf[h.fr[f].hidx]);
+    if (!fs.empty()) {
+      FrontOpDev* fops = front_ops(h, fs);
+      int nmax = 0;
+      for (HFront* F : fs) nmax = std::max(nmax, F->n);
+      std::vector<int> iota(nmax);
+      for (int i = 0; i < nmax; ++i) iota[i] = i;
+      int* d_iota = upload(h, iota);
+      compress_level(h, fs, fops, d_iota);
+      ulv_level(h, fs);
+      schur_level(h, fs);
+    }
+    // check for zero pivots after each level
+    int info = 0;
+    HIP_CHECK(hipMemcpyAsync(&info, h.d_info, sizeof(int), hipMemcpyDeviceToHost, h.st));
+    HIP_CHECK(hipStreamSynchronize(h.st));
+    h.stager.sync();
+    if (info != 0) {
+      h.failed_front = info - 1;
+      throw Error(HSSMF_ESINGULAR, "zero pivot in front " + std::to_string(info - 1), info - 1);
+    }
+  }
+}
+
+}  // namespace hssmf

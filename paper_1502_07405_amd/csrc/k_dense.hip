@@ -1,0 +1,349 @@
+// Dense-front kernels of the multifrontal method (Sec. 3.2, Sec. 3.3):
+// assembly of original entries, extend-add of children's update matrices,
+// the pieces of a batched right-looking blocked partial LU with pivoting
+// restricted to F11, and the per-front triangular solves / products of the
+// forward and backward sweeps.  All fronts of one elimination-tree level go
+// through each launch together.
+#include "kernels.hpp"
+
+namespace hssmf {
+
+// ------------------------------------------------------------- utilities --
+__global__ void fill_kernel(double* p, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+void launch_fill(double* p, int64_t n, double v, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+  HIP_CHECK(hipGetLastError());
+}
+
+// assembly: front entries from the CSR values (Eq. frontal_1); each front
+// position receives exactly one entry, so the scatter has no conflicts
+__global__ void assemble_kernel(double* base, const int64_t* __restrict__ dst, const int64_t* __restrict__ src,
+                                const double* __restrict__ val, int64_t count) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x)
+    base[dst[e]] = val[src[e]];
+}
+
+void launch_assemble(double* base, const int64_t* dst, const int64_t* src, const double* val, int64_t count,
+                     hipStream_t s) {
+  if (count <= 0) return;
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)blocks), dim3(256), 0, s, base, dst, src, val, count);
+  HIP_CHECK(hipGetLastError());
+}
+
+// extend-add (Eq. extend-add) as an owner-computes update: one launch per
+// child slot, so two children of a parent never race and the summation
+// order is fixed (no floating-point atomics)
+__global__ void extend_add_kernel(const EADesc* __restrict__ descs) {
+  const EADesc d = descs[blockIdx.y];
+  const int64_t uu = (int64_t)d.u * d.u;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < uu; e += (int64_t)gridDim.x * blockDim.x) {
+    int i = (int)(e % d.u), j = (int)(e / d.u);
+    d.F[d.map[i] + (int64_t)d.map[j] * d.ldf] += d.U[i + (int64_t)j * d.ldu];
+  }
+}
+
+void launch_extend_add(const EADesc* d, int nd, int max_u, hipStream_t s) {
+  if (nd <= 0 || max_u <= 0) return;
+  int64_t blocks = ((int64_t)max_u * max_u + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(extend_add_kernel, dim3((unsigned)blocks, nd), dim3(256), 0, s, d);
+  HIP_CHECK(hipGetLastError());
+}
+
+// ---------------------------------------------------------- blocked LU ---
+// Panel: columns [jb, jb+w) over rows [jb, n) of each front; pivot search
+// over rows [col, s) only (partial pivoting inside F11, Sec. 3.2).  Rows
+// below s are eliminated with the same multipliers, which yields
+// L21 = F21 U11^{-1}.
+__global__ __launch_bounds__(256) void lu_panel_kernel(const LUFront* __restrict__ fr, int jb, int nb, int* info) {
+  const LUFront f = fr[blockIdx.x];
+  if (jb >= f.s) return;
+  const int w = min(nb, f.s - jb);
+  const int tid = threadIdx.x;
+  __shared__ double rv[256];
+  __shared__ int ri[256];
+  __shared__ double prow[64];
+  double* F = f.F;
+  const int64_t ld = f.ld;
+  for (int c = 0; c < w; ++c) {
+    const int col = jb + c;
+    double best = -1.0;
+    int bi = col;
+    for (int i = col + tid; i < f.s; i += 256) {
+      double a = fabs(F[i + col * ld]);
+      if (a > best) { best = a; bi = i; }
+    }
+    rv[tid] = best;
+    ri[tid] = bi;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if (tid < off) {
+        double o = rv[tid + off];
+        int oi = ri[tid + off];
+        if (o > rv[tid] || (o == rv[tid] && oi < ri[tid])) { rv[tid] = o; ri[tid] = oi; }
+      }
+      __syncthreads();
+    }
+    const int p = ri[0];
+    if (tid == 0) {
+      f.ipiv[col] = p;
+      if (rv[0] == 0.0) atomicCAS(info, 0, f.id + 1);
+    }
+    if (p != col && tid < w) {
+      double* a = F + col + (int64_t)(jb + tid) * ld;
+      double* b = F + p + (int64_t)(jb + tid) * ld;
+      double t = *a; *a = *b; *b = t;
+    }
+    __syncthreads();
+    if (tid < w) prow[tid] = F[col + (int64_t)(jb + tid) * ld];
+    __syncthreads();
+    const double piv = prow[c];
+    const double rp = (piv != 0.0) ? 1.0 / piv : 0.0;
+    for (int i = col + 1 + tid; i < f.n; i += 256) {
+      double l = F[i + col * ld] * rp;
+      F[i + col * ld] = l;
+      for (int cc = c + 1; cc < w; ++cc) F[i + (int64_t)(jb + cc) * ld] -= l * prow[cc];
+    }
+    __syncthreads();
+  }
+}
+
+void launch_lu_panel(const LUFront* fr, int nf, int jb, int nb, int* info, hipStream_t s) {
+  if (nf <= 0) return;
+  REQUIRE(nb <= 64, HSSMF_EINVAL, "panel width");
+  hipLaunchKernelGGL(lu_panel_kernel, dim3(nf), dim3(256), 0, s, fr, jb, nb, info);
+  HIP_CHECK(hipGetLastError());
+}
+
+// apply the panel's interchanges to the columns outside the panel
+__global__ void laswp_kernel(const LUFront* __restrict__ fr, int jb, int nb) {
+  const LUFront f = fr[blockIdx.y];
+  if (jb >= f.s) return;
+  const int w = min(nb, f.s - jb);
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= f.n || (col >= jb && col < jb + w)) return;
+  double* c = f.F + (int64_t)col * f.ld;
+  for (int t = 0; t < w; ++t) {
+    int r1 = jb + t, r2 = f.ipiv[r1];
+    if (r1 != r2) { double x = c[r1]; c[r1] = c[r2]; c[r2] = x; }
+  }
+}
+
+void launch_laswp(const LUFront* fr, int nf, int jb, int nb, int max_n, hipStream_t s) {
+  if (nf <= 0 || max_n <= 0) return;
+  hipLaunchKernelGGL(laswp_kernel, dim3((max_n + 255) / 256, nf), dim3(256), 0, s, fr, jb, nb);
+  HIP_CHECK(hipGetLastError());
+}
+
+// U12 block row: X = L_pp^{-1} X for rows [jb, jb+w), columns [jb+w, n)
+__global__ __launch_bounds__(256) void trsm_u12_kernel(const LUFront* __restrict__ fr, int jb, int nb) {
+  const LUFront f = fr[blockIdx.y];
+  if (jb >= f.s) return;
+  const int w = min(nb, f.s - jb);
+  __shared__ double Lp[64][65];
+  for (int e = threadIdx.x; e < w * w; e += 256) {
+    int i = e % w, j = e / w;
+    Lp[i][j] = f.F[(jb + i) + (int64_t)(jb + j) * f.ld];
+  }
+  __syncthreads();
+  const int col = jb + w + blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= f.n) return;
+  double* c = f.F + (int64_t)col * f.ld + jb;
+  double x[64];
+#pragma unroll
+  for (int i = 0; i < 64; ++i)
+    if (i < w) x[i] = c[i];
+#pragma unroll
+  for (int i = 0; i < 64; ++i) {
+    if (i < w) {
+      double v = x[i];
+#pragma unroll
+      for (int j = 0; j < 64; ++j)
+        if (j < i) v -= Lp[i][j] * x[j];
+      x[i] = v;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 64; ++i)
+    if (i < w) c[i] = x[i];
+}
+
+void launch_trsm_u12(const LUFront* fr, int nf, int jb, int nb, int max_n, hipStream_t s) {
+  if (nf <= 0 || max_n <= 0) return;
+  hipLaunchKernelGGL(trsm_u12_kernel, dim3((max_n + 255) / 256, nf), dim3(256), 0, s, fr, jb, nb);
+  HIP_CHECK(hipGetLastError());
+}
+
+// -------------------------------------------------------------- solves ---
+// batched GEMV: each workgroup owns 64 outputs (non-transposed) or 4
+// outputs (transposed: one wavefront per column dot product)
+__global__ __launch_bounds__(256) void gemv_kernel(const GemvDesc* __restrict__ descs) {
+  const GemvDesc d = descs[blockIdx.y];
+  const int tid = threadIdx.x;
+  if (!d.trans) {
+    const int r = blockIdx.x * 64 + (tid & 63);
+    const int ph = tid >> 6;
+    __shared__ double red[4][64];
+    double acc = 0.0;
+    if (r < d.rows && d.alpha != 0.0) {
+      for (int j = ph; j < d.cols; j += 4) {
+        int xj = d.xmap ? d.xmap[j] : j;
+        acc += d.M[r + (int64_t)j * d.ld] * d.x[xj];
+      }
+    }
+    if (blockIdx.x * 64 >= d.rows) return;
+    red[ph][tid & 63] = acc;
+    __syncthreads();
+    if (ph == 0 && r < d.rows) {
+      double v = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+      int yr = d.ymap ? d.ymap[r] : r;
+      d.y[yr] = d.overwrite ? d.alpha * v : d.y[yr] + d.alpha * v;
+    }
+  } else {
+    const int c = blockIdx.x * 4 + (tid >> 6);
+    const int lane = tid & 63;
+    if (c >= d.cols) return;
+    double acc = 0.0;
+    const double* col = d.M + (int64_t)c * d.ld;
+    for (int i = lane; i < d.rows && d.alpha != 0.0; i += 64) {
+      int xi = d.xmap ? d.xmap[i] : i;
+      acc += col[i] * d.x[xi];
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) {
+      int yc = d.ymap ? d.ymap[c] : c;
+      d.y[yc] = d.overwrite ? d.alpha * acc : d.y[yc] + d.alpha * acc;
+    }
+  }
+}
+
+void launch_gemv(const GemvDesc* d, int nd, int max_out, hipStream_t s) {
+  if (nd <= 0 || max_out <= 0) return;
+  // grid.x covers the larger of the two layouts; workgroups past a
+  // descriptor's extent return immediately
+  int gx = (max_out + 3) / 4;
+  hipLaunchKernelGGL(gemv_kernel, dim3(gx, nd), dim3(256), 0, s, d);
+  HIP_CHECK(hipGetLastError());
+}
+
+// Triangular solves with the F11 factors, one workgroup per front, the
+// right-hand side staged in LDS.  Blocks of 64: one wavefront solves the
+// diagonal block with lane shuffles, then all threads update the rest.
+template <int KIND>
+__global__ __launch_bounds__(256) void trsv_kernel(const TrsvDesc* __restrict__ descs) {
+  extern __shared__ double xs[];
+  const TrsvDesc d = descs[blockIdx.x];
+  const int s = d.s, tid = threadIdx.x, lane = tid & 63;
+  const int64_t ld = d.ld;
+  for (int i = tid; i < s; i += 256) xs[i] = d.x[i];
+  __syncthreads();
+  if (KIND == 0 && d.ipiv && tid == 0)
+    for (int i = 0; i < s; ++i) {
+      int p = d.ipiv[i];
+      if (p != i) { double t = xs[i]; xs[i] = xs[p]; xs[p] = t; }
+    }
+  __syncthreads();
+  // logical matrix T: KIND 0: L (unit lower), 1: U (upper), 2: U^T (lower),
+  // 3: L^T (unit upper), 4: L (non-unit lower), 5: L^T (non-unit upper)
+  constexpr bool trans = (KIND == 2 || KIND == 3 || KIND == 5);
+  auto T = [&](int i, int j) -> double {
+    return trans ? d.F[j + (int64_t)i * ld] : d.F[i + (int64_t)j * ld];
+  };
+  constexpr bool lower = (KIND == 0 || KIND == 2 || KIND == 4);
+  constexpr bool unit = (KIND == 0 || KIND == 3);
+  if (lower) {
+    for (int b0 = 0; b0 < s; b0 += 64) {
+      const int bs = min(64, s - b0);
+      if (tid < 64) {
+        double v = (lane < bs) ? xs[b0 + lane] : 0.0;
+        for (int j = 0; j < bs; ++j) {
+          if (!unit && lane == j) v /= T(b0 + j, b0 + j);
+          double vj = __shfl(v, j);
+          if (lane > j && lane < bs) v -= T(b0 + lane, b0 + j) * vj;
+        }
+        if (lane < bs) xs[b0 + lane] = v;
+      }
+      __syncthreads();
+      for (int i = b0 + bs + tid; i < s; i += 256) {
+        double acc = 0.0;
+        for (int j = 0; j < bs; ++j) acc += T(i, b0 + j) * xs[b0 + j];
+        xs[i] -= acc;
+      }
+      __syncthreads();
+    }
+  } else {
+    for (int b1 = s; b1 > 0; b1 -= 64) {
+      const int b0 = max(0, b1 - 64), bs = b1 - b0;
+      if (tid < 64) {
+        double v = (lane < bs) ? xs[b0 + lane] : 0.0;
+        for (int j = bs - 1; j >= 0; --j) {
+          if (!unit && lane == j) v /= T(b0 + j, b0 + j);
+          double vj = __shfl(v, j);
+          if (lane < j) v -= T(b0 + lane, b0 + j) * vj;
+        }
+        if (lane < bs) xs[b0 + lane] = v;
+      }
+      __syncthreads();
+      for (int i = tid; i < b0; i += 256) {
+        double acc = 0.0;
+        for (int j = 0; j < bs; ++j) acc += T(i, b0 + j) * xs[b0 + j];
+        xs[i] -= acc;
+      }
+      __syncthreads();
+    }
+  }
+  if (KIND == 3 && d.ipiv && tid == 0)
+    for (int i = s - 1; i >= 0; --i) {
+      int p = d.ipiv[i];
+      if (p != i) { double t = xs[i]; xs[i] = xs[p]; xs[p] = t; }
+    }
+  __syncthreads();
+  for (int i = tid; i < s; i += 256) d.x[i] = xs[i];
+}
+
+void launch_trsv(const TrsvDesc* d, int nd, int kind, int max_s, hipStream_t s) {
+  if (nd <= 0) return;
+  // LDS holds the whole right-hand side
+  REQUIRE(max_s <= 8192, HSSMF_EINVAL, "triangular solve: block larger than 8192 rows");
+  size_t lds = (size_t)std::max(max_s, 1) * sizeof(double);
+  switch (kind) {
+    case 0: hipLaunchKernelGGL(trsv_kernel<0>, dim3(nd), dim3(256), lds, s, d); break;
+    case 1: hipLaunchKernelGGL(trsv_kernel<1>, dim3(nd), dim3(256), lds, s, d); break;
+    case 2: hipLaunchKernelGGL(trsv_kernel<2>, dim3(nd), dim3(256), lds, s, d); break;
+    case 3: hipLaunchKernelGGL(trsv_kernel<3>, dim3(nd), dim3(256), lds, s, d); break;
+    case 4: hipLaunchKernelGGL(trsv_kernel<4>, dim3(nd), dim3(256), lds, s, d); break;
+    default: hipLaunchKernelGGL(trsv_kernel<5>, dim3(nd), dim3(256), lds, s, d); break;
+  }
+  HIP_CHECK(hipGetLastError());
+}
+
+// forward-sweep right-hand side of a front: own separator entries plus the
+// children's update vectors, gathered through parent-to-child index maps
+__global__ void rhs_gather_kernel(const RhsDesc* __restrict__ descs) {
+  const RhsDesc d = descs[blockIdx.y];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  double v = (i < d.s) ? d.y[d.sep_lo + i] : 0.0;
+  for (int c = 0; c < d.nkids; ++c) {
+    int k = d.inv[c][i];
+    if (k >= 0) v += d.wc[c][k];
+  }
+  if (i < d.s) d.y[d.sep_lo + i] = v; else d.w[i - d.s] = v;
+}
+
+void launch_rhs_gather(const RhsDesc* d, int nd, int max_n, hipStream_t s) {
+  if (nd <= 0 || max_n <= 0) return;
+  hipLaunchKernelGGL(rhs_gather_kernel, dim3((max_n + 255) / 256, nd), dim3(256), 0, s, d);
+  HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace hssmf

@@ -1,0 +1,218 @@
+// Variable-size batched GEMM on CDNA4 matrix cores.
+//
+// One launch covers a list of independent products C = alpha op(A) op(B) +
+// beta C (column major) of arbitrary shapes; every workgroup owns one 64x64
+// tile of one product (found by binary search over the tile prefix sums).
+// Four 64-lane wavefronts each own a 32x32 quadrant built from 16x16 MFMA
+// blocks.  FP64 uses v_mfma_f64_16x16x4; FP32 and BF16 inputs accumulate in
+// FP32 with v_mfma_f32_16x16x4_f32 / v_mfma_f32_16x16x32_bf16.
+// Optional row maps fuse the gathers / scatters of the multifrontal
+// extend-add into the product.
+#include "common.hpp"
+
+namespace hssmf {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int TM = 64, TN = 64;
+
+__device__ __forceinline__ int find_desc(const GemmDesc* __restrict__ d, int nd, int64_t tile) {
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (d[mid].tile_base <= tile) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <class T>
+__device__ __forceinline__ T load_a(const GemmDesc& g, int i, int kk) {
+  const T* A = static_cast<const T*>(g.A);
+  if (i >= g.m || kk >= g.k) return T(0);
+  if (g.transA) return A[kk + (int64_t)i * g.lda];
+  int r = g.amap ? g.amap[i] : i;
+  return A[r + (int64_t)kk * g.lda];
+}
+
+template <class T>
+__device__ __forceinline__ T load_b(const GemmDesc& g, int kk, int j) {
+  const T* B = static_cast<const T*>(g.B);
+  if (j >= g.n || kk >= g.k) return T(0);
+  if (g.transB) return B[j + (int64_t)kk * g.ldb];
+  int r = g.bmap ? g.bmap[kk] : kk;
+  return B[r + (int64_t)j * g.ldb];
+}
+
+// ---------------------------------------------------------------- FP64 -----
+__global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restrict__ descs, int nd) {
+  constexpr int TK = 16;
+  __shared__ double As[TK][TM + 1];
+  __shared__ double Bs[TK][TN + 1];
+  const int di = find_desc(descs, nd, blockIdx.x);
+  const GemmDesc g = descs[di];
+  const int64_t t = blockIdx.x - g.tile_base;
+  if (t >= (int64_t)g.tiles_m * g.tiles_n) return;
+  const int row0 = (int)(t % g.tiles_m) * TM;
+  const int col0 = (int)(t / g.tiles_m) * TN;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  dbl4 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0, 0, 0, 0};
+  for (int k0 = 0; k0 < g.k; k0 += TK) {
+    // stage op(A)[row0:row0+64, k0:k0+16] and op(B)[k0:k0+16, col0:col0+64]
+    for (int e = tid; e < TM * TK; e += 256) {
+      int i, kk;
+      if (g.transA) { kk = e % TK; i = e / TK; } else { i = e % TM; kk = e / TM; }
+      As[kk][i] = load_a<double>(g, row0 + i, k0 + kk);
+    }
+    for (int e = tid; e < TN * TK; e += 256) {
+      int j, kk;
+      if (g.transB) { j = e % TN; kk = e / TN; } else { kk = e % TK; j = e / TK; }
+      Bs[kk][j] = load_b<double>(g, k0 + kk, col0 + j);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < TK; ks += 4) {
+      const int kk = ks + (lane >> 4);
+      double a0 = As[kk][wr + (lane & 15)];
+      double a1 = As[kk][wr + 16 + (lane & 15)];
+      double b0 = Bs[kk][wc + (lane & 15)];
+      double b1 = Bs[kk][wc + 16 + (lane & 15)];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // FP64 16x16x4 result layout: lane l, slot v holds (row l/16 + 4v, col l%16)
+  double* C = static_cast<double*>(g.C);
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int v = 0; v < 4; ++v) {
+        int i = row0 + wr + a * 16 + (lane >> 4) + 4 * v;
+        int j = col0 + wc + b * 16 + (lane & 15);
+        if (i < g.m && j < g.n) {
+          int r = g.cmap ? g.cmap[i] : i;
+          double* c = C + r + (int64_t)j * g.ldc;
+          double val = g.alpha * acc[a][b][v];
+          *c = (g.beta == 0.0) ? val : val + g.beta * (*c);
+        }
+      }
+}
+
+// ------------------------------------------------- FP32 / BF16 inputs -----
+// A, B stored in float (FP32 path) or __bf16 (BF16 path); products
+// accumulate in FP32; C is stored as TOut (float, or double when a low
+// precision product is added into an FP64 result).
+template <class TIn, class TOut>
+__global__ __launch_bounds__(256) void gemm_lp_kernel(const GemmDesc* __restrict__ descs, int nd) {
+  constexpr int TK = 32;
+  __shared__ float As[TK][TM + 1];
+  __shared__ float Bs[TK][TN + 1];
+  const int di = find_desc(descs, nd, blockIdx.x);
+  const GemmDesc g = descs[di];
+  const int64_t t = blockIdx.x - g.tile_base;
+  if (t >= (int64_t)g.tiles_m * g.tiles_n) return;
+  const int row0 = (int)(t % g.tiles_m) * TM;
+  const int col0 = (int)(t / g.tiles_m) * TN;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  flt4 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = flt4{0, 0, 0, 0};
+  for (int k0 = 0; k0 < g.k; k0 += TK) {
+    for (int e = tid; e < TM * TK; e += 256) {
+      int i, kk;
+      if (g.transA) { kk = e % TK; i = e / TK; } else { i = e % TM; kk = e / TM; }
+      As[kk][i] = (float)load_a<TIn>(g, row0 + i, k0 + kk);
+    }
+    for (int e = tid; e < TN * TK; e += 256) {
+      int j, kk;
+      if (g.transB) { j = e % TN; kk = e / TN; } else { kk = e % TK; j = e / TK; }
+      Bs[kk][j] = (float)load_b<TIn>(g, k0 + kk, col0 + j);
+    }
+    __syncthreads();
+    if constexpr (sizeof(TIn) == 4) {
+#pragma unroll
+      for (int ks = 0; ks < TK; ks += 4) {
+        const int kk = ks + (lane >> 4);
+        float a0 = As[kk][wr + (lane & 15)], a1 = As[kk][wr + 16 + (lane & 15)];
+        float b0 = Bs[kk][wc + (lane & 15)], b1 = Bs[kk][wc + 16 + (lane & 15)];
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+      }
+    } else {
+      // one 16x16x32 BF16 step: lane l holds k = 8*(l/16) .. +7
+      bf16x8 a0, a1, b0, b1;
+      const int kb = 8 * (lane >> 4);
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        a0[v] = (__bf16)As[kb + v][wr + (lane & 15)];
+        a1[v] = (__bf16)As[kb + v][wr + 16 + (lane & 15)];
+        b0[v] = (__bf16)Bs[kb + v][wc + (lane & 15)];
+        b1[v] = (__bf16)Bs[kb + v][wc + 16 + (lane & 15)];
+      }
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // FP32 16x16 result layout: lane l, slot v holds (row 4(l/16) + v, col l%16)
+  TOut* C = static_cast<TOut*>(g.C);
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int v = 0; v < 4; ++v) {
+        int i = row0 + wr + a * 16 + 4 * (lane >> 4) + v;
+        int j = col0 + wc + b * 16 + (lane & 15);
+        if (i < g.m && j < g.n) {
+          int r = g.cmap ? g.cmap[i] : i;
+          TOut* c = C + r + (int64_t)j * g.ldc;
+          TOut val = (TOut)(g.alpha * (double)acc[a][b][v]);
+          *c = (g.beta == 0.0) ? val : (TOut)(val + (TOut)g.beta * (*c));
+        }
+      }
+}
+
+void gemm_batched(const std::vector<GemmDesc>& in, GemmType type, Stager& st, hipStream_t s) {
+  std::vector<GemmDesc> d;
+  d.reserve(in.size());
+  int64_t tiles = 0;
+  for (const GemmDesc& g0 : in) {
+    if (g0.m <= 0 || g0.n <= 0) continue;
+    GemmDesc g = g0;
+    if (g.k <= 0) {
+      if (g.beta == 1.0) continue;
+      g.k = 0;  // alpha * 0 + beta * C: still launched to scale C
+    }
+    g.tiles_m = (g.m + TM - 1) / TM;
+    g.tiles_n = (g.n + TN - 1) / TN;
+    g.tile_base = tiles;
+    tiles += (int64_t)g.tiles_m * g.tiles_n;
+    d.push_back(g);
+  }
+  if (d.empty()) return;
+  REQUIRE(tiles < (1LL << 31), HSSMF_EINVAL, "gemm batch too large");
+  GemmDesc* dd = st.put_vec(d, s);
+  dim3 grid((unsigned)tiles), blk(256);
+  const int n = (int)d.size();
+  switch (type) {
+    case GEMM_F64: hipLaunchKernelGGL(gemm_f64_kernel, grid, blk, 0, s, dd, n); break;
+    case GEMM_F32: hipLaunchKernelGGL((gemm_lp_kernel<float, float>), grid, blk, 0, s, dd, n); break;
+    case GEMM_F32_D: hipLaunchKernelGGL((gemm_lp_kernel<float, double>), grid, blk, 0, s, dd, n); break;
+    case GEMM_BF16: hipLaunchKernelGGL((gemm_lp_kernel<__bf16, float>), grid, blk, 0, s, dd, n); break;
+    case GEMM_BF16_D: hipLaunchKernelGGL((gemm_lp_kernel<__bf16, double>), grid, blk, 0, s, dd, n); break;
+  }
+  HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace hssmf

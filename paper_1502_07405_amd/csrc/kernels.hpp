@@ -1,0 +1,161 @@
+// Device-side descriptor types and host launchers of the kernels.
+#pragma once
+#include <algorithm>
+
+#include "common.hpp"
+
+namespace hssmf {
+
+// A dense front (or any square matrix factored by the batched blocked LU):
+// F is n x n column major (ld = ld); pivoting is restricted to rows [0, s).
+struct LUFront {
+  double* F;
+  int* ipiv;     // s pivot rows (front-local row indices)
+  int s, n, ld;
+  int id;        // reported on a zero pivot
+};
+
+// extend-add: F[map[i], map[j]] += U[i, j] for i, j < u
+struct EADesc {
+  const double* U;
+  double* F;
+  const int* map;
+  int u, ldu, ldf, pad;
+};
+
+// y[rmap ? rmap[r] : r] += alpha * sum_j M[r, j] x[xmap ? xmap[j] : j]
+// (trans: M^T, i.e. r indexes columns of M)
+struct GemvDesc {
+  const double* M;
+  const double* x;
+  double* y;
+  const int* xmap;
+  const int* ymap;
+  int rows, cols, ld, trans;
+  double alpha;
+  int overwrite;   // y = alpha M x instead of y += alpha M x
+  int pad;
+};
+
+// triangular solve of one front's F11 block in place on a vector
+struct TrsvDesc {
+  const double* F;   // F11 at F, ld
+  const int* ipiv;   // pivots (nullptr: none)
+  double* x;         // s entries
+  int s, ld;
+};
+
+// gather of the multifrontal right-hand side (forward sweep): for front
+// local index i: v = (i < s ? y[sep_lo + i] : 0) + sum_c w_c[inv_c[i]];
+// written to y[sep_lo + i] or w[i - s].
+struct RhsDesc {
+  double* y;       // global vector (new ordering)
+  double* w;       // this front's update vector (u)
+  const double* wc[2];
+  const int* inv[2];
+  int n, s, sep_lo, nkids;
+};
+
+void launch_fill(double* p, int64_t n, double v, hipStream_t s);
+void launch_assemble(double* base, const int64_t* dst, const int64_t* src, const double* val,
+                     int64_t count, hipStream_t s);
+void launch_extend_add(const EADesc* d, int nd, int max_u, hipStream_t s);
+void launch_lu_panel(const LUFront* fr, int nf, int jb, int nb, int* info, hipStream_t s);
+void launch_laswp(const LUFront* fr, int nf, int jb, int nb, int max_n, hipStream_t s);
+void launch_trsm_u12(const LUFront* fr, int nf, int jb, int nb, int max_n, hipStream_t s);
+void launch_gemv(const GemvDesc* d, int nd, int max_rows, hipStream_t s);
+// kind: 0 = L^{-1} P (unit lower, pivots first), 1 = U^{-1} (upper),
+// 2 = U^{-T}, 3 = P^T L^{-T} (unit, pivots last), 4 = L^{-1} (non-unit
+// lower), 5 = L^{-T} (non-unit lower, transposed)
+void launch_trsv(const TrsvDesc* d, int nd, int kind, int max_s, hipStream_t s);
+void launch_rhs_gather(const RhsDesc* d, int nd, int max_n, hipStream_t s);
+
+}  // namespace hssmf
+
+namespace hssmf {
+
+// front-local sparse block A_i (rows and columns local to the front, only
+// entries with row < s or column < s), values read through vidx from the
+// CSR value array
+struct SpFront {
+  const int* rowptr;
+  const int* col;
+  const int64_t* vidx;
+};
+
+// y[i, c] = (beta ? y : 0) + sum_e A[i, col[e]] * x[col[e], c]
+struct SpmmDesc {
+  SpFront A;
+  const double* val;
+  const double* X;
+  double* Y;
+  int nrows, ncols, ldx, ldy;
+};
+
+// dst[i, j] (+)= src[rmap(i), cmap(j)] (or src^T when trans), i < m, j < n
+struct CopyDesc {
+  const void* src;
+  void* dst;
+  const int* rmap;
+  const int* cmap;
+  int m, n, lds, ldd;
+  int accumulate, trans;
+  double alpha;
+};
+
+// what element extraction needs to know about a front F_i = A_i (+) U_kids
+struct FrontOpDev {
+  SpFront A;
+  const double* val;
+  const double* U[2];
+  const int* inv[2];   // front-local index -> child-local index or -1
+  int ldu[2];
+  int nkids, n;
+};
+
+struct ExtractDesc {
+  double* dst;
+  const int* I;
+  const int* J;
+  int m, n, ldd, fop;
+};
+
+// pivoted (ID) or plain Householder QR of Y = S^T, S m x d
+struct QRDesc {
+  const double* S;
+  double* W;       // d x m work (ld d)
+  int* perm;       // m
+  int* rank;       // 1
+  double* E;       // (m-k) x k, ld m-k (ID mode)
+  double* Q;       // d x d explicit Q (QR mode, may be null)
+  double* L;       // k x k lower = R^T (QR mode)
+  int m, d, lds;
+  double eps;
+};
+
+struct TrsmDesc {
+  const double* T;
+  double* X;
+  int n, ncols, ldt, ldx;
+  int b0, bs;
+};
+
+void launch_rng(double* R, int ldr, const int* orig, int nrows, int c0, int nc, uint64_t seed, hipStream_t s);
+void launch_spmm(const SpmmDesc* d, int nd, int max_rows, int max_cols, hipStream_t s);
+void launch_copy(const CopyDesc* d, int nd, int64_t max_elems, int f32, hipStream_t s);
+void launch_extract(const ExtractDesc* d, int nd, const FrontOpDev* fops, int64_t max_elems, hipStream_t s);
+void launch_qr(const QRDesc* d, int nd, int pivot, int max_m, hipStream_t s);
+// dst (m x k, ld ldd) = Pi [I; E]: dst[perm[i], :] = row i of [I; E]
+struct InterpDesc {
+  double* dst;
+  const int* perm;
+  const double* E;   // (m-k) x k, ld m-k
+  int m, k, ldd, pad;
+};
+void launch_interp_dense(const InterpDesc* d, int nd, int64_t max_elems, hipStream_t s);
+void launch_pivots(double* M, int ld, int ncols, const int* ipiv, int k, int reverse, hipStream_t s);
+// logical T(i,j) = trans ? T[j + i ld] : T[i + j ld]; solve rows [b0, b0+bs) in place
+void launch_trsm_block(const TrsmDesc* d, int nd, int lower, int unit, int trans, int max_cols, hipStream_t s);
+void launch_convert(const double* src, void* dst, int64_t n, int to_bf16, hipStream_t s);
+
+}  // namespace hssmf

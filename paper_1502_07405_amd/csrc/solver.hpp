@@ -1,0 +1,181 @@
+// Host-side structures of a factorization: symbolic plan, per-front device
+// storage, HSS node storage.
+#pragma once
+#include <memory>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace hssmf {
+
+// ------------------------------------------------------------- plan -------
+struct FrontPlan {
+  int id = 0, lo = 0, hi = 0, s = 0, u = 0, n = 0, parent = -1, height = 0;
+  bool hss = false;
+  std::vector<int> kids;
+  std::vector<int> upd;                 // sorted new indices of I_upd
+  std::vector<std::vector<int>> kidmap; // per kid: kid-local update index -> local index here
+};
+
+struct Plan {
+  int n = 0, nfront = 0;
+  int64_t nnz = 0;
+  std::vector<int> perm, iperm;
+  // P A P^T in CSR (new indices); pvidx points into the caller's value array
+  std::vector<int64_t> prow;
+  std::vector<int> pcol;
+  std::vector<int64_t> pvidx;
+  // transpose structure of P A P^T
+  std::vector<int64_t> trow;
+  std::vector<int> tcol;
+  std::vector<int64_t> tvidx;
+  std::vector<FrontPlan> fr;
+  std::vector<std::vector<int>> levels;  // by height, 0 = leaves
+};
+
+void build_plan(const hssmf_csr* A, const hssmf_ordering* ord, const hssmf_opts* o, Plan& P);
+
+// front-local CSR of A_i: rows with local index < s keep every entry inside
+// the front, rows >= s keep the entries in columns < s (Eq. frontal_1)
+struct LocalCSR {
+  std::vector<int> rowptr, col;
+  std::vector<int64_t> vidx;
+};
+void front_local_csr(const Plan& P, const FrontPlan& f, bool transpose, LocalCSR& out);
+
+// ----------------------------------------------------------- HSS nodes -----
+struct HNode {
+  int lo = 0, hi = 0, parent = -1, height = 0;
+  int kid[2] = {-1, -1};
+  bool leaf() const { return kid[0] < 0; }
+  int m() const { return hi - lo; }
+  // compression state
+  bool done = false;
+  int r = 0, c = 0, mr = 0, mc = 0;
+  std::vector<int> permr, permc, Ir, Ic;  // host copies (local to the front)
+  int *dpermr = nullptr, *dpermc = nullptr, *dIr = nullptr, *dIc = nullptr;
+  int *drank = nullptr;                   // 2 ints: r, c
+  double *D = nullptr, *B12 = nullptr, *B21 = nullptr;
+  double *Er = nullptr, *Ec = nullptr;
+  double *Sr = nullptr, *Sc = nullptr;            // node samples (before the ID)
+  double *Srr = nullptr, *Scr = nullptr, *Rrr = nullptr, *Rcr = nullptr;  // reduced
+  // ULV
+  int nl = 0;
+  double *Q = nullptr, *L = nullptr, *WQ = nullptr, *QV = nullptr;  // D21|Dh = WQ, V1;Vh = QV
+  double *Dbar = nullptr, *Vbar = nullptr;
+  double *Ud = nullptr, *Vd = nullptr;    // dense interpolative generators
+  double *Ubig = nullptr, *Vbig = nullptr;
+  // solve buffers (fixed addresses, so the solve launches are built once)
+  double *bbar = nullptr, *ctop = nullptr, *cbot = nullptr, *w = nullptr, *wab = nullptr;
+  double *xin = nullptr, *xbar = nullptr, *gt = nullptr, *gbar = nullptr, *lbar = nullptr, *hv = nullptr;
+  double *tmp1 = nullptr, *tmpv = nullptr;
+  int* diperm = nullptr;      // inverse of permr
+};
+
+struct HFront {
+  int f = 0, n = 0, s = 0, u = 0;
+  std::vector<HNode> nd;
+  int root = -1, k = -1, q = -1, maxh = 0;
+  // sampling
+  int d = 0, dcap = 0, rounds = 0;
+  double *R = nullptr, *Sr = nullptr, *Sc = nullptr;
+  int* orig = nullptr;       // original row ids of the front's indices
+  bool finished = false, refresh = false;
+  // front operator
+  int *a_row = nullptr, *a_col = nullptr, *at_row = nullptr, *at_col = nullptr;
+  int64_t *a_vidx = nullptr, *at_vidx = nullptr;
+  int fop = -1;
+  // ULV top node and low-rank Schur complement
+  double* Dk = nullptr;
+  int* ipivk = nullptr;
+  int mk = 0;
+  double *Vbark = nullptr, *ThT = nullptr, *Phi = nullptr;
+  double* Upd = nullptr;     // dense update matrix (u x u)
+  void* UpdLP = nullptr;     // low-precision copy for sampling GEMMs
+  double *X = nullptr, *t1 = nullptr, *t2 = nullptr;  // solve buffers
+};
+
+// one recorded launch of the solve phase
+struct Op {
+  int kind;      // OP_*
+  const void* d; // device descriptor array
+  int n;         // descriptors
+  int64_t p0;    // kernel parameter (max extent / trsv kind)
+};
+enum { OP_GEMV = 0, OP_COPY = 1, OP_TRSV = 2, OP_RHS = 3 };
+
+// ---------------------------------------------------------- fronts ---------
+struct FrontRT {
+  // dense front storage (whole front kept: F11 = L\U, F12 = U12, F21 = L21,
+  // F22 = update matrix until the parent consumed it)
+  double* F = nullptr;
+  int* ipiv = nullptr;
+  // update matrix seen by the parent
+  const double* U = nullptr;
+  int ldu = 0;
+  const void* Ulp = nullptr;  // low-precision copy (HSS parents in mixed mode)
+  int* d_upd = nullptr;       // global new indices of I_upd
+  int* d_kidmap[2] = {nullptr, nullptr};  // kid-local -> local (device)
+  int* d_inv[2] = {nullptr, nullptr};     // local -> kid-local or -1 (device)
+  double* w = nullptr;        // forward-sweep update vector (u)
+  int hidx = -1;              // index into Handle::hf for HSS fronts
+  int64_t asm_off = 0, asm_cnt = 0;  // range in the assembly map arrays
+};
+
+struct Handle {
+  Plan P;
+  hssmf_opts o{};
+  hipStream_t st = nullptr;
+  Arena arena;       // plan data that survives refactorization
+  Arena narena;      // numeric factors, reset by every refactorization
+  Arena* cur = &arena;
+  Stager stager;
+  std::vector<Op> sops[2][2];  // [trans][0 = forward, 1 = backward]
+  double* yws = nullptr;       // n, the right-hand side in the new ordering
+  int* d_iperm = nullptr;
+  int *d_row = nullptr, *d_col = nullptr;  // CSR entry coordinates (adjoint)
+  int64_t *d_trowptr = nullptr, *d_tvidx = nullptr;  // A^T in CSR (original order)
+  int* d_tcolind = nullptr;
+  double* d_scal = nullptr;    // device scalars of the outer solvers
+  double* d_part = nullptr;    // dot-product partial sums
+  int device = 0;
+  double* d_val = nullptr;    // caller's CSR values (original order)
+  int64_t* d_rowptr = nullptr;
+  int* d_colind = nullptr;
+  int* d_perm = nullptr;
+  int64_t* d_asm_dst = nullptr;  // assembly: front element offset (relative to the level buffer)
+  int64_t* d_asm_src = nullptr;  // assembly: value index
+  std::vector<double*> level_buf;
+  std::vector<FrontRT> fr;
+  std::vector<HFront> hf;
+  int* d_info = nullptr;
+  int failed_front = -1;
+  double* vec_ws = nullptr;   // solve workspace (n doubles x several)
+  hssmf_stats stats{};
+  GemmType gt() const;
+};
+
+void numeric_factor(Handle& h);
+void apply_inverse(Handle& h, int trans, const double* x, double* y);
+void spmv(Handle& h, int trans, const double* x, double* y, double alpha, double beta);
+double dnrm2(Handle& h, const double* x, int n);
+
+// device helpers shared by factor and solve
+void blocked_lu(Handle& h, const std::vector<LUFront>& fronts);
+void tri_solve_many(Handle& h, const double* T, int ldt, int n, double* X, int ldx, int ncols, bool lower,
+                    bool unit, bool trans);
+
+void build_solve_ops(Handle& h);
+void run_ops(Handle& h, const std::vector<Op>& ops);
+
+template <class T>
+T* upload(Handle& h, const std::vector<T>& v) {
+  T* d = h.cur->get<T>(v.size());
+  if (!v.empty()) {
+    void* src = h.stager.put(v.data(), v.size() * sizeof(T), h.st);
+    HIP_CHECK(hipMemcpyAsync(d, src, v.size() * sizeof(T), hipMemcpyDeviceToDevice, h.st));
+  }
+  return d;
+}
+
+}  // namespace hssmf

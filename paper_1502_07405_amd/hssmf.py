@@ -1,0 +1,238 @@
+"""Python binding of libhssmf (include/hssmf.h): argument marshalling only.
+
+Every step of factorization and solve runs in the HIP library; PyTorch only
+provides device memory (float64 CUDA tensors) and the stream.  There is no
+CPU fallback: if the library is missing or no GPU is present the calls raise.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhssmf.so")
+
+HSSMF_OK, HSSMF_EINVAL, HSSMF_ENOMEM, HSSMF_ESINGULAR, HSSMF_ERANK, HSSMF_ENOCONV, HSSMF_EDEVICE = 0, -1, -2, -3, -4, -5, -6
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+OUTER = {"ir": 0, "gmres": 1}
+
+EXPORTS = ["hssmf_default_opts", "hssmf_factor", "hssmf_refactor", "hssmf_apply", "hssmf_solve",
+           "hssmf_solve_transpose", "hssmf_adjoint", "hssmf_stats_get", "hssmf_hss_ranks",
+           "hssmf_last_failed_front", "hssmf_destroy", "hssmf_strerror"]
+
+
+class HssmfError(RuntimeError):
+    def __init__(self, code, what, front=-1):
+        super().__init__(f"{what}: {strerror(code)} ({code})" + (f", front {front}" if front >= 0 else ""))
+        self.code = code
+        self.front = front
+
+
+class CSRArg(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("rowptr", ctypes.c_void_p), ("colind", ctypes.c_void_p),
+                ("val", ctypes.c_void_p)]
+
+
+class OrderingArg(ctypes.Structure):
+    _fields_ = [("perm", ctypes.c_void_p), ("nfront", ctypes.c_int32), ("sep_ptr", ctypes.c_void_p),
+                ("parent", ctypes.c_void_p)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("rel_tol", ctypes.c_double), ("leaf_size", ctypes.c_int32), ("min_sep_hss", ctypes.c_int32),
+                ("d0", ctypes.c_int32), ("dd", ctypes.c_int32), ("p", ctypes.c_int32), ("d_max", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("gemm_prec", ctypes.c_int32), ("outer", ctypes.c_int32),
+                ("restart", ctypes.c_int32), ("tol", ctypes.c_double), ("max_it", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("rel_residual", ctypes.c_double),
+                ("failed_front", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nfront", ctypes.c_int32), ("n_hss_fronts", ctypes.c_int32),
+                ("max_rank", ctypes.c_int32), ("max_d", ctypes.c_int32), ("growth_rounds", ctypes.c_int32),
+                ("factor_bytes", ctypes.c_int64), ("t_plan_ms", ctypes.c_double),
+                ("t_factor_ms", ctypes.c_double), ("flops_factor", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load libhssmf.so (built in-tree by paper_1502_07405_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run paper_1502_07405_amd/build.py first")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32 = ctypes.c_void_p, ctypes.c_int32
+        L.hssmf_default_opts.argtypes = [ctypes.POINTER(Opts)]
+        L.hssmf_factor.argtypes = [ctypes.POINTER(CSRArg), ctypes.POINTER(OrderingArg), ctypes.POINTER(Opts), vp,
+                                   ctypes.POINTER(vp)]
+        L.hssmf_refactor.argtypes = [vp, vp]
+        L.hssmf_apply.argtypes = [vp, i32, vp, vp]
+        L.hssmf_solve.argtypes = [vp, vp, vp, ctypes.POINTER(Info)]
+        L.hssmf_solve_transpose.argtypes = [vp, vp, vp, ctypes.POINTER(Info)]
+        L.hssmf_adjoint.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(Info)]
+        L.hssmf_stats_get.argtypes = [vp, ctypes.POINTER(Stats)]
+        L.hssmf_hss_ranks.argtypes = [vp, vp, i32]
+        L.hssmf_last_failed_front.argtypes = [vp]
+        L.hssmf_destroy.argtypes = [vp]
+        L.hssmf_destroy.restype = None
+        L.hssmf_strerror.argtypes = [i32]
+        L.hssmf_strerror.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def strerror(code):
+    return load().hssmf_strerror(int(code)).decode()
+
+
+def default_opts(**kw):
+    o = Opts()
+    load().hssmf_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "gemm_prec" and isinstance(v, str):
+            v = PREC[v]
+        if k == "outer" and isinstance(v, str):
+            v = OUTER[v]
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_f64(x, n, torch):
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64 and x.is_contiguous()
+            and x.numel() == n):
+        raise ValueError(f"expected a contiguous float64 CUDA tensor with {n} entries")
+    return x
+
+
+class Factorization:
+    """hssmf_factor on host CSR / ordering arrays; solves on CUDA tensors."""
+
+    def __init__(self, A, ordering, opts=None, stream=None, **kw):
+        import torch
+        self._torch = torch
+        self.lib = load()
+        self.n = int(A.n)
+        self.nnz = int(A.rowptr[-1])
+        self._rowptr = np.ascontiguousarray(A.rowptr, dtype=np.int64)
+        self._colind = np.ascontiguousarray(A.colind, dtype=np.int32)
+        self._val = np.ascontiguousarray(A.val, dtype=np.float64)
+        self._perm = np.ascontiguousarray(ordering.perm, dtype=np.int32)
+        self._sep = np.ascontiguousarray(ordering.sep_ptr, dtype=np.int32)
+        self._par = np.ascontiguousarray(ordering.parent, dtype=np.int32)
+        self.opts = opts if opts is not None else default_opts(**kw)
+        csr = CSRArg(self.n, self._rowptr.ctypes.data, self._colind.ctypes.data, self._val.ctypes.data)
+        ordg = OrderingArg(self._perm.ctypes.data, len(self._par), self._sep.ctypes.data, self._par.ctypes.data)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self._stream = stream
+        h = ctypes.c_void_p()
+        rc = self.lib.hssmf_factor(ctypes.byref(csr), ctypes.byref(ordg), ctypes.byref(self.opts),
+                                   ctypes.c_void_p(stream), ctypes.byref(h))
+        if rc != HSSMF_OK:
+            raise HssmfError(rc, "hssmf_factor", self.lib.hssmf_last_failed_front(None))
+        self.h = h
+
+    def _check(self, rc, what, allow_noconv=False):
+        if rc == HSSMF_OK or (allow_noconv and rc == HSSMF_ENOCONV):
+            return rc
+        raise HssmfError(rc, what, self.lib.hssmf_last_failed_front(self.h))
+
+    def refactor(self, val):
+        v = np.ascontiguousarray(val, dtype=np.float64)
+        assert v.size == self.nnz
+        self._check(self.lib.hssmf_refactor(self.h, v.ctypes.data), "hssmf_refactor")
+
+    def apply(self, x, trans=False):
+        torch = self._torch
+        _dev_f64(x, self.n, torch)
+        y = torch.empty_like(x)
+        self._check(self.lib.hssmf_apply(self.h, int(bool(trans)), _ptr(x), _ptr(y)), "hssmf_apply")
+        return y
+
+    def solve(self, b, allow_noconv=False):
+        torch = self._torch
+        _dev_f64(b, self.n, torch)
+        x = torch.empty_like(b)
+        info = Info()
+        rc = self.lib.hssmf_solve(self.h, _ptr(b), _ptr(x), ctypes.byref(info))
+        self._check(rc, "hssmf_solve", allow_noconv)
+        return x, info
+
+    def solve_transpose(self, g, allow_noconv=False):
+        torch = self._torch
+        _dev_f64(g, self.n, torch)
+        lam = torch.empty_like(g)
+        info = Info()
+        rc = self.lib.hssmf_solve_transpose(self.h, _ptr(g), _ptr(lam), ctypes.byref(info))
+        self._check(rc, "hssmf_solve_transpose", allow_noconv)
+        return lam, info
+
+    def adjoint(self, x, g):
+        torch = self._torch
+        _dev_f64(x, self.n, torch)
+        _dev_f64(g, self.n, torch)
+        db = torch.empty_like(g)
+        dval = torch.empty(self.nnz, dtype=torch.float64, device=g.device)
+        info = Info()
+        rc = self.lib.hssmf_adjoint(self.h, _ptr(x), _ptr(g), _ptr(db), _ptr(dval), ctypes.byref(info))
+        self._check(rc, "hssmf_adjoint")
+        return db, dval, info
+
+    def stats(self):
+        s = Stats()
+        self._check(self.lib.hssmf_stats_get(self.h, ctypes.byref(s)), "hssmf_stats_get")
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def hss_ranks(self):
+        nf = self.lib.hssmf_hss_ranks(self.h, None, 0)
+        out = np.zeros(5 * max(nf, 1), dtype=np.int32)
+        self.lib.hssmf_hss_ranks(self.h, out.ctypes.data, nf)
+        return [tuple(int(v) for v in out[5 * i:5 * i + 5]) for i in range(nf)]
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.hssmf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class LinearSolve:
+    """x = A(val)^{-1} b as a torch.autograd.Function whose backward is the
+    hand-written adjoint: one transposed solve with the same factors gives
+    dL/db = lambda and dL/dval = -lambda_i x_j on the pattern."""
+
+    @staticmethod
+    def make(fact):
+        import torch
+
+        class _Fn(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, val, b):
+                x, _ = fact.solve(b.contiguous())
+                ctx.save_for_backward(x)
+                return x
+
+            @staticmethod
+            def backward(ctx, gx):
+                (x,) = ctx.saved_tensors
+                db, dval, _ = fact.adjoint(x, gx.contiguous())
+                return dval, db
+
+        return _Fn.apply
