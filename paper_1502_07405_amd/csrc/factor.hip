@@ -317,7 +317,18 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
       F->rounds = 0;
       F->finished = false;
       F->refresh = false;
-      for (auto& nd : F->nd) { nd.done = false; nd.D = nullptr; }
+      // every numeric pass starts from the structure only: buffers of an
+      // earlier pass live in memory that the pass has released
+      for (auto& nd : F->nd) {
+        HNode fresh;
+        fresh.lo = nd.lo; fresh.hi = nd.hi; fresh.parent = nd.parent; fresh.height = nd.height;
+        fresh.kid[0] = nd.kid[0]; fresh.kid[1] = nd.kid[1];
+        nd = std::move(fresh);
+      }
+      F->Dk = nullptr; F->ipivk = nullptr; F->mk = 0;
+      F->Vbark = F->ThT = F->Phi = F->Upd = nullptr;
+      F->UpdLP = nullptr;
+      F->X = F->t1 = F->t2 = nullptr;
       launch_rng(F->R, F->n, F->orig, F->n, 0, F->d, o.seed, h.st);
       c0.push_back(0);
     }
@@ -744,6 +755,30 @@ void schur_level(Handle& h, std::vector<HFront*>& fs) {
 
 }  // namespace
 
+// per-front norms of Theta, Phi and the update matrix (diagnostics)
+static double dev_fro(Handle& h, const double* p, int64_t n) {
+  if (!p || n <= 0) return 0.0;
+  std::vector<double> v(n);
+  HIP_CHECK(hipMemcpyAsync(v.data(), p, n * sizeof(double), hipMemcpyDeviceToHost, h.st));
+  HIP_CHECK(hipStreamSynchronize(h.st));
+  double s = 0;
+  for (double x : v) s += x * x;
+  return std::sqrt(s);
+}
+
+static void debug_fronts(Handle& h, std::vector<HFront*>& fs) {
+  for (HFront* F : fs) {
+    int rr = 0;
+    for (auto& nd : F->nd) rr = std::max(rr, nd.r);
+    std::fprintf(stderr, "front %d s %d u %d rank %d d %d", F->f, F->s, F->u, rr, F->d);
+    if (F->q >= 0)
+      std::fprintf(stderr, " mk %d |Th| %.6e |Phi| %.6e |U| %.6e |Dk| %.6e", F->mk,
+                   dev_fro(h, F->ThT, (int64_t)F->mk * F->u), dev_fro(h, F->Phi, (int64_t)F->mk * F->u),
+                   dev_fro(h, F->Upd, (int64_t)F->u * F->u), dev_fro(h, F->Dk, (int64_t)F->mk * F->mk));
+    std::fprintf(stderr, "\n");
+  }
+}
+
 // -------------------------------------------------------- numeric ---------
 void numeric_factor(Handle& h) {
   const Plan& P = h.P;
@@ -800,6 +835,7 @@ void numeric_factor(Handle& h) {
       compress_level(h, fs, fops, d_iota);
       ulv_level(h, fs);
       schur_level(h, fs);
+      if (std::getenv("HSSMF_DEBUG")) debug_fronts(h, fs);
     }
     // check for zero pivots after each level
     int info = 0;
