@@ -153,6 +153,22 @@ int hssmf_hss_ranks(void* h, int32_t* out, int32_t cap);
 
 int hssmf_last_failed_front(void* h);
 
+/* Kernel timing hooks (diagnostics for benchmarks).  While enabled, the
+ * library records a HIP event pair on the launch stream around every launch
+ * of the listed kernel classes and accumulates the launches' algorithmic
+ * work computed on the host.  hssmf_profile_read() waits for the recorded
+ * events and returns, for one class, the summed kernel time (ms), the number
+ * of launches and the summed work (flops).  Reading resets the class.
+ * Classes: 0 = pivoted QR of the interpolative decompositions,
+ * 1 = FP64 batched GEMM (matrix cores), 2 = low-precision batched GEMM,
+ * 3 = blocked LU panel. */
+#define HSSMF_KCLASS_ID 0
+#define HSSMF_KCLASS_GEMM64 1
+#define HSSMF_KCLASS_GEMMLP 2
+#define HSSMF_KCLASS_LUPANEL 3
+int hssmf_profile_enable(int32_t on);
+int hssmf_profile_read(int32_t kclass, double* ms, int64_t* launches, double* flops);
+
 void hssmf_destroy(void* h);
 
 const char* hssmf_strerror(int code);

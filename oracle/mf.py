@@ -133,8 +133,10 @@ class Factorization:
     opts: Options
 
 
-def factor(A, ordering, opts):
+def factor(A, ordering, opts, stop_after=None):
     """Numeric multifrontal factorization, fronts in postorder (Sec. 3.2).
+    ``stop_after`` ends the loop after that front id (a bounded sample of the
+    work for timing; the result is then not a usable factorization).
     Dense fronts: assembly, extend-add, partial LU.  HSS fronts: random
     matrix keyed by original row id, samples by skinny extend-add, Alg. 1
     with adaptive rank, ULV of F11 and Theta^*, Phi (Sec. 4)."""
@@ -144,6 +146,8 @@ def factor(A, ordering, opts):
     updates = {}
     factors = []
     for f in fronts:
+        if stop_after is not None and f.id > stop_after:
+            break
         idx = f.idx
         if f.s >= opts.min_sep_hss:
             op = FrontOp(Ap, f, fronts, updates)

@@ -380,13 +380,15 @@ int hssmf_factor(const hssmf_csr* A, const hssmf_ordering* ord, const hssmf_opts
   Handle* h = new (std::nothrow) Handle();
   if (!h) return HSSMF_ENOMEM;
   int rc = guard_impl(h, [&]() {
+    double t0 = now_ms();
+    // host validation and symbolic analysis first: malformed input is
+    // reported without touching the device
+    build_plan(A, ord, opts, h->P);
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) throw Error(HSSMF_EDEVICE, "no HIP device");
     HIP_CHECK(hipGetDevice(&h->device));
     h->o = *opts;
     h->st = static_cast<hipStream_t>(stream);
-    double t0 = now_ms();
-    build_plan(A, ord, opts, h->P);
     setup(*h, A);
     h->stats.t_plan_ms = now_ms() - t0;
     h->stats.n = h->P.n;

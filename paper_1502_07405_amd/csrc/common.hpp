@@ -114,4 +114,13 @@ class Stager {
   size_t cap_ = 0, off_ = 0;
 };
 
+// kernel timing hooks (see hssmf_profile_enable)
+namespace prof {
+bool enabled();
+// returns a token for end(); -1 when profiling is off
+int begin(int kclass, hipStream_t s);
+void end(int token, hipStream_t s, double flops);
+void add_flops(int kclass, double flops);
+}  // namespace prof
+
 }  // namespace hssmf

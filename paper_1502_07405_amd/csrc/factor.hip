@@ -400,12 +400,32 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
         q.push_back(b);
         maxm = std::max(maxm, std::max(nd.mr, nd.mc));
       }
-      if (!q.empty()) launch_qr(upload(h, q), (int)q.size(), 1, maxm, h.st);
+      if (!q.empty()) {
+        QRDesc* dq = upload(h, q);
+        int tok = prof::begin(0, h.st);
+        launch_qr(dq, (int)q.size(), 1, maxm, h.st);
+        prof::end(tok, h.st, 0.0);
+      }
       std::vector<int> hbuf(off.back());
       if (!hbuf.empty())
         HIP_CHECK(hipMemcpyAsync(hbuf.data(), ibuf, hbuf.size() * sizeof(int), hipMemcpyDeviceToHost, h.st));
       HIP_CHECK(hipStreamSynchronize(h.st));
       h.stager.sync();
+      if (prof::enabled()) {
+        // algorithmic flops of the IDs: Householder steps 4dmk - 2k^2(d+m)
+        // + 4/3 k^3 and the triangular solve k^2 (m - k), per side
+        double fl = 0.0;
+        for (size_t i = 0; i < cand.size(); ++i) {
+          const int* b = hbuf.data() + off[i];
+          const double d = cand[i].F->d;
+          const int ms[2] = {cand[i].n().mr, cand[i].n().mc};
+          for (int sd = 0; sd < 2; ++sd) {
+            double k = b[sd], m = ms[sd];
+            fl += 4.0 * d * m * k - 2.0 * k * k * (d + m) + 4.0 / 3.0 * k * k * k + k * k * (m - k);
+          }
+        }
+        prof::add_flops(0, fl);
+      }
       std::vector<NRef> ok = refresh;
       std::vector<int> ivec;
       std::vector<std::pair<HNode*, int>> ipos;

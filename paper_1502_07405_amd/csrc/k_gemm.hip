@@ -203,6 +203,10 @@ void gemm_batched(const std::vector<GemmDesc>& in, GemmType type, Stager& st, hi
   if (d.empty()) return;
   REQUIRE(tiles < (1LL << 31), HSSMF_EINVAL, "gemm batch too large");
   GemmDesc* dd = st.put_vec(d, s);
+  double flops = 0.0;
+  if (prof::enabled())
+    for (auto& g : d) flops += 2.0 * g.m * g.n * (double)g.k;
+  int tok = prof::begin(type == GEMM_F64 ? 1 : 2, s);
   dim3 grid((unsigned)tiles), blk(256);
   const int n = (int)d.size();
   switch (type) {
@@ -212,6 +216,7 @@ void gemm_batched(const std::vector<GemmDesc>& in, GemmType type, Stager& st, hi
     case GEMM_BF16: hipLaunchKernelGGL((gemm_lp_kernel<__bf16, float>), grid, blk, 0, s, dd, n); break;
     case GEMM_BF16_D: hipLaunchKernelGGL((gemm_lp_kernel<__bf16, double>), grid, blk, 0, s, dd, n); break;
   }
+  prof::end(tok, s, flops);
   HIP_CHECK(hipGetLastError());
 }
 

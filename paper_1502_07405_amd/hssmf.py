@@ -18,7 +18,9 @@ OUTER = {"ir": 0, "gmres": 1}
 
 EXPORTS = ["hssmf_default_opts", "hssmf_factor", "hssmf_refactor", "hssmf_apply", "hssmf_solve",
            "hssmf_solve_transpose", "hssmf_adjoint", "hssmf_stats_get", "hssmf_hss_ranks",
-           "hssmf_last_failed_front", "hssmf_destroy", "hssmf_strerror"]
+           "hssmf_last_failed_front", "hssmf_destroy", "hssmf_strerror", "hssmf_profile_enable",
+           "hssmf_profile_read"]
+KCLASS = {"id": 0, "gemm64": 1, "gemmlp": 2, "lupanel": 3}
 
 
 class HssmfError(RuntimeError):
@@ -83,8 +85,27 @@ def load():
         L.hssmf_destroy.restype = None
         L.hssmf_strerror.argtypes = [i32]
         L.hssmf_strerror.restype = ctypes.c_char_p
+        L.hssmf_profile_enable.argtypes = [i32]
+        L.hssmf_profile_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_double)]
         _lib = L
     return _lib
+
+
+def profile_enable(on=True):
+    """Turn the library's kernel timing hooks on or off."""
+    rc = load().hssmf_profile_enable(int(bool(on)))
+    if rc != HSSMF_OK:
+        raise HssmfError(rc, "hssmf_profile_enable")
+
+
+def profile_read(kclass):
+    """(ms, launches, flops) accumulated for a kernel class since the last read."""
+    ms, n, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+    rc = load().hssmf_profile_read(KCLASS.get(kclass, kclass), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl))
+    if rc != HSSMF_OK:
+        raise HssmfError(rc, "hssmf_profile_read")
+    return ms.value, n.value, fl.value
 
 
 def strerror(code):

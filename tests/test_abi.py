@@ -1,0 +1,108 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/hssmf.h declares, and rejects malformed input on the host before any
+device work (HSSMF_EINVAL)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1502_07405_amd import hssmf as H
+from paper_1502_07405_amd import problems as P
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "hssmf.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(?:int|void|const char\*)\s+(hssmf_\w+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(H.LIB_PATH):
+        pytest.skip("libhssmf.so not built")
+    return H.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(H.EXPORTS)
+
+
+def test_default_options_and_strerror(lib):
+    o = H.default_opts()
+    assert o.leaf_size == 64 and o.d0 == 128 and o.dd == 128 and o.p == 10 and o.restart == 30
+    assert o.tol == 1e-10 and o.rel_tol == 1e-6 and o.min_sep_hss == 2 ** 31 - 1
+    assert H.strerror(0) == "ok" and H.strerror(H.HSSMF_ERANK) == "HSS rank exceeds d_max"
+
+
+def _call_factor(A_rowptr, A_col, A_val, perm, sep, par, n, opts=None):
+    L = H.load()
+    rp = np.ascontiguousarray(A_rowptr, dtype=np.int64)
+    ci = np.ascontiguousarray(A_col, dtype=np.int32)
+    va = np.ascontiguousarray(A_val, dtype=np.float64)
+    pe = np.ascontiguousarray(perm, dtype=np.int32)
+    sp = np.ascontiguousarray(sep, dtype=np.int32)
+    pa = np.ascontiguousarray(par, dtype=np.int32)
+    csr = H.CSRArg(n, rp.ctypes.data, ci.ctypes.data, va.ctypes.data)
+    od = H.OrderingArg(pe.ctypes.data, len(pa), sp.ctypes.data, pa.ctypes.data)
+    o = opts if opts is not None else H.default_opts()
+    h = ctypes.c_void_p()
+    rc = L.hssmf_factor(ctypes.byref(csr), ctypes.byref(od), ctypes.byref(o), None, ctypes.byref(h))
+    if h:
+        L.hssmf_destroy(h)
+    return rc
+
+
+@pytest.fixture(scope="module")
+def small():
+    A = P.poisson2d(8)
+    o = P.geometric_nd((8, 8), 2)
+    return A, o
+
+
+def test_rejects_bad_permutation(lib, small):
+    A, o = small
+    perm = o.perm.copy()
+    perm[3] = perm[4]
+    assert _call_factor(A.rowptr, A.colind, A.val, perm, o.sep_ptr, o.parent, A.n) == H.HSSMF_EINVAL
+
+
+def test_rejects_bad_tree(lib, small):
+    A, o = small
+    par = o.parent.copy()
+    par[0] = 0                                  # not after its child
+    assert _call_factor(A.rowptr, A.colind, A.val, o.perm, o.sep_ptr, par, A.n) == H.HSSMF_EINVAL
+    sep = o.sep_ptr.copy()
+    sep[-1] -= 1                                # does not span [0, n)
+    assert _call_factor(A.rowptr, A.colind, A.val, o.perm, sep, o.parent, A.n) == H.HSSMF_EINVAL
+
+
+def test_rejects_bad_csr(lib, small):
+    A, o = small
+    col = A.colind.copy()
+    col[5] = A.n + 3
+    assert _call_factor(A.rowptr, col, A.val, o.perm, o.sep_ptr, o.parent, A.n) == H.HSSMF_EINVAL
+    rp = A.rowptr.copy()
+    rp[4], rp[5] = rp[5], rp[4]
+    assert _call_factor(rp, A.colind, A.val, o.perm, o.sep_ptr, o.parent, A.n) == H.HSSMF_EINVAL
+
+
+def test_rejects_separator_violation(lib, small):
+    """An ordering whose separators do not separate (identity permutation
+    with the ND tree) is refused."""
+    A, o = small
+    assert _call_factor(A.rowptr, A.colind, A.val, np.arange(A.n), o.sep_ptr, o.parent, A.n) == H.HSSMF_EINVAL
+
+
+def test_rejects_bad_options(lib, small):
+    A, o = small
+    for field, val in (("leaf_size", 0), ("d0", 0), ("dd", 0), ("restart", 0), ("gemm_prec", 7), ("rel_tol", -1.0)):
+        opts = H.default_opts(**{field: val})
+        assert _call_factor(A.rowptr, A.colind, A.val, o.perm, o.sep_ptr, o.parent, A.n, opts) == H.HSSMF_EINVAL
