@@ -378,34 +378,74 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
       std::vector<NRef> all = refresh;
       all.insert(all.end(), cand.begin(), cand.end());
       node_samples(h, all);
-      // interpolative decompositions of the candidates (both sides)
+      // interpolative decompositions of the candidates (both sides): a
+      // column-pivoted QR per side, several workgroups per problem, one
+      // launch per pivot step (k_id.hip)
       std::vector<int> off(cand.size() + 1, 0);
-      for (size_t i = 0; i < cand.size(); ++i) off[i + 1] = off[i] + 2 + cand[i].n().mr + cand[i].n().mc;
+      for (size_t i = 0; i < cand.size(); ++i) off[i + 1] = off[i] + cand[i].n().mr + cand[i].n().mc;
       int* ibuf = ialloc(h, off.back());
-      std::vector<QRDesc> q;
-      int maxm = 0;
+      int* sbuf = ialloc(h, 4 * (int64_t)cand.size());
+      std::vector<IDProb> q;
+      int maxm = 0, maxd = 0, tmax = 0, wg = 0;
       for (size_t i = 0; i < cand.size(); ++i) {
         HNode& nd = cand[i].n();
         const int d = cand[i].F->d;
-        nd.drank = ibuf + off[i];
-        nd.dpermr = nd.drank + 2;
+        nd.dpermr = ibuf + off[i];
         nd.dpermc = nd.dpermr + nd.mr;
         nd.Er = dalloc(h, (int64_t)nd.mr * std::min(nd.mr, d));
         nd.Ec = dalloc(h, (int64_t)nd.mc * std::min(nd.mc, d));
-        QRDesc a{nd.Sr, dalloc(h, (int64_t)nd.mr * d), nd.dpermr, nd.drank, nd.Er, nullptr, nullptr, nd.mr, d,
-                 nd.mr, o.rel_tol};
-        QRDesc b{nd.Sc, dalloc(h, (int64_t)nd.mc * d), nd.dpermc, nd.drank + 1, nd.Ec, nullptr, nullptr, nd.mc,
-                 d, nd.mc, o.rel_tol};
-        q.push_back(a);
-        q.push_back(b);
-        maxm = std::max(maxm, std::max(nd.mr, nd.mc));
+        for (int sd = 0; sd < 2; ++sd) {
+          const int m = sd ? nd.mc : nd.mr;
+          const int mn = std::min(m, d);
+          IDProb pr{};
+          pr.S = sd ? nd.Sc : nd.Sr;
+          pr.lds = std::max(m, 1);
+          pr.W = dalloc(h, (int64_t)m * d);
+          pr.norms = dalloc(h, m);
+          pr.alpha = dalloc(h, mn);
+          pr.P = std::max(1, (m + kIDCols - 1) / kIDCols);
+          pr.slots = dalloc(h, 4 * (int64_t)pr.P);
+          pr.R1 = dalloc(h, (int64_t)mn * mn);
+          pr.E = sd ? nd.Ec : nd.Er;
+          pr.perm = sd ? nd.dpermc : nd.dpermr;
+          pr.ipos = ialloc(h, m);
+          pr.state = sbuf + 4 * i + 2 * sd;
+          pr.first = dalloc(h, 1);
+          pr.active = reinterpret_cast<unsigned char*>(ialloc(h, (m + 3) / 4 + 1));
+          pr.m = m;
+          pr.d = d;
+          pr.wg0 = wg;
+          pr.eps = o.rel_tol;
+          wg += pr.P;
+          q.push_back(pr);
+          maxm = std::max(maxm, m);
+          maxd = std::max(maxd, d);
+          tmax = std::max(tmax, mn);
+        }
       }
       if (!q.empty()) {
-        QRDesc* dq = upload(h, q);
+        IDProb* dq = upload(h, q);
+        const int np = (int)q.size();
         int tok = prof::begin(0, h.st);
-        launch_qr(dq, (int)q.size(), 1, maxm, h.st);
+        launch_id_init(dq, np, wg, maxd, h.st);
+        std::vector<int> st(4 * cand.size());
+        for (int t = 0; t <= tmax; ++t) {
+          launch_id_step(dq, np, wg, t, maxd, h.st);
+          if ((t & 63) == 63 && t < tmax) {  // stop early once every problem has its rank
+            HIP_CHECK(hipMemcpyAsync(st.data(), sbuf, st.size() * sizeof(int), hipMemcpyDeviceToHost, h.st));
+            HIP_CHECK(hipStreamSynchronize(h.st));
+            h.stager.sync();
+            bool all = true;
+            for (size_t i = 0; i < cand.size(); ++i) all = all && st[4 * i] && st[4 * i + 2];
+            if (all) break;
+          }
+        }
+        launch_id_finish(dq, np, maxm, h.st);
         prof::end(tok, h.st, 0.0);
       }
+      std::vector<int> sh(4 * cand.size());
+      if (!sh.empty())
+        HIP_CHECK(hipMemcpyAsync(sh.data(), sbuf, sh.size() * sizeof(int), hipMemcpyDeviceToHost, h.st));
       std::vector<int> hbuf(off.back());
       if (!hbuf.empty())
         HIP_CHECK(hipMemcpyAsync(hbuf.data(), ibuf, hbuf.size() * sizeof(int), hipMemcpyDeviceToHost, h.st));
@@ -416,11 +456,10 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
         // + 4/3 k^3 and the triangular solve k^2 (m - k), per side
         double fl = 0.0;
         for (size_t i = 0; i < cand.size(); ++i) {
-          const int* b = hbuf.data() + off[i];
           const double d = cand[i].F->d;
           const int ms[2] = {cand[i].n().mr, cand[i].n().mc};
           for (int sd = 0; sd < 2; ++sd) {
-            double k = b[sd], m = ms[sd];
+            double k = sh[4 * i + 1 + 2 * sd], m = ms[sd];
             fl += 4.0 * d * m * k - 2.0 * k * k * (d + m) + 4.0 / 3.0 * k * k * k + k * k * (m - k);
           }
         }
@@ -433,14 +472,14 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
         HFront& F = *cand[i].F;
         HNode& nd = cand[i].n();
         const int* b = hbuf.data() + off[i];
-        int r = b[0], c = b[1];
+        int r = sh[4 * i + 1], c = sh[4 * i + 3];
         bool okr = r <= F.d - o.p || r == nd.mr;
         bool okc = c <= F.d - o.p || c == nd.mc;
         if (!(okr && okc)) continue;
         nd.r = r;
         nd.c = c;
-        nd.permr.assign(b + 2, b + 2 + nd.mr);
-        nd.permc.assign(b + 2 + nd.mr, b + 2 + nd.mr + nd.mc);
+        nd.permr.assign(b, b + nd.mr);
+        nd.permc.assign(b + nd.mr, b + nd.mr + nd.mc);
         std::vector<int> base_r, base_c;
         if (nd.leaf()) {
           for (int j = nd.lo; j < nd.hi; ++j) { base_r.push_back(j); base_c.push_back(j); }

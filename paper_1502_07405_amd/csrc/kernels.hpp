@@ -159,3 +159,32 @@ void launch_trsm_block(const TrsmDesc* d, int nd, int lower, int unit, int trans
 void launch_convert(const double* src, void* dst, int64_t n, int to_bf16, hipStream_t s);
 
 }  // namespace hssmf
+
+namespace hssmf {
+
+// Column-pivoted QR for the interpolative decomposition, spread over several
+// workgroups per problem with one launch per pivot step (see k_id.hip).
+struct IDProb {
+  const double* S;      // m x d samples (rows are the candidates), ld lds
+  double* W;            // d x m work, ld d
+  double* norms;        // m
+  double* alpha;        // min(m, d): R diagonal
+  double* slots;        // 2 (parity) x P x 2: partial (norm, column)
+  double* R1;           // k x k scratch (upper triangle, pivot order)
+  double* E;            // output (m - k) x k, ld m - k
+  int* perm;            // output: position -> candidate
+  int* ipos;            // candidate -> position
+  int* state;           // [0] done, [1] rank
+  double* first;        // first pivot norm
+  unsigned char* active;
+  int m, d, lds, P;     // P workgroups of kIDCols candidates each
+  int wg0, pad;         // first workgroup of this problem in the launch grid
+  double eps;
+};
+constexpr int kIDCols = 32;
+
+void launch_id_init(const IDProb* p, int np, int total_wg, int max_d, hipStream_t s);
+void launch_id_step(const IDProb* p, int np, int total_wg, int t, int max_d, hipStream_t s);
+void launch_id_finish(const IDProb* p, int np, int max_m, hipStream_t s);
+
+}  // namespace hssmf
