@@ -135,6 +135,28 @@ void tri_solve_many(Handle& h, const double* T, int ldt, int n, double* X, int l
   }
 }
 
+// X := T^{-1} X for a batch of upper triangular T (non-unit), blocks of 64
+// from the bottom, all problems of the batch in the same launches
+void tri_solve_upper_batched(Handle& h, const std::vector<TriProb>& ps) {
+  int nmax = 0, cmax = 0;
+  for (auto& p : ps) { nmax = std::max(nmax, p.n); cmax = std::max(cmax, p.ncols); }
+  for (int j = 0; 64 * j < nmax; ++j) {
+    std::vector<TrsmDesc> td;
+    std::vector<GemmDesc> g;
+    for (auto& p : ps) {
+      const int b1 = p.n - 64 * j;
+      if (b1 <= 0) continue;
+      const int b0 = std::max(0, b1 - 64), bs = b1 - b0;
+      td.push_back({p.T, p.X, p.n, p.ncols, p.ldt, p.ldx, b0, bs});
+      if (b0 > 0)
+        g.push_back(G(p.T + (int64_t)b0 * p.ldt, p.ldt, 0, p.X + b0, p.ldx, 0, p.X, p.ldx, b0, p.ncols, bs, -1.0, 1.0));
+    }
+    if (td.empty()) continue;
+    launch_trsm_block(h.stager.put_vec(td, h.st), (int)td.size(), 0, 0, 0, cmax, h.st);
+    run_gemm(h, g);
+  }
+}
+
 // ------------------------------------------------------------ HSS ---------
 namespace {
 
@@ -406,6 +428,7 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
           pr.P = std::max(1, (m + kIDCols - 1) / kIDCols);
           pr.slots = dalloc(h, 4 * (int64_t)pr.P);
           pr.R1 = dalloc(h, (int64_t)mn * mn);
+          pr.W2 = dalloc(h, (int64_t)m * mn);
           pr.E = sd ? nd.Ec : nd.Er;
           pr.perm = sd ? nd.dpermc : nd.dpermr;
           pr.ipos = ialloc(h, m);
@@ -426,11 +449,15 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
       if (!q.empty()) {
         IDProb* dq = upload(h, q);
         const int np = (int)q.size();
+        std::vector<int> wgm(wg);
+        for (int pi = 0; pi < np; ++pi)
+          for (int w = 0; w < q[pi].P; ++w) wgm[q[pi].wg0 + w] = pi;
+        int* dwgm = upload(h, wgm);
         int tok = prof::begin(0, h.st);
         launch_id_init(dq, np, wg, maxd, h.st);
         std::vector<int> st(4 * cand.size());
         for (int t = 0; t <= tmax; ++t) {
-          launch_id_step(dq, np, wg, t, maxd, h.st);
+          launch_id_step(dq, dwgm, wg, t, maxd, h.st);
           if ((t & 63) == 63 && t < tmax) {  // stop early once every problem has its rank
             HIP_CHECK(hipMemcpyAsync(st.data(), sbuf, st.size() * sizeof(int), hipMemcpyDeviceToHost, h.st));
             HIP_CHECK(hipStreamSynchronize(h.st));
@@ -498,6 +525,25 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
         ivec.insert(ivec.end(), nd.Ic.begin(), nd.Ic.end());
         nd.done = true;
         ok.push_back(cand[i]);
+      }
+      {
+        // E = (R1^{-1} R2)^T for the successful IDs: batched blocked
+        // triangular solve (64-row diagonal blocks + GEMM updates)
+        std::vector<TriProb> tp;
+        std::vector<CopyDesc> tc;
+        for (size_t i = 0; i < cand.size(); ++i) {
+          HNode& nd = cand[i].n();
+          if (!nd.done) continue;
+          for (int sd = 0; sd < 2; ++sd) {
+            const IDProb& pr = q[2 * i + sd];
+            const int k = sd ? nd.c : nd.r, nrest = pr.m - k;
+            if (k == 0 || nrest == 0) continue;
+            tp.push_back({pr.R1, k, k, pr.W2, k, nrest});
+            tc.push_back(Cp(pr.W2, k, nullptr, pr.E, nrest, nrest, k, 0, 1.0, nullptr, 1));
+          }
+        }
+        tri_solve_upper_batched(h, tp);
+        run_copy(h, tc);
       }
       if (!ivec.empty()) {
         int* dI = upload(h, ivec);

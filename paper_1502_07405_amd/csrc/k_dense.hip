@@ -155,31 +155,24 @@ __global__ __launch_bounds__(256) void trsm_u12_kernel(const LUFront* __restrict
     Lp[i][j] = f.F[(jb + i) + (int64_t)(jb + j) * f.ld];
   }
   __syncthreads();
-  const int col = jb + w + blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= f.n) return;
-  double* c = f.F + (int64_t)col * f.ld + jb;
-  double x[64];
-#pragma unroll
-  for (int i = 0; i < 64; ++i)
-    if (i < w) x[i] = c[i];
-#pragma unroll
-  for (int i = 0; i < 64; ++i) {
-    if (i < w) {
-      double v = x[i];
-#pragma unroll
-      for (int j = 0; j < 64; ++j)
-        if (j < i) v -= Lp[i][j] * x[j];
-      x[i] = v;
+  // one wavefront per column, lane i holding row jb + i (unit lower solve)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int col = jb + w + blockIdx.x * 4 + wave; col < f.n; col += gridDim.x * 4) {
+    double* c = f.F + (int64_t)col * f.ld + jb;
+    double v = (lane < w) ? c[lane] : 0.0;
+    for (int j = 0; j < w; ++j) {
+      const double xj = __shfl(v, j);
+      if (lane > j && lane < w) v -= Lp[lane][j] * xj;
     }
+    if (lane < w) c[lane] = v;
   }
-#pragma unroll
-  for (int i = 0; i < 64; ++i)
-    if (i < w) c[i] = x[i];
 }
 
 void launch_trsm_u12(const LUFront* fr, int nf, int jb, int nb, int max_n, hipStream_t s) {
   if (nf <= 0 || max_n <= 0) return;
-  hipLaunchKernelGGL(trsm_u12_kernel, dim3((max_n + 255) / 256, nf), dim3(256), 0, s, fr, jb, nb);
+  int gx = (max_n + 3) / 4;
+  if (gx > 256) gx = 256;
+  hipLaunchKernelGGL(trsm_u12_kernel, dim3(gx, nf), dim3(256), 0, s, fr, jb, nb);
   HIP_CHECK(hipGetLastError());
 }
 

@@ -379,9 +379,10 @@ void launch_pivots(double* M, int ld, int ncols, const int* ipiv, int k, int rev
 }
 
 // ------------------------------------------------ blocked triangular solve --
-// one diagonal block (rows [b0, b0+bs), bs <= 64) of T X = B, one thread per
-// right-hand-side column; the caller applies the off-diagonal updates with
-// GEMMs between blocks
+// one diagonal block (rows [b0, b0+bs), bs <= 64) of T X = B: one
+// wavefront per right-hand-side column, lane i holding row b0 + i, the
+// substitution carried out with lane shuffles; the caller applies the
+// off-diagonal updates with GEMMs between blocks
 template <int LOWER, int UNIT, int TRANS>
 __global__ __launch_bounds__(256) void trsm_block_kernel(const TrsmDesc* __restrict__ descs) {
   const TrsmDesc d = descs[blockIdx.y];
@@ -393,42 +394,33 @@ __global__ __launch_bounds__(256) void trsm_block_kernel(const TrsmDesc* __restr
     Tb[i][j] = TRANS ? d.T[gj + (int64_t)gi * d.ldt] : d.T[gi + (int64_t)gj * d.ldt];
   }
   __syncthreads();
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= d.ncols) return;
-  double* x = d.X + (int64_t)c * d.ldx + d.b0;
-  double v[64];
-#pragma unroll
-  for (int i = 0; i < 64; ++i)
-    if (i < bs) v[i] = x[i];
-  if (LOWER) {
-#pragma unroll
-    for (int i = 0; i < 64; ++i)
-      if (i < bs) {
-        double a = v[i];
-#pragma unroll
-        for (int j = 0; j < 64; ++j)
-          if (j < i) a -= Tb[i][j] * v[j];
-        v[i] = UNIT ? a : a / Tb[i][i];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  for (int c = blockIdx.x * 4 + wave; c < d.ncols; c += gridDim.x * 4) {
+    double* x = d.X + (int64_t)c * d.ldx + d.b0;
+    double v = (lane < bs) ? x[lane] : 0.0;
+    if (LOWER) {
+      for (int j = 0; j < bs; ++j) {
+        if (!UNIT && lane == j) v /= Tb[j][j];
+        const double xj = __shfl(v, j);
+        if (lane > j && lane < bs) v -= Tb[lane][j] * xj;
       }
-  } else {
-#pragma unroll
-    for (int i = 63; i >= 0; --i)
-      if (i < bs) {
-        double a = v[i];
-#pragma unroll
-        for (int j = 0; j < 64; ++j)
-          if (j > i && j < bs) a -= Tb[i][j] * v[j];
-        v[i] = UNIT ? a : a / Tb[i][i];
+    } else {
+      for (int j = bs - 1; j >= 0; --j) {
+        if (!UNIT && lane == j) v /= Tb[j][j];
+        const double xj = __shfl(v, j);
+        if (lane < j) v -= Tb[lane][j] * xj;
       }
+    }
+    if (lane < bs) x[lane] = v;
   }
-#pragma unroll
-  for (int i = 0; i < 64; ++i)
-    if (i < bs) x[i] = v[i];
 }
 
 void launch_trsm_block(const TrsmDesc* d, int nd, int lower, int unit, int trans, int max_cols, hipStream_t s) {
   if (nd <= 0 || max_cols <= 0) return;
-  dim3 g((max_cols + 255) / 256, nd), b(256);
+  int gx = (max_cols + 3) / 4;
+  if (gx > 512) gx = 512;
+  dim3 g(gx, nd), b(256);
   int code = lower * 4 + unit * 2 + trans;
   switch (code) {
     case 0: hipLaunchKernelGGL((trsm_block_kernel<0, 0, 0>), g, b, 0, s, d); break;

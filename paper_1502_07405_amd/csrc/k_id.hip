@@ -96,30 +96,49 @@ __global__ __launch_bounds__(256) void id_init_kernel(const IDProb* __restrict__
   write_partial(q, b, 0, red, redi);
 }
 
-__global__ __launch_bounds__(256) void id_step_kernel(const IDProb* __restrict__ probs, int np, int t) {
+// NR: entries of a column each lane keeps in registers between the dot
+// product and the update (columns up to 64 NR rows; longer columns are read
+// twice)
+template <int NR>
+__global__ __launch_bounds__(256) void id_step_kernel(const IDProb* __restrict__ probs, const int* __restrict__ wgmap,
+                                                      int t) {
   extern __shared__ double x[];           // pivot column, rows t..d-1
   __shared__ double red[256];
   __shared__ int redi[256];
-  __shared__ double bc[3];
-  const int pi = find_prob(probs, np, blockIdx.x);
-  const IDProb q = probs[pi];
+  __shared__ double nloc[kIDCols];
+  __shared__ double bc[1];
+  const IDProb& q = probs[wgmap[blockIdx.x]];
   const int b = blockIdx.x - q.wg0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (q.state[0]) return;
-  const int kmax = min(q.m, q.d);
-  // pivot from the partial maxima of step t-1
-  double best = -1.0;
-  int p = 0x7fffffff;
+  const int m = q.m, d = q.d;
+  const int kmax = min(m, d);
+  // pivot from the partial maxima of step t-1 (parallel reduction)
   {
     const double* sl = q.slots + (size_t)(t & 1) * q.P * 2;
-    for (int w = 0; w < q.P; ++w) {
-      double v = sl[2 * w];
-      int c = (int)sl[2 * w + 1];
-      if (v > best || (v == best && c < p)) { best = v; p = c; }
+    double v = -1.0;
+    int c = 0x7fffffff;
+    for (int w = tid; w < q.P; w += 256) {
+      double vw = sl[2 * w];
+      int cw = (int)sl[2 * w + 1];
+      if (vw > v || (vw == v && cw < c)) { v = vw; c = cw; }
+    }
+    red[tid] = v;
+    redi[tid] = c;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if (tid < off) {
+        double o = red[tid + off];
+        int oi = redi[tid + off];
+        if (o > red[tid] || (o == red[tid] && oi < redi[tid])) { red[tid] = o; redi[tid] = oi; }
+      }
+      __syncthreads();
     }
   }
-  double first = (t == 0) ? best : q.first[0];
-  bool stop = (t >= kmax) || (t == 0 ? best <= 0.0 : best <= q.eps * first);
+  const double best = red[0];
+  const int p = redi[0];
+  const double first = (t == 0) ? best : q.first[0];
+  const bool stop = (t >= kmax) || (t == 0 ? best <= 0.0 : best <= q.eps * first);
   if (stop) {
     if (b == 0 && tid == 0) {
       q.state[1] = (t == 0 && best <= 0.0) ? 0 : t;
@@ -127,8 +146,7 @@ __global__ __launch_bounds__(256) void id_step_kernel(const IDProb* __restrict__
     }
     return;
   }
-  // pivot bookkeeping (one workgroup) and the R diagonal (the owner)
-  const double* colp = q.W + (int64_t)p * q.d;
+  const double* colp = q.W + (int64_t)p * d;
   const double x0 = colp[t];
   const double alpha = (x0 >= 0.0) ? -best : best;
   if (b == 0 && tid == 0) {
@@ -144,9 +162,9 @@ __global__ __launch_bounds__(256) void id_step_kernel(const IDProb* __restrict__
     q.active[p] = 0;
     q.alpha[t] = alpha;
   }
-  // reflector v = x - alpha e_1 (stored in LDS), tau = 2 / v^T v
-  const int len = q.d - t;
+  const int len = d - t;
   for (int i = tid; i < len; i += 256) x[i] = colp[t + i];
+  if (tid < kIDCols) nloc[tid] = -1.0;
   __syncthreads();
   if (tid == 0) {
     double v0 = x0 - alpha;
@@ -156,45 +174,51 @@ __global__ __launch_bounds__(256) void id_step_kernel(const IDProb* __restrict__
   }
   __syncthreads();
   const double tau = bc[0];
-  const int j0 = b * kIDCols, j1 = min(q.m, j0 + kIDCols);
-  for (int j = j0 + wave; j < j1; j += 4) {
-    if (j == p || !q.active[j]) continue;
-    double* col = q.W + (int64_t)j * q.d + t;
+  const int j0 = b * kIDCols;
+  for (int jj = wave; jj < kIDCols; jj += 4) {
+    const int j = j0 + jj;
+    if (j >= m || j == p || !q.active[j]) continue;
+    double* col = q.W + (int64_t)j * d + t;
+    double rc[NR];
     double dot = 0.0;
-    if (tau != 0.0) {
-      for (int i = lane; i < len; i += 64) dot += x[i] * col[i];
-      dot = wsum(dot) * tau;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int i = lane + 64 * r;
+      rc[r] = (i < len) ? col[i] : 0.0;
+      if (i < len) dot += x[i] * rc[r];
     }
+    for (int i = lane + 64 * NR; i < len; i += 64) dot += x[i] * col[i];
+    dot = wsum(dot) * tau;
     double ss = 0.0;
-    for (int i = lane; i < len; i += 64) {
-      double y = col[i] - dot * x[i];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int i = lane + 64 * r;
+      if (i < len) {
+        const double y = rc[r] - dot * x[i];
+        col[i] = y;
+        if (i > 0) ss += y * y;
+      }
+    }
+    for (int i = lane + 64 * NR; i < len; i += 64) {
+      const double y = col[i] - dot * x[i];
       col[i] = y;
-      if (i > 0) ss += y * y;
+      ss += y * y;
     }
     ss = wsum(ss);
-    if (lane == 0) q.norms[j] = sqrt(ss);
+    if (lane == 0) nloc[jj] = sqrt(ss);   // exact recomputation, no downdating
   }
   __syncthreads();
-  // partial maximum for step t+1 (the pivot is no longer active)
-  double bv = -1.0;
-  int bi = 0x7fffffff;
-  const int j = j0 + tid;
-  if (tid < kIDCols && j < q.m && q.active[j] && j != p) { bv = q.norms[j]; bi = j; }
-  red[tid] = bv;
-  redi[tid] = bi;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (tid < off) {
-      double o = red[tid + off];
-      int oi = redi[tid + off];
-      if (o > red[tid] || (o == red[tid] && oi < redi[tid])) { red[tid] = o; redi[tid] = oi; }
-    }
-    __syncthreads();
-  }
+  // partial maximum over this workgroup's candidates for step t+1
   if (tid == 0) {
+    double bv = -1.0;
+    int bi = 0x7fffffff;
+    for (int jj = 0; jj < kIDCols; ++jj) {
+      const int j = j0 + jj;
+      if (j < m && j != p && q.active[j] && nloc[jj] > bv) { bv = nloc[jj]; bi = j; }
+    }
     double* sl = q.slots + ((size_t)((t + 1) & 1) * q.P + b) * 2;
-    sl[0] = red[0];
-    sl[1] = (double)redi[0];
+    sl[0] = bv;
+    sl[1] = (double)bi;
   }
 }
 
@@ -212,18 +236,17 @@ __global__ void id_r1_kernel(const IDProb* __restrict__ probs) {
   }
 }
 
-// X = R1^{-1} R2 by back substitution, one candidate per thread; E = X^T
-__global__ void id_solve_kernel(const IDProb* __restrict__ probs) {
+// R2 (k x (m-k)) gathered into E's storage as a k x (m-k) block; the host
+// then solves R1 X = R2 in place with the batched blocked triangular solve
+// and transposes X into E
+__global__ void id_r2_kernel(const IDProb* __restrict__ probs) {
   const IDProb q = probs[blockIdx.y];
   const int k = q.state[1];
   const int nrest = q.m - k;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nrest || k == 0) return;
-  const double* col = q.W + (int64_t)q.perm[k + c] * q.d;
-  for (int i = k - 1; i >= 0; --i) {
-    double acc = col[i];
-    for (int l = i + 1; l < k; ++l) acc -= q.R1[i + (int64_t)l * k] * q.E[c + (int64_t)l * nrest];
-    q.E[c + (int64_t)i * nrest] = acc / q.R1[i + (int64_t)i * k];
+  const int64_t tot = (int64_t)k * nrest;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    int i = (int)(e % k), c = (int)(e / k);
+    q.W2[i + (int64_t)c * k] = q.W[i + (int64_t)q.perm[k + c] * q.d];
   }
 }
 
@@ -234,11 +257,16 @@ void launch_id_init(const IDProb* p, int np, int total_wg, int max_d, hipStream_
   HIP_CHECK(hipGetLastError());
 }
 
-void launch_id_step(const IDProb* p, int np, int total_wg, int t, int max_d, hipStream_t s) {
-  if (np <= 0 || total_wg <= 0) return;
+void launch_id_step(const IDProb* p, const int* wgmap, int total_wg, int t, int max_d, hipStream_t s) {
+  if (total_wg <= 0) return;
   size_t lds = (size_t)std::max(max_d, 1) * sizeof(double);
   REQUIRE(lds <= 48 * 1024, HSSMF_ERANK, "interpolative decomposition: more than 6144 samples");
-  hipLaunchKernelGGL(id_step_kernel, dim3(total_wg), dim3(256), lds, s, p, np, t);
+  if (max_d <= 64 * 4)
+    hipLaunchKernelGGL(id_step_kernel<4>, dim3(total_wg), dim3(256), lds, s, p, wgmap, t);
+  else if (max_d <= 64 * 10)
+    hipLaunchKernelGGL(id_step_kernel<10>, dim3(total_wg), dim3(256), lds, s, p, wgmap, t);
+  else
+    hipLaunchKernelGGL(id_step_kernel<16>, dim3(total_wg), dim3(256), lds, s, p, wgmap, t);
   HIP_CHECK(hipGetLastError());
 }
 
@@ -248,7 +276,7 @@ void launch_id_finish(const IDProb* p, int np, int max_m, hipStream_t s) {
   int64_t bx = (kk + 255) / 256;
   if (bx > 1024) bx = 1024;
   hipLaunchKernelGGL(id_r1_kernel, dim3((unsigned)bx, np), dim3(256), 0, s, p);
-  hipLaunchKernelGGL(id_solve_kernel, dim3((max_m + 255) / 256, np), dim3(256), 0, s, p);
+  hipLaunchKernelGGL(id_r2_kernel, dim3((unsigned)bx, np), dim3(256), 0, s, p);
   HIP_CHECK(hipGetLastError());
 }
 

@@ -171,6 +171,7 @@ struct IDProb {
   double* alpha;        // min(m, d): R diagonal
   double* slots;        // 2 (parity) x P x 2: partial (norm, column)
   double* R1;           // k x k scratch (upper triangle, pivot order)
+  double* W2;           // k x (m - k) scratch: R2, then X = R1^{-1} R2
   double* E;            // output (m - k) x k, ld m - k
   int* perm;            // output: position -> candidate
   int* ipos;            // candidate -> position
@@ -181,10 +182,10 @@ struct IDProb {
   int wg0, pad;         // first workgroup of this problem in the launch grid
   double eps;
 };
-constexpr int kIDCols = 32;
+constexpr int kIDCols = 8;
 
 void launch_id_init(const IDProb* p, int np, int total_wg, int max_d, hipStream_t s);
-void launch_id_step(const IDProb* p, int np, int total_wg, int t, int max_d, hipStream_t s);
+void launch_id_step(const IDProb* p, const int* wgmap, int total_wg, int t, int max_d, hipStream_t s);
 void launch_id_finish(const IDProb* p, int np, int max_m, hipStream_t s);
 
 }  // namespace hssmf

@@ -5,6 +5,7 @@
 // is done, so the launches (with their descriptor arrays) are recorded once
 // per factorization and replayed for every application of M^{-1}.
 #include <algorithm>
+#include <cstring>
 
 #include "solver.hpp"
 #include "vec.hpp"
@@ -13,9 +14,25 @@ namespace hssmf {
 
 namespace {
 
+// descriptor arrays of all recorded launches go into one host blob that is
+// uploaded once; ops hold offsets until the blob has a device address
+struct Blob {
+  std::vector<char> bytes;
+  template <class T>
+  const void* add(const std::vector<T>& v) {
+    size_t off = (bytes.size() + 255) / 256 * 256;
+    bytes.resize(off + v.size() * sizeof(T));
+    std::memcpy(bytes.data() + off, v.data(), v.size() * sizeof(T));
+    return reinterpret_cast<const void*>(off);
+  }
+};
+
 struct Rec {
   Handle& h;
   std::vector<Op>& ops;
+  Blob& blob;
+  template <class T>
+  const void* upload(Handle&, const std::vector<T>& v) { return blob.add(v); }
   void gemv(const std::vector<GemvDesc>& v) {
     std::vector<GemvDesc> w;
     int64_t mx = 0;
@@ -307,9 +324,10 @@ void build_solve_ops(Handle& h) {
   for (int tr = 0; tr < 2; ++tr)
     for (int sw = 0; sw < 2; ++sw) h.sops[tr][sw].clear();
   double* y = h.yws;
+  Blob blob;
   for (int tr = 0; tr < 2; ++tr) {
     // forward sweep, bottom-up
-    Rec R{h, h.sops[tr][0]};
+    Rec R{h, h.sops[tr][0], blob};
     for (size_t lev = 0; lev < P.levels.size(); ++lev) {
       const auto& ids = P.levels[lev];
       std::vector<RhsDesc> rd;
@@ -368,7 +386,7 @@ void build_solve_ops(Handle& h) {
       }
     }
     // backward sweep, top-down
-    Rec B{h, h.sops[tr][1]};
+    Rec B{h, h.sops[tr][1], blob};
     for (int lev = (int)P.levels.size() - 1; lev >= 0; --lev) {
       const auto& ids = P.levels[lev];
       std::vector<GemvDesc> g;
@@ -414,6 +432,13 @@ void build_solve_ops(Handle& h) {
       }
     }
   }
+  char* dev = h.cur->get<char>(std::max<size_t>(blob.bytes.size(), 1));
+  if (!blob.bytes.empty())
+    HIP_CHECK(hipMemcpyAsync(dev, blob.bytes.data(), blob.bytes.size(), hipMemcpyHostToDevice, h.st));
+  HIP_CHECK(hipStreamSynchronize(h.st));  // the blob is pageable host memory
+  for (int tr = 0; tr < 2; ++tr)
+    for (int sw = 0; sw < 2; ++sw)
+      for (Op& o : h.sops[tr][sw]) o.d = dev + reinterpret_cast<size_t>(o.d);
 }
 
 void run_ops(Handle& h, const std::vector<Op>& ops) {

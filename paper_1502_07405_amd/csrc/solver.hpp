@@ -165,6 +165,14 @@ void blocked_lu(Handle& h, const std::vector<LUFront>& fronts);
 void tri_solve_many(Handle& h, const double* T, int ldt, int n, double* X, int ldx, int ncols, bool lower,
                     bool unit, bool trans);
 
+struct TriProb {
+  const double* T;
+  int ldt, n;
+  double* X;
+  int ldx, ncols;
+};
+void tri_solve_upper_batched(Handle& h, const std::vector<TriProb>& ps);
+
 void build_solve_ops(Handle& h);
 void run_ops(Handle& h, const std::vector<Op>& ops);
 
