@@ -105,8 +105,14 @@ class Stager {
   T* put_vec(const std::vector<T>& v, hipStream_t s) {
     return static_cast<T*>(put(v.data(), v.size() * sizeof(T), s));
   }
+  // copy host bytes straight into device memory the caller owns (one
+  // pinned H2D copy)
+  void put_to(void* dst, const void* src, size_t bytes, hipStream_t s);
   // caller guarantees the stream has drained
   void sync() { off_ = 0; }
+  // device workspace for split-K partial products (stream ordered)
+  double* ws = nullptr;
+  size_t ws_elems = 0;
 
  private:
   char* host_ = nullptr;

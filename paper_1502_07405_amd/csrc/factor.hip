@@ -601,7 +601,7 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
 
 // ULV-like factorization of every k-subtree (Sec. 2.3), bottom-up by
 // height, then the LU of the merged top block
-void ulv_level(Handle& h, std::vector<HFront*>& fs) {
+void ulv_level(Handle& h, std::vector<HFront*>& fs, const int* iota) {
   int maxh = 0;
   for (HFront* F : fs) maxh = std::max(maxh, F->nd[F->k].height);
   auto in_k = [](HFront* F, int t) {
@@ -661,42 +661,76 @@ void ulv_level(Handle& h, std::vector<HFront*>& fs) {
     }
     run_gemm(h, g2);
     // W = Omega Dbar: top rows Dbar[perm[r:]] - E Dbar[perm[:r]], bottom Dbar[perm[:r]]
-    std::vector<CopyDesc> wc;
+    std::vector<CopyDesc> wc, cc;
     std::vector<GemmDesc> wg;
-    std::vector<QRDesc> q;
-    int maxm = 0;
-    std::vector<double*> Wt(L.size()), Wb(L.size());
+    std::vector<InterpDesc> eye;
+    std::vector<double*> Wt(L.size()), Wb(L.size()), Cb(L.size()), Yb(L.size()), Tb(L.size()), Mb(L.size()),
+        M2(L.size());
+    std::vector<int> ncomb(L.size());
+    int nlmax = 0;
     for (size_t i = 0; i < L.size(); ++i) {
       HNode& nd = L[i].n();
-      const int m = nd.mr, r = nd.r, nl = m - r;
+      const int m = nd.mr, r = nd.r, nl = m - r, c = nd.c;
       nd.nl = nl;
+      nlmax = std::max(nlmax, nl);
       Wt[i] = dalloc(h, (int64_t)std::max(nl, 1) * m);
       Wb[i] = dalloc(h, (int64_t)std::max(r, 1) * m);
       wc.push_back(Cp(nd.Dbar, m, nd.dpermr + r, Wt[i], std::max(nl, 1), nl, m));
       wc.push_back(Cp(nd.Dbar, m, nd.dpermr, Wb[i], std::max(r, 1), r, m));
       if (nl > 0 && r > 0)
         wg.push_back(G(nd.Er, nl, 0, nd.Dbar, m, 0, Wt[i], nl, nl, m, r, -1.0, 1.0, nd.dpermr));
-      nd.Q = dalloc(h, (int64_t)m * m);
-      nd.L = dalloc(h, (int64_t)std::max(nl, 1) * std::max(nl, 1));
-      // LQ of Wt: QR of Wt^T (columns = rows of Wt, length m)
-      q.push_back({Wt[i], dalloc(h, (int64_t)m * std::max(nl, 1)), ialloc(h, std::max(nl, 1)), ialloc(h, 1),
-                   nullptr, nd.Q, nd.L, nl, m, std::max(nl, 1), 0.0});
-      maxm = std::max(maxm, std::max(nl, 1));
+      // combined block [W_top^T | W_bot^T | Vbar | I] (m rows): the QR of the
+      // first nl columns applies Qtilde^T to the rest
+      ncomb[i] = nl + r + c + m;
+      Cb[i] = dalloc(h, (int64_t)m * ncomb[i]);
+      Yb[i] = dalloc(h, (int64_t)m * kPanel);
+      Tb[i] = dalloc(h, (int64_t)kPanel * kPanel);
+      Mb[i] = dalloc(h, (int64_t)kPanel * ncomb[i]);
+      M2[i] = dalloc(h, (int64_t)kPanel * ncomb[i]);
+      cc.push_back(Cp(Wt[i], std::max(nl, 1), nullptr, Cb[i], m, m, nl, 0, 1.0, nullptr, 1));
+      cc.push_back(Cp(Wb[i], std::max(r, 1), nullptr, Cb[i] + (int64_t)nl * m, m, m, r, 0, 1.0, nullptr, 1));
+      cc.push_back(Cp(nd.Vbar, m, nullptr, Cb[i] + (int64_t)(nl + r) * m, m, m, c));
+      eye.push_back({Cb[i] + (int64_t)(nl + r + c) * m, iota, nullptr, m, m, m, 0});
     }
     run_copy(h, wc);
     run_gemm(h, wg);
-    launch_qr(upload(h, q), (int)q.size(), 0, maxm, h.st);
-    // [D^21 D^] = Wb Q ;  [V^1; V^] = Q^T Vbar
-    std::vector<GemmDesc> g3;
+    run_copy(h, cc);
+    run_interp(h, eye);
+    // blocked Householder QR: 32-column panels, compact-WY trailing updates
+    for (int j0 = 0; j0 < nlmax; j0 += kPanel) {
+      std::vector<PanelDesc> pd;
+      std::vector<GemmDesc> g1, g2, g3;
+      for (size_t i = 0; i < L.size(); ++i) {
+        HNode& nd = L[i].n();
+        const int m = nd.mr;
+        if (j0 >= nd.nl) continue;
+        const int nb = std::min(kPanel, nd.nl - j0);
+        pd.push_back({Cb[i], Yb[i], Tb[i], m, j0, nb, 0});
+        const int ntr = ncomb[i] - (j0 + nb);
+        if (ntr <= 0) continue;
+        double* Ct = Cb[i] + j0 + (int64_t)(j0 + nb) * m;
+        g1.push_back(G(Yb[i] + j0, m, 1, Ct, m, 0, Mb[i], kPanel, nb, ntr, m - j0, 1.0, 0.0));
+        g2.push_back(G(Tb[i], kPanel, 1, Mb[i], kPanel, 0, M2[i], kPanel, nb, ntr, nb, 1.0, 0.0));
+        g3.push_back(G(Yb[i] + j0, m, 0, M2[i], kPanel, 0, Ct, m, m - j0, ntr, nb, -1.0, 1.0));
+      }
+      launch_qr_panel(h.stager.put_vec(pd, h.st), (int)pd.size(), h.st);
+      run_gemm(h, g1);
+      run_gemm(h, g2);
+      run_gemm(h, g3);
+    }
+    // L = R^T, [D^21 D^] = W_bot Qtilde, [V^1; V^] = Qtilde^T Vbar, Qtilde^T kept
+    std::vector<CopyDesc> fin;
     for (size_t i = 0; i < L.size(); ++i) {
       HNode& nd = L[i].n();
-      const int m = nd.mr, r = nd.r;
+      const int m = nd.mr, r = nd.r, nl = nd.nl, c = nd.c;
+      nd.L = dalloc(h, (int64_t)std::max(nl, 1) * std::max(nl, 1));
       nd.WQ = dalloc(h, (int64_t)std::max(r, 1) * m);
-      nd.QV = dalloc(h, (int64_t)m * std::max(nd.c, 1));
-      if (r > 0) g3.push_back(G(Wb[i], r, 0, nd.Q, m, 0, nd.WQ, r, r, m, m, 1.0, 0.0));
-      if (nd.c > 0) g3.push_back(G(nd.Q, m, 1, nd.Vbar, m, 0, nd.QV, m, m, nd.c, m, 1.0, 0.0));
+      fin.push_back(Cp(Cb[i], m, nullptr, nd.L, std::max(nl, 1), nl, nl, 0, 1.0, nullptr, 1));
+      fin.push_back(Cp(Cb[i] + (int64_t)nl * m, m, nullptr, nd.WQ, std::max(r, 1), r, m, 0, 1.0, nullptr, 1));
+      nd.QV = Cb[i] + (int64_t)(nl + r) * m;
+      nd.Q = Cb[i] + (int64_t)(nl + r + c) * m;  // holds Qtilde^T
     }
-    run_gemm(h, g3);
+    run_copy(h, fin);
   }
   // top node k: merged block and its LU
   std::vector<CopyDesc> cp;
@@ -938,7 +972,7 @@ void numeric_factor(Handle& h) {
       for (int i = 0; i < nmax; ++i) iota[i] = i;
       int* d_iota = upload(h, iota);
       compress_level(h, fs, fops, d_iota);
-      ulv_level(h, fs);
+      ulv_level(h, fs, d_iota);
       schur_level(h, fs);
       if (std::getenv("HSSMF_DEBUG")) debug_fronts(h, fs);
     }

@@ -183,30 +183,38 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(const GemmDesc* __restrict
       }
 }
 
-void gemm_batched(const std::vector<GemmDesc>& in, GemmType type, Stager& st, hipStream_t s) {
-  std::vector<GemmDesc> d;
-  d.reserve(in.size());
-  int64_t tiles = 0;
-  for (const GemmDesc& g0 : in) {
-    if (g0.m <= 0 || g0.n <= 0) continue;
-    GemmDesc g = g0;
-    if (g.k <= 0) {
-      if (g.beta == 1.0) continue;
-      g.k = 0;  // alpha * 0 + beta * C: still launched to scale C
-    }
-    g.tiles_m = (g.m + TM - 1) / TM;
-    g.tiles_n = (g.n + TN - 1) / TN;
-    g.tile_base = tiles;
-    tiles += (int64_t)g.tiles_m * g.tiles_n;
-    d.push_back(g);
+// C(cmap(i), j) = alpha * sum_c P_c(i, j) + beta * C(cmap(i), j): the
+// fixed-order reduction of split-K partial products (no atomics)
+struct SplitRed {
+  const double* P;   // nsplit partial m x n blocks, ld m
+  void* C;
+  const int* cmap;
+  int m, n, ldc, nsplit;
+  double alpha, beta;
+};
+
+template <class TOut>
+__global__ void splitk_reduce_kernel(const SplitRed* __restrict__ rs) {
+  const SplitRed r = rs[blockIdx.y];
+  const int64_t mn = (int64_t)r.m * r.n;
+  TOut* C = static_cast<TOut*>(r.C);
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < mn; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % r.m), j = (int)(e / r.m);
+    double acc = 0.0;
+    for (int c = 0; c < r.nsplit; ++c) acc += r.P[e + c * mn];
+    const int ri = r.cmap ? r.cmap[i] : i;
+    TOut* o = C + ri + (int64_t)j * r.ldc;
+    const double v = r.alpha * acc;
+    *o = (TOut)(r.beta == 0.0 ? v : v + r.beta * (double)*o);
   }
-  if (d.empty()) return;
-  REQUIRE(tiles < (1LL << 31), HSSMF_EINVAL, "gemm batch too large");
+}
+
+namespace {
+// element size of the A / B operands of a GEMM type
+size_t in_bytes(GemmType t) { return t == GEMM_F64 ? 8 : (t == GEMM_F32 || t == GEMM_F32_D) ? 4 : 2; }
+
+void launch_tiles(const std::vector<GemmDesc>& d, int64_t tiles, GemmType type, Stager& st, hipStream_t s) {
   GemmDesc* dd = st.put_vec(d, s);
-  double flops = 0.0;
-  if (prof::enabled())
-    for (auto& g : d) flops += 2.0 * g.m * g.n * (double)g.k;
-  int tok = prof::begin(type == GEMM_F64 ? 1 : 2, s);
   dim3 grid((unsigned)tiles), blk(256);
   const int n = (int)d.size();
   switch (type) {
@@ -216,8 +224,91 @@ void gemm_batched(const std::vector<GemmDesc>& in, GemmType type, Stager& st, hi
     case GEMM_BF16: hipLaunchKernelGGL((gemm_lp_kernel<__bf16, float>), grid, blk, 0, s, dd, n); break;
     case GEMM_BF16_D: hipLaunchKernelGGL((gemm_lp_kernel<__bf16, double>), grid, blk, 0, s, dd, n); break;
   }
-  prof::end(tok, s, flops);
   HIP_CHECK(hipGetLastError());
+}
+}  // namespace
+
+void gemm_batched(const std::vector<GemmDesc>& in, GemmType type, Stager& st, hipStream_t s) {
+  std::vector<GemmDesc> d;
+  d.reserve(in.size());
+  int64_t tiles = 0;
+  double flops = 0.0;
+  for (const GemmDesc& g0 : in) {
+    if (g0.m <= 0 || g0.n <= 0) continue;
+    GemmDesc g = g0;
+    if (g.k <= 0) {
+      if (g.beta == 1.0) continue;
+      g.k = 0;  // alpha * 0 + beta * C: still launched to scale C
+    }
+    g.tiles_m = (g.m + TM - 1) / TM;
+    g.tiles_n = (g.n + TN - 1) / TN;
+    tiles += (int64_t)g.tiles_m * g.tiles_n;
+    flops += 2.0 * g.m * g.n * (double)g.k;
+    d.push_back(g);
+  }
+  if (d.empty()) return;
+  REQUIRE(tiles < (1LL << 31), HSSMF_EINVAL, "gemm batch too large");
+  int tok = prof::begin(type == GEMM_F64 ? 1 : 2, s);
+  // split-K when the batch has too few output tiles to fill the chip and
+  // the reductions are long: partial products into the workspace, then a
+  // fixed-order reduction (the result is bitwise reproducible)
+  int64_t kmax = 0, mnsum = 0;
+  for (auto& g : d) { kmax = std::max<int64_t>(kmax, g.k); mnsum += (int64_t)g.m * g.n; }
+  int nsplit = 1;
+  while (nsplit < 16 && tiles * nsplit < 1024 && kmax / (2 * nsplit) >= 256) nsplit *= 2;
+  if (nsplit > 1 && (size_t)(mnsum * nsplit) <= st.ws_elems) {
+    std::vector<GemmDesc> parts;
+    std::vector<SplitRed> red;
+    int64_t wsoff = 0, ptiles = 0;
+    for (auto& g : d) {
+      const int64_t mn = (int64_t)g.m * g.n;
+      SplitRed r{st.ws + wsoff, g.C, g.cmap, g.m, g.n, g.ldc, nsplit, g.alpha, g.beta};
+      const int kc = (g.k + nsplit - 1) / nsplit;
+      const size_t eb = in_bytes(type);
+      for (int c = 0; c < nsplit; ++c) {
+        GemmDesc p = g;
+        const int k0 = c * kc;
+        p.k = std::max(0, std::min(g.k, k0 + kc) - k0);
+        const char* A = static_cast<const char*>(g.A);
+        const char* B = static_cast<const char*>(g.B);
+        if (g.transA) A += (size_t)k0 * eb; else A += (size_t)k0 * g.lda * eb;
+        if (g.transB) B += (size_t)k0 * g.ldb * eb;
+        else if (g.bmap) p.bmap = g.bmap + k0;
+        else B += (size_t)k0 * eb;
+        p.A = A;
+        p.B = B;
+        p.C = st.ws + wsoff + c * mn;
+        p.ldc = g.m;
+        p.cmap = nullptr;
+        p.alpha = 1.0;
+        p.beta = 0.0;
+        p.tile_base = ptiles;
+        ptiles += (int64_t)p.tiles_m * p.tiles_n;
+        parts.push_back(p);
+      }
+      red.push_back(r);
+      wsoff += mn * nsplit;
+    }
+    // partial products are always accumulated and stored in FP64 here
+    GemmType pt = type;
+    if (type == GEMM_F32) pt = GEMM_F32_D;
+    if (type == GEMM_BF16) pt = GEMM_BF16_D;
+    launch_tiles(parts, ptiles, pt, st, s);
+    int64_t mx = 0;
+    for (auto& r : red) mx = std::max<int64_t>(mx, (int64_t)r.m * r.n);
+    int64_t bx = std::min<int64_t>((mx + 255) / 256, 2048);
+    SplitRed* dr = st.put_vec(red, s);
+    if (type == GEMM_F32 || type == GEMM_BF16)
+      hipLaunchKernelGGL(splitk_reduce_kernel<float>, dim3((unsigned)bx, (unsigned)red.size()), dim3(256), 0, s, dr);
+    else
+      hipLaunchKernelGGL(splitk_reduce_kernel<double>, dim3((unsigned)bx, (unsigned)red.size()), dim3(256), 0, s, dr);
+    HIP_CHECK(hipGetLastError());
+  } else {
+    int64_t t = 0;
+    for (auto& g : d) { g.tile_base = t; t += (int64_t)g.tiles_m * g.tiles_n; }
+    launch_tiles(d, tiles, type, st, s);
+  }
+  prof::end(tok, s, flops);
 }
 
 }  // namespace hssmf

@@ -189,3 +189,21 @@ void launch_id_step(const IDProb* p, const int* wgmap, int total_wg, int t, int 
 void launch_id_finish(const IDProb* p, int np, int max_m, hipStream_t s);
 
 }  // namespace hssmf
+
+namespace hssmf {
+
+// one 32-column panel of a blocked Householder QR of C[:, 0:ncols_qr]
+// (column major, m rows, ld m): factors columns [j0, j0+nb) in place (R on
+// and above the diagonal), writes the reflectors as a dense m x nb block Y
+// (zeros above row j0+l in column l) and the nb x nb upper triangular T of
+// the compact WY form  H_j0 ... H_j0+nb-1 = I - Y T Y^T
+struct PanelDesc {
+  double* C;
+  double* Y;
+  double* T;
+  int m, j0, nb, pad;
+};
+constexpr int kPanel = 32;
+void launch_qr_panel(const PanelDesc* d, int nd, hipStream_t s);
+
+}  // namespace hssmf

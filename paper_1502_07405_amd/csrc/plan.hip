@@ -72,11 +72,14 @@ void Stager::init(size_t bytes) {
   cap_ = bytes;
   HIP_CHECK(hipHostMalloc((void**)&host_, bytes, hipHostMallocDefault));
   HIP_CHECK(hipMalloc((void**)&dev_, bytes));
+  ws_elems = size_t(32) << 20;  // 256 MB of doubles
+  HIP_CHECK(hipMalloc((void**)&ws, ws_elems * sizeof(double)));
 }
 
 Stager::~Stager() {
   if (host_) (void)hipHostFree(host_);
   if (dev_) (void)hipFree(dev_);
+  if (ws) (void)hipFree(ws);
 }
 
 void* Stager::put(const void* src, size_t bytes, hipStream_t s) {
@@ -91,6 +94,22 @@ void* Stager::put(const void* src, size_t bytes, hipStream_t s) {
   void* r = dev_ + off_;
   off_ += need;
   return r;
+}
+
+void Stager::put_to(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  size_t need = (bytes + 255) / 256 * 256;
+  if (need > cap_) {
+    HIP_CHECK(hipStreamSynchronize(s));
+    HIP_CHECK(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    return;
+  }
+  if (off_ + need > cap_) {
+    HIP_CHECK(hipStreamSynchronize(s));
+    off_ = 0;
+  }
+  std::memcpy(host_ + off_, src, bytes);
+  HIP_CHECK(hipMemcpyAsync(dst, host_ + off_, bytes, hipMemcpyHostToDevice, s));
+  off_ += need;
 }
 
 // ------------------------------------------------------------- plan --------

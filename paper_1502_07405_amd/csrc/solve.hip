@@ -187,7 +187,7 @@ void ulv_solve_rec(Rec& R, std::vector<std::pair<HFront*, double*>>& fs) {
       c.push_back(CV(nd.ctop, nullptr, nd.xin, nd.nl));
       c.push_back(CV(y2, nullptr, nd.xin + nd.nl, nd.r));
       double* out = nd.leaf() ? x.xv + nd.lo : nd.xbar;
-      g.push_back(GV(nd.Q, nd.mr, nd.mr, nd.mr, 0, nd.xin, out, 1.0, 1));
+      g.push_back(GV(nd.Q, nd.mr, nd.mr, nd.mr, 1, nd.xin, out, 1.0, 1));  // Q holds Qtilde^T
     }
     R.copy(c);
     R.gemv(g);
@@ -228,7 +228,7 @@ void ulv_solve_t_rec(Rec& R, std::vector<std::pair<HFront*, double*>>& fs) {
     std::vector<GemvDesc> g;
     for (auto& x : v) {
       HNode& nd = x.F->nd[x.t];
-      g.push_back(GV(nd.Q, nd.mr, nd.mr, nd.mr, 1, gin(x), nd.gt, 1.0, 1));
+      g.push_back(GV(nd.Q, nd.mr, nd.mr, nd.mr, 0, gin(x), nd.gt, 1.0, 1));  // Qtilde^T g
     }
     R.gemv(g);
   }
@@ -305,12 +305,22 @@ void alloc_solve_buffers(Handle& h) {
       nd.bbar = D(m); nd.ctop = D(m); nd.cbot = D(m); nd.w = D(std::max(nd.c, 1)); nd.wab = D(std::max(nd.mc, 1));
       nd.xin = D(m); nd.xbar = D(m); nd.gt = D(m); nd.gbar = D(m); nd.lbar = D(m); nd.hv = D(std::max(nd.c, 1));
       nd.tmp1 = D(m); nd.tmpv = D(m);
-      if (!nd.permr.empty()) {
-        std::vector<int> ip(nd.permr.size());
-        for (size_t i = 0; i < ip.size(); ++i) ip[nd.permr[i]] = (int)i;
-        nd.diperm = upload(h, ip);
-      }
     }
+  }
+  // inverse row permutations of all nodes, one upload
+  std::vector<int> all;
+  std::vector<std::pair<HNode*, size_t>> at;
+  for (auto& F : h.hf)
+    for (auto& nd : F.nd)
+      if (!nd.permr.empty()) {
+        at.push_back({&nd, all.size()});
+        size_t base = all.size();
+        all.resize(base + nd.permr.size());
+        for (size_t i = 0; i < nd.permr.size(); ++i) all[base + nd.permr[i]] = (int)i;
+      }
+  int* dall = upload(h, all);
+  for (auto& pr : at) pr.first->diperm = dall + pr.second;
+  for (auto& F : h.hf) {
     HNode& k = F.nd[F.k];
     if (!k.leaf()) k.bbar = D(F.mk), k.gbar = D(F.mk);
   }

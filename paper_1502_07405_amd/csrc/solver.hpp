@@ -61,7 +61,7 @@ struct HNode {
   double *Srr = nullptr, *Scr = nullptr, *Rrr = nullptr, *Rcr = nullptr;  // reduced
   // ULV
   int nl = 0;
-  double *Q = nullptr, *L = nullptr, *WQ = nullptr, *QV = nullptr;  // D21|Dh = WQ, V1;Vh = QV
+  double *Q = nullptr, *L = nullptr, *WQ = nullptr, *QV = nullptr;  // Q: Qtilde^T; D21|Dh = WQ, V1;Vh = QV
   double *Dbar = nullptr, *Vbar = nullptr;
   double *Ud = nullptr, *Vd = nullptr;    // dense interpolative generators
   double *Ubig = nullptr, *Vbig = nullptr;
@@ -179,10 +179,7 @@ void run_ops(Handle& h, const std::vector<Op>& ops);
 template <class T>
 T* upload(Handle& h, const std::vector<T>& v) {
   T* d = h.cur->get<T>(v.size());
-  if (!v.empty()) {
-    void* src = h.stager.put(v.data(), v.size() * sizeof(T), h.st);
-    HIP_CHECK(hipMemcpyAsync(d, src, v.size() * sizeof(T), hipMemcpyDeviceToDevice, h.st));
-  }
+  if (!v.empty()) h.stager.put_to(d, v.data(), v.size() * sizeof(T), h.st);
   return d;
 }
 
