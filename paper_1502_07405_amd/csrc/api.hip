@@ -184,6 +184,8 @@ void numeric(Handle& h) {
   build_solve_ops(h);
   HIP_CHECK(hipStreamSynchronize(h.st));
   h.stager.sync();
+  h.larena.release();
+  h.sarena.release();
   h.stats.t_factor_ms = now_ms() - t0;
   h.cur = &h.arena;
   // statistics
@@ -485,6 +487,7 @@ void hssmf_destroy(void* hv) {
   if (!h) return;
   (void)hipStreamSynchronize(h->st);
   delete h;
+  arena_trim_cache();
 }
 
 const char* hssmf_strerror(int code) {

@@ -61,6 +61,9 @@ class Arena {
   size_t used_ = 0;
 };
 
+// returns every released chunk held for reuse to the runtime
+void arena_trim_cache();
+
 // --- batched GEMM descriptor ------------------------------------------------
 // C(m x n) = alpha * op(A) op(B) + beta * C, column major.  Optional row maps:
 // op(A) row i reads A row amap[i] (transA == 0 only), op(B) row kk reads B

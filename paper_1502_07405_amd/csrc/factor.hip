@@ -18,7 +18,9 @@
 
 namespace hssmf {
 
-GemmType Handle::gt() const { return GEMM_F64; }
+GemmType Handle::gt() const {
+  return o.gemm_prec == HSSMF_PREC_FP32 ? GEMM_F32_D : o.gemm_prec == HSSMF_PREC_BF16 ? GEMM_BF16_D : GEMM_F64;
+}
 
 namespace {
 
@@ -168,22 +170,48 @@ struct NRef {
 
 double* dalloc(Handle& h, int64_t n) { return h.cur->get<double>((size_t)std::max<int64_t>(n, 1)); }
 int* ialloc(Handle& h, int64_t n) { return h.cur->get<int>((size_t)std::max<int64_t>(n, 1)); }
+// temporaries: every launch that uses them is ordered on the one stream
+// before any later reuse of the memory, so the arenas can be recycled
+// without waiting
+double* salloc(Handle& h, int64_t n) { return h.sarena.get<double>((size_t)std::max<int64_t>(n, 1)); }
+int* sialloc(Handle& h, int64_t n) { return h.sarena.get<int>((size_t)std::max<int64_t>(n, 1)); }
+double* lalloc(Handle& h, int64_t n) { return h.larena.get<double>((size_t)std::max<int64_t>(n, 1)); }
 
 // allocate / grow R, S^r, S^c of a front to hold dnew columns
 void grow_samples(Handle& h, HFront& F, int dnew) {
   if (dnew <= F.dcap) return;
-  int cap = dnew;
-  double* R = dalloc(h, (int64_t)F.n * cap);
-  double* Sr = dalloc(h, (int64_t)F.n * cap);
-  double* Sc = dalloc(h, (int64_t)F.n * cap);
+  // geometric growth keeps the copies of every growth round within 2x
+  int cap = std::max(dnew, std::min(2 * F.dcap, h.o.d_max));
+  double* R = lalloc(h, (int64_t)F.n * cap);
+  double* Sr = lalloc(h, (int64_t)F.n * cap);
+  double* Sc = lalloc(h, (int64_t)F.n * cap);
   if (F.R && F.d > 0) {
     size_t bytes = sizeof(double) * (size_t)F.n * F.d;
     HIP_CHECK(hipMemcpyAsync(R, F.R, bytes, hipMemcpyDeviceToDevice, h.st));
     HIP_CHECK(hipMemcpyAsync(Sr, F.Sr, bytes, hipMemcpyDeviceToDevice, h.st));
     HIP_CHECK(hipMemcpyAsync(Sc, F.Sc, bytes, hipMemcpyDeviceToDevice, h.st));
   }
+  if (h.o.gemm_prec != HSSMF_PREC_FP64) {
+    const size_t eb = h.o.gemm_prec == HSSMF_PREC_BF16 ? 2 : 4;
+    void* lp = h.larena.alloc(eb * (size_t)F.n * cap);
+    if (F.Rlp && F.d > 0)
+      HIP_CHECK(hipMemcpyAsync(lp, F.Rlp, eb * (size_t)F.n * F.d, hipMemcpyDeviceToDevice, h.st));
+    F.Rlp = lp;
+  }
   F.R = R; F.Sr = Sr; F.Sc = Sc;
   F.dcap = cap;
+}
+
+// new columns of R: keyed Gaussian generator, then (mixed precision) one
+// rounding to the product precision, kept in both copies so every use of R
+// sees the same rounded values
+void gen_random(Handle& h, HFront& F, int c0, int nc) {
+  launch_rng(F.R, F.n, F.orig, F.n, c0, nc, h.o.seed, h.st);
+  if (h.o.gemm_prec != HSSMF_PREC_FP64) {
+    const int bf = h.o.gemm_prec == HSSMF_PREC_BF16;
+    char* lp = static_cast<char*>(F.Rlp) + (size_t)c0 * F.n * (bf ? 2 : 4);
+    launch_round_lp(F.R + (int64_t)c0 * F.n, lp, (int64_t)F.n * nc, bf, h.st);
+  }
 }
 
 // columns [c0, c0+nc) of S^r = F R and S^c = F^T R (Eq. FtimesR): the
@@ -212,10 +240,18 @@ void sample(Handle& h, const std::vector<HFront*>& fs, const std::vector<int>& c
       if (u == 0) continue;
       const int* map = h.fr[F.f].d_kidmap[slot];
       const int64_t off = (int64_t)c0[i] * F.n;
-      g.push_back(G(K.U, K.ldu, 0, F.R + off, F.n, 0, F.Sr + off, F.n, u, nc, u, 1.0, 1.0, map, map));
-      g.push_back(G(K.U, K.ldu, 1, F.R + off, F.n, 0, F.Sc + off, F.n, u, nc, u, 1.0, 1.0, map, map));
+      if (h.o.gemm_prec == HSSMF_PREC_FP64) {
+        g.push_back(G(K.U, K.ldu, 0, F.R + off, F.n, 0, F.Sr + off, F.n, u, nc, u, 1.0, 1.0, map, map));
+        g.push_back(G(K.U, K.ldu, 1, F.R + off, F.n, 0, F.Sc + off, F.n, u, nc, u, 1.0, 1.0, map, map));
+      } else {
+        // low-precision products with FP32 accumulation, added into FP64 samples
+        const size_t eb = h.o.gemm_prec == HSSMF_PREC_BF16 ? 2 : 4;
+        const void* Rl = static_cast<const char*>(F.Rlp) + off * eb;
+        g.push_back(G(K.Ulp, u, 0, Rl, F.n, 0, F.Sr + off, F.n, u, nc, u, 1.0, 1.0, map, map));
+        g.push_back(G(K.Ulp, u, 1, Rl, F.n, 0, F.Sc + off, F.n, u, nc, u, 1.0, 1.0, map, map));
+      }
     }
-    run_gemm(h, g);
+    run_gemm(h, g, h.gt());
   }
 }
 
@@ -228,8 +264,8 @@ void node_samples(Handle& h, const std::vector<NRef>& nodes) {
     HFront& F = *x.F;
     HNode& nd = x.n();
     const int d = F.d;
-    nd.Sr = dalloc(h, (int64_t)nd.mr * d);
-    nd.Sc = dalloc(h, (int64_t)nd.mc * d);
+    nd.Sr = salloc(h, (int64_t)nd.mr * d);
+    nd.Sc = salloc(h, (int64_t)nd.mc * d);
     if (nd.leaf()) {
       const int m = nd.m();
       cp.push_back(Cp(F.Sr + nd.lo, F.n, nullptr, nd.Sr, m, m, d));
@@ -264,10 +300,10 @@ void reduce_nodes(Handle& h, const std::vector<NRef>& nodes) {
     HFront& F = *x.F;
     HNode& nd = x.n();
     const int d = F.d;
-    nd.Srr = dalloc(h, (int64_t)nd.r * d);
-    nd.Scr = dalloc(h, (int64_t)nd.c * d);
-    nd.Rrr = dalloc(h, (int64_t)nd.c * d);
-    nd.Rcr = dalloc(h, (int64_t)nd.r * d);
+    nd.Srr = lalloc(h, (int64_t)nd.r * d);
+    nd.Scr = lalloc(h, (int64_t)nd.c * d);
+    nd.Rrr = lalloc(h, (int64_t)nd.c * d);
+    nd.Rcr = lalloc(h, (int64_t)nd.r * d);
     const double *Rin_r, *Rin_c;
     int ld_r, ld_c;
     if (nd.leaf()) {
@@ -276,8 +312,8 @@ void reduce_nodes(Handle& h, const std::vector<NRef>& nodes) {
     } else {
       HNode& a = F.nd[nd.kid[0]];
       HNode& b = F.nd[nd.kid[1]];
-      double* tr = dalloc(h, (int64_t)nd.mc * d);
-      double* tc = dalloc(h, (int64_t)nd.mr * d);
+      double* tr = salloc(h, (int64_t)nd.mc * d);
+      double* tc = salloc(h, (int64_t)nd.mr * d);
       stack.push_back(Cp(a.Rrr, a.c, nullptr, tr, nd.mc, a.c, d));
       stack.push_back(Cp(b.Rrr, b.c, nullptr, tr + a.c, nd.mc, b.c, d));
       stack.push_back(Cp(a.Rcr, a.r, nullptr, tc, nd.mr, a.r, d));
@@ -328,6 +364,8 @@ FrontOpDev* front_ops(Handle& h, const std::vector<HFront*>& fs) {
 void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops, const int* iota) {
   const hssmf_opts& o = h.o;
   // initial samples
+  h.larena.release();
+  h.sarena.release();
   {
     std::vector<int> c0;
     for (HFront* F : fs) {
@@ -351,7 +389,7 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
       F->Vbark = F->ThT = F->Phi = F->Upd = nullptr;
       F->UpdLP = nullptr;
       F->X = F->t1 = F->t2 = nullptr;
-      launch_rng(F->R, F->n, F->orig, F->n, 0, F->d, o.seed, h.st);
+      gen_random(h, *F, 0, F->d);
       c0.push_back(0);
     }
     sample(h, fs, c0, o.d0);
@@ -360,6 +398,7 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
   for (HFront* F : fs) maxh = std::max(maxh, F->maxh);
   while (true) {
     for (int hh = 0; hh <= maxh; ++hh) {
+      h.sarena.release();
       std::vector<NRef> refresh, cand;
       for (HFront* F : fs) {
         if (F->finished) continue;
@@ -390,10 +429,12 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
           HNode& b = F.nd[nd.kid[1]];
           nd.mr = a.r + b.r;
           nd.mc = a.c + b.c;
-          nd.B12 = dalloc(h, (int64_t)a.r * b.c);
-          nd.B21 = dalloc(h, (int64_t)b.r * a.c);
-          ex.push_back({nd.B12, a.dIr, b.dIc, a.r, b.c, a.r, F.fop});
-          ex.push_back({nd.B21, b.dIr, a.dIc, b.r, a.c, b.r, F.fop});
+          if (!nd.B12) {  // the children keep their skeletons across growth rounds
+            nd.B12 = dalloc(h, (int64_t)a.r * b.c);
+            nd.B21 = dalloc(h, (int64_t)b.r * a.c);
+            ex.push_back({nd.B12, a.dIr, b.dIc, a.r, b.c, a.r, F.fop});
+            ex.push_back({nd.B21, b.dIr, a.dIc, b.r, a.c, b.r, F.fop});
+          }
         }
       }
       run_extract(h, ex, fops);
@@ -406,7 +447,7 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
       std::vector<int> off(cand.size() + 1, 0);
       for (size_t i = 0; i < cand.size(); ++i) off[i + 1] = off[i] + cand[i].n().mr + cand[i].n().mc;
       int* ibuf = ialloc(h, off.back());
-      int* sbuf = ialloc(h, 4 * (int64_t)cand.size());
+      int* sbuf = sialloc(h, 4 * (int64_t)cand.size());
       std::vector<IDProb> q;
       int maxm = 0, maxd = 0, tmax = 0, wg = 0;
       for (size_t i = 0; i < cand.size(); ++i) {
@@ -414,27 +455,24 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
         const int d = cand[i].F->d;
         nd.dpermr = ibuf + off[i];
         nd.dpermc = nd.dpermr + nd.mr;
-        nd.Er = dalloc(h, (int64_t)nd.mr * std::min(nd.mr, d));
-        nd.Ec = dalloc(h, (int64_t)nd.mc * std::min(nd.mc, d));
         for (int sd = 0; sd < 2; ++sd) {
           const int m = sd ? nd.mc : nd.mr;
           const int mn = std::min(m, d);
           IDProb pr{};
           pr.S = sd ? nd.Sc : nd.Sr;
           pr.lds = std::max(m, 1);
-          pr.W = dalloc(h, (int64_t)m * d);
-          pr.norms = dalloc(h, m);
-          pr.alpha = dalloc(h, mn);
+          pr.W = salloc(h, (int64_t)m * d);
+          pr.norms = salloc(h, m);
+          pr.alpha = salloc(h, mn);
           pr.P = std::max(1, (m + kIDCols - 1) / kIDCols);
-          pr.slots = dalloc(h, 4 * (int64_t)pr.P);
-          pr.R1 = dalloc(h, (int64_t)mn * mn);
-          pr.W2 = dalloc(h, (int64_t)m * mn);
-          pr.E = sd ? nd.Ec : nd.Er;
+          pr.slots = salloc(h, 4 * (int64_t)pr.P);
+          pr.R1 = salloc(h, (int64_t)mn * mn);
+          pr.W2 = salloc(h, (int64_t)m * mn);
           pr.perm = sd ? nd.dpermc : nd.dpermr;
-          pr.ipos = ialloc(h, m);
+          pr.ipos = sialloc(h, m);
           pr.state = sbuf + 4 * i + 2 * sd;
-          pr.first = dalloc(h, 1);
-          pr.active = reinterpret_cast<unsigned char*>(ialloc(h, (m + 3) / 4 + 1));
+          pr.first = salloc(h, 1);
+          pr.active = reinterpret_cast<unsigned char*>(sialloc(h, (m + 3) / 4 + 1));
           pr.m = m;
           pr.d = d;
           pr.wg0 = wg;
@@ -516,6 +554,8 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
           base_r = a.Ir; base_r.insert(base_r.end(), bb.Ir.begin(), bb.Ir.end());
           base_c = a.Ic; base_c.insert(base_c.end(), bb.Ic.begin(), bb.Ic.end());
         }
+        nd.Er = dalloc(h, (int64_t)(nd.mr - r) * r);
+        nd.Ec = dalloc(h, (int64_t)(nd.mc - c) * c);
         nd.Ir.resize(r);
         nd.Ic.resize(c);
         for (int j = 0; j < r; ++j) nd.Ir[j] = base_r[nd.permr[j]];
@@ -539,7 +579,7 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
             const int k = sd ? nd.c : nd.r, nrest = pr.m - k;
             if (k == 0 || nrest == 0) continue;
             tp.push_back({pr.R1, k, k, pr.W2, k, nrest});
-            tc.push_back(Cp(pr.W2, k, nullptr, pr.E, nrest, nrest, k, 0, 1.0, nullptr, 1));
+            tc.push_back(Cp(pr.W2, k, nullptr, sd ? nd.Ec : nd.Er, nrest, nrest, k, 0, 1.0, nullptr, 1));
           }
         }
         tri_solve_upper_batched(h, tp);
@@ -588,7 +628,7 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
       if (F->finished) continue;
       if (F->d + o.dd > o.d_max) throw Error(HSSMF_ERANK, "HSS compression reached d_max", F->f);
       grow_samples(h, *F, F->d + o.dd);
-      launch_rng(F->R, F->n, F->orig, F->n, F->d, o.dd, o.seed, h.st);
+      gen_random(h, *F, F->d, o.dd);
       c0.push_back(F->d);
       grow.push_back(F);
       F->d += o.dd;
@@ -609,6 +649,7 @@ void ulv_level(Handle& h, std::vector<HFront*>& fs, const int* iota) {
     return t == F->k;
   };
   for (int hh = 0; hh <= maxh; ++hh) {
+    h.sarena.release();
     std::vector<NRef> L;
     for (HFront* F : fs)
       for (int t = 0; t < (int)F->nd.size(); ++t)
@@ -631,8 +672,8 @@ void ulv_level(Handle& h, std::vector<HFront*>& fs, const int* iota) {
       } else {
         HNode& a = F.nd[nd.kid[0]];
         HNode& b = F.nd[nd.kid[1]];
-        nd.Dbar = dalloc(h, (int64_t)m * m);
-        nd.Vbar = dalloc(h, (int64_t)m * nd.c);
+        nd.Dbar = salloc(h, (int64_t)m * m);
+        nd.Vbar = salloc(h, (int64_t)m * nd.c);
         // diagonal blocks: D^ of the children (last r columns of WQ)
         cp.push_back(Cp(a.WQ + (int64_t)a.nl * a.r, a.r, nullptr, nd.Dbar, m, a.r, a.r));
         cp.push_back(Cp(b.WQ + (int64_t)b.nl * b.r, b.r, nullptr, nd.Dbar + a.r + (int64_t)a.r * m, m, b.r, b.r));
@@ -673,8 +714,8 @@ void ulv_level(Handle& h, std::vector<HFront*>& fs, const int* iota) {
       const int m = nd.mr, r = nd.r, nl = m - r, c = nd.c;
       nd.nl = nl;
       nlmax = std::max(nlmax, nl);
-      Wt[i] = dalloc(h, (int64_t)std::max(nl, 1) * m);
-      Wb[i] = dalloc(h, (int64_t)std::max(r, 1) * m);
+      Wt[i] = salloc(h, (int64_t)std::max(nl, 1) * m);
+      Wb[i] = salloc(h, (int64_t)std::max(r, 1) * m);
       wc.push_back(Cp(nd.Dbar, m, nd.dpermr + r, Wt[i], std::max(nl, 1), nl, m));
       wc.push_back(Cp(nd.Dbar, m, nd.dpermr, Wb[i], std::max(r, 1), r, m));
       if (nl > 0 && r > 0)
@@ -683,10 +724,10 @@ void ulv_level(Handle& h, std::vector<HFront*>& fs, const int* iota) {
       // first nl columns applies Qtilde^T to the rest
       ncomb[i] = nl + r + c + m;
       Cb[i] = dalloc(h, (int64_t)m * ncomb[i]);
-      Yb[i] = dalloc(h, (int64_t)m * kPanel);
-      Tb[i] = dalloc(h, (int64_t)kPanel * kPanel);
-      Mb[i] = dalloc(h, (int64_t)kPanel * ncomb[i]);
-      M2[i] = dalloc(h, (int64_t)kPanel * ncomb[i]);
+      Yb[i] = salloc(h, (int64_t)m * kPanel);
+      Tb[i] = salloc(h, (int64_t)kPanel * kPanel);
+      Mb[i] = salloc(h, (int64_t)kPanel * ncomb[i]);
+      M2[i] = salloc(h, (int64_t)kPanel * ncomb[i]);
       cc.push_back(Cp(Wt[i], std::max(nl, 1), nullptr, Cb[i], m, m, nl, 0, 1.0, nullptr, 1));
       cc.push_back(Cp(Wb[i], std::max(r, 1), nullptr, Cb[i] + (int64_t)nl * m, m, m, r, 0, 1.0, nullptr, 1));
       cc.push_back(Cp(nd.Vbar, m, nullptr, Cb[i] + (int64_t)(nl + r) * m, m, m, c));
@@ -824,6 +865,7 @@ void schur_level(Handle& h, std::vector<HFront*>& fs) {
     run_gemm(h, g);
   }
   // Theta^T = U_LU^{-T} (Vbar_k B_qk^T) Ubig_q^T ; Phi = L_LU^{-1} P U_k B_kq Vbig_q^T
+  h.sarena.release();
   std::vector<GemmDesc> g1, g2, g3;
   std::vector<double*> T1(wu.size()), T3(wu.size());
   for (size_t i = 0; i < wu.size(); ++i) {
@@ -833,12 +875,12 @@ void schur_level(Handle& h, std::vector<HFront*>& fs) {
     HNode& q = F.nd[F.q];
     const int mk = F.mk, u = F.u;
     // root children are (k, q): B12 = B_kq (r_k x c_q), B21 = B_qk (r_q x c_k)
-    T1[i] = dalloc(h, (int64_t)mk * std::max(q.r, 1));  // Vbar_k B_qk^T : mk x r_q
+    T1[i] = salloc(h, (int64_t)mk * std::max(q.r, 1));  // Vbar_k B_qk^T : mk x r_q
     g1.push_back(G(F.Vbark, mk, 0, rt.B21, q.r, 1, T1[i], mk, mk, q.r, k.c, 1.0, 0.0));
-    T3[i] = dalloc(h, (int64_t)std::max(k.r, 1) * u);   // B_kq Vbig_q^T : r_k x u
+    T3[i] = salloc(h, (int64_t)std::max(k.r, 1) * u);   // B_kq Vbig_q^T : r_k x u
     g1.push_back(G(rt.B12, k.r, 0, q.Vbig, u, 1, T3[i], std::max(k.r, 1), k.r, u, q.c, 1.0, 0.0));
-    F.ThT = dalloc(h, (int64_t)mk * u);
-    F.Phi = dalloc(h, (int64_t)mk * u);
+    F.ThT = salloc(h, (int64_t)mk * u);
+    F.Phi = salloc(h, (int64_t)mk * u);
     g2.push_back(G(T1[i], mk, 0, q.Ubig, u, 1, F.ThT, mk, mk, u, q.r, 1.0, 0.0));
     g2.push_back(G(k.Ud, mk, 0, T3[i], std::max(k.r, 1), 0, F.Phi, mk, mk, u, k.r, 1.0, 0.0));
   }
@@ -874,8 +916,8 @@ void schur_level(Handle& h, std::vector<HFront*>& fs) {
       HNode& a = F->nd[nd.kid[0]];
       HNode& b = F->nd[nd.kid[1]];
       // block (a, b) = Ubig_a B12 Vbig_b^T ; block (b, a) = Ubig_b B21 Vbig_a^T
-      double* ta = dalloc(h, (int64_t)std::max(a.r, 1) * b.m());
-      double* tb = dalloc(h, (int64_t)std::max(b.r, 1) * a.m());
+      double* ta = salloc(h, (int64_t)std::max(a.r, 1) * b.m());
+      double* tb = salloc(h, (int64_t)std::max(b.r, 1) * a.m());
       e1.push_back(G(nd.B12, a.r, 0, b.Vbig, b.m(), 1, ta, std::max(a.r, 1), a.r, b.m(), b.c, 1.0, 0.0));
       e1.push_back(G(nd.B21, b.r, 0, a.Vbig, a.m(), 1, tb, std::max(b.r, 1), b.r, a.m(), a.c, 1.0, 0.0));
       const int oa = a.lo - F->s, ob = b.lo - F->s;
@@ -893,6 +935,16 @@ void schur_level(Handle& h, std::vector<HFront*>& fs) {
 }
 
 }  // namespace
+
+// bf16 copy of a (possibly strided) u x u update matrix
+static void launch_copy_bf16(Handle& h, const double* U, int ldu, void* dst, int u) {
+  double* tmp = h.cur->get<double>((size_t)u * u);
+  CopyDesc c{};
+  c.src = U; c.dst = tmp; c.m = u; c.n = u; c.lds = ldu; c.ldd = u; c.alpha = 1.0;
+  CopyDesc* dc = static_cast<CopyDesc*>(h.stager.put(&c, sizeof(c), h.st));
+  launch_copy(dc, 1, (int64_t)u * u, 0, h.st);
+  launch_convert(tmp, dst, (int64_t)u * u, 1, h.st);
+}
 
 // per-front norms of Theta, Phi and the update matrix (diagnostics)
 static double dev_fro(Handle& h, const double* p, int64_t n) {
@@ -971,6 +1023,25 @@ void numeric_factor(Handle& h) {
       std::vector<int> iota(nmax);
       for (int i = 0; i < nmax; ++i) iota[i] = i;
       int* d_iota = upload(h, iota);
+      if (h.o.gemm_prec != HSSMF_PREC_FP64) {
+        // low-precision compact copies of the children's update matrices
+        const int bf = h.o.gemm_prec == HSSMF_PREC_BF16;
+        std::vector<CopyDesc> cv;
+        for (HFront* F : fs)
+          for (int c : P.fr[F->f].kids) {
+            const int u = P.fr[c].u;
+            if (u == 0) continue;
+            void* lp = h.cur->alloc((size_t)u * u * (bf ? 2 : 4));
+            h.fr[c].Ulp = lp;
+            if (bf) launch_copy_bf16(h, h.fr[c].U, h.fr[c].ldu, lp, u);
+            else cv.push_back(Cp(h.fr[c].U, h.fr[c].ldu, nullptr, lp, u, u, u));
+          }
+        if (!cv.empty()) {
+          int64_t mx = 0;
+          for (auto& c : cv) mx = std::max<int64_t>(mx, (int64_t)c.m * c.n);
+          launch_copy(h.stager.put_vec(cv, h.st), (int)cv.size(), mx, 1, h.st);
+        }
+      }
       compress_level(h, fs, fops, d_iota);
       ulv_level(h, fs, d_iota);
       schur_level(h, fs);

@@ -114,6 +114,28 @@ void launch_convert(const double* src, void* dst, int64_t n, int to_bf16, hipStr
   HIP_CHECK(hipGetLastError());
 }
 
+__global__ void round_lp_kernel(double* x, void* lp, int64_t n, int to_bf16) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (to_bf16) {
+      __bf16 v = (__bf16)(float)x[i];
+      static_cast<__bf16*>(lp)[i] = v;
+      x[i] = (double)(float)v;
+    } else {
+      float v = (float)x[i];
+      static_cast<float*>(lp)[i] = v;
+      x[i] = (double)v;
+    }
+  }
+}
+
+void launch_round_lp(double* x, void* lp, int64_t n, int to_bf16, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(round_lp_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, lp, n, to_bf16);
+  HIP_CHECK(hipGetLastError());
+}
+
 // ---------------------------------------------------------- extraction ---
 // F_i(I, J) = A_i(I, J) + sum over children of U_child(inv(I), inv(J))
 // (the element access that Alg. 1 needs for D and B, Sec. 4.3)
@@ -145,198 +167,6 @@ void launch_extract(const ExtractDesc* d, int nd, const FrontOpDev* fops, int64_
   int64_t blocks = (max_elems + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(extract_kernel, dim3((unsigned)blocks, nd), dim3(256), 0, s, d, fops);
-  HIP_CHECK(hipGetLastError());
-}
-
-// ------------------------------------------------------ Householder QR ---
-// Y = S^T (d x m) is staged column by column (column j = row j of S), so
-// every candidate is a contiguous vector.  One workgroup per problem; four
-// wavefronts take the trailing columns round robin, each doing its dot
-// product and update with a lane-stride loop and a shuffle reduction.
-//
-// PIVOT = true (interpolative decomposition, Sec. 2.2 and Sec. 5.4): the
-// pivot is the column with the largest remaining 2-norm, recomputed from
-// the updated column after every step (ties to the lowest index); stop
-// before step i+1 when that norm <= eps * (first pivot norm).  Then
-// X = R1^{-1} R2 and E = X^T.
-// PIVOT = false: plain QR of all min(d, m) columns; writes L = R^T and the
-// explicit d x d orthogonal factor Q (Y = Q R).
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
-
-template <bool PIVOT>
-__global__ __launch_bounds__(256) void qr_kernel(const QRDesc* __restrict__ descs) {
-  extern __shared__ char lds_raw[];
-  const QRDesc q = descs[blockIdx.x];
-  const int m = q.m, d = q.d;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double* nrm = reinterpret_cast<double*>(lds_raw);          // m
-  double* tau = nrm + m;                                     // min(d, m)
-  double* rv = tau + ((m < d) ? m : d);                      // 256 reduction values
-  int* ri = reinterpret_cast<int*>(rv + 256);                // 256 reduction indices
-  int* perm = ri + 256;                                      // m
-  __shared__ double bcast[4];
-  __shared__ int kout;
-  double* W = q.W;
-  // stage Y = S^T
-  for (int64_t e = tid; e < (int64_t)m * d; e += 256) {
-    int j = (int)(e / d), kk = (int)(e % d);
-    W[kk + (int64_t)j * d] = q.S[j + (int64_t)kk * q.lds];
-  }
-  for (int j = tid; j < m; j += 256) perm[j] = j;
-  __syncthreads();
-  for (int j = wave; j < m; j += 4) {
-    double acc = 0.0;
-    for (int i = lane; i < d; i += 64) { double x = W[i + (int64_t)j * d]; acc += x * x; }
-    acc = wave_sum(acc);
-    if (lane == 0) nrm[j] = sqrt(acc);
-  }
-  __syncthreads();
-  const int kmax = (m < d) ? m : d;
-  double first = 0.0;
-  int k = kmax;
-  for (int t = 0; t < kmax; ++t) {
-    int p = t;
-    double best = nrm[t];
-    if (PIVOT) {
-      best = -1.0;
-      for (int j = t + tid; j < m; j += 256)
-        if (nrm[j] > best) { best = nrm[j]; p = j; }
-      rv[tid] = best;
-      ri[tid] = p;
-      __syncthreads();
-      for (int off = 128; off > 0; off >>= 1) {
-        if (tid < off) {
-          double o = rv[tid + off];
-          int oi = ri[tid + off];
-          if (o > rv[tid] || (o == rv[tid] && oi < ri[tid])) { rv[tid] = o; ri[tid] = oi; }
-        }
-        __syncthreads();
-      }
-      best = rv[0];
-      p = ri[0];
-      __syncthreads();
-      if (t == 0) {
-        first = best;
-        if (first == 0.0) { k = 0; break; }
-      } else if (best <= q.eps * first) {
-        k = t;
-        break;
-      }
-      if (p != t) {
-        for (int i = tid; i < d; i += 256) {
-          double a = W[i + (int64_t)t * d];
-          W[i + (int64_t)t * d] = W[i + (int64_t)p * d];
-          W[i + (int64_t)p * d] = a;
-        }
-        if (tid == 0) {
-          double x = nrm[t]; nrm[t] = nrm[p]; nrm[p] = x;
-          int y = perm[t]; perm[t] = perm[p]; perm[p] = y;
-        }
-      }
-      __syncthreads();
-    }
-    // Householder reflector for W[t:, t]; best = its 2-norm
-    if (tid == 0) {
-      double x0 = W[t + (int64_t)t * d];
-      double alpha = (x0 >= 0.0) ? -best : best;
-      double v0 = x0 - alpha;
-      double vtv = v0 * v0 + (best * best - x0 * x0);
-      double tv = (vtv > 0.0 && best > 0.0) ? 2.0 / vtv : 0.0;
-      bcast[0] = v0;
-      bcast[1] = tv;
-      bcast[2] = alpha;
-      tau[t] = tv;
-      W[t + (int64_t)t * d] = v0;
-    }
-    __syncthreads();
-    {
-      const double tv = bcast[1];
-      const double* v = W + (int64_t)t * d;
-      for (int j = t + 1 + wave; j < m; j += 4) {
-        double* col = W + (int64_t)j * d;
-        double dot = 0.0;
-        if (tv != 0.0) {
-          for (int i = t + lane; i < d; i += 64) dot += v[i] * col[i];
-          dot = wave_sum(dot) * tv;
-        }
-        double ss = 0.0;
-        for (int i = t + lane; i < d; i += 64) {
-          double x = col[i] - dot * v[i];
-          col[i] = x;
-          if (i > t) ss += x * x;
-        }
-        ss = wave_sum(ss);
-        if (lane == 0) nrm[j] = sqrt(ss);   // exact recomputation, no downdating
-      }
-    }
-    __syncthreads();
-    if (tid == 0) {
-      nrm[t] = bcast[0];                    // keep v0 (needed to form Q)
-      W[t + (int64_t)t * d] = bcast[2];     // R_tt
-    }
-    __syncthreads();
-  }
-  if (tid == 0) kout = k;
-  __syncthreads();
-  k = kout;
-  if (PIVOT) {
-    if (tid == 0) *q.rank = k;
-    for (int j = tid; j < m; j += 256) q.perm[j] = perm[j];
-    // X = R1^{-1} R2, one column per thread, then E = X^T
-    const int nrest = m - k;
-    for (int j = k + tid; j < m; j += 256) {
-      double* col = W + (int64_t)j * d;
-      for (int i = k - 1; i >= 0; --i) {
-        double acc = col[i];
-        for (int l = i + 1; l < k; ++l) acc -= W[i + (int64_t)l * d] * col[l];
-        col[i] = acc / W[i + (int64_t)i * d];
-      }
-      for (int l = 0; l < k; ++l) q.E[(j - k) + (int64_t)l * nrest] = col[l];
-    }
-  } else {
-    if (tid == 0) *q.rank = k;
-    // L = R^T (k x k)
-    for (int64_t e = tid; e < (int64_t)k * k; e += 256) {
-      int i = (int)(e % k), j = (int)(e / k);
-      q.L[i + (int64_t)j * k] = (i >= j) ? W[j + (int64_t)i * d] : 0.0;
-    }
-    // Q = H_0 H_1 ... H_{k-1}: apply the reflectors in reverse order to I
-    if (q.Q) {
-      double* Q = q.Q;
-      for (int64_t e = tid; e < (int64_t)d * d; e += 256) {
-        int i = (int)(e % d), j = (int)(e / d);
-        Q[i + (int64_t)j * d] = (i == j) ? 1.0 : 0.0;
-      }
-      __syncthreads();
-      for (int t = k - 1; t >= 0; --t) {
-        const double tv = tau[t];
-        if (tv == 0.0) continue;
-        const double v0 = nrm[t];
-        const double* v = W + (int64_t)t * d;  // v[i] for i > t; v[t] = v0
-        for (int j = wave; j < d; j += 4) {
-          double* col = Q + (int64_t)j * d;
-          double dot = 0.0;
-          for (int i = t + lane; i < d; i += 64) dot += ((i == t) ? v0 : v[i]) * col[i];
-          dot = wave_sum(dot) * tv;
-          for (int i = t + lane; i < d; i += 64) col[i] -= dot * ((i == t) ? v0 : v[i]);
-        }
-        __syncthreads();
-      }
-    }
-  }
-}
-
-void launch_qr(const QRDesc* d, int nd, int pivot, int max_m, hipStream_t s) {
-  if (nd <= 0) return;
-  size_t lds = (size_t)max_m * 8 * 2 + 256 * 8 + 256 * 4 + (size_t)max_m * 4;
-  REQUIRE(lds <= 64 * 1024, HSSMF_ERANK, "interpolative decomposition: node too large for one workgroup");
-  if (pivot)
-    hipLaunchKernelGGL(qr_kernel<true>, dim3(nd), dim3(256), lds, s, d);
-  else
-    hipLaunchKernelGGL(qr_kernel<false>, dim3(nd), dim3(256), lds, s, d);
   HIP_CHECK(hipGetLastError());
 }
 

@@ -120,18 +120,6 @@ struct ExtractDesc {
   int m, n, ldd, fop;
 };
 
-// pivoted (ID) or plain Householder QR of Y = S^T, S m x d
-struct QRDesc {
-  const double* S;
-  double* W;       // d x m work (ld d)
-  int* perm;       // m
-  int* rank;       // 1
-  double* E;       // (m-k) x k, ld m-k (ID mode)
-  double* Q;       // d x d explicit Q (QR mode, may be null)
-  double* L;       // k x k lower = R^T (QR mode)
-  int m, d, lds;
-  double eps;
-};
 
 struct TrsmDesc {
   const double* T;
@@ -144,7 +132,6 @@ void launch_rng(double* R, int ldr, const int* orig, int nrows, int c0, int nc, 
 void launch_spmm(const SpmmDesc* d, int nd, int max_rows, int max_cols, hipStream_t s);
 void launch_copy(const CopyDesc* d, int nd, int64_t max_elems, int f32, hipStream_t s);
 void launch_extract(const ExtractDesc* d, int nd, const FrontOpDev* fops, int64_t max_elems, hipStream_t s);
-void launch_qr(const QRDesc* d, int nd, int pivot, int max_m, hipStream_t s);
 // dst (m x k, ld ldd) = Pi [I; E]: dst[perm[i], :] = row i of [I; E]
 struct InterpDesc {
   double* dst;
@@ -157,6 +144,8 @@ void launch_pivots(double* M, int ld, int ncols, const int* ipiv, int k, int rev
 // logical T(i,j) = trans ? T[j + i ld] : T[i + j ld]; solve rows [b0, b0+bs) in place
 void launch_trsm_block(const TrsmDesc* d, int nd, int lower, int unit, int trans, int max_cols, hipStream_t s);
 void launch_convert(const double* src, void* dst, int64_t n, int to_bf16, hipStream_t s);
+// round x to the low precision in place and write the low-precision copy
+void launch_round_lp(double* x, void* lp, int64_t n, int to_bf16, hipStream_t s);
 
 }  // namespace hssmf
 
@@ -172,7 +161,6 @@ struct IDProb {
   double* slots;        // 2 (parity) x P x 2: partial (norm, column)
   double* R1;           // k x k scratch (upper triangle, pivot order)
   double* W2;           // k x (m - k) scratch: R2, then X = R1^{-1} R2
-  double* E;            // output (m - k) x k, ld m - k
   int* perm;            // output: position -> candidate
   int* ipos;            // candidate -> position
   int* state;           // [0] done, [1] rank

@@ -15,6 +15,22 @@ namespace hssmf {
 namespace {
 std::mutex g_cache_mu;
 std::vector<std::pair<char*, size_t>> g_cache;  // released chunks for reuse
+size_t g_cached = 0;
+constexpr size_t kCacheCap = size_t(64) << 30;  // keep at most 64 GB of released chunks
+
+void cache_put(char* p, size_t sz) {
+  g_cache.push_back({p, sz});
+  g_cached += sz;
+  // bounded cache: give the largest chunks back to the runtime first
+  while (g_cached > kCacheCap && !g_cache.empty()) {
+    size_t big = 0;
+    for (size_t i = 1; i < g_cache.size(); ++i)
+      if (g_cache[i].second > g_cache[big].second) big = i;
+    (void)hipFree(g_cache[big].first);
+    g_cached -= g_cache[big].second;
+    g_cache.erase(g_cache.begin() + big);
+  }
+}
 }  // namespace
 
 void* Arena::alloc(size_t bytes, size_t align) {
@@ -24,20 +40,34 @@ void* Arena::alloc(size_t bytes, size_t align) {
     size_t sz = std::max<size_t>(need, size_t(256) << 20);
     char* p = nullptr;
     {
+      // best fit among the cached chunks
       std::lock_guard<std::mutex> g(g_cache_mu);
+      size_t bi = g_cache.size();
       for (size_t i = 0; i < g_cache.size(); ++i)
-        if (g_cache[i].second >= sz) {
-          p = g_cache[i].first;
-          sz = g_cache[i].second;
-          g_cache.erase(g_cache.begin() + i);
-          break;
-        }
+        if (g_cache[i].second >= sz && (bi == g_cache.size() || g_cache[i].second < g_cache[bi].second)) bi = i;
+      if (bi < g_cache.size() && g_cache[bi].second <= 4 * sz) {
+        p = g_cache[bi].first;
+        sz = g_cache[bi].second;
+        g_cached -= sz;
+        g_cache.erase(g_cache.begin() + bi);
+      }
     }
     if (!p) {
       hipError_t e = hipMalloc(&p, sz);
       if (e != hipSuccess) {
         (void)hipGetLastError();
-        throw Error(HSSMF_ENOMEM, "device allocation of " + std::to_string(sz) + " bytes failed");
+        // return the cache to the runtime and try once more
+        {
+          std::lock_guard<std::mutex> g(g_cache_mu);
+          for (auto& c : g_cache) (void)hipFree(c.first);
+          g_cache.clear();
+          g_cached = 0;
+        }
+        e = hipMalloc(&p, sz);
+        if (e != hipSuccess) {
+          (void)hipGetLastError();
+          throw Error(HSSMF_ENOMEM, "device allocation of " + std::to_string(sz) + " bytes failed");
+        }
       }
     }
     chunks_.push_back({p, sz});
@@ -53,16 +83,23 @@ void Arena::reset(const Mark& m) {
   // chunks allocated after the mark go back to the cache
   std::lock_guard<std::mutex> g(g_cache_mu);
   while (chunks_.size() > m.chunk + 1) {
-    g_cache.push_back({chunks_.back().p, chunks_.back().size});
+    cache_put(chunks_.back().p, chunks_.back().size);
     chunks_.pop_back();
   }
   off_ = m.off;
   used_ = m.used;
 }
 
+void arena_trim_cache() {
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  for (auto& c : g_cache) (void)hipFree(c.first);
+  g_cache.clear();
+  g_cached = 0;
+}
+
 void Arena::release() {
   std::lock_guard<std::mutex> g(g_cache_mu);
-  for (auto& c : chunks_) g_cache.push_back({c.p, c.size});
+  for (auto& c : chunks_) cache_put(c.p, c.size);
   chunks_.clear();
   off_ = used_ = 0;
 }

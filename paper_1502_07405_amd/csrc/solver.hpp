@@ -79,6 +79,7 @@ struct HFront {
   // sampling
   int d = 0, dcap = 0, rounds = 0;
   double *R = nullptr, *Sr = nullptr, *Sc = nullptr;
+  void* Rlp = nullptr;       // low-precision copy of R (mixed precision)
   int* orig = nullptr;       // original row ids of the front's indices
   bool finished = false, refresh = false;
   // front operator
@@ -128,6 +129,8 @@ struct Handle {
   hipStream_t st = nullptr;
   Arena arena;       // plan data that survives refactorization
   Arena narena;      // numeric factors, reset by every refactorization
+  Arena larena;      // compression state of one elimination-tree level
+  Arena sarena;      // temporaries of one batched pass (stream ordered reuse)
   Arena* cur = &arena;
   Stager stager;
   std::vector<Op> sops[2][2];  // [trans][0 = forward, 1 = backward]
