@@ -487,22 +487,36 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
       if (!q.empty()) {
         IDProb* dq = upload(h, q);
         const int np = (int)q.size();
-        std::vector<int> wgm(wg);
-        for (int pi = 0; pi < np; ++pi)
-          for (int w = 0; w < q[pi].P; ++w) wgm[q[pi].wg0 + w] = pi;
-        int* dwgm = upload(h, wgm);
+        // grid of the live problems' workgroups: rebuilt at every check so
+        // that finished problems stop taking workgroups
+        auto wgmap = [&](const std::vector<int>& live, int& nwg) {
+          std::vector<int2> wgm;
+          for (int pi : live)
+            for (int w = 0; w < q[pi].P; ++w) wgm.push_back(make_int2(pi, w));
+          nwg = (int)wgm.size();
+          return upload(h, wgm);
+        };
+        std::vector<int> live(np);
+        for (int pi = 0; pi < np; ++pi) live[pi] = pi;
+        int nwg = 0;
+        const int2* dwgm = wgmap(live, nwg);
         int tok = prof::begin(0, h.st);
         launch_id_init(dq, np, wg, maxd, h.st);
         std::vector<int> st(4 * cand.size());
         for (int t = 0; t <= tmax; ++t) {
-          launch_id_step(dq, dwgm, wg, t, maxd, h.st);
+          launch_id_step(dq, dwgm, nwg, t, maxd, h.st);
           if ((t & 63) == 63 && t < tmax) {  // stop early once every problem has its rank
             HIP_CHECK(hipMemcpyAsync(st.data(), sbuf, st.size() * sizeof(int), hipMemcpyDeviceToHost, h.st));
             HIP_CHECK(hipStreamSynchronize(h.st));
             h.stager.sync();
-            bool all = true;
-            for (size_t i = 0; i < cand.size(); ++i) all = all && st[4 * i] && st[4 * i + 2];
-            if (all) break;
+            std::vector<int> nl;
+            for (int pi : live)
+              if (!st[2 * pi]) nl.push_back(pi);
+            if (nl.empty()) break;
+            if (nl.size() < live.size()) {
+              live.swap(nl);
+              dwgm = wgmap(live, nwg);
+            }
           }
         }
         launch_id_finish(dq, np, maxm, h.st);

@@ -96,48 +96,100 @@ __global__ __launch_bounds__(256) void id_init_kernel(const IDProb* __restrict__
   write_partial(q, b, 0, red, redi);
 }
 
-// NR: entries of a column each lane keeps in registers between the dot
-// product and the update (columns up to 64 NR rows; longer columns are read
-// twice)
+// H = I - tau v v^T applied to one candidate column (rows t.. in rc, the
+// first NR * 64 of them, the rest streamed from col); writes the column back
+// and the 2-norm of its rows t+1.. to *norm
 template <int NR>
-__global__ __launch_bounds__(256) void id_step_kernel(const IDProb* __restrict__ probs, const int* __restrict__ wgmap,
-                                                      int t) {
-  extern __shared__ double x[];           // pivot column, rows t..d-1
-  __shared__ double red[256];
-  __shared__ int redi[256];
-  __shared__ double nloc[kIDCols];
-  __shared__ double bc[1];
-  const IDProb& q = probs[wgmap[blockIdx.x]];
-  const int b = blockIdx.x - q.wg0;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (q.state[0]) return;
-  const int m = q.m, d = q.d;
-  const int kmax = min(m, d);
-  // pivot from the partial maxima of step t-1 (parallel reduction)
-  {
-    const double* sl = q.slots + (size_t)(t & 1) * q.P * 2;
-    double v = -1.0;
-    int c = 0x7fffffff;
-    for (int w = tid; w < q.P; w += 256) {
-      double vw = sl[2 * w];
-      int cw = (int)sl[2 * w + 1];
-      if (vw > v || (vw == v && cw < c)) { v = vw; c = cw; }
-    }
-    red[tid] = v;
-    redi[tid] = c;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-      if (tid < off) {
-        double o = red[tid + off];
-        int oi = redi[tid + off];
-        if (o > red[tid] || (o == red[tid] && oi < redi[tid])) { red[tid] = o; redi[tid] = oi; }
-      }
-      __syncthreads();
+__device__ __forceinline__ void reflect(double (&rc)[NR], double* __restrict__ col, const double* __restrict__ x,
+                                        double v0, double tau, int len, int lane, double* norm) {
+  double dot = 0.0;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int i = lane + 64 * r;
+    if (i < len) dot += ((i == 0) ? v0 : x[i]) * rc[r];
+  }
+  for (int i = lane + 64 * NR; i < len; i += 64) dot += x[i] * col[i];
+  dot = wsum(dot) * tau;
+  double ss = 0.0;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int i = lane + 64 * r;
+    if (i < len) {
+      const double y = rc[r] - dot * ((i == 0) ? v0 : x[i]);
+      col[i] = y;
+      if (i > 0) ss += y * y;
     }
   }
-  const double best = red[0];
-  const int p = redi[0];
-  const double first = (t == 0) ? best : q.first[0];
+  for (int i = lane + 64 * NR; i < len; i += 64) {
+    const double y = col[i] - dot * x[i];
+    col[i] = y;
+    ss += y * y;
+  }
+  ss = wsum(ss);
+  if (lane == 0) *norm = sqrt(ss);   // exact recomputation, no downdating
+}
+
+// One pivot step.  Each of the four wavefronts owns two of the workgroup's
+// candidates and keeps rows t.. of both in registers (NR entries per lane;
+// rows beyond 64 NR are streamed).  Every global load that does not depend
+// on the pivot (state, partial maxima, first norm, the own columns) is
+// issued at entry, so a step costs two dependent memory round trips: the
+// partial maxima, then the pivot column.
+template <int NR>
+__global__ __launch_bounds__(256) void id_step_kernel(const IDProb* __restrict__ probs, const int2* __restrict__ wgmap,
+                                                      int t) {
+  extern __shared__ double x[];           // pivot column, rows t..d-1
+  __shared__ double wred[4];
+  __shared__ int wredi[4];
+  __shared__ double nloc[kIDCols];
+  const int2 wm = wgmap[blockIdx.x];
+  const IDProb& q = probs[wm.x];
+  const int b = wm.y;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m = q.m, d = q.d;
+  const int kmax = min(m, d);
+  const int len = d - t;
+  const int j0 = b * kIDCols;
+  const int ja = j0 + wave, jb = j0 + wave + 4;
+  // independent loads first
+  const int done = q.state[0];
+  double first = (t == 0) ? 0.0 : q.first[0];
+  double sv = -1.0;
+  int sc = 0x7fffffff;
+  if (wave == 0) {
+    const double* sl = q.slots + (size_t)(t & 1) * q.P * 2;
+    for (int w = lane; w < q.P; w += 64) {
+      const double vw = sl[2 * w];
+      const int cw = (int)sl[2 * w + 1];
+      if (vw > sv || (vw == sv && cw < sc)) { sv = vw; sc = cw; }
+    }
+  }
+  double ra[NR], rb[NR];
+  const bool hasa = ja < m, hasb = jb < m;
+  const double* ca = q.W + (int64_t)ja * d + t;
+  const double* cb = q.W + (int64_t)jb * d + t;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int i = lane + 64 * r;
+    ra[r] = (hasa && i < len) ? ca[i] : 0.0;
+    rb[r] = (hasb && i < len) ? cb[i] : 0.0;
+  }
+  const bool acta = hasa && q.active[ja];
+  const bool actb = hasb && q.active[jb];
+  if (done) return;
+  // pivot: largest partial maximum, ties to the lowest candidate index
+  if (wave == 0) {
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(sv, off);
+      const int oi = __shfl_xor(sc, off);
+      if (o > sv || (o == sv && oi < sc)) { sv = o; sc = oi; }
+    }
+    if (lane == 0) { wred[0] = sv; wredi[0] = sc; }
+  }
+  __syncthreads();
+  const double best = wred[0];
+  const int p = wredi[0];
+  if (t == 0) first = best;
   const bool stop = (t >= kmax) || (t == 0 ? best <= 0.0 : best <= q.eps * first);
   if (stop) {
     if (b == 0 && tid == 0) {
@@ -146,75 +198,40 @@ __global__ __launch_bounds__(256) void id_step_kernel(const IDProb* __restrict__
     }
     return;
   }
-  const double* colp = q.W + (int64_t)p * d;
-  const double x0 = colp[t];
-  const double alpha = (x0 >= 0.0) ? -best : best;
-  if (b == 0 && tid == 0) {
-    if (t == 0) q.first[0] = best;
-    int qpos = q.ipos[p];
-    int ct = q.perm[t];
-    q.perm[t] = p;
-    q.perm[qpos] = ct;
-    q.ipos[p] = t;
-    q.ipos[ct] = qpos;
-  }
-  if (tid == 0 && p / kIDCols == b) {
-    q.active[p] = 0;
-    q.alpha[t] = alpha;
-  }
-  const int len = d - t;
-  for (int i = tid; i < len; i += 256) x[i] = colp[t + i];
+  const double* colp = q.W + (int64_t)p * d + t;
+  for (int i = tid; i < len; i += 256) x[i] = colp[i];
   if (tid < kIDCols) nloc[tid] = -1.0;
   __syncthreads();
+  const double x0 = x[0];
+  const double alpha = (x0 >= 0.0) ? -best : best;
+  const double v0 = x0 - alpha;
+  const double vtv = v0 * v0 + (best * best - x0 * x0);
+  const double tau = (vtv > 0.0 && best > 0.0) ? 2.0 / vtv : 0.0;
   if (tid == 0) {
-    double v0 = x0 - alpha;
-    double vtv = v0 * v0 + (best * best - x0 * x0);
-    bc[0] = (vtv > 0.0 && best > 0.0) ? 2.0 / vtv : 0.0;
-    x[0] = v0;
+    if (b == 0) {
+      if (t == 0) q.first[0] = best;
+      const int qpos = q.ipos[p];
+      const int ct = q.perm[t];
+      q.perm[t] = p;
+      q.perm[qpos] = ct;
+      q.ipos[p] = t;
+      q.ipos[ct] = qpos;
+    }
+    if (p / kIDCols == b) {
+      q.active[p] = 0;
+      q.alpha[t] = alpha;
+    }
   }
-  __syncthreads();
-  const double tau = bc[0];
-  const int j0 = b * kIDCols;
-  for (int jj = wave; jj < kIDCols; jj += 4) {
-    const int j = j0 + jj;
-    if (j >= m || j == p || !q.active[j]) continue;
-    double* col = q.W + (int64_t)j * d + t;
-    double rc[NR];
-    double dot = 0.0;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const int i = lane + 64 * r;
-      rc[r] = (i < len) ? col[i] : 0.0;
-      if (i < len) dot += x[i] * rc[r];
-    }
-    for (int i = lane + 64 * NR; i < len; i += 64) dot += x[i] * col[i];
-    dot = wsum(dot) * tau;
-    double ss = 0.0;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const int i = lane + 64 * r;
-      if (i < len) {
-        const double y = rc[r] - dot * x[i];
-        col[i] = y;
-        if (i > 0) ss += y * y;
-      }
-    }
-    for (int i = lane + 64 * NR; i < len; i += 64) {
-      const double y = col[i] - dot * x[i];
-      col[i] = y;
-      ss += y * y;
-    }
-    ss = wsum(ss);
-    if (lane == 0) nloc[jj] = sqrt(ss);   // exact recomputation, no downdating
-  }
+  // apply the reflector (v = x with v[0] = v0) to the own active candidates
+  if (acta && ja != p) reflect<NR>(ra, q.W + (int64_t)ja * d + t, x, v0, tau, len, lane, &nloc[wave]);
+  if (actb && jb != p) reflect<NR>(rb, q.W + (int64_t)jb * d + t, x, v0, tau, len, lane, &nloc[wave + 4]);
   __syncthreads();
   // partial maximum over this workgroup's candidates for step t+1
   if (tid == 0) {
     double bv = -1.0;
     int bi = 0x7fffffff;
     for (int jj = 0; jj < kIDCols; ++jj) {
-      const int j = j0 + jj;
-      if (j < m && j != p && q.active[j] && nloc[jj] > bv) { bv = nloc[jj]; bi = j; }
+      if (nloc[jj] > bv) { bv = nloc[jj]; bi = j0 + jj; }
     }
     double* sl = q.slots + ((size_t)((t + 1) & 1) * q.P + b) * 2;
     sl[0] = bv;
@@ -257,7 +274,7 @@ void launch_id_init(const IDProb* p, int np, int total_wg, int max_d, hipStream_
   HIP_CHECK(hipGetLastError());
 }
 
-void launch_id_step(const IDProb* p, const int* wgmap, int total_wg, int t, int max_d, hipStream_t s) {
+void launch_id_step(const IDProb* p, const int2* wgmap, int total_wg, int t, int max_d, hipStream_t s) {
   if (total_wg <= 0) return;
   size_t lds = (size_t)std::max(max_d, 1) * sizeof(double);
   REQUIRE(lds <= 48 * 1024, HSSMF_ERANK, "interpolative decomposition: more than 6144 samples");

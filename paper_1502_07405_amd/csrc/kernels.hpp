@@ -173,7 +173,8 @@ struct IDProb {
 constexpr int kIDCols = 8;
 
 void launch_id_init(const IDProb* p, int np, int total_wg, int max_d, hipStream_t s);
-void launch_id_step(const IDProb* p, const int* wgmap, int total_wg, int t, int max_d, hipStream_t s);
+// wgmap[w] = (problem, workgroup within the problem) of grid workgroup w
+void launch_id_step(const IDProb* p, const int2* wgmap, int total_wg, int t, int max_d, hipStream_t s);
 void launch_id_finish(const IDProb* p, int np, int max_m, hipStream_t s);
 
 }  // namespace hssmf
