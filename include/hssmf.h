@@ -7,7 +7,7 @@
  * randomized sampling" (arXiv 1502.07405).  The solver computes an (exact or
  * HSS-approximate) multifrontal LU factorization of a general sparse
  * non-singular matrix (Sec. 3, Sec. 4) and uses it inside iterative
- * refinement or restarted GMRES (Sec. 4.5, Sec. 6.1) to solve A x = b.
+ * refinement or restarted GMRES (Sec. 4.6, Sec. 6.1) to solve A x = b.
  *
  * Conventions
  *  - Every function returns HSSMF_OK (0) or a negative status code; no C++
@@ -77,7 +77,7 @@ typedef struct {
 /* Options.  Use hssmf_default_opts() and override fields. */
 typedef struct {
   double rel_tol;      /* HSS compression tolerance eps: rank stops at
-                          |R_{i+1,i+1}| <= eps |R_11| (Sec. 5.4) */
+                          |R_{i+1,i+1}| <= eps |R_11| (Sec. 5.3) */
   int32_t leaf_size;   /* max HSS leaf size (Sec. 4.2, b) */
   int32_t min_sep_hss; /* a front is HSS iff its separator has at least this
                           many indices; large value = pure multifrontal */
@@ -129,7 +129,7 @@ int hssmf_refactor(void* h, const double* val);
  * device arrays of n doubles (may alias). */
 int hssmf_apply(void* h, int32_t trans, const double* x, double* y);
 
-/* Solve A x = b with the outer solver of the options (Sec. 4.5): b, x are
+/* Solve A x = b with the outer solver of the options (Sec. 4.6): b, x are
  * device arrays of n doubles.  ENOCONV still writes the best x and fills
  * info. */
 int hssmf_solve(void* h, const double* b, double* x, hssmf_info* info);
@@ -153,15 +153,17 @@ int hssmf_hss_ranks(void* h, int32_t* out, int32_t cap);
 
 int hssmf_last_failed_front(void* h);
 
-/* Kernel timing hooks (diagnostics for benchmarks).  While enabled, the
- * library records a HIP event pair on the launch stream around every launch
- * of the listed kernel classes and accumulates the launches' algorithmic
- * work computed on the host.  hssmf_profile_read() waits for the recorded
+/* Kernel timing hooks (diagnostics for benchmarks).  While enabled, every
+ * launch of the listed kernel classes is made with hipExtLaunchKernelGGL and
+ * an event pair that the launch stamps with that kernel's own start and end,
+ * and the launches' algorithmic work, computed on the host, is accumulated.  hssmf_profile_read() waits for the recorded
  * events and returns, for one class, the summed kernel time (ms), the number
  * of launches and the summed work (flops).  Reading resets the class.
- * Classes: 0 = pivoted QR of the interpolative decompositions,
- * 1 = FP64 batched GEMM (matrix cores), 2 = low-precision batched GEMM,
- * 3 = blocked LU panel. */
+ * Classes: 0 = pivot steps of the column-pivoted QR behind the
+ * interpolative decompositions (one launch per step, work 4dmk - 2k^2(d+m)
+ * + 4/3 k^3 per d x m problem truncated at k), 1 = FP64 batched GEMM
+ * (matrix cores, 2mnk), 2 = low-precision batched GEMM (2mnk), 3 = panel
+ * factorization of the blocked dense LU (m w^2 - w^3/3 per m x w panel). */
 #define HSSMF_KCLASS_ID 0
 #define HSSMF_KCLASS_GEMM64 1
 #define HSSMF_KCLASS_GEMMLP 2

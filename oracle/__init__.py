@@ -15,7 +15,7 @@ dense      dense fronts: extend-add and partial LU (Sec. 3)
 hss        ID, randomized HSS compression (Alg. 1), HSS matvec / extraction,
            ULV-like factorization and solves (Sec. 2)
 mf         multifrontal factorization with dense and HSS fronts (Sec. 3, 4)
-krylov     iterative refinement and GMRES(30) (Sec. 4.5, Sec. 6.1)
+krylov     iterative refinement and GMRES(30) (Sec. 4.6, Sec. 6.1)
 adjoint    transpose solve based gradients
 
 Parity pins live in ``tests/test_oracle_*.py``.  Functions without a pin say

@@ -22,7 +22,7 @@ class RankError(RuntimeError):
 
 
 # ---------------------------------------------------------------------------
-# interpolative decomposition (Sec. 2.2, Eq. for ID; stopping rule Sec. 5.4)
+# interpolative decomposition (Sec. 2.2, Eq. for ID; stopping rule Sec. 5.3)
 # ---------------------------------------------------------------------------
 
 def cpqr_eps(Y, eps):
@@ -31,7 +31,7 @@ def cpqr_eps(Y, eps):
     part has the largest 2-norm, recomputed from the updated column (ties go
     to the lowest index).  The factorization stops before step i+1 when that
     norm is <= eps times the first pivot's norm, i.e. |R_{i+1,i+1}| <= eps
-    |R_11| (the modified geqp3 of Sec. 5.4).  A zero matrix has rank 0.
+    |R_11| (the modified geqp3 of Sec. 5.3).  A zero matrix has rank 0.
 
     Returns (perm, R, k): Y[:, perm] = Q R with R (min(d,m) x m) upper
     trapezoidal in its first k rows; only R[:k] is meaningful."""

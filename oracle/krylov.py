@@ -2,7 +2,7 @@
 
 The paper uses the (approximate) multifrontal factorization as a
 preconditioner for restarted GMRES(30) with modified Gram-Schmidt and a zero
-initial guess, and iterative refinement when no HSS is used (Sec. 4.5,
+initial guess, and iterative refinement when no HSS is used (Sec. 4.6,
 Sec. 6.1).  Reading of the stopping rule: stop on the true relative residual
 ||b - A x||_2 / ||b||_2 <= tol (the paper tests the preconditioned residual);
 GMRES checks it whenever its preconditioned estimate has dropped by tol and

@@ -78,7 +78,7 @@ class HSSUpdate:
 class FrontOp:
     """The frontal matrix F_i = A_i (+) U_nu1 (+) U_nu2 (Eq. frontal_1), known
     only through products with random blocks (Eq. FtimesR: A_i R plus the
-    row-extended children's products) and entry extraction (Sec. 4.3)."""
+    row-extended children's products, Sec. 4.3) and entry extraction (Sec. 4.5)."""
 
     def __init__(self, Ap, front, fronts, updates):
         idx = front.idx

@@ -2,7 +2,7 @@
 
 The paper fills R element by element with a pseudo-random engine seeded per
 row by the global row index, so that the R of two sibling fronts agree on
-shared rows and a parent can reuse them (Sec. 2.2.2, Sec. 4.3, Eq. Rmerge).
+shared rows and a parent can reuse them (Sec. 2.2.3, Sec. 4.3, Eq. Rmerge).
 Here that property is obtained with a counter-based generator: entry (row, c)
 is a pure function of (seed, original row id, column c), so every front that
 contains a row sees the same value and the extend-merge of Eq. Rmerge holds

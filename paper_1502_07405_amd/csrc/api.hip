@@ -1,7 +1,7 @@
 // C ABI (include/hssmf.h): setup of a factorization (plan, uploads, maps,
 // HSS trees), numeric refactorization, preconditioner application, the
 // outer solvers (iterative refinement, restarted GMRES with modified
-// Gram-Schmidt, Sec. 4.5 / Sec. 6.1), transpose solve and adjoint.
+// Gram-Schmidt, Sec. 4.6 / Sec. 6.1), transpose solve and adjoint.
 #include <algorithm>
 #include <chrono>
 #include <climits>

@@ -1,6 +1,7 @@
 // Shared host/device definitions of the HIP library: status handling,
 // device memory arena, launch descriptors.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -126,10 +127,10 @@ class Stager {
 // kernel timing hooks (see hssmf_profile_enable)
 namespace prof {
 bool enabled();
-// returns a token for end(); -1 when profiling is off
-int begin(int kclass, hipStream_t s);
-void end(int token, hipStream_t s, double flops);
 void add_flops(int kclass, double flops);
+// one timed kernel: events for hipExtLaunchKernelGGL, which stamps them with
+// that kernel's own start and end (nullptr events and -1 when off)
+int ext(int kclass, double flops, hipEvent_t* start, hipEvent_t* stop);
 }  // namespace prof
 
 }  // namespace hssmf

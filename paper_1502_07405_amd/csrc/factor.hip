@@ -88,7 +88,14 @@ void blocked_lu(Handle& h, const std::vector<LUFront>& fronts) {
   for (auto& f : fronts) { maxs = std::max(maxs, f.s); maxn = std::max(maxn, f.n); }
   const int nf = (int)fronts.size();
   for (int jb = 0; jb < maxs; jb += NB) {
-    launch_lu_panel(d, nf, jb, NB, h.d_info, h.st);
+    double pfl = 0.0;   // panel flops: w columns of height m = n - jb, m w^2 - w^3 / 3
+    if (prof::enabled())
+      for (auto& f : fronts)
+        if (jb < f.s) {
+          const double w = std::min(NB, f.s - jb), m = f.n - jb;
+          pfl += m * w * w - w * w * w / 3.0;
+        }
+    launch_lu_panel(d, nf, jb, NB, h.d_info, h.st, pfl);
     launch_laswp(d, nf, jb, NB, maxn, h.st);
     launch_trsm_u12(d, nf, jb, NB, maxn, h.st);
     std::vector<GemmDesc> g;
@@ -500,7 +507,6 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
         for (int pi = 0; pi < np; ++pi) live[pi] = pi;
         int nwg = 0;
         const int2* dwgm = wgmap(live, nwg);
-        int tok = prof::begin(0, h.st);
         launch_id_init(dq, np, wg, maxd, h.st);
         std::vector<int> st(4 * cand.size());
         for (int t = 0; t <= tmax; ++t) {
@@ -520,7 +526,6 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
           }
         }
         launch_id_finish(dq, np, maxm, h.st);
-        prof::end(tok, h.st, 0.0);
       }
       std::vector<int> sh(4 * cand.size());
       if (!sh.empty())
@@ -531,15 +536,15 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
       HIP_CHECK(hipStreamSynchronize(h.st));
       h.stager.sync();
       if (prof::enabled()) {
-        // algorithmic flops of the IDs: Householder steps 4dmk - 2k^2(d+m)
-        // + 4/3 k^3 and the triangular solve k^2 (m - k), per side
+        // algorithmic flops of the pivot steps: Householder QR of the d x m
+        // matrix truncated at k columns, 4dmk - 2k^2(d+m) + 4/3 k^3 per side
         double fl = 0.0;
         for (size_t i = 0; i < cand.size(); ++i) {
           const double d = cand[i].F->d;
           const int ms[2] = {cand[i].n().mr, cand[i].n().mc};
           for (int sd = 0; sd < 2; ++sd) {
             double k = sh[4 * i + 1 + 2 * sd], m = ms[sd];
-            fl += 4.0 * d * m * k - 2.0 * k * k * (d + m) + 4.0 / 3.0 * k * k * k + k * k * (m - k);
+            fl += 4.0 * d * m * k - 2.0 * k * k * (d + m) + 4.0 / 3.0 * k * k * k;
           }
         }
         prof::add_flops(0, fl);

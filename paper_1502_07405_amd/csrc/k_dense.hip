@@ -117,10 +117,12 @@ __global__ __launch_bounds__(256) void lu_panel_kernel(const LUFront* __restrict
   }
 }
 
-void launch_lu_panel(const LUFront* fr, int nf, int jb, int nb, int* info, hipStream_t s) {
+void launch_lu_panel(const LUFront* fr, int nf, int jb, int nb, int* info, hipStream_t s, double flops) {
   if (nf <= 0) return;
   REQUIRE(nb <= 64, HSSMF_EINVAL, "panel width");
-  hipLaunchKernelGGL(lu_panel_kernel, dim3(nf), dim3(256), 0, s, fr, jb, nb, info);
+  hipEvent_t e0, e1;
+  prof::ext(3, flops, &e0, &e1);   // timing hook (no-op when off)
+  hipExtLaunchKernelGGL(lu_panel_kernel, dim3(nf), dim3(256), 0, s, e0, e1, 0, fr, jb, nb, info);
   HIP_CHECK(hipGetLastError());
 }
 

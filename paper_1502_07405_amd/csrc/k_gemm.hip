@@ -213,16 +213,25 @@ namespace {
 // element size of the A / B operands of a GEMM type
 size_t in_bytes(GemmType t) { return t == GEMM_F64 ? 8 : (t == GEMM_F32 || t == GEMM_F32_D) ? 4 : 2; }
 
-void launch_tiles(const std::vector<GemmDesc>& d, int64_t tiles, GemmType type, Stager& st, hipStream_t s) {
+void launch_tiles(const std::vector<GemmDesc>& d, int64_t tiles, GemmType type, Stager& st, hipStream_t s,
+                  double flops) {
   GemmDesc* dd = st.put_vec(d, s);
   dim3 grid((unsigned)tiles), blk(256);
   const int n = (int)d.size();
+  hipEvent_t e0, e1;
+  prof::ext(type == GEMM_F64 ? 1 : 2, flops, &e0, &e1);   // timing hook (no-op when off)
   switch (type) {
-    case GEMM_F64: hipLaunchKernelGGL(gemm_f64_kernel, grid, blk, 0, s, dd, n); break;
-    case GEMM_F32: hipLaunchKernelGGL((gemm_lp_kernel<float, float>), grid, blk, 0, s, dd, n); break;
-    case GEMM_F32_D: hipLaunchKernelGGL((gemm_lp_kernel<float, double>), grid, blk, 0, s, dd, n); break;
-    case GEMM_BF16: hipLaunchKernelGGL((gemm_lp_kernel<__bf16, float>), grid, blk, 0, s, dd, n); break;
-    case GEMM_BF16_D: hipLaunchKernelGGL((gemm_lp_kernel<__bf16, double>), grid, blk, 0, s, dd, n); break;
+    case GEMM_F64: hipExtLaunchKernelGGL(gemm_f64_kernel, grid, blk, 0, s, e0, e1, 0, dd, n); break;
+    case GEMM_F32: hipExtLaunchKernelGGL((gemm_lp_kernel<float, float>), grid, blk, 0, s, e0, e1, 0, dd, n); break;
+    case GEMM_F32_D:
+      hipExtLaunchKernelGGL((gemm_lp_kernel<float, double>), grid, blk, 0, s, e0, e1, 0, dd, n);
+      break;
+    case GEMM_BF16:
+      hipExtLaunchKernelGGL((gemm_lp_kernel<__bf16, float>), grid, blk, 0, s, e0, e1, 0, dd, n);
+      break;
+    case GEMM_BF16_D:
+      hipExtLaunchKernelGGL((gemm_lp_kernel<__bf16, double>), grid, blk, 0, s, e0, e1, 0, dd, n);
+      break;
   }
   HIP_CHECK(hipGetLastError());
 }
@@ -248,7 +257,6 @@ void gemm_batched(const std::vector<GemmDesc>& in, GemmType type, Stager& st, hi
   }
   if (d.empty()) return;
   REQUIRE(tiles < (1LL << 31), HSSMF_EINVAL, "gemm batch too large");
-  int tok = prof::begin(type == GEMM_F64 ? 1 : 2, s);
   // split-K when the batch has too few output tiles to fill the chip and
   // the reductions are long: partial products into the workspace, then a
   // fixed-order reduction (the result is bitwise reproducible)
@@ -293,7 +301,7 @@ void gemm_batched(const std::vector<GemmDesc>& in, GemmType type, Stager& st, hi
     GemmType pt = type;
     if (type == GEMM_F32) pt = GEMM_F32_D;
     if (type == GEMM_BF16) pt = GEMM_BF16_D;
-    launch_tiles(parts, ptiles, pt, st, s);
+    launch_tiles(parts, ptiles, pt, st, s, flops);
     int64_t mx = 0;
     for (auto& r : red) mx = std::max<int64_t>(mx, (int64_t)r.m * r.n);
     int64_t bx = std::min<int64_t>((mx + 255) / 256, 2048);
@@ -306,9 +314,8 @@ void gemm_batched(const std::vector<GemmDesc>& in, GemmType type, Stager& st, hi
   } else {
     int64_t t = 0;
     for (auto& g : d) { g.tile_base = t; t += (int64_t)g.tiles_m * g.tiles_n; }
-    launch_tiles(d, tiles, type, st, s);
+    launch_tiles(d, tiles, type, st, s, flops);
   }
-  prof::end(tok, s, flops);
 }
 
 }  // namespace hssmf

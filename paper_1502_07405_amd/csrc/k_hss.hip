@@ -138,7 +138,7 @@ void launch_round_lp(double* x, void* lp, int64_t n, int to_bf16, hipStream_t s)
 
 // ---------------------------------------------------------- extraction ---
 // F_i(I, J) = A_i(I, J) + sum over children of U_child(inv(I), inv(J))
-// (the element access that Alg. 1 needs for D and B, Sec. 4.3)
+// (the element access that Alg. 1 needs for D and B, Sec. 4.5)
 __global__ void extract_kernel(const ExtractDesc* __restrict__ descs, const FrontOpDev* __restrict__ fops) {
   const ExtractDesc d = descs[blockIdx.y];
   const FrontOpDev& f = fops[d.fop];

@@ -60,7 +60,7 @@ void launch_fill(double* p, int64_t n, double v, hipStream_t s);
 void launch_assemble(double* base, const int64_t* dst, const int64_t* src, const double* val,
                      int64_t count, hipStream_t s);
 void launch_extend_add(const EADesc* d, int nd, int max_u, hipStream_t s);
-void launch_lu_panel(const LUFront* fr, int nf, int jb, int nb, int* info, hipStream_t s);
+void launch_lu_panel(const LUFront* fr, int nf, int jb, int nb, int* info, hipStream_t s, double flops = 0.0);
 void launch_laswp(const LUFront* fr, int nf, int jb, int nb, int max_n, hipStream_t s);
 void launch_trsm_u12(const LUFront* fr, int nf, int jb, int nb, int max_n, hipStream_t s);
 void launch_gemv(const GemvDesc* d, int nd, int max_rows, hipStream_t s);

@@ -1,4 +1,5 @@
-// Kernel timing hooks: HIP event pairs around selected launches.
+// Kernel timing hooks: event pairs stamped by hipExtLaunchKernelGGL with the
+// start and end of selected kernels.
 #include <mutex>
 #include <vector>
 
@@ -33,20 +34,15 @@ hipEvent_t get_event() {
 
 bool enabled() { return on; }
 
-int begin(int kclass, hipStream_t s) {
+int ext(int kclass, double flops, hipEvent_t* start, hipEvent_t* stop) {
+  *start = *stop = nullptr;
   if (!on) return -1;
   std::lock_guard<std::mutex> g(mu);
-  Rec r{kclass, get_event(), get_event(), 0.0};
-  HIP_CHECK(hipEventRecord(r.a, s));
+  Rec r{kclass, get_event(), get_event(), flops};
+  *start = r.a;
+  *stop = r.b;
   recs.push_back(r);
   return (int)recs.size() - 1;
-}
-
-void end(int token, hipStream_t s, double flops) {
-  if (token < 0) return;
-  std::lock_guard<std::mutex> g(mu);
-  HIP_CHECK(hipEventRecord(recs[token].b, s));
-  recs[token].flops = flops;
 }
 
 void add_flops(int kclass, double flops) {

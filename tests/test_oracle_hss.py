@@ -112,7 +112,7 @@ def test_cpqr_matches_library_on_well_separated_columns(rng):
 
 @pytest.mark.parametrize("eps", [1e-2, 1e-5, 1e-9])
 def test_epsilon_rank_rule(rng, eps):
-    """Rank stops at the first i with |R_{i+1,i+1}| / |R_11| <= eps (Sec. 5.4);
+    """Rank stops at the first i with |R_{i+1,i+1}| / |R_11| <= eps (Sec. 5.3);
     with prescribed, well separated singular values the ranks are known."""
     n = 60
     sv = 10.0 ** -np.arange(0, 12, 1.0)
