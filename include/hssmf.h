@@ -92,7 +92,17 @@ typedef struct {
   int32_t restart;     /* GMRES restart length (30 in Sec. 6.1) */
   double tol;          /* stop when ||b - A x||_2 / ||b||_2 <= tol */
   int32_t max_it;      /* max refinement steps / GMRES iterations */
+  int32_t id_kernel;   /* HSSMF_ID_*: how the pivoted QR of the IDs runs */
 } hssmf_opts;
+
+/* id_kernel: STEPWISE (default) = one launch per pivot step for each batch
+ * of IDs; COOPERATIVE = when every workgroup of a batch fits on the device
+ * at once, one cooperative launch that keeps the candidates in registers and
+ * passes the partial maxima and the pivot column between workgroups through
+ * agent-coherent memory (one launch per step otherwise).  Both take the
+ * same pivot rule; they differ only in the order of floating-point sums. */
+#define HSSMF_ID_STEPWISE 0
+#define HSSMF_ID_COOPERATIVE 1
 
 typedef struct {
   int32_t iterations;    /* refinement steps or GMRES iterations */

@@ -377,7 +377,7 @@ int hssmf_factor(const hssmf_csr* A, const hssmf_ordering* ord, const hssmf_opts
   *out = nullptr;
   if (opts->leaf_size < 1 || opts->d0 < 1 || opts->dd < 1 || opts->p < 0 || opts->d_max < opts->d0 ||
       !(opts->rel_tol >= 0.0) || opts->restart < 1 || opts->max_it < 0 || opts->gemm_prec < 0 ||
-      opts->gemm_prec > 2)
+      opts->gemm_prec > 2 || opts->id_kernel < 0 || opts->id_kernel > 1)
     return HSSMF_EINVAL;
   Handle* h = new (std::nothrow) Handle();
   if (!h) return HSSMF_ENOMEM;

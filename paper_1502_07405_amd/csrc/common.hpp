@@ -128,6 +128,10 @@ class Stager {
 namespace prof {
 bool enabled();
 void add_flops(int kclass, double flops);
+// event pair recorded around a launch on stream s (for launches that cannot
+// take hipExtLaunchKernelGGL events); returns a token for end(), -1 when off
+int begin(int kclass, hipStream_t s);
+void end(int token, hipStream_t s);
 // one timed kernel: events for hipExtLaunchKernelGGL, which stamps them with
 // that kernel's own start and end (nullptr events and -1 when off)
 int ext(int kclass, double flops, hipEvent_t* start, hipEvent_t* stop);

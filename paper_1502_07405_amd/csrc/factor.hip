@@ -491,9 +491,37 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
           tmax = std::max(tmax, mn);
         }
       }
+      int* derr = nullptr;
       if (!q.empty()) {
-        IDProb* dq = upload(h, q);
         const int np = (int)q.size();
+        int maxp = 0;
+        for (auto& pr : q) maxp = std::max(maxp, pr.P);
+        const int cap = o.id_kernel == HSSMF_ID_COOPERATIVE ? id_coop_capacity(maxd) : 0;
+        if (cap > 0 && wg <= cap) {
+          // every problem of the pass resident at once: one cooperative launch
+          derr = sialloc(h, 1);
+          double* slots = salloc(h, 8 * (int64_t)wg);   // per problem 2 x P x (norm, index, step tag, pad)
+          for (int pi = 0; pi < np; ++pi) {
+            q[pi].cand = salloc(h, 2 * (int64_t)q[pi].P * q[pi].d);
+            q[pi].slots = slots + 8 * (int64_t)q[pi].wg0;
+          }
+          IDProb* dq = upload(h, q);
+          launch_fill(slots, 8 * (int64_t)wg, -1.0, h.st);   // step tags start at -1
+          HIP_CHECK(hipMemsetAsync(derr, 0, sizeof(int), h.st));
+          std::vector<int2> wgm;
+          auto flush = [&]() {
+            if (wgm.empty()) return;
+            launch_id_coop(dq, upload(h, wgm), (int)wgm.size(), maxd, derr, h.st);
+            wgm.clear();
+          };
+          for (int pi = 0; pi < np; ++pi) {
+            if ((int)wgm.size() + q[pi].P > cap) flush();
+            for (int w = 0; w < q[pi].P; ++w) wgm.push_back(make_int2(pi, w));
+          }
+          flush();
+          launch_id_finish(dq, np, maxm, h.st);
+        } else {
+        IDProb* dq = upload(h, q);
         // grid of the live problems' workgroups: rebuilt at every check so
         // that finished problems stop taking workgroups
         auto wgmap = [&](const std::vector<int>& live, int& nwg) {
@@ -526,7 +554,10 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
           }
         }
         launch_id_finish(dq, np, maxm, h.st);
+        }
       }
+      int herr = 0;
+      if (derr) HIP_CHECK(hipMemcpyAsync(&herr, derr, sizeof(int), hipMemcpyDeviceToHost, h.st));
       std::vector<int> sh(4 * cand.size());
       if (!sh.empty())
         HIP_CHECK(hipMemcpyAsync(sh.data(), sbuf, sh.size() * sizeof(int), hipMemcpyDeviceToHost, h.st));
@@ -535,6 +566,7 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
         HIP_CHECK(hipMemcpyAsync(hbuf.data(), ibuf, hbuf.size() * sizeof(int), hipMemcpyDeviceToHost, h.st));
       HIP_CHECK(hipStreamSynchronize(h.st));
       h.stager.sync();
+      REQUIRE(herr == 0, HSSMF_EDEVICE, "interpolative decomposition: a workgroup barrier timed out");
       if (prof::enabled()) {
         // algorithmic flops of the pivot steps: Householder QR of the d x m
         // matrix truncated at k columns, 4dmk - 2k^2(d+m) + 4/3 k^3 per side

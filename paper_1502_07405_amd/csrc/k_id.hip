@@ -239,6 +239,267 @@ __global__ __launch_bounds__(256) void id_step_kernel(const IDProb* __restrict__
   }
 }
 
+// ---------------------------------------------------------------------------
+// Cooperative variant.  The whole grid is resident (cooperative launch), so
+// the workgroups of one problem can wait for each other: each keeps its
+// eight candidates in registers for the whole factorization (rows by
+// absolute index, row = lane + 64 r), publishes only its best remaining
+// candidate column and partial maximum per step (double-buffered by step
+// parity), and waits for the step tags of the problem's other workgroups.
+// A wait is bounded: after kSpinLimit polls it sets *err and the problem's
+// workgroups leave, so the launch always ends.  Workgroup 0 of a
+// problem alone keeps the pivot order (perm / ipos).
+namespace {
+constexpr unsigned kSpinLimit = 1u << 22;
+
+// Only the partial maxima and the published candidate columns cross
+// workgroups inside the launch.  They are written and read with agent-scope
+// atomic accesses (coherent across the chip's L2 caches, no cache-wide
+// writeback).  A workgroup publishes its candidate column, waits for those
+// stores to complete, then writes its slot (norm, index) and last the step
+// tag; readers poll the tags.
+__device__ __forceinline__ void st_coh(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_coh(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// reflector on a register-resident column: rows t..d-1 take part, v[t] = v0
+template <int NR>
+__device__ __forceinline__ void reflect_abs(double (&rc)[NR], const double* __restrict__ x, double v0, double tau,
+                                            int t, int d, int lane, double* norm) {
+  double dot = 0.0;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int i = lane + 64 * r;
+    if (i >= t && i < d) dot += ((i == t) ? v0 : x[i]) * rc[r];
+  }
+  dot = wsum(dot) * tau;
+  double ss = 0.0;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int i = lane + 64 * r;
+    if (i >= t && i < d) {
+      rc[r] -= dot * ((i == t) ? v0 : x[i]);
+      if (i > t) ss += rc[r] * rc[r];
+    }
+  }
+  ss = wsum(ss);
+  if (lane == 0) *norm = sqrt(ss);
+}
+
+template <int NR, bool COH>
+__device__ __forceinline__ void store_col(const double (&rc)[NR], double* __restrict__ dst, int r0, int d, int lane) {
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int i = lane + 64 * r;
+    if (i >= r0 && i < d) {
+      if (COH) st_coh(dst + i, rc[r]);
+      else dst[i] = rc[r];
+    }
+  }
+}
+}  // namespace
+
+template <int NR>
+__global__ __launch_bounds__(256) void id_coop_kernel(const IDProb* __restrict__ probs,
+                                                      const int2* __restrict__ wgmap, int* err) {
+  extern __shared__ double x[];   // pivot column by absolute row
+  __shared__ double tile[kIDCols * 64];
+  __shared__ double nloc[kIDCols];
+  __shared__ double pbest;
+  __shared__ int pidx, win, flag;
+  const int2 wm = wgmap[blockIdx.x];
+  const IDProb& q = probs[wm.x];
+  const int b = wm.y;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m = q.m, d = q.d, P = q.P;
+  const int kmax = min(m, d);
+  const int j0 = b * kIDCols;
+  const int ja = j0 + wave, jb = ja + 4;
+  bool acta = ja < m, actb = jb < m;
+  // stage the eight candidates (rows j0.. of S) 64 samples at a time
+  double ra[NR], rb[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    for (int e = tid; e < kIDCols * 64; e += 256) {
+      const int jj = e & 7, kk = e >> 3;
+      const int j = j0 + jj, k = 64 * r + kk;
+      tile[jj * 64 + kk] = (j < m && k < d) ? q.S[j + (int64_t)k * q.lds] : 0.0;
+    }
+    __syncthreads();
+    ra[r] = tile[wave * 64 + lane];
+    rb[r] = tile[(wave + 4) * 64 + lane];
+    __syncthreads();
+  }
+  {
+    double sa = 0.0, sb = 0.0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) { sa += ra[r] * ra[r]; sb += rb[r] * rb[r]; }
+    sa = wsum(sa);
+    sb = wsum(sb);
+    if (lane == 0) {
+      nloc[wave] = acta ? sqrt(sa) : -1.0;
+      nloc[wave + 4] = actb ? sqrt(sb) : -1.0;
+    }
+  }
+  if (b == 0) {   // the pivot order is kept by workgroup 0 alone
+    for (int j = tid; j < m; j += 256) {
+      q.perm[j] = j;
+      q.ipos[j] = j;
+    }
+    if (tid == 0) {
+      q.state[0] = 0;
+      q.state[1] = 0;
+    }
+  }
+  double first = 0.0;
+  for (int t = 0;; ++t) {
+    // publish this workgroup's best remaining candidate for step t: the
+    // column first, then (after it has completed) the slot with its step tag
+    __syncthreads();
+    if (tid == 0) {
+      double bv = -1.0;
+      int bi = 0x7fffffff, bw = -1;
+      for (int jj = 0; jj < kIDCols; ++jj)
+        if (nloc[jj] > bv) { bv = nloc[jj]; bi = j0 + jj; bw = jj; }
+      pbest = bv;
+      pidx = bi;
+      win = bw;
+    }
+    __syncthreads();
+    if (win >= 0 && (win & 3) == wave) {
+      double* dst = q.cand + ((size_t)(t & 1) * P + b) * d;
+      if (win < 4) store_col<NR, true>(ra, dst, t, d, lane);
+      else store_col<NR, true>(rb, dst, t, d, lane);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) {
+      double* sl = q.slots + ((size_t)(t & 1) * P + b) * 4;
+      st_coh(sl, pbest);
+      st_coh(sl + 1, (double)pidx);
+      __builtin_amdgcn_s_waitcnt(0);
+      st_coh(sl + 2, (double)t);
+    }
+    // pivot: wait for every workgroup's step-t slot, then the largest
+    // partial maximum, ties to the lowest candidate index
+    if (wave == 0) {
+      const double* sl = q.slots + (size_t)(t & 1) * P * 4;
+      double sv = -1.0;
+      int sc = 0x7fffffff;
+      bool ok = true;
+      for (int w0 = 0; w0 < P; w0 += 64) {
+        const int w = w0 + lane;
+        unsigned spins = 0;
+        bool ready = w >= P;
+        while (true) {
+          if (!ready) ready = ld_coh(sl + 4 * w + 2) == (double)t;
+          if (__all(ready)) break;
+          if (++spins > kSpinLimit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            ok = false;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+        if (!ok) break;
+        if (w < P) {
+          const double vw = ld_coh(sl + 4 * w);
+          const int cw = (int)ld_coh(sl + 4 * w + 1);
+          if (vw > sv || (vw == sv && cw < sc)) { sv = vw; sc = cw; }
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(sv, off);
+        const int oi = __shfl_xor(sc, off);
+        if (o > sv || (o == sv && oi < sc)) { sv = o; sc = oi; }
+      }
+      if (lane == 0) {
+        if (!ok) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        flag = ok;
+        pbest = sv;
+        pidx = sc;
+      }
+    }
+    __syncthreads();
+    if (!flag) return;
+    const double best = pbest;
+    const int p = pidx;
+    if (t == 0) first = best;
+    const bool stop = (t >= kmax) || (t == 0 ? best <= 0.0 : best <= q.eps * first);
+    if (stop) {
+      if (b == 0 && tid == 0) {
+        q.first[0] = first;
+        q.state[1] = (t == 0 && best <= 0.0) ? 0 : t;
+        q.state[0] = 1;
+      }
+      break;
+    }
+    const double* pc = q.cand + ((size_t)(t & 1) * P + p / kIDCols) * d;
+    for (int i = t + tid; i < d; i += 256) x[i] = ld_coh(pc + i);
+    if (tid < kIDCols) nloc[tid] = -1.0;
+    __syncthreads();
+    const double x0 = x[t];
+    const double alpha = (x0 >= 0.0) ? -best : best;
+    const double v0 = x0 - alpha;
+    const double vtv = v0 * v0 + (best * best - x0 * x0);
+    const double tau = (vtv > 0.0 && best > 0.0) ? 2.0 / vtv : 0.0;
+    if (tid == 0) {
+      if (b == 0) {
+        const int qpos = q.ipos[p];
+        const int ct = q.perm[t];
+        q.perm[t] = p;
+        q.perm[qpos] = ct;
+        q.ipos[p] = t;
+        q.ipos[ct] = qpos;
+      }
+      if (p / kIDCols == b) q.alpha[t] = alpha;
+    }
+    if (p == ja) acta = false;
+    if (p == jb) actb = false;
+    if (acta) reflect_abs<NR>(ra, x, v0, tau, t, d, lane, &nloc[wave]);
+    if (actb) reflect_abs<NR>(rb, x, v0, tau, t, d, lane, &nloc[wave + 4]);
+  }
+  // the factored columns (R in rows < k) for the R1 / R2 gathers
+  if (ja < m) store_col<NR, false>(ra, q.W + (int64_t)ja * d, 0, d, lane);
+  if (jb < m) store_col<NR, false>(rb, q.W + (int64_t)jb * d, 0, d, lane);
+}
+
+namespace {
+template <int NR>
+int coop_capacity_nr(int max_d) {
+  int dev = 0, cus = 0, coop = 0, nb = 0;
+  HIP_CHECK(hipGetDevice(&dev));
+  HIP_CHECK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+  if (!coop) return 0;
+  HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, id_coop_kernel<NR>, 256,
+                                                         (size_t)std::max(max_d, 1) * sizeof(double)));
+  return nb * cus;
+}
+}  // namespace
+
+int id_coop_capacity(int max_d) {
+  if (max_d <= 64 * 4) return coop_capacity_nr<4>(max_d);
+  if (max_d <= 64 * 10) return coop_capacity_nr<10>(max_d);
+  if (max_d <= 64 * 16) return coop_capacity_nr<16>(max_d);
+  return 0;
+}
+
+void launch_id_coop(const IDProb* p, const int2* wgmap, int total_wg, int max_d, int* err, hipStream_t s) {
+  if (total_wg <= 0) return;
+  REQUIRE(max_d <= 64 * 16, HSSMF_EINVAL, "cooperative interpolative decomposition: more than 1024 samples");
+  const size_t lds = (size_t)std::max(max_d, 1) * sizeof(double);
+  void* args[] = {(void*)&p, (void*)&wgmap, (void*)&err};
+  const void* fn = max_d <= 64 * 4    ? (const void*)id_coop_kernel<4>
+                   : max_d <= 64 * 10 ? (const void*)id_coop_kernel<10>
+                                      : (const void*)id_coop_kernel<16>;
+  const int tok = prof::begin(0, s);   // timing hook (no-op when off)
+  HIP_CHECK(hipLaunchCooperativeKernel(fn, dim3(total_wg), dim3(256), args, lds, s));
+  prof::end(tok, s);
+}
+
 // R1 (k x k upper, pivot order) gathered from the untouched columns
 __global__ void id_r1_kernel(const IDProb* __restrict__ probs) {
   const IDProb q = probs[blockIdx.y];

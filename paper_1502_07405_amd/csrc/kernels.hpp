@@ -166,6 +166,7 @@ struct IDProb {
   int* state;           // [0] done, [1] rank
   double* first;        // first pivot norm
   unsigned char* active;
+  double* cand;         // 2 (parity) x P x d: each workgroup's best candidate column (cooperative path)
   int m, d, lds, P;     // P workgroups of kIDCols candidates each
   int wg0, pad;         // first workgroup of this problem in the launch grid
   double eps;
@@ -176,6 +177,16 @@ void launch_id_init(const IDProb* p, int np, int total_wg, int max_d, hipStream_
 // wgmap[w] = (problem, workgroup within the problem) of grid workgroup w
 void launch_id_step(const IDProb* p, const int2* wgmap, int total_wg, int t, int max_d, hipStream_t s);
 void launch_id_finish(const IDProb* p, int np, int max_m, hipStream_t s);
+// Cooperative variant: every pivot step of the listed problems in one launch
+// whose workgroups are all resident (hipLaunchCooperativeKernel), with the
+// candidates kept in registers and a per-problem barrier between steps.
+// id_coop_capacity(max_d) = workgroups that can be resident at once (0 when
+// the device has no cooperative launch or max_d > 1024).  slots are then
+// 2 x P x 4 doubles with every step tag (entry 2) preset to -1, and *err
+// zero before the launch; *err != 0 afterwards means a wait gave up and the
+// results are invalid.
+int id_coop_capacity(int max_d);
+void launch_id_coop(const IDProb* p, const int2* wgmap, int total_wg, int max_d, int* err, hipStream_t s);
 
 }  // namespace hssmf
 

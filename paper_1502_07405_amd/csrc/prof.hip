@@ -34,6 +34,21 @@ hipEvent_t get_event() {
 
 bool enabled() { return on; }
 
+int begin(int kclass, hipStream_t s) {
+  if (!on) return -1;
+  std::lock_guard<std::mutex> g(mu);
+  Rec r{kclass, get_event(), get_event(), 0.0};
+  HIP_CHECK(hipEventRecord(r.a, s));
+  recs.push_back(r);
+  return (int)recs.size() - 1;
+}
+
+void end(int token, hipStream_t s) {
+  if (token < 0) return;
+  std::lock_guard<std::mutex> g(mu);
+  HIP_CHECK(hipEventRecord(recs[token].b, s));
+}
+
 int ext(int kclass, double flops, hipEvent_t* start, hipEvent_t* stop) {
   *start = *stop = nullptr;
   if (!on) return -1;

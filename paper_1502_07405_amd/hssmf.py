@@ -44,7 +44,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("rel_tol", ctypes.c_double), ("leaf_size", ctypes.c_int32), ("min_sep_hss", ctypes.c_int32),
                 ("d0", ctypes.c_int32), ("dd", ctypes.c_int32), ("p", ctypes.c_int32), ("d_max", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("gemm_prec", ctypes.c_int32), ("outer", ctypes.c_int32),
-                ("restart", ctypes.c_int32), ("tol", ctypes.c_double), ("max_it", ctypes.c_int32)]
+                ("restart", ctypes.c_int32), ("tol", ctypes.c_double), ("max_it", ctypes.c_int32),
+                ("id_kernel", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -120,6 +121,8 @@ def default_opts(**kw):
             v = PREC[v]
         if k == "outer" and isinstance(v, str):
             v = OUTER[v]
+        if k == "id_kernel" and isinstance(v, str):
+            v = {"stepwise": 0, "cooperative": 1}[v]
         if not hasattr(o, k):
             raise KeyError(k)
         setattr(o, k, v)

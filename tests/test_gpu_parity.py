@@ -70,18 +70,31 @@ HSS_CASES = {
 }
 
 
+_ORACLE = {}
+
+
+def _oracle_case(case):
+    if case not in _ORACLE:
+        mk, kw = HSS_CASES[case]
+        A, o = mk()
+        _ORACLE[case] = (A, o, mf.factor(A, o, mf.Options(**kw)))
+    return _ORACLE[case]
+
+
+@pytest.mark.parametrize("idk", ["stepwise", "cooperative"])
 @pytest.mark.parametrize("case", sorted(HSS_CASES))
-def test_hss_multifrontal_matches_oracle(case):
-    mk, kw = HSS_CASES[case]
-    A, o = mk()
-    fac = H.Factorization(A, o, **kw)
-    ofac = mf.factor(A, o, mf.Options(**kw))
+def test_hss_multifrontal_matches_oracle(case, idk):
+    """Both ID kernels (one launch per pivot step, cooperative) against the
+    oracle: equal ranks per HSS front, M^-1 b to 1e-9."""
+    kw = HSS_CASES[case][1]
+    A, o, ofac = _oracle_case(case)
+    fac = H.Factorization(A, o, id_kernel=idk, **kw)
     assert fac.hss_ranks() == _orc_ranks(ofac)
     b = np.random.default_rng(4).standard_normal(A.n)
     for tr in (False, True):
         y = fac.apply(_t(b), trans=tr).cpu().numpy()
         yo = mf.apply_inverse(ofac, b, trans=tr)
-        assert np.linalg.norm(y - yo) <= 1e-9 * np.linalg.norm(yo), (case, tr)
+        assert np.linalg.norm(y - yo) <= 1e-9 * np.linalg.norm(yo), (case, idk, tr)
     fac.close()
 
 
