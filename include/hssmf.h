@@ -129,6 +129,27 @@ int hssmf_default_opts(hssmf_opts* o);
 int hssmf_factor(const hssmf_csr* A, const hssmf_ordering* ord, const hssmf_opts* opts,
                  void* stream, void** out);
 
+/* Many independent systems in one factorization: A[0..nsys), ord[0..nsys)
+ * describe the systems as hssmf_factor's arguments would (each ordering in
+ * its own numbering).  They are joined into one block-diagonal matrix whose
+ * elimination forest has one tree per system (system s owns unknowns
+ * [off[s], off[s+1]), see hssmf_systems), so every level of every system's
+ * tree and every HSS level of their fronts is factored in the same batched
+ * launches (the level batching of Sec. 5 applied across systems).  The
+ * random matrix of a system is keyed by its own row numbering, so each
+ * system gets the factorization it would get alone.  Vectors
+ * of the handle are the systems' vectors back to back; hssmf_refactor takes
+ * the systems' values back to back.  The outer solvers stop when every
+ * system reaches ||b_s - A_s x_s|| / ||b_s|| <= tol, and report the largest
+ * of these.  Errors as hssmf_factor (EINVAL also for nsys < 1). */
+int hssmf_factor_batch(int32_t nsys, const hssmf_csr* A, const hssmf_ordering* ord, const hssmf_opts* opts,
+                       void* stream, void** out);
+
+/* Number of systems of a handle (1 for hssmf_factor); when cap >= that
+ * number + 1, off[0..nsys] receives the first unknown of every system and
+ * the total. */
+int hssmf_systems(void* h, int64_t* off, int32_t cap);
+
 /* Re-run the numeric factorization with new values (same pattern as the
  * matrix given to hssmf_factor; val has rowptr[n] entries, host memory). */
 int hssmf_refactor(void* h, const double* val);

@@ -157,9 +157,16 @@ void setup(Handle& h, const hssmf_csr* A) {
       F.q = -1;
     }
     F.maxh = F.nd[F.root].height;
+    // R is keyed by the row's id in its own system's numbering, so a system
+    // factored in a batch draws the same random matrix as on its own
     std::vector<int> orig(fp.n);
-    for (int i = 0; i < fp.s; ++i) orig[i] = P.perm[fp.lo + i];
-    for (int i = 0; i < fp.u; ++i) orig[fp.s + i] = P.perm[fp.upd[i]];
+    int64_t base = 0;
+    if (fp.n > 0 && h.sys_off.size() > 2) {
+      const int64_t v = P.perm[fp.lo < fp.hi ? fp.lo : fp.upd[0]];
+      base = *(std::upper_bound(h.sys_off.begin(), h.sys_off.end(), v) - 1);
+    }
+    for (int i = 0; i < fp.s; ++i) orig[i] = (int)(P.perm[fp.lo + i] - base);
+    for (int i = 0; i < fp.u; ++i) orig[fp.s + i] = (int)(P.perm[fp.upd[i]] - base);
     F.orig = upload_big(h, orig);
     LocalCSR L, T;
     front_local_csr(P, fp, false, L);
@@ -225,6 +232,30 @@ int guard_impl(Handle* h, const std::function<void()>& fn) {
   }
 }
 
+// 2-norms of the systems' parts of a vector (one entry for a single system)
+std::vector<double> sys_norms(Handle& h, const double* x) {
+  const int ns = (int)h.sys_off.size() - 1;
+  if (ns <= 1) return {dnrm2(h, x, h.P.n)};
+  std::vector<double> v(ns);
+  launch_seg_sumsq(x, h.d_sys_off, ns, h.d_seg, h.st);
+  HIP_CHECK(hipMemcpyAsync(v.data(), h.d_seg, sizeof(double) * ns, hipMemcpyDeviceToHost, h.st));
+  HIP_CHECK(hipStreamSynchronize(h.st));
+  h.stager.sync();
+  for (double& e : v) e = std::sqrt(e);
+  return v;
+}
+
+// largest relative residual over the systems, ||r_s|| / ||b_s||
+double max_rel(Handle& h, const double* r, const std::vector<double>& nb) {
+  std::vector<double> nr = sys_norms(h, r);
+  double rel = 0.0;
+  for (size_t s = 0; s < nr.size(); ++s) {
+    double q = nb[s] > 0 ? nr[s] / nb[s] : (nr[s] > 0 ? INFINITY : 0.0);
+    rel = std::max(rel, q);
+  }
+  return rel;
+}
+
 // restarted, left-preconditioned GMRES(m) with modified Gram-Schmidt on the
 // device and Givens rotations on the host; x0 = 0; stops on the true
 // relative residual
@@ -235,6 +266,7 @@ int gmres(Handle& h, int trans, const double* b, double* x, hssmf_info* info) {
   double* w = h.arena.get<double>(n);
   double* r = h.arena.get<double>(n);
   double* hcol = h.d_scal;  // m+2 device scalars
+  const std::vector<double> nbs = sys_norms(h, b);
   const double nb = dnrm2(h, b, n);
   HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * n, h.st));
   if (nb == 0.0) {
@@ -248,7 +280,7 @@ int gmres(Handle& h, int trans, const double* b, double* x, hssmf_info* info) {
   auto true_res = [&](const double* xx) {
     spmv(h, trans, xx, r, -1.0, 0.0);
     launch_axpy(r, b, n, nullptr, 1.0, 0, h.st);
-    return dnrm2(h, r, n) / nb;
+    return max_rel(h, r, nbs);
   };
   while (its < h.o.max_it) {
     // r = M^{-1} (b - A x)
@@ -326,14 +358,14 @@ int refine(Handle& h, int trans, const double* b, double* x, hssmf_info* info) {
   Arena::Mark mk = h.arena.mark();
   double* r = h.arena.get<double>(n);
   double* z = h.arena.get<double>(n);
-  const double nb = dnrm2(h, b, n);
+  const std::vector<double> nbs = sys_norms(h, b);
   apply_inverse(h, trans, b, x);
   double rel = 0.0;
   int it = 0;
   for (;; ++it) {
     spmv(h, trans, x, r, -1.0, 0.0);
     launch_axpy(r, b, n, nullptr, 1.0, 0, h.st);
-    rel = nb > 0 ? dnrm2(h, r, n) / nb : 0.0;
+    rel = max_rel(h, r, nbs);
     if (rel <= h.o.tol || it >= h.o.max_it) break;
     apply_inverse(h, trans, r, z);
     launch_axpy(x, z, n, nullptr, 1.0, 0, h.st);
@@ -372,13 +404,18 @@ int hssmf_default_opts(hssmf_opts* o) {
   return HSSMF_OK;
 }
 
-int hssmf_factor(const hssmf_csr* A, const hssmf_ordering* ord, const hssmf_opts* opts, void* stream, void** out) {
-  if (!out || !A || !ord || !opts) return HSSMF_EINVAL;
-  *out = nullptr;
-  if (opts->leaf_size < 1 || opts->d0 < 1 || opts->dd < 1 || opts->p < 0 || opts->d_max < opts->d0 ||
-      !(opts->rel_tol >= 0.0) || opts->restart < 1 || opts->max_it < 0 || opts->gemm_prec < 0 ||
-      opts->gemm_prec > 2 || opts->id_kernel < 0 || opts->id_kernel > 1)
-    return HSSMF_EINVAL;
+}  // extern "C"
+
+namespace {
+
+bool opts_ok(const hssmf_opts* o) {
+  return !(o->leaf_size < 1 || o->d0 < 1 || o->dd < 1 || o->p < 0 || o->d_max < o->d0 || !(o->rel_tol >= 0.0) ||
+           o->restart < 1 || o->max_it < 0 || o->gemm_prec < 0 || o->gemm_prec > 2 || o->id_kernel < 0 ||
+           o->id_kernel > 1);
+}
+
+int factor_impl(const hssmf_csr* A, const hssmf_ordering* ord, const hssmf_opts* opts, void* stream, void** out,
+                std::vector<int64_t> sys_off) {
   Handle* h = new (std::nothrow) Handle();
   if (!h) return HSSMF_ENOMEM;
   int rc = guard_impl(h, [&]() {
@@ -391,7 +428,15 @@ int hssmf_factor(const hssmf_csr* A, const hssmf_ordering* ord, const hssmf_opts
     HIP_CHECK(hipGetDevice(&h->device));
     h->o = *opts;
     h->st = static_cast<hipStream_t>(stream);
+    h->sys_off = std::move(sys_off);
     setup(*h, A);
+    if (h->sys_off.size() > 2) {
+      h->d_sys_off = h->arena.get<int64_t>(h->sys_off.size());
+      h->d_seg = h->arena.get<double>(h->sys_off.size());
+      HIP_CHECK(hipMemcpyAsync(h->d_sys_off, h->sys_off.data(), sizeof(int64_t) * h->sys_off.size(),
+                               hipMemcpyHostToDevice, h->st));
+      HIP_CHECK(hipStreamSynchronize(h->st));
+    }
     h->stats.t_plan_ms = now_ms() - t0;
     h->stats.n = h->P.n;
     h->stats.nfront = h->P.nfront;
@@ -405,6 +450,71 @@ int hssmf_factor(const hssmf_csr* A, const hssmf_ordering* ord, const hssmf_opts
   g_failed_front = -1;
   *out = h;
   return HSSMF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hssmf_factor(const hssmf_csr* A, const hssmf_ordering* ord, const hssmf_opts* opts, void* stream, void** out) {
+  if (!out || !A || !ord || !opts) return HSSMF_EINVAL;
+  *out = nullptr;
+  if (!opts_ok(opts)) return HSSMF_EINVAL;
+  return factor_impl(A, ord, opts, stream, out, {0, (int64_t)std::max(A->n, 0)});
+}
+
+int hssmf_factor_batch(int32_t nsys, const hssmf_csr* A, const hssmf_ordering* ord, const hssmf_opts* opts,
+                       void* stream, void** out) {
+  if (!out || !A || !ord || !opts || nsys < 1) return HSSMF_EINVAL;
+  *out = nullptr;
+  if (!opts_ok(opts)) return HSSMF_EINVAL;
+  // one block-diagonal matrix whose elimination forest has one tree per
+  // system, numbered system by system (each system's postorder kept)
+  int64_t n = 0, nnz = 0, nf = 0;
+  for (int s = 0; s < nsys; ++s) {
+    if (A[s].n < 0 || !A[s].rowptr || (A[s].n > 0 && (!A[s].colind || !A[s].val)) || ord[s].nfront < 0 ||
+        !ord[s].sep_ptr || !ord[s].parent || (A[s].n > 0 && !ord[s].perm))
+      return HSSMF_EINVAL;
+    n += A[s].n;
+    nnz += A[s].rowptr[A[s].n];
+    nf += ord[s].nfront;
+  }
+  if (n > INT32_MAX || nf > INT32_MAX) return HSSMF_EINVAL;
+  std::vector<int64_t> rowptr(n + 1, 0), off(nsys + 1, 0);
+  std::vector<int> col(nnz), perm(n), sep(nf + 1, 0), par(nf);
+  std::vector<double> val(nnz);
+  int64_t r0 = 0, e0 = 0, f0 = 0;
+  for (int s = 0; s < nsys; ++s) {
+    const hssmf_csr& a = A[s];
+    const hssmf_ordering& o = ord[s];
+    const int64_t base = a.rowptr[0];
+    for (int i = 0; i < a.n; ++i) rowptr[r0 + i + 1] = e0 + (a.rowptr[i + 1] - base);
+    for (int64_t e = 0; e < a.rowptr[a.n] - base; ++e) {
+      col[e0 + e] = a.colind[base + e] + (int)r0;
+      val[e0 + e] = a.val[base + e];
+    }
+    for (int i = 0; i < a.n; ++i) perm[r0 + i] = o.perm[i] + (int)r0;
+    for (int f = 0; f < o.nfront; ++f) {
+      sep[f0 + f + 1] = o.sep_ptr[f + 1] + (int)r0;
+      par[f0 + f] = o.parent[f] < 0 ? -1 : o.parent[f] + (int)f0;
+    }
+    if (o.nfront > 0 && o.sep_ptr[0] != 0) return HSSMF_EINVAL;
+    r0 += a.n;
+    e0 += a.rowptr[a.n] - base;
+    f0 += o.nfront;
+    off[s + 1] = r0;
+  }
+  hssmf_csr ca{(int32_t)n, rowptr.data(), col.data(), val.data()};
+  hssmf_ordering co{perm.data(), (int32_t)nf, sep.data(), par.data()};
+  return factor_impl(&ca, &co, opts, stream, out, off);
+}
+
+int hssmf_systems(void* hv, int64_t* off, int32_t cap) {
+  Handle* h = static_cast<Handle*>(hv);
+  if (!h || (cap > 0 && !off)) return HSSMF_EINVAL;
+  const int ns = (int)h->sys_off.size() - 1;
+  for (int i = 0; i <= ns && i < cap; ++i) off[i] = h->sys_off[i];
+  return ns;
 }
 
 int hssmf_refactor(void* hv, const double* val) {

@@ -88,6 +88,29 @@ void launch_gather(double* y, const double* x, const int* map, int n, hipStream_
 }
 
 // dL/dval[e] = -lambda[row(e)] * x[col(e)]
+// sum of squares of each segment [off[s], off[s+1]) of x: one workgroup per
+// segment, fixed reduction order
+__global__ __launch_bounds__(256) void seg_sumsq_kernel(const double* __restrict__ x,
+                                                        const int64_t* __restrict__ off, double* out) {
+  __shared__ double red[256];
+  const int64_t b = off[blockIdx.x], e = off[blockIdx.x + 1];
+  double acc = 0.0;
+  for (int64_t i = b + threadIdx.x; i < e; i += 256) acc += x[i] * x[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+void launch_seg_sumsq(const double* x, const int64_t* off, int nseg, double* out, hipStream_t s) {
+  if (nseg <= 0) return;
+  hipLaunchKernelGGL(seg_sumsq_kernel, dim3(nseg), dim3(256), 0, s, x, off, out);
+  HIP_CHECK(hipGetLastError());
+}
+
 __global__ void adjoint_grad_kernel(const int* __restrict__ row, const int* __restrict__ col,
                                     const double* __restrict__ lam, const double* __restrict__ x, double* g,
                                     int64_t nnz) {

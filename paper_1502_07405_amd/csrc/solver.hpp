@@ -154,6 +154,11 @@ struct Handle {
   int* d_info = nullptr;
   int failed_front = -1;
   double* vec_ws = nullptr;   // solve workspace (n doubles x several)
+  // independent systems factored together (hssmf_factor_batch): unknowns
+  // [sys_off[s], sys_off[s+1]) belong to system s; one system otherwise
+  std::vector<int64_t> sys_off;
+  int64_t* d_sys_off = nullptr;
+  double* d_seg = nullptr;     // per-system sums of squares
   hssmf_stats stats{};
   GemmType gt() const;
 };

@@ -19,7 +19,7 @@ OUTER = {"ir": 0, "gmres": 1}
 EXPORTS = ["hssmf_default_opts", "hssmf_factor", "hssmf_refactor", "hssmf_apply", "hssmf_solve",
            "hssmf_solve_transpose", "hssmf_adjoint", "hssmf_stats_get", "hssmf_hss_ranks",
            "hssmf_last_failed_front", "hssmf_destroy", "hssmf_strerror", "hssmf_profile_enable",
-           "hssmf_profile_read"]
+           "hssmf_profile_read", "hssmf_factor_batch", "hssmf_systems"]
 KCLASS = {"id": 0, "gemm64": 1, "gemmlp": 2, "lupanel": 3}
 
 
@@ -86,6 +86,9 @@ def load():
         L.hssmf_destroy.restype = None
         L.hssmf_strerror.argtypes = [i32]
         L.hssmf_strerror.restype = ctypes.c_char_p
+        L.hssmf_factor_batch.argtypes = [i32, ctypes.POINTER(CSRArg), ctypes.POINTER(OrderingArg),
+                                         ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
+        L.hssmf_systems.argtypes = [vp, vp, i32]
         L.hssmf_profile_enable.argtypes = [i32]
         L.hssmf_profile_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(ctypes.c_double)]
@@ -140,6 +143,17 @@ def _dev_f64(x, n, torch):
     return x
 
 
+def _args(A, ordering, keep):
+    arrs = (np.ascontiguousarray(A.rowptr, dtype=np.int64), np.ascontiguousarray(A.colind, dtype=np.int32),
+            np.ascontiguousarray(A.val, dtype=np.float64), np.ascontiguousarray(ordering.perm, dtype=np.int32),
+            np.ascontiguousarray(ordering.sep_ptr, dtype=np.int32),
+            np.ascontiguousarray(ordering.parent, dtype=np.int32))
+    keep.append(arrs)
+    rp, ci, va, pe, sp, pa = arrs
+    return (CSRArg(int(A.n), rp.ctypes.data, ci.ctypes.data, va.ctypes.data),
+            OrderingArg(pe.ctypes.data, len(pa), sp.ctypes.data, pa.ctypes.data))
+
+
 class Factorization:
     """hssmf_factor on host CSR / ordering arrays; solves on CUDA tensors."""
 
@@ -149,15 +163,9 @@ class Factorization:
         self.lib = load()
         self.n = int(A.n)
         self.nnz = int(A.rowptr[-1])
-        self._rowptr = np.ascontiguousarray(A.rowptr, dtype=np.int64)
-        self._colind = np.ascontiguousarray(A.colind, dtype=np.int32)
-        self._val = np.ascontiguousarray(A.val, dtype=np.float64)
-        self._perm = np.ascontiguousarray(ordering.perm, dtype=np.int32)
-        self._sep = np.ascontiguousarray(ordering.sep_ptr, dtype=np.int32)
-        self._par = np.ascontiguousarray(ordering.parent, dtype=np.int32)
+        self._keep = []
+        csr, ordg = _args(A, ordering, self._keep)
         self.opts = opts if opts is not None else default_opts(**kw)
-        csr = CSRArg(self.n, self._rowptr.ctypes.data, self._colind.ctypes.data, self._val.ctypes.data)
-        ordg = OrderingArg(self._perm.ctypes.data, len(self._par), self._sep.ctypes.data, self._par.ctypes.data)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self._stream = stream
@@ -167,6 +175,7 @@ class Factorization:
         if rc != HSSMF_OK:
             raise HssmfError(rc, "hssmf_factor", self.lib.hssmf_last_failed_front(None))
         self.h = h
+        self.offsets = [0, self.n]
 
     def _check(self, rc, what, allow_noconv=False):
         if rc == HSSMF_OK or (allow_noconv and rc == HSSMF_ENOCONV):
@@ -235,6 +244,49 @@ class Factorization:
             self.close()
         except Exception:
             pass
+
+
+class BatchFactorization(Factorization):
+    """hssmf_factor_batch over a list of (A, ordering) systems: one handle,
+    vectors are the systems' vectors back to back (see offsets / split)."""
+
+    def __init__(self, systems, opts=None, stream=None, **kw):
+        import torch
+        self._torch = torch
+        self.lib = load()
+        self._keep = []
+        args = [_args(A, o, self._keep) for A, o in systems]
+        csrs = (CSRArg * len(args))(*[a[0] for a in args])
+        ords = (OrderingArg * len(args))(*[a[1] for a in args])
+        self.n = int(sum(int(A.n) for A, _ in systems))
+        self.nnz = int(sum(int(A.rowptr[-1]) for A, _ in systems))
+        self.front_offsets = np.cumsum([0] + [len(o.parent) for _, o in systems])
+        self.opts = opts if opts is not None else default_opts(**kw)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self._stream = stream
+        h = ctypes.c_void_p()
+        rc = self.lib.hssmf_factor_batch(len(args), csrs, ords, ctypes.byref(self.opts), ctypes.c_void_p(stream),
+                                         ctypes.byref(h))
+        if rc != HSSMF_OK:
+            raise HssmfError(rc, "hssmf_factor_batch", self.lib.hssmf_last_failed_front(None))
+        self.h = h
+        ns = self.lib.hssmf_systems(h, None, 0)
+        off = np.zeros(ns + 1, dtype=np.int64)
+        self.lib.hssmf_systems(h, off.ctypes.data, ns + 1)
+        self.offsets = [int(v) for v in off]
+
+    def split(self, x):
+        return [x[a:b] for a, b in zip(self.offsets[:-1], self.offsets[1:])]
+
+    def hss_ranks_by_system(self):
+        """hss_ranks() with the fronts renumbered per system:
+        {system: [(local front, row rank, col rank, d, rounds), ...]}."""
+        out = {}
+        for r in self.hss_ranks():
+            s = int(np.searchsorted(self.front_offsets, r[0], side="right") - 1)
+            out.setdefault(s, []).append((r[0] - int(self.front_offsets[s]),) + tuple(r[1:]))
+        return out
 
 
 class LinearSolve:

@@ -298,3 +298,26 @@ def workload(kind, n, leaf_side, rhs_seed=1, **_):
         raise ValueError(kind)
     b = np.random.default_rng(rhs_seed).standard_normal(A.n)
     return A, order, b
+
+
+def convdiff_batch(count=256, seed=2, side_lo=48, side_hi=160, wmax=20.0, leaf_side=8):
+    """Independent 2D convection-diffusion systems of uneven sizes: with
+    ``rng = default_rng(seed)``, sides ``n_j = rng.integers(side_lo,
+    side_hi + 1, count)``, speeds ``|w_j| = rng.uniform(0, wmax, count)``,
+    angles ``theta_j = rng.uniform(0, 2 pi, count)``, then right-hand sides
+    ``b_j = rng.standard_normal(n_j^2)`` in order of j.  Each system is the
+    upwind operator of :func:`convdiff2d` with w = |w|(cos theta, sin theta),
+    ordered by :func:`geometric_nd` with ``leaf_side``.  Returns a list of
+    (A, ordering, b)."""
+    rng = np.random.default_rng(seed)
+    sides = rng.integers(side_lo, side_hi + 1, count)
+    speed = rng.uniform(0.0, wmax, count)
+    theta = rng.uniform(0.0, 2.0 * np.pi, count)
+    out = []
+    for j in range(count):
+        n = int(sides[j])
+        A = convdiff2d(n, float(speed[j] * np.cos(theta[j])), float(speed[j] * np.sin(theta[j])))
+        out.append([A, geometric_nd((n, n), leaf_side), None])
+    for j in range(count):
+        out[j][2] = rng.standard_normal(int(sides[j]) ** 2)
+    return [tuple(t) for t in out]

@@ -106,3 +106,27 @@ def test_rejects_bad_options(lib, small):
     for field, val in (("leaf_size", 0), ("d0", 0), ("dd", 0), ("restart", 0), ("gemm_prec", 7), ("rel_tol", -1.0), ("id_kernel", 5)):
         opts = H.default_opts(**{field: val})
         assert _call_factor(A.rowptr, A.colind, A.val, o.perm, o.sep_ptr, o.parent, A.n, opts) == H.HSSMF_EINVAL
+
+
+def test_batch_rejects_bad_input(lib, small):
+    """hssmf_factor_batch: nsys < 1 and a malformed system are refused on the
+    host."""
+    A, o = small
+    keep = []
+    good = H._args(A, o, keep)
+    bad_perm = o.perm.copy()
+    bad_perm[0] = bad_perm[1]
+
+    class _O:
+        perm, sep_ptr, parent = bad_perm, o.sep_ptr, o.parent
+    bad = H._args(A, _O, keep)
+    L = H.load()
+    opts = H.default_opts()
+    for systems, nsys in (([good], 0), ([good, bad], 2)):
+        csrs = (H.CSRArg * len(systems))(*[s[0] for s in systems])
+        ords = (H.OrderingArg * len(systems))(*[s[1] for s in systems])
+        h = ctypes.c_void_p()
+        rc = L.hssmf_factor_batch(nsys, csrs, ords, ctypes.byref(opts), None, ctypes.byref(h))
+        if h:
+            L.hssmf_destroy(h)
+        assert rc == H.HSSMF_EINVAL
