@@ -93,6 +93,10 @@ typedef struct {
   double tol;          /* stop when ||b - A x||_2 / ||b||_2 <= tol */
   int32_t max_it;      /* max refinement steps / GMRES iterations */
   int32_t id_kernel;   /* HSSMF_ID_*: how the pivoted QR of the IDs runs */
+  int32_t use_graph;   /* 1: the preconditioner's forward and backward sweeps
+                          are captured once per factorization as a HIP graph
+                          (on a private stream) and replayed on the handle's
+                          stream; 0: launched one by one */
 } hssmf_opts;
 
 /* id_kernel: STEPWISE (default) = one launch per pivot step for each batch
@@ -119,7 +123,8 @@ typedef struct {
 
 /* Fill *o with defaults: rel_tol 1e-6, leaf_size 64, min_sep_hss INT32_MAX
  * (pure multifrontal), d0 128, dd 128, p 10, d_max 4096, seed 0, FP64,
- * iterative refinement, restart 30, tol 1e-10, max_it 50. */
+ * iterative refinement, restart 30, tol 1e-10, max_it 50, stepwise ID
+ * kernel, graph replay of the sweeps. */
 int hssmf_default_opts(hssmf_opts* o);
 
 /* Symbolic analysis, upload and numeric factorization (Sec. 3.2, Sec. 4).

@@ -187,6 +187,7 @@ void numeric(Handle& h) {
   h.narena.release();
   h.cur = &h.narena;
   double t0 = now_ms();
+  h.drop_graphs();   // the sweeps change with the factors
   numeric_factor(h);
   build_solve_ops(h);
   HIP_CHECK(hipStreamSynchronize(h.st));
@@ -401,6 +402,8 @@ int hssmf_default_opts(hssmf_opts* o) {
   o->restart = 30;
   o->tol = 1e-10;
   o->max_it = 50;
+  o->id_kernel = HSSMF_ID_STEPWISE;
+  o->use_graph = 1;
   return HSSMF_OK;
 }
 
@@ -411,7 +414,7 @@ namespace {
 bool opts_ok(const hssmf_opts* o) {
   return !(o->leaf_size < 1 || o->d0 < 1 || o->dd < 1 || o->p < 0 || o->d_max < o->d0 || !(o->rel_tol >= 0.0) ||
            o->restart < 1 || o->max_it < 0 || o->gemm_prec < 0 || o->gemm_prec > 2 || o->id_kernel < 0 ||
-           o->id_kernel > 1);
+           o->id_kernel > 1 || o->use_graph < 0 || o->use_graph > 1);
 }
 
 int factor_impl(const hssmf_csr* A, const hssmf_ordering* ord, const hssmf_opts* opts, void* stream, void** out,

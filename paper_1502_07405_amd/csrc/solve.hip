@@ -462,11 +462,43 @@ void run_ops(Handle& h, const std::vector<Op>& ops) {
   }
 }
 
+// forward and backward sweeps on the handle's work vector, replayed as one
+// HIP graph when enabled (captured on first use after each factorization:
+// the sweeps only launch kernels on descriptors already on the device)
+void sweeps(Handle& h, int trans) {
+  if (!h.o.use_graph) {
+    run_ops(h, h.sops[trans][0]);
+    run_ops(h, h.sops[trans][1]);
+    return;
+  }
+  if (!h.gexec[trans]) {
+    if (!h.gst) HIP_CHECK(hipStreamCreateWithFlags(&h.gst, hipStreamNonBlocking));
+    hipStream_t user = h.st;
+    h.st = h.gst;
+    hipGraph_t g = nullptr;
+    HIP_CHECK(hipStreamBeginCapture(h.gst, hipStreamCaptureModeThreadLocal));
+    try {
+      run_ops(h, h.sops[trans][0]);
+      run_ops(h, h.sops[trans][1]);
+    } catch (...) {
+      (void)hipStreamEndCapture(h.gst, &g);
+      if (g) (void)hipGraphDestroy(g);
+      h.st = user;
+      throw;
+    }
+    h.st = user;
+    HIP_CHECK(hipStreamEndCapture(h.gst, &g));
+    hipError_t e = hipGraphInstantiate(&h.gexec[trans], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIP_CHECK(e);
+  }
+  HIP_CHECK(hipGraphLaunch(h.gexec[trans], h.st));
+}
+
 void apply_inverse(Handle& h, int trans, const double* x, double* yout) {
   const int n = h.P.n;
   launch_gather(h.yws, x, h.d_perm, n, h.st);
-  run_ops(h, h.sops[trans][0]);
-  run_ops(h, h.sops[trans][1]);
+  sweeps(h, trans);
   launch_gather(yout, h.yws, h.d_iperm, n, h.st);
 }
 

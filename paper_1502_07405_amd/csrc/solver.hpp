@@ -159,6 +159,18 @@ struct Handle {
   std::vector<int64_t> sys_off;
   int64_t* d_sys_off = nullptr;
   double* d_seg = nullptr;     // per-system sums of squares
+  // preconditioner sweeps captured as HIP graphs ([trans]), rebuilt after
+  // every numeric factorization; captured on a private stream
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  hipStream_t gst = nullptr;
+  void drop_graphs() {
+    for (auto& g : gexec)
+      if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+  }
+  ~Handle() {
+    drop_graphs();
+    if (gst) (void)hipStreamDestroy(gst);
+  }
   hssmf_stats stats{};
   GemmType gt() const;
 };
