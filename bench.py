@@ -146,7 +146,9 @@ def main():
     extra = {"step_s_without_timing_hooks": sec_plain, "iterations": infos[-1][0], "rel_residual": relres(x), "max_rank": st["max_rank"],
              "max_d": st["max_d"], "growth_rounds": st["growth_rounds"],
              "kernel_ms_per_step": {k: prof[k][0] / args.steps for k in KCLASSES},
-             "kernel_launches_per_step": {k: prof[k][1] / args.steps for k in KCLASSES}}
+             "kernel_launches_per_step": {k: prof[k][1] / args.steps for k in KCLASSES},
+             "kernel_tflops": {k: (prof[k][2] / (prof[k][0] * 1e-3) / 1e12 if prof[k][0] > 0 else 0.0)
+                               for k in KCLASSES}}
     # FP64 HSS beside it (the comparison the metric names) and the error of
     # the mixed-precision preconditioner against it
     if args.prec != "fp64":

@@ -95,7 +95,11 @@ void blocked_lu(Handle& h, const std::vector<LUFront>& fronts) {
           const double w = std::min(NB, f.s - jb), m = f.n - jb;
           pfl += m * w * w - w * w * w / 3.0;
         }
-    launch_lu_panel(d, nf, jb, NB, h.d_info, h.st, pfl);
+    int m1 = 0, mu = 0;
+    for (auto& f : fronts)
+      if (jb < f.s) { m1 = std::max(m1, f.s - jb); mu = std::max(mu, f.n - f.s); }
+    if (lu_panel_split_fits(m1, NB)) launch_lu_panel_split(d, nf, jb, NB, m1, mu, h.d_info, h.st, pfl);
+    else launch_lu_panel(d, nf, jb, NB, h.d_info, h.st, pfl);
     launch_laswp(d, nf, jb, NB, maxn, h.st);
     launch_trsm_u12(d, nf, jb, NB, maxn, h.st);
     std::vector<GemmDesc> g;

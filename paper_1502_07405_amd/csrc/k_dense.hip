@@ -117,6 +117,149 @@ __global__ __launch_bounds__(256) void lu_panel_kernel(const LUFront* __restrict
   }
 }
 
+// Panel of the F11 rows only, resident in LDS: rows [jb, s) x columns
+// [jb, jb+w) of each front (m1 = s - jb rows, column major with ld m1).
+// Same pivot rule and the same operations per element as lu_panel_kernel;
+// the F21 rows of the panel are done afterwards by lu_panel21_kernel.
+__global__ __launch_bounds__(256) void lu_panel11_kernel(const LUFront* __restrict__ fr, int jb, int nb, int* info) {
+  extern __shared__ double P[];
+  __shared__ double wv[4];
+  __shared__ int wi[4];
+  __shared__ int pshared;
+  __shared__ double pval;
+  const LUFront f = fr[blockIdx.x];
+  if (jb >= f.s) return;
+  const int w = min(nb, f.s - jb), m1 = f.s - jb;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* F = f.F;
+  const int64_t ld = f.ld;
+  for (int e = tid; e < m1 * w; e += 256) {
+    const int r = e % m1, c = e / m1;
+    P[e] = F[(jb + r) + (int64_t)(jb + c) * ld];
+  }
+  __syncthreads();
+  for (int c = 0; c < w; ++c) {
+    // pivot: largest |value| in column c over rows c.., ties to the lowest row
+    double best = -1.0;
+    int bi = c;
+    for (int r = c + tid; r < m1; r += 256) {
+      const double a = fabs(P[r + c * m1]);
+      if (a > best) { best = a; bi = r; }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bi, off);
+      if (o > best || (o == best && oi < bi)) { best = o; bi = oi; }
+    }
+    if (lane == 0) { wv[wave] = best; wi[wave] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      double b = wv[0];
+      int i = wi[0];
+      for (int q = 1; q < 4; ++q)
+        if (wv[q] > b || (wv[q] == b && wi[q] < i)) { b = wv[q]; i = wi[q]; }
+      pshared = i;
+      pval = b;
+      f.ipiv[jb + c] = jb + i;
+      if (b == 0.0) atomicCAS(info, 0, f.id + 1);
+    }
+    __syncthreads();
+    const int p = pshared;
+    if (p != c && tid < w) {
+      const double t = P[c + tid * m1];
+      P[c + tid * m1] = P[p + tid * m1];
+      P[p + tid * m1] = t;
+    }
+    __syncthreads();
+    const double piv = P[c + c * m1];
+    const double rp = (piv != 0.0) ? 1.0 / piv : 0.0;
+    for (int r = c + 1 + tid; r < m1; r += 256) {
+      const double l = P[r + c * m1] * rp;
+      P[r + c * m1] = l;
+      for (int cc = c + 1; cc < w; ++cc) P[r + cc * m1] -= l * P[c + cc * m1];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < m1 * w; e += 256) {
+    const int r = e % m1, c = e / m1;
+    F[(jb + r) + (int64_t)(jb + c) * ld] = P[e];
+  }
+}
+
+// F21 rows of the panel: every row x of F[s:n, jb:jb+w) becomes x U^{-1}
+// with the panel's w x w upper block, which is what the column-by-column
+// elimination does to those rows (same operations, same order).  One thread
+// per row, the row in registers.
+template <int NB>
+__global__ __launch_bounds__(256) void lu_panel21_kernel(const LUFront* __restrict__ fr, int jb) {
+  __shared__ double U[NB][NB + 1];
+  const LUFront f = fr[blockIdx.y];
+  if (jb >= f.s) return;
+  const int w = min(NB, f.s - jb);
+  const int tid = threadIdx.x;
+  double* F = f.F;
+  const int64_t ld = f.ld;
+  if ((int64_t)blockIdx.x * 256 >= f.n - f.s) return;
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int r = e % NB, c = e / NB;
+    U[r][c] = (r < w && c < w) ? F[(jb + r) + (int64_t)(jb + c) * ld] : 0.0;
+  }
+  __syncthreads();
+  const int i = f.s + blockIdx.x * 256 + tid;
+  if (i >= f.n) return;
+  double x[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) x[c] = (c < w) ? F[i + (int64_t)(jb + c) * ld] : 0.0;
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    if (c < w) {
+      const double piv = U[c][c];
+      const double rp = (piv != 0.0) ? 1.0 / piv : 0.0;
+      const double l = x[c] * rp;
+      x[c] = l;
+#pragma unroll
+      for (int cc = c + 1; cc < NB; ++cc)
+        if (cc < w) x[cc] -= l * U[c][cc];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NB; ++c)
+    if (c < w) F[i + (int64_t)(jb + c) * ld] = x[c];
+}
+
+// dynamic LDS a workgroup may take on this device, less what the kernels
+// hold statically
+size_t lds_budget(size_t static_bytes) {
+  static size_t limit = 0;
+  if (!limit) {
+    int dev = 0, v = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    HIP_CHECK(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    limit = (size_t)v;
+  }
+  return limit > static_bytes ? limit - static_bytes : 0;
+}
+
+bool lu_panel_split_fits(int max_m1, int nb) {
+  return (size_t)max_m1 * nb * sizeof(double) <= std::min<size_t>(144 * 1024, lds_budget(1024));
+}
+
+void launch_lu_panel_split(const LUFront* fr, int nf, int jb, int nb, int max_m1, int max_u, int* info, hipStream_t s,
+                           double flops) {
+  if (nf <= 0) return;
+  REQUIRE(nb == 32, HSSMF_EINVAL, "panel width");
+  REQUIRE(lu_panel_split_fits(max_m1, nb), HSSMF_EINVAL, "panel too tall for LDS");
+  hipEvent_t e0, e1;
+  prof::ext(3, flops, &e0, &e1);   // timing hook (no-op when off)
+  hipExtLaunchKernelGGL(lu_panel11_kernel, dim3(nf), dim3(256), (size_t)std::max(max_m1, 1) * nb * sizeof(double), s,
+                        e0, e1, 0, fr, jb, nb, info);
+  HIP_CHECK(hipGetLastError());
+  if (max_u > 0) {
+    hipLaunchKernelGGL(lu_panel21_kernel<32>, dim3((max_u + 255) / 256, nf), dim3(256), 0, s, fr, jb);
+    HIP_CHECK(hipGetLastError());
+  }
+}
+
 void launch_lu_panel(const LUFront* fr, int nf, int jb, int nb, int* info, hipStream_t s, double flops) {
   if (nf <= 0) return;
   REQUIRE(nb <= 64, HSSMF_EINVAL, "panel width");
@@ -231,12 +374,14 @@ void launch_gemv(const GemvDesc* d, int nd, int max_out, hipStream_t s) {
 }
 
 // Triangular solves with the F11 factors, one workgroup per front, the
-// right-hand side staged in LDS.  Blocks of 64: one wavefront solves the
-// diagonal block with lane shuffles, then all threads update the rest.
-template <int KIND>
+// right-hand side staged in LDS.  Blocks of 64: the diagonal block is staged
+// in LDS with coalesced loads, one wavefront solves it with lane shuffles,
+// then all threads update the rest of the right-hand side.
+template <int KIND, bool STAGE>
 __global__ __launch_bounds__(256) void trsv_kernel(const TrsvDesc* __restrict__ descs) {
-  extern __shared__ double xs[];
+  extern __shared__ double xs[];   // s entries, then (STAGE) the 64 x 65 block
   const TrsvDesc d = descs[blockIdx.x];
+  double (*Tb)[65] = reinterpret_cast<double (*)[65]>(xs + ((d.s + 1) & ~1));
   const int s = d.s, tid = threadIdx.x, lane = tid & 63;
   const int64_t ld = d.ld;
   for (int i = tid; i < s; i += 256) xs[i] = d.x[i];
@@ -253,17 +398,28 @@ __global__ __launch_bounds__(256) void trsv_kernel(const TrsvDesc* __restrict__ 
   auto T = [&](int i, int j) -> double {
     return trans ? d.F[j + (int64_t)i * ld] : d.F[i + (int64_t)j * ld];
   };
+  // Tb[r][c] = T(b0 + r, b0 + c) for r, c < bs, read along the stored columns
+  auto stage = [&](int b0, int bs) {
+    if (!STAGE) return;
+    for (int e = tid; e < 64 * 64; e += 256) {
+      const int fast = e & 63, slow = e >> 6;
+      const int r = trans ? slow : fast, c = trans ? fast : slow;
+      if (r < bs && c < bs) Tb[r][c] = T(b0 + r, b0 + c);
+    }
+  };
   constexpr bool lower = (KIND == 0 || KIND == 2 || KIND == 4);
   constexpr bool unit = (KIND == 0 || KIND == 3);
   if (lower) {
     for (int b0 = 0; b0 < s; b0 += 64) {
       const int bs = min(64, s - b0);
+      stage(b0, bs);
+      __syncthreads();
       if (tid < 64) {
         double v = (lane < bs) ? xs[b0 + lane] : 0.0;
         for (int j = 0; j < bs; ++j) {
-          if (!unit && lane == j) v /= T(b0 + j, b0 + j);
+          if (!unit && lane == j) v /= STAGE ? Tb[j][j] : T(b0 + j, b0 + j);
           double vj = __shfl(v, j);
-          if (lane > j && lane < bs) v -= T(b0 + lane, b0 + j) * vj;
+          if (lane > j && lane < bs) v -= (STAGE ? Tb[lane][j] : T(b0 + lane, b0 + j)) * vj;
         }
         if (lane < bs) xs[b0 + lane] = v;
       }
@@ -278,12 +434,14 @@ __global__ __launch_bounds__(256) void trsv_kernel(const TrsvDesc* __restrict__ 
   } else {
     for (int b1 = s; b1 > 0; b1 -= 64) {
       const int b0 = max(0, b1 - 64), bs = b1 - b0;
+      stage(b0, bs);
+      __syncthreads();
       if (tid < 64) {
         double v = (lane < bs) ? xs[b0 + lane] : 0.0;
         for (int j = bs - 1; j >= 0; --j) {
-          if (!unit && lane == j) v /= T(b0 + j, b0 + j);
+          if (!unit && lane == j) v /= STAGE ? Tb[j][j] : T(b0 + j, b0 + j);
           double vj = __shfl(v, j);
-          if (lane < j) v -= T(b0 + lane, b0 + j) * vj;
+          if (lane < j) v -= (STAGE ? Tb[lane][j] : T(b0 + lane, b0 + j)) * vj;
         }
         if (lane < bs) xs[b0 + lane] = v;
       }
@@ -307,17 +465,26 @@ __global__ __launch_bounds__(256) void trsv_kernel(const TrsvDesc* __restrict__ 
 
 void launch_trsv(const TrsvDesc* d, int nd, int kind, int max_s, hipStream_t s) {
   if (nd <= 0) return;
-  // LDS holds the whole right-hand side
-  REQUIRE(max_s <= 8192, HSSMF_EINVAL, "triangular solve: block larger than 8192 rows");
-  size_t lds = (size_t)std::max(max_s, 1) * sizeof(double);
+  // LDS holds the whole right-hand side and, when it fits, the 64 x 64
+  // diagonal block being solved
+  const size_t xs = (size_t)(std::max(max_s, 1) + 1) / 2 * 2 * sizeof(double);
+  const size_t blk = 64 * 65 * sizeof(double);
+  const size_t budget = lds_budget(256);
+  REQUIRE(xs <= budget, HSSMF_EINVAL, "triangular solve: right-hand side too long for LDS");
+  const bool stage = xs + blk <= budget;
+  const size_t lds = stage ? xs + blk : xs;
+#define HSSMF_TRSV(K)                                                                              \
+  if (stage) hipLaunchKernelGGL((trsv_kernel<K, true>), dim3(nd), dim3(256), lds, s, d);           \
+  else hipLaunchKernelGGL((trsv_kernel<K, false>), dim3(nd), dim3(256), lds, s, d);
   switch (kind) {
-    case 0: hipLaunchKernelGGL(trsv_kernel<0>, dim3(nd), dim3(256), lds, s, d); break;
-    case 1: hipLaunchKernelGGL(trsv_kernel<1>, dim3(nd), dim3(256), lds, s, d); break;
-    case 2: hipLaunchKernelGGL(trsv_kernel<2>, dim3(nd), dim3(256), lds, s, d); break;
-    case 3: hipLaunchKernelGGL(trsv_kernel<3>, dim3(nd), dim3(256), lds, s, d); break;
-    case 4: hipLaunchKernelGGL(trsv_kernel<4>, dim3(nd), dim3(256), lds, s, d); break;
-    default: hipLaunchKernelGGL(trsv_kernel<5>, dim3(nd), dim3(256), lds, s, d); break;
+    case 0: HSSMF_TRSV(0) break;
+    case 1: HSSMF_TRSV(1) break;
+    case 2: HSSMF_TRSV(2) break;
+    case 3: HSSMF_TRSV(3) break;
+    case 4: HSSMF_TRSV(4) break;
+    default: HSSMF_TRSV(5) break;
   }
+#undef HSSMF_TRSV
   HIP_CHECK(hipGetLastError());
 }
 

@@ -61,6 +61,11 @@ void launch_assemble(double* base, const int64_t* dst, const int64_t* src, const
                      int64_t count, hipStream_t s);
 void launch_extend_add(const EADesc* d, int nd, int max_u, hipStream_t s);
 void launch_lu_panel(const LUFront* fr, int nf, int jb, int nb, int* info, hipStream_t s, double flops = 0.0);
+// the same panel as two kernels: the F11 rows resident in LDS (max_m1 = the
+// largest s - jb of the batch), then the F21 rows (max_u = largest n - s)
+bool lu_panel_split_fits(int max_m1, int nb);
+void launch_lu_panel_split(const LUFront* fr, int nf, int jb, int nb, int max_m1, int max_u, int* info, hipStream_t s,
+                           double flops = 0.0);
 void launch_laswp(const LUFront* fr, int nf, int jb, int nb, int max_n, hipStream_t s);
 void launch_trsm_u12(const LUFront* fr, int nf, int jb, int nb, int max_n, hipStream_t s);
 void launch_gemv(const GemvDesc* d, int nd, int max_rows, hipStream_t s);
