@@ -194,6 +194,7 @@ void numeric(Handle& h) {
   h.stager.sync();
   h.larena.release();
   h.sarena.release();
+  gemm_census_print();
   h.stats.t_factor_ms = now_ms() - t0;
   h.cur = &h.arena;
   // statistics

@@ -95,6 +95,8 @@ enum GemmType {
 
 // launch a batch of GEMMs (descriptors in host memory; staged to the device)
 class Stager;
+// prints and clears the GEMM shape census when HSSMF_GEMM_CENSUS=1
+void gemm_census_print();
 void gemm_batched(const std::vector<GemmDesc>& d, GemmType t, Stager& st, hipStream_t s);
 
 // Pinned host ring + device mirror for per-launch descriptor arrays.

@@ -809,7 +809,9 @@ void ulv_level(Handle& h, std::vector<HFront*>& fs, const int* iota) {
         g2.push_back(G(Tb[i], kPanel, 1, Mb[i], kPanel, 0, M2[i], kPanel, nb, ntr, nb, 1.0, 0.0));
         g3.push_back(G(Yb[i] + j0, m, 0, M2[i], kPanel, 0, Ct, m, m - j0, ntr, nb, -1.0, 1.0));
       }
-      launch_qr_panel(h.stager.put_vec(pd, h.st), (int)pd.size(), h.st);
+      int mpx = 0;
+      for (auto& q : pd) mpx = std::max(mpx, q.m - q.j0);
+      launch_qr_panel(h.stager.put_vec(pd, h.st), (int)pd.size(), mpx, h.st);
       run_gemm(h, g1);
       run_gemm(h, g2);
       run_gemm(h, g3);

@@ -8,6 +8,9 @@
 // FP32 with v_mfma_f32_16x16x4_f32 / v_mfma_f32_16x16x32_bf16.
 // Optional row maps fuse the gathers / scatters of the multifrontal
 // extend-add into the product.
+#include <cstdlib>
+#include <map>
+
 #include "common.hpp"
 
 namespace hssmf {
@@ -46,10 +49,13 @@ __device__ __forceinline__ T load_b(const GemmDesc& g, int kk, int j) {
 }
 
 // ---------------------------------------------------------------- FP64 -----
+// k-tiles of 16 double-buffered in LDS: while the matrix cores work on tile
+// k0, every thread already holds its share of tile k0+16 in registers and
+// stores it into the other buffer afterwards (one barrier per k-tile).
 __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restrict__ descs, int nd) {
-  constexpr int TK = 16;
-  __shared__ double As[TK][TM + 1];
-  __shared__ double Bs[TK][TN + 1];
+  constexpr int TK = 16, PER = TM * TK / 256;   // elements of A (and of B) per thread per k-tile
+  __shared__ double As[2][TK][TM + 1];
+  __shared__ double Bs[2][TK][TN + 1];
   const int di = find_desc(descs, nd, blockIdx.x);
   const GemmDesc g = descs[di];
   const int64_t t = blockIdx.x - g.tile_base;
@@ -59,35 +65,64 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restric
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  // element e = tid + 256 q of a k-tile: (i, kk) of A and (kk, j) of B,
+  // ordered so that consecutive threads read consecutive addresses
+  auto a_idx = [&](int q, int& i, int& kk) {
+    const int e = tid + 256 * q;
+    if (g.transA) { kk = e % TK; i = e / TK; } else { i = e % TM; kk = e / TM; }
+  };
+  auto b_idx = [&](int q, int& kk, int& j) {
+    const int e = tid + 256 * q;
+    if (g.transB) { j = e % TN; kk = e / TN; } else { kk = e % TK; j = e / TK; }
+  };
+  double ra[PER], rb[PER];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      int i, kk, j, kb;
+      a_idx(q, i, kk);
+      ra[q] = load_a<double>(g, row0 + i, k0 + kk);
+      b_idx(q, kb, j);
+      rb[q] = load_b<double>(g, k0 + kb, col0 + j);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      int i, kk, j, kb;
+      a_idx(q, i, kk);
+      As[buf][kk][i] = ra[q];
+      b_idx(q, kb, j);
+      Bs[buf][kb][j] = rb[q];
+    }
+  };
   dbl4 acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0, 0, 0, 0};
+  int buf = 0;
+  if (g.k > 0) {
+    fetch(0);
+    store(0);
+  }
+  __syncthreads();
   for (int k0 = 0; k0 < g.k; k0 += TK) {
-    // stage op(A)[row0:row0+64, k0:k0+16] and op(B)[k0:k0+16, col0:col0+64]
-    for (int e = tid; e < TM * TK; e += 256) {
-      int i, kk;
-      if (g.transA) { kk = e % TK; i = e / TK; } else { i = e % TM; kk = e / TM; }
-      As[kk][i] = load_a<double>(g, row0 + i, k0 + kk);
-    }
-    for (int e = tid; e < TN * TK; e += 256) {
-      int j, kk;
-      if (g.transB) { j = e % TN; kk = e / TN; } else { kk = e % TK; j = e / TK; }
-      Bs[kk][j] = load_b<double>(g, k0 + kk, col0 + j);
-    }
-    __syncthreads();
+    const bool more = k0 + TK < g.k;
+    if (more) fetch(k0 + TK);   // in flight while the matrix cores run
 #pragma unroll
     for (int ks = 0; ks < TK; ks += 4) {
       const int kk = ks + (lane >> 4);
-      double a0 = As[kk][wr + (lane & 15)];
-      double a1 = As[kk][wr + 16 + (lane & 15)];
-      double b0 = Bs[kk][wc + (lane & 15)];
-      double b1 = Bs[kk][wc + 16 + (lane & 15)];
+      const double a0 = As[buf][kk][wr + (lane & 15)];
+      const double a1 = As[buf][kk][wr + 16 + (lane & 15)];
+      const double b0 = Bs[buf][kk][wc + (lane & 15)];
+      const double b1 = Bs[buf][kk][wc + 16 + (lane & 15)];
       acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
       acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
       acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
       acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
+    if (more) store(buf ^ 1);   // the other buffer was last read before the previous barrier
     __syncthreads();
+    buf ^= 1;
   }
   // FP64 16x16x4 result layout: lane l, slot v holds (row l/16 + 4v, col l%16)
   double* C = static_cast<double*>(g.C);
@@ -237,6 +272,43 @@ void launch_tiles(const std::vector<GemmDesc>& d, int64_t tiles, GemmType type, 
 }
 }  // namespace
 
+namespace {
+// shape census of the batched GEMMs (diagnostics, HSSMF_GEMM_CENSUS=1):
+// every call is timed with a synchronizing event pair and binned by its
+// largest k and its tile count
+struct CensusBin {
+  int64_t calls = 0, tiles = 0;
+  double flops = 0, ms = 0;
+};
+bool census_on() {
+  static int on = -1;
+  if (on < 0) {
+    const char* e = std::getenv("HSSMF_GEMM_CENSUS");
+    on = (e && *e == '1') ? 1 : 0;
+  }
+  return on == 1;
+}
+std::map<std::pair<int, int>, CensusBin>& census() {
+  static std::map<std::pair<int, int>, CensusBin> c;
+  return c;
+}
+int log2bin(int64_t v) {
+  int b = 0;
+  while ((int64_t(1) << (b + 1)) <= v) ++b;
+  return b;
+}
+}  // namespace
+
+void gemm_census_print() {
+  if (!census_on()) return;
+  std::fprintf(stderr, "gemm census: kmax-bin tiles-bin calls tiles GFLOP ms TFLOP/s\n");
+  for (auto& kv : census())
+    std::fprintf(stderr, "  k<2^%d tiles<2^%d %8lld %10lld %9.2f %9.2f %6.2f\n", kv.first.first + 1,
+                 kv.first.second + 1, (long long)kv.second.calls, (long long)kv.second.tiles, kv.second.flops / 1e9,
+                 kv.second.ms, kv.second.ms > 0 ? kv.second.flops / kv.second.ms / 1e9 : 0.0);
+  census().clear();
+}
+
 void gemm_batched(const std::vector<GemmDesc>& in, GemmType type, Stager& st, hipStream_t s) {
   std::vector<GemmDesc> d;
   d.reserve(in.size());
@@ -257,6 +329,12 @@ void gemm_batched(const std::vector<GemmDesc>& in, GemmType type, Stager& st, hi
   }
   if (d.empty()) return;
   REQUIRE(tiles < (1LL << 31), HSSMF_EINVAL, "gemm batch too large");
+  hipEvent_t ce0 = nullptr, ce1 = nullptr;
+  if (census_on()) {
+    HIP_CHECK(hipEventCreate(&ce0));
+    HIP_CHECK(hipEventCreate(&ce1));
+    HIP_CHECK(hipEventRecord(ce0, s));
+  }
   // split-K when the batch has too few output tiles to fill the chip and
   // the reductions are long: partial products into the workspace, then a
   // fixed-order reduction (the result is bitwise reproducible)
@@ -315,6 +393,21 @@ void gemm_batched(const std::vector<GemmDesc>& in, GemmType type, Stager& st, hi
     int64_t t = 0;
     for (auto& g : d) { g.tile_base = t; t += (int64_t)g.tiles_m * g.tiles_n; }
     launch_tiles(d, tiles, type, st, s, flops);
+  }
+  if (ce0) {
+    HIP_CHECK(hipEventRecord(ce1, s));
+    HIP_CHECK(hipEventSynchronize(ce1));
+    float ms = 0;
+    HIP_CHECK(hipEventElapsedTime(&ms, ce0, ce1));
+    (void)hipEventDestroy(ce0);
+    (void)hipEventDestroy(ce1);
+    int64_t km = 0;
+    for (auto& g : d) km = std::max<int64_t>(km, g.k);
+    CensusBin& b = census()[{log2bin(std::max<int64_t>(km, 1)), log2bin(tiles)}];
+    b.calls++;
+    b.tiles += tiles;
+    b.flops += flops;
+    b.ms += ms;
   }
 }
 

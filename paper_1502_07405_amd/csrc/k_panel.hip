@@ -12,24 +12,45 @@ __device__ __forceinline__ double wsum(double v) {
 }
 }  // namespace
 
+// LDS = true: the panel (rows j0..m-1 of its nb columns) is staged in LDS
+// for the column loop and written back; false: the loop works on global
+// memory (panels too tall for LDS).  The Gram matrix Y^T Y is accumulated
+// from 64-row chunks by all threads, and T column by column in parallel.
+template <bool LDS>
 __global__ __launch_bounds__(256) void qr_panel_kernel(const PanelDesc* __restrict__ descs) {
-  const PanelDesc pd = descs[blockIdx.x];
-  __shared__ double tau[kPanel], v0s[kPanel], G[kPanel][kPanel + 1];
+  extern __shared__ double Pl[];
+  __shared__ double tau[kPanel], v0s[kPanel], G[kPanel][kPanel + 1], Ts[kPanel][kPanel + 1];
+  __shared__ double Yc[64][kPanel + 1];
   __shared__ double bc[3];
+  const PanelDesc pd = descs[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m = pd.m, j0 = pd.j0, nb = pd.nb;
+  const int m = pd.m, j0 = pd.j0, nb = pd.nb, mp = m - j0;
   double* C = pd.C;
+  // element (absolute row i >= j0, panel column l)
+  auto el = [&](int l, int i) -> double& {
+    if (LDS) return Pl[(i - j0) + (int64_t)l * mp];
+    return C[i + (int64_t)(j0 + l) * m];
+  };
+  if (LDS) {
+    for (int64_t e = tid; e < (int64_t)mp * nb; e += 256) {
+      const int r = (int)(e % mp), l = (int)(e / mp);
+      Pl[e] = C[(j0 + r) + (int64_t)(j0 + l) * m];
+    }
+    __syncthreads();
+  }
   for (int l = 0; l < nb; ++l) {
     const int t = j0 + l;
-    double* col = C + (int64_t)t * m;
-    // norm of col[t:m]
+    // norm of column l, rows t..m-1
     if (wave == 0) {
       double ss = 0.0;
-      for (int i = t + lane; i < m; i += 64) ss += col[i] * col[i];
+      for (int i = t + lane; i < m; i += 64) {
+        const double v = el(l, i);
+        ss += v * v;
+      }
       ss = wsum(ss);
       if (lane == 0) {
         const double nrm = sqrt(ss);
-        const double x0 = col[t];
+        const double x0 = el(l, t);
         const double alpha = (x0 >= 0.0) ? -nrm : nrm;
         const double v0 = x0 - alpha;
         const double vtv = v0 * v0 + (ss - x0 * x0);
@@ -42,60 +63,102 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const PanelDesc* __restri
     const double tv = bc[0], v0 = bc[1];
     // apply H_t to the remaining panel columns
     for (int c = l + 1 + wave; c < nb; c += 4) {
-      double* cc = C + (int64_t)(j0 + c) * m;
       double dot = 0.0;
-      for (int i = t + lane; i < m; i += 64) dot += ((i == t) ? v0 : col[i]) * cc[i];
+      for (int i = t + lane; i < m; i += 64) dot += ((i == t) ? v0 : el(l, i)) * el(c, i);
       dot = wsum(dot) * tv;
-      for (int i = t + lane; i < m; i += 64) cc[i] -= dot * ((i == t) ? v0 : col[i]);
+      for (int i = t + lane; i < m; i += 64) el(c, i) -= dot * ((i == t) ? v0 : el(l, i));
     }
     __syncthreads();
     if (tid == 0) {
       tau[l] = tv;
       v0s[l] = v0;
-      col[t] = bc[2];  // R_tt
+      el(l, t) = bc[2];  // R_tt
     }
     __syncthreads();
   }
-  // Y (m x nb): column l = [0 ... 0, v0, C[t+1:m, t]]
+  // Y (m x nb): column l = [0 ... 0, v0, rows t+1.. of panel column l]
+  auto yv = [&](int i, int l) -> double {
+    const int t = j0 + l;
+    if (i < t) return 0.0;
+    if (i == t) return v0s[l];
+    return el(l, i);
+  };
   for (int64_t e = tid; e < (int64_t)m * nb; e += 256) {
     const int i = (int)(e % m), l = (int)(e / m);
-    const int t = j0 + l;
-    double v = 0.0;
-    if (i == t) v = v0s[l];
-    else if (i > t) v = C[i + (int64_t)t * m];
-    pd.Y[i + (int64_t)l * m] = v;
+    pd.Y[i + (int64_t)l * m] = (i < j0) ? 0.0 : yv(i, l);
   }
-  __syncthreads();
-  // Gram matrix G = Y^T Y over rows j0..m-1
-  for (int pidx = wave; pidx < nb * nb; pidx += 4) {
-    const int a = pidx % nb, b = pidx / nb;
-    if (a > b) continue;
-    const double* ya = pd.Y + (int64_t)a * m;
-    const double* yb = pd.Y + (int64_t)b * m;
-    double s = 0.0;
-    for (int i = j0 + lane; i < m; i += 64) s += ya[i] * yb[i];
-    s = wsum(s);
-    if (lane == 0) G[a][b] = s;
+  if (LDS) {
+    for (int64_t e = tid; e < (int64_t)mp * nb; e += 256) {
+      const int r = (int)(e % mp), l = (int)(e / mp);
+      C[(j0 + r) + (int64_t)(j0 + l) * m] = Pl[e];
+    }
   }
+  // Gram matrix G = Y^T Y over rows j0..m-1 (pairs a <= b, up to 3 per thread)
+  double g[3] = {0.0, 0.0, 0.0};
+  int pa[3], pb[3];
+  for (int q = 0; q < 3; ++q) {
+    int p = tid + 256 * q, a = 0;
+    if (p >= kPanel * (kPanel + 1) / 2) {   // no pair for this slot
+      pa[q] = pb[q] = kPanel;
+      continue;
+    }
+    while (p >= kPanel - a) { p -= kPanel - a; ++a; }   // row a of the upper triangle
+    pa[q] = a;
+    pb[q] = a + p;
+  }
+  for (int r0 = j0; r0 < m; r0 += 64) {
+    __syncthreads();
+    for (int e = tid; e < 64 * kPanel; e += 256) {
+      const int r = e % 64, l = e / 64;
+      Yc[r][l] = (r0 + r < m && l < nb) ? yv(r0 + r, l) : 0.0;
+    }
+    __syncthreads();
+    for (int q = 0; q < 3; ++q) {
+      if (pa[q] >= nb || pb[q] >= nb) continue;
+      double acc = 0.0;
+      for (int r = 0; r < 64; ++r) acc += Yc[r][pa[q]] * Yc[r][pb[q]];
+      g[q] += acc;
+    }
+  }
+  for (int q = 0; q < 3; ++q)
+    if (pa[q] < nb && pb[q] < nb) G[pa[q]][pb[q]] = g[q];
   __syncthreads();
   // T: T(i,i) = tau_i, T(0:i, i) = -tau_i T(0:i, 0:i) G(0:i, i)
-  if (tid == 0) {
-    double* T = pd.T;
-    for (int i = 0; i < nb; ++i) {
-      for (int r = 0; r < nb; ++r) T[r + i * kPanel] = 0.0;
-      T[i + i * kPanel] = tau[i];
-      for (int r = 0; r < i; ++r) {
-        double s = 0.0;
-        for (int c = r; c < i; ++c) s += T[r + c * kPanel] * G[c][i];
-        T[r + i * kPanel] = -tau[i] * s;
-      }
+  for (int i = 0; i < nb; ++i) {
+    if (tid < i) {
+      double sacc = 0.0;
+      for (int c = tid; c < i; ++c) sacc += Ts[tid][c] * G[c][i];
+      Ts[tid][i] = -tau[i] * sacc;
+    } else if (tid == i) {
+      Ts[i][i] = tau[i];
     }
+    __syncthreads();
+  }
+  for (int e = tid; e < kPanel * kPanel; e += 256) {
+    const int r = e % kPanel, i = e / kPanel;
+    pd.T[r + i * kPanel] = (r <= i && i < nb) ? Ts[r][i] : 0.0;
   }
 }
 
-void launch_qr_panel(const PanelDesc* d, int nd, hipStream_t s) {
+size_t qr_panel_lds_budget() {
+  static size_t b = 0;
+  if (!b) {
+    int dev = 0, v = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    HIP_CHECK(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const size_t fixed = sizeof(double) * (2 * kPanel + 2 * kPanel * (kPanel + 1) + 64 * (kPanel + 1) + 3) + 512;
+    b = (size_t)v > fixed ? (size_t)v - fixed : 0;
+  }
+  return b;
+}
+
+void launch_qr_panel(const PanelDesc* d, int nd, int max_mp, hipStream_t s) {
   if (nd <= 0) return;
-  hipLaunchKernelGGL(qr_panel_kernel, dim3(nd), dim3(256), 0, s, d);
+  const size_t lds = (size_t)std::max(max_mp, 1) * kPanel * sizeof(double);
+  if (lds <= qr_panel_lds_budget())
+    hipLaunchKernelGGL(qr_panel_kernel<true>, dim3(nd), dim3(256), lds, s, d);
+  else
+    hipLaunchKernelGGL(qr_panel_kernel<false>, dim3(nd), dim3(256), 0, s, d);
   HIP_CHECK(hipGetLastError());
 }
 

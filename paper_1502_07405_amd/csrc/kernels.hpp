@@ -209,6 +209,7 @@ struct PanelDesc {
   int m, j0, nb, pad;
 };
 constexpr int kPanel = 32;
-void launch_qr_panel(const PanelDesc* d, int nd, hipStream_t s);
+// max_mp: the largest m - j0 of the batch (rows of a panel)
+void launch_qr_panel(const PanelDesc* d, int nd, int max_mp, hipStream_t s);
 
 }  // namespace hssmf
