@@ -946,7 +946,7 @@ void schur_level(Handle& h, std::vector<HFront*>& fs) {
   for (HFront* F : wu) {
     // Theta^T := U^{-T} Theta^T  (logical lower, non-unit, transposed access)
     tri_solve_many(h, F->Dk, F->mk, F->mk, F->ThT, F->mk, F->u, true, false, true);
-    launch_pivots(F->Phi, F->mk, F->u, F->ipivk, F->mk, 0, h.st);
+    launch_pivots(F->Phi, F->mk, F->u, F->ipivk, F->mk, 0, sialloc(h, F->mk), h.st);
     tri_solve_many(h, F->Dk, F->mk, F->mk, F->Phi, F->mk, F->u, true, true, false);
   }
   // dense update matrix: expand F22 of the q-subtree, subtract Theta^* Phi

@@ -249,10 +249,11 @@ void launch_lu_panel_split(const LUFront* fr, int nf, int jb, int nb, int max_m1
   if (nf <= 0) return;
   REQUIRE(nb == 32, HSSMF_EINVAL, "panel width");
   REQUIRE(lu_panel_split_fits(max_m1, nb), HSSMF_EINVAL, "panel too tall for LDS");
-  hipEvent_t e0, e1;
-  prof::ext(3, flops, &e0, &e1);   // timing hook (no-op when off)
-  hipExtLaunchKernelGGL(lu_panel11_kernel, dim3(nf), dim3(256), (size_t)std::max(max_m1, 1) * nb * sizeof(double), s,
-                        e0, e1, 0, fr, jb, nb, info);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (prof::enabled()) prof::ext(3, flops, &e0, &e1);   // timing hook
+  const size_t lds = (size_t)std::max(max_m1, 1) * nb * sizeof(double);
+  if (e0) hipExtLaunchKernelGGL(lu_panel11_kernel, dim3(nf), dim3(256), lds, s, e0, e1, 0, fr, jb, nb, info);
+  else hipLaunchKernelGGL(lu_panel11_kernel, dim3(nf), dim3(256), lds, s, fr, jb, nb, info);
   HIP_CHECK(hipGetLastError());
   if (max_u > 0) {
     hipLaunchKernelGGL(lu_panel21_kernel<32>, dim3((max_u + 255) / 256, nf), dim3(256), 0, s, fr, jb);
@@ -263,9 +264,10 @@ void launch_lu_panel_split(const LUFront* fr, int nf, int jb, int nb, int max_m1
 void launch_lu_panel(const LUFront* fr, int nf, int jb, int nb, int* info, hipStream_t s, double flops) {
   if (nf <= 0) return;
   REQUIRE(nb <= 64, HSSMF_EINVAL, "panel width");
-  hipEvent_t e0, e1;
-  prof::ext(3, flops, &e0, &e1);   // timing hook (no-op when off)
-  hipExtLaunchKernelGGL(lu_panel_kernel, dim3(nf), dim3(256), 0, s, e0, e1, 0, fr, jb, nb, info);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (prof::enabled()) prof::ext(3, flops, &e0, &e1);   // timing hook
+  if (e0) hipExtLaunchKernelGGL(lu_panel_kernel, dim3(nf), dim3(256), 0, s, e0, e1, 0, fr, jb, nb, info);
+  else hipLaunchKernelGGL(lu_panel_kernel, dim3(nf), dim3(256), 0, s, fr, jb, nb, info);
   HIP_CHECK(hipGetLastError());
 }
 
@@ -333,9 +335,23 @@ __global__ __launch_bounds__(256) void gemv_kernel(const GemvDesc* __restrict__ 
     __shared__ double red[4][64];
     double acc = 0.0;
     if (r < d.rows && d.alpha != 0.0) {
-      for (int j = ph; j < d.cols; j += 4) {
-        int xj = d.xmap ? d.xmap[j] : j;
-        acc += d.M[r + (int64_t)j * d.ld] * d.x[xj];
+      // eight columns' loads in flight per step; the sum keeps column order
+      for (int j0 = ph; j0 < d.cols; j0 += 32) {
+        double mv[8], xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int j = j0 + 4 * u;
+          mv[u] = 0.0;
+          xv[u] = 0.0;
+          if (j < d.cols) {
+            const int xj = d.xmap ? d.xmap[j] : j;
+            mv[u] = d.M[r + (int64_t)j * d.ld];
+            xv[u] = d.x[xj];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (j0 + 4 * u < d.cols) acc += mv[u] * xv[u];
       }
     }
     if (blockIdx.x * 64 >= d.rows) return;
@@ -352,10 +368,24 @@ __global__ __launch_bounds__(256) void gemv_kernel(const GemvDesc* __restrict__ 
     if (c >= d.cols) return;
     double acc = 0.0;
     const double* col = d.M + (int64_t)c * d.ld;
-    for (int i = lane; i < d.rows && d.alpha != 0.0; i += 64) {
-      int xi = d.xmap ? d.xmap[i] : i;
-      acc += col[i] * d.x[xi];
-    }
+    if (d.alpha != 0.0)
+      for (int i0 = lane; i0 < d.rows; i0 += 512) {
+        double mv[8], xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = i0 + 64 * u;
+          mv[u] = 0.0;
+          xv[u] = 0.0;
+          if (i < d.rows) {
+            const int xi = d.xmap ? d.xmap[i] : i;
+            mv[u] = col[i];
+            xv[u] = d.x[xi];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (i0 + 64 * u < d.rows) acc += mv[u] * xv[u];
+      }
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
     if (lane == 0) {
       int yc = d.ymap ? d.ymap[c] : c;
@@ -384,14 +414,20 @@ __global__ __launch_bounds__(256) void trsv_kernel(const TrsvDesc* __restrict__ 
   double (*Tb)[65] = reinterpret_cast<double (*)[65]>(xs + ((d.s + 1) & ~1));
   const int s = d.s, tid = threadIdx.x, lane = tid & 63;
   const int64_t ld = d.ld;
+  __shared__ int pv[256];   // pivot indices, staged 256 at a time for the sequential swaps
   for (int i = tid; i < s; i += 256) xs[i] = d.x[i];
   __syncthreads();
-  if (KIND == 0 && d.ipiv && tid == 0)
-    for (int i = 0; i < s; ++i) {
-      int p = d.ipiv[i];
-      if (p != i) { double t = xs[i]; xs[i] = xs[p]; xs[p] = t; }
+  if (KIND == 0 && d.ipiv)
+    for (int c0 = 0; c0 < s; c0 += 256) {
+      if (c0 + tid < s) pv[tid] = d.ipiv[c0 + tid];
+      __syncthreads();
+      if (tid == 0)
+        for (int i = c0; i < min(s, c0 + 256); ++i) {
+          const int p = pv[i - c0];
+          if (p != i) { double t = xs[i]; xs[i] = xs[p]; xs[p] = t; }
+        }
+      __syncthreads();
     }
-  __syncthreads();
   // logical matrix T: KIND 0: L (unit lower), 1: U (upper), 2: U^T (lower),
   // 3: L^T (unit upper), 4: L (non-unit lower), 5: L^T (non-unit upper)
   constexpr bool trans = (KIND == 2 || KIND == 3 || KIND == 5);
@@ -406,6 +442,20 @@ __global__ __launch_bounds__(256) void trsv_kernel(const TrsvDesc* __restrict__ 
       const int r = trans ? slow : fast, c = trans ? fast : slow;
       if (r < bs && c < bs) Tb[r][c] = T(b0 + r, b0 + c);
     }
+  };
+  // sum over the block's columns of T(i, b0 + j) x(b0 + j), sixteen loads in
+  // flight at a time, in column order
+  auto row_dot = [&](int i, int b0, int bs) {
+    double acc = 0.0;
+    for (int j0 = 0; j0 < bs; j0 += 16) {
+      double tv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) tv[u] = (j0 + u < bs) ? T(i, b0 + j0 + u) : 0.0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (j0 + u < bs) acc += tv[u] * xs[b0 + j0 + u];
+    }
+    return acc;
   };
   constexpr bool lower = (KIND == 0 || KIND == 2 || KIND == 4);
   constexpr bool unit = (KIND == 0 || KIND == 3);
@@ -424,11 +474,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(const TrsvDesc* __restrict__ 
         if (lane < bs) xs[b0 + lane] = v;
       }
       __syncthreads();
-      for (int i = b0 + bs + tid; i < s; i += 256) {
-        double acc = 0.0;
-        for (int j = 0; j < bs; ++j) acc += T(i, b0 + j) * xs[b0 + j];
-        xs[i] -= acc;
-      }
+      for (int i = b0 + bs + tid; i < s; i += 256) xs[i] -= row_dot(i, b0, bs);
       __syncthreads();
     }
   } else {
@@ -446,18 +492,21 @@ __global__ __launch_bounds__(256) void trsv_kernel(const TrsvDesc* __restrict__ 
         if (lane < bs) xs[b0 + lane] = v;
       }
       __syncthreads();
-      for (int i = tid; i < b0; i += 256) {
-        double acc = 0.0;
-        for (int j = 0; j < bs; ++j) acc += T(i, b0 + j) * xs[b0 + j];
-        xs[i] -= acc;
-      }
+      for (int i = tid; i < b0; i += 256) xs[i] -= row_dot(i, b0, bs);
       __syncthreads();
     }
   }
-  if (KIND == 3 && d.ipiv && tid == 0)
-    for (int i = s - 1; i >= 0; --i) {
-      int p = d.ipiv[i];
-      if (p != i) { double t = xs[i]; xs[i] = xs[p]; xs[p] = t; }
+  if (KIND == 3 && d.ipiv)
+    for (int c1 = s; c1 > 0; c1 -= 256) {
+      const int c0 = max(0, c1 - 256);
+      __syncthreads();
+      if (c0 + tid < c1) pv[tid] = d.ipiv[c0 + tid];
+      __syncthreads();
+      if (tid == 0)
+        for (int i = c1 - 1; i >= c0; --i) {
+          const int p = pv[i - c0];
+          if (p != i) { double t = xs[i]; xs[i] = xs[p]; xs[p] = t; }
+        }
     }
   __syncthreads();
   for (int i = tid; i < s; i += 256) d.x[i] = xs[i];

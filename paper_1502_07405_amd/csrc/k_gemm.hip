@@ -253,21 +253,19 @@ void launch_tiles(const std::vector<GemmDesc>& d, int64_t tiles, GemmType type, 
   GemmDesc* dd = st.put_vec(d, s);
   dim3 grid((unsigned)tiles), blk(256);
   const int n = (int)d.size();
-  hipEvent_t e0, e1;
-  prof::ext(type == GEMM_F64 ? 1 : 2, flops, &e0, &e1);   // timing hook (no-op when off)
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (prof::enabled()) prof::ext(type == GEMM_F64 ? 1 : 2, flops, &e0, &e1);   // timing hook
+#define HSSMF_GEMM_LAUNCH(K)                                                      \
+  if (e0) hipExtLaunchKernelGGL(K, grid, blk, 0, s, e0, e1, 0, dd, n);            \
+  else hipLaunchKernelGGL(K, grid, blk, 0, s, dd, n);
   switch (type) {
-    case GEMM_F64: hipExtLaunchKernelGGL(gemm_f64_kernel, grid, blk, 0, s, e0, e1, 0, dd, n); break;
-    case GEMM_F32: hipExtLaunchKernelGGL((gemm_lp_kernel<float, float>), grid, blk, 0, s, e0, e1, 0, dd, n); break;
-    case GEMM_F32_D:
-      hipExtLaunchKernelGGL((gemm_lp_kernel<float, double>), grid, blk, 0, s, e0, e1, 0, dd, n);
-      break;
-    case GEMM_BF16:
-      hipExtLaunchKernelGGL((gemm_lp_kernel<__bf16, float>), grid, blk, 0, s, e0, e1, 0, dd, n);
-      break;
-    case GEMM_BF16_D:
-      hipExtLaunchKernelGGL((gemm_lp_kernel<__bf16, double>), grid, blk, 0, s, e0, e1, 0, dd, n);
-      break;
+    case GEMM_F64: HSSMF_GEMM_LAUNCH(gemm_f64_kernel) break;
+    case GEMM_F32: HSSMF_GEMM_LAUNCH((gemm_lp_kernel<float, float>)) break;
+    case GEMM_F32_D: HSSMF_GEMM_LAUNCH((gemm_lp_kernel<float, double>)) break;
+    case GEMM_BF16: HSSMF_GEMM_LAUNCH((gemm_lp_kernel<__bf16, float>)) break;
+    case GEMM_BF16_D: HSSMF_GEMM_LAUNCH((gemm_lp_kernel<__bf16, double>)) break;
   }
+#undef HSSMF_GEMM_LAUNCH
   HIP_CHECK(hipGetLastError());
 }
 }  // namespace

@@ -191,20 +191,43 @@ void launch_interp_dense(const InterpDesc* d, int nd, int64_t max_elems, hipStre
 }
 
 // ---------------------------------------------------- row interchanges ---
-__global__ void pivots_kernel(double* M, int ld, int ncols, const int* ipiv, int k, int reverse) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncols) return;
-  double* col = M + (int64_t)c * ld;
-  if (!reverse) {
-    for (int i = 0; i < k; ++i) { int p = ipiv[i]; if (p != i) { double t = col[i]; col[i] = col[p]; col[p] = t; } }
-  } else {
-    for (int i = k - 1; i >= 0; --i) { int p = ipiv[i]; if (p != i) { double t = col[i]; col[i] = col[p]; col[p] = t; } }
+// Row interchanges ipiv[0..k) (LAPACK order; reverse = undo them) applied to
+// every column of M.  The interchange sequence is first folded into a
+// permutation (one workgroup, in LDS), then every column is permuted through
+// LDS: row i of the result is row perm[i] of the input.
+__global__ __launch_bounds__(256) void perm_from_ipiv_kernel(const int* __restrict__ ipiv, int k, int* perm,
+                                                             int reverse) {
+  extern __shared__ int pm[];   // 2k ints: permutation, then the interchanges
+  int* iv = pm + k;
+  for (int i = threadIdx.x; i < k; i += 256) {
+    pm[i] = i;
+    iv[i] = ipiv[i];
   }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (!reverse)
+      for (int i = 0; i < k; ++i) { const int p = iv[i]; const int t = pm[i]; pm[i] = pm[p]; pm[p] = t; }
+    else
+      for (int i = k - 1; i >= 0; --i) { const int p = iv[i]; const int t = pm[i]; pm[i] = pm[p]; pm[p] = t; }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < k; i += 256) perm[i] = pm[i];
 }
 
-void launch_pivots(double* M, int ld, int ncols, const int* ipiv, int k, int reverse, hipStream_t s) {
+__global__ __launch_bounds__(256) void permute_rows_kernel(double* M, int ld, int k, const int* __restrict__ perm) {
+  extern __shared__ double cv[];
+  double* col = M + (int64_t)blockIdx.x * ld;
+  for (int i = threadIdx.x; i < k; i += 256) cv[i] = col[i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < k; i += 256) col[i] = cv[perm[i]];
+}
+
+void launch_pivots(double* M, int ld, int ncols, const int* ipiv, int k, int reverse, int* perm_ws, hipStream_t s) {
   if (ncols <= 0 || k <= 0) return;
-  hipLaunchKernelGGL(pivots_kernel, dim3((ncols + 255) / 256), dim3(256), 0, s, M, ld, ncols, ipiv, k, reverse);
+  REQUIRE((size_t)k * 8 <= 64 * 1024, HSSMF_EINVAL, "row interchanges: more than 8192 rows");
+  hipLaunchKernelGGL(perm_from_ipiv_kernel, dim3(1), dim3(256), (size_t)k * 2 * sizeof(int), s, ipiv, k, perm_ws,
+                     reverse);
+  hipLaunchKernelGGL(permute_rows_kernel, dim3(ncols), dim3(256), (size_t)k * sizeof(double), s, M, ld, k, perm_ws);
   HIP_CHECK(hipGetLastError());
 }
 

@@ -539,14 +539,14 @@ void launch_id_step(const IDProb* p, const int2* wgmap, int total_wg, int t, int
   if (total_wg <= 0) return;
   size_t lds = (size_t)std::max(max_d, 1) * sizeof(double);
   REQUIRE(lds <= 48 * 1024, HSSMF_ERANK, "interpolative decomposition: more than 6144 samples");
-  hipEvent_t e0, e1;
-  prof::ext(0, 0.0, &e0, &e1);   // timing hook (no-op when off); work is added per pass
-  if (max_d <= 64 * 4)
-    hipExtLaunchKernelGGL(id_step_kernel<4>, dim3(total_wg), dim3(256), lds, s, e0, e1, 0, p, wgmap, t);
-  else if (max_d <= 64 * 10)
-    hipExtLaunchKernelGGL(id_step_kernel<10>, dim3(total_wg), dim3(256), lds, s, e0, e1, 0, p, wgmap, t);
-  else
-    hipExtLaunchKernelGGL(id_step_kernel<16>, dim3(total_wg), dim3(256), lds, s, e0, e1, 0, p, wgmap, t);
+  auto fn = max_d <= 64 * 4 ? id_step_kernel<4> : max_d <= 64 * 10 ? id_step_kernel<10> : id_step_kernel<16>;
+  if (prof::enabled()) {
+    hipEvent_t e0, e1;
+    prof::ext(0, 0.0, &e0, &e1);   // timing hook; the work is added per pass
+    hipExtLaunchKernelGGL(fn, dim3(total_wg), dim3(256), lds, s, e0, e1, 0, p, wgmap, t);
+  } else {
+    hipLaunchKernelGGL(fn, dim3(total_wg), dim3(256), lds, s, p, wgmap, t);
+  }
   HIP_CHECK(hipGetLastError());
 }
 

@@ -145,7 +145,9 @@ struct InterpDesc {
   int m, k, ldd, pad;
 };
 void launch_interp_dense(const InterpDesc* d, int nd, int64_t max_elems, hipStream_t s);
-void launch_pivots(double* M, int ld, int ncols, const int* ipiv, int k, int reverse, hipStream_t s);
+// row interchanges ipiv[0..k) (reverse: undone) on all ncols columns of M;
+// perm_ws: k ints of device workspace
+void launch_pivots(double* M, int ld, int ncols, const int* ipiv, int k, int reverse, int* perm_ws, hipStream_t s);
 // logical T(i,j) = trans ? T[j + i ld] : T[i + j ld]; solve rows [b0, b0+bs) in place
 void launch_trsm_block(const TrsmDesc* d, int nd, int lower, int unit, int trans, int max_cols, hipStream_t s);
 void launch_convert(const double* src, void* dst, int64_t n, int to_bf16, hipStream_t s);
