@@ -97,6 +97,10 @@ typedef struct {
                           are captured once per factorization as a HIP graph
                           (on a private stream) and replayed on the handle's
                           stream; 0: launched one by one */
+  int32_t gemm_tile;   /* FP64 matrix-core GEMM tile side: 0 = chosen per
+                          shape class by the built-in autotuner (timed once
+                          per process), 64 or 128 = forced; the results do
+                          not depend on it */
 } hssmf_opts;
 
 /* id_kernel: STEPWISE (default) = one launch per pivot step for each batch

@@ -97,7 +97,9 @@ enum GemmType {
 class Stager;
 // prints and clears the GEMM shape census when HSSMF_GEMM_CENSUS=1
 void gemm_census_print();
-void gemm_batched(const std::vector<GemmDesc>& d, GemmType t, Stager& st, hipStream_t s);
+// tile_pref: 64 or 128 forces the FP64 tile size, anything else lets the
+// autotuner pick (per process, per shape class; results do not depend on it)
+void gemm_batched(const std::vector<GemmDesc>& d, GemmType t, Stager& st, hipStream_t s, int tile_pref = 0);
 
 // Pinned host ring + device mirror for per-launch descriptor arrays.
 class Stager {

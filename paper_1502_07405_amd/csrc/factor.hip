@@ -46,7 +46,7 @@ CopyDesc Cp(const void* src, int lds, const int* rmap, void* dst, int ldd, int m
 }
 
 void run_gemm(Handle& h, const std::vector<GemmDesc>& v, GemmType t = GEMM_F64) {
-  if (!v.empty()) gemm_batched(v, t, h.stager, h.st);
+  if (!v.empty()) gemm_batched(v, t, h.stager, h.st, h.o.gemm_tile);
 }
 
 void run_copy(Handle& h, const std::vector<CopyDesc>& v) {

@@ -10,6 +10,7 @@
 // extend-add into the product.
 #include <cstdlib>
 #include <map>
+#include <mutex>
 
 #include "common.hpp"
 
@@ -140,6 +141,101 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restric
       }
 }
 
+// 128 x 128 tiles for large products: four wavefronts each own a 64 x 64
+// quadrant (4 x 4 MFMA blocks).  Every output accumulates over k in the same
+// order as gemm_f64_kernel (k-tiles of 16, one 16x16x4 MFMA per 4), so the
+// two kernels give identical results; the choice between them is speed only.
+__global__ __launch_bounds__(256) void gemm_f64_128_kernel(const GemmDesc* __restrict__ descs, int nd) {
+  constexpr int BM = 128, BN = 128, TK = 16, PER = BM * TK / 256;
+  __shared__ double As[2][TK][BM + 1];
+  __shared__ double Bs[2][TK][BN + 1];
+  const int di = find_desc(descs, nd, blockIdx.x);
+  const GemmDesc g = descs[di];
+  const int64_t t = blockIdx.x - g.tile_base;
+  if (t >= (int64_t)g.tiles_m * g.tiles_n) return;
+  const int row0 = (int)(t % g.tiles_m) * BM;
+  const int col0 = (int)(t / g.tiles_m) * BN;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave & 1) * 64, wc = (wave >> 1) * 64;
+  auto a_idx = [&](int q, int& i, int& kk) {
+    const int e = tid + 256 * q;
+    if (g.transA) { kk = e % TK; i = e / TK; } else { i = e % BM; kk = e / BM; }
+  };
+  auto b_idx = [&](int q, int& kk, int& j) {
+    const int e = tid + 256 * q;
+    if (g.transB) { j = e % BN; kk = e / BN; } else { kk = e % TK; j = e / TK; }
+  };
+  double ra[PER], rb[PER];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      int i, kk, j, kb;
+      a_idx(q, i, kk);
+      ra[q] = load_a<double>(g, row0 + i, k0 + kk);
+      b_idx(q, kb, j);
+      rb[q] = load_b<double>(g, k0 + kb, col0 + j);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      int i, kk, j, kb;
+      a_idx(q, i, kk);
+      As[buf][kk][i] = ra[q];
+      b_idx(q, kb, j);
+      Bs[buf][kb][j] = rb[q];
+    }
+  };
+  dbl4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = dbl4{0, 0, 0, 0};
+  int buf = 0;
+  if (g.k > 0) {
+    fetch(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int k0 = 0; k0 < g.k; k0 += TK) {
+    const bool more = k0 + TK < g.k;
+    if (more) fetch(k0 + TK);
+#pragma unroll
+    for (int ks = 0; ks < TK; ks += 4) {
+      const int kk = ks + (lane >> 4);
+      double av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[buf][kk][wr + 16 * a + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = Bs[buf][kk][wc + 16 * b + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  double* C = static_cast<double*>(g.C);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = row0 + wr + a * 16 + (lane >> 4) + 4 * v;
+        const int j = col0 + wc + b * 16 + (lane & 15);
+        if (i < g.m && j < g.n) {
+          const int r = g.cmap ? g.cmap[i] : i;
+          double* c = C + r + (int64_t)j * g.ldc;
+          const double val = g.alpha * acc[a][b][v];
+          *c = (g.beta == 0.0) ? val : val + g.beta * (*c);
+        }
+      }
+}
+
 // ------------------------------------------------- FP32 / BF16 inputs -----
 // A, B stored in float (FP32 path) or __bf16 (BF16 path); products
 // accumulate in FP32; C is stored as TOut (float, or double when a low
@@ -249,7 +345,7 @@ namespace {
 size_t in_bytes(GemmType t) { return t == GEMM_F64 ? 8 : (t == GEMM_F32 || t == GEMM_F32_D) ? 4 : 2; }
 
 void launch_tiles(const std::vector<GemmDesc>& d, int64_t tiles, GemmType type, Stager& st, hipStream_t s,
-                  double flops) {
+                  double flops, int tile) {
   GemmDesc* dd = st.put_vec(d, s);
   dim3 grid((unsigned)tiles), blk(256);
   const int n = (int)d.size();
@@ -259,7 +355,10 @@ void launch_tiles(const std::vector<GemmDesc>& d, int64_t tiles, GemmType type, 
   if (e0) hipExtLaunchKernelGGL(K, grid, blk, 0, s, e0, e1, 0, dd, n);            \
   else hipLaunchKernelGGL(K, grid, blk, 0, s, dd, n);
   switch (type) {
-    case GEMM_F64: HSSMF_GEMM_LAUNCH(gemm_f64_kernel) break;
+    case GEMM_F64:
+      if (tile == 128) { HSSMF_GEMM_LAUNCH(gemm_f64_128_kernel) }
+      else { HSSMF_GEMM_LAUNCH(gemm_f64_kernel) }
+      break;
     case GEMM_F32: HSSMF_GEMM_LAUNCH((gemm_lp_kernel<float, float>)) break;
     case GEMM_F32_D: HSSMF_GEMM_LAUNCH((gemm_lp_kernel<float, double>)) break;
     case GEMM_BF16: HSSMF_GEMM_LAUNCH((gemm_lp_kernel<__bf16, float>)) break;
@@ -267,6 +366,73 @@ void launch_tiles(const std::vector<GemmDesc>& d, int64_t tiles, GemmType type, 
   }
 #undef HSSMF_GEMM_LAUNCH
   HIP_CHECK(hipGetLastError());
+}
+
+// tile counts and prefix offsets of a batch for square tiles of side T
+int64_t set_tiles(std::vector<GemmDesc>& d, int T) {
+  int64_t t = 0;
+  for (auto& g : d) {
+    g.tiles_m = (g.m + T - 1) / T;
+    g.tiles_n = (g.n + T - 1) / T;
+    g.tile_base = t;
+    t += (int64_t)g.tiles_m * g.tiles_n;
+  }
+  return t;
+}
+
+// Tile autotuner: the first time an FP64 batch of a given shape class (log2
+// of its largest k, log2 of its 64 x 64 tile count) is large enough to
+// matter, both tile sizes are timed on the same operands with the products
+// written to the workspace, and the faster one is kept for that class for
+// the rest of the process.  The results do not depend on the choice.
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, int>& tune_table() {
+  static std::map<std::pair<int, int>, int> t;
+  return t;
+}
+
+int tuned_tile(const std::vector<GemmDesc>& d, int64_t tiles64, int64_t kmax, double flops, Stager& st,
+               hipStream_t s) {
+  if (flops < 2e8 || tiles64 < 16) return 64;
+  auto lg = [](int64_t v) { int b = 0; while ((int64_t(1) << (b + 1)) <= v) ++b; return b; };
+  const std::pair<int, int> key{lg(std::max<int64_t>(kmax, 1)), lg(tiles64)};
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = tune_table().find(key);
+    if (it != tune_table().end()) return it->second;
+  }
+  int64_t mn = 0;
+  for (auto& g : d) mn += (int64_t)g.m * g.n;
+  int choice = 64;
+  if ((size_t)mn <= st.ws_elems) {
+    std::vector<GemmDesc> tr = d;
+    int64_t off = 0;
+    for (auto& g : tr) {
+      g.C = st.ws + off;
+      g.ldc = g.m;
+      g.cmap = nullptr;
+      g.beta = 0.0;
+      off += (int64_t)g.m * g.n;
+    }
+    hipEvent_t ev[5];
+    for (auto& e : ev) HIP_CHECK(hipEventCreate(&e));
+    HIP_CHECK(hipEventRecord(ev[0], s));
+    for (int rep = 0; rep < 2; ++rep)
+      for (int T : {64, 128}) {
+        const int64_t nt = set_tiles(tr, T);
+        launch_tiles(tr, nt, GEMM_F64, st, s, 0.0, T);
+        HIP_CHECK(hipEventRecord(ev[1 + 2 * rep + (T == 128)], s));
+      }
+    HIP_CHECK(hipEventSynchronize(ev[4]));
+    float t64 = 0, t128 = 0;
+    HIP_CHECK(hipEventElapsedTime(&t64, ev[2], ev[3]));    // second round, 64
+    HIP_CHECK(hipEventElapsedTime(&t128, ev[3], ev[4]));   // second round, 128
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    choice = t128 < t64 ? 128 : 64;
+  }
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  tune_table()[key] = choice;
+  return choice;
 }
 }  // namespace
 
@@ -307,7 +473,7 @@ void gemm_census_print() {
   census().clear();
 }
 
-void gemm_batched(const std::vector<GemmDesc>& in, GemmType type, Stager& st, hipStream_t s) {
+void gemm_batched(const std::vector<GemmDesc>& in, GemmType type, Stager& st, hipStream_t s, int tile_pref) {
   std::vector<GemmDesc> d;
   d.reserve(in.size());
   int64_t tiles = 0;
@@ -340,7 +506,15 @@ void gemm_batched(const std::vector<GemmDesc>& in, GemmType type, Stager& st, hi
   for (auto& g : d) { kmax = std::max<int64_t>(kmax, g.k); mnsum += (int64_t)g.m * g.n; }
   int nsplit = 1;
   while (nsplit < 16 && tiles * nsplit < 1024 && kmax / (2 * nsplit) >= 256) nsplit *= 2;
-  if (nsplit > 1 && (size_t)(mnsum * nsplit) <= st.ws_elems) {
+  const bool split = nsplit > 1 && (size_t)(mnsum * nsplit) <= st.ws_elems;
+  // tile size (FP64 only): forced, or from the autotuner (the split-K
+  // decision above uses the 64 x 64 tile count either way)
+  int tile = 64;
+  if (type == GEMM_F64) {
+    if (tile_pref == 64 || tile_pref == 128) tile = tile_pref;
+    else if (!split) tile = tuned_tile(d, tiles, kmax, flops, st, s);
+  }
+  if (split) {
     std::vector<GemmDesc> parts;
     std::vector<SplitRed> red;
     int64_t wsoff = 0, ptiles = 0;
@@ -377,7 +551,8 @@ void gemm_batched(const std::vector<GemmDesc>& in, GemmType type, Stager& st, hi
     GemmType pt = type;
     if (type == GEMM_F32) pt = GEMM_F32_D;
     if (type == GEMM_BF16) pt = GEMM_BF16_D;
-    launch_tiles(parts, ptiles, pt, st, s, flops);
+    if (tile != 64) ptiles = set_tiles(parts, tile);
+    launch_tiles(parts, ptiles, pt, st, s, flops, tile);
     int64_t mx = 0;
     for (auto& r : red) mx = std::max<int64_t>(mx, (int64_t)r.m * r.n);
     int64_t bx = std::min<int64_t>((mx + 255) / 256, 2048);
@@ -388,9 +563,8 @@ void gemm_batched(const std::vector<GemmDesc>& in, GemmType type, Stager& st, hi
       hipLaunchKernelGGL(splitk_reduce_kernel<double>, dim3((unsigned)bx, (unsigned)red.size()), dim3(256), 0, s, dr);
     HIP_CHECK(hipGetLastError());
   } else {
-    int64_t t = 0;
-    for (auto& g : d) { g.tile_base = t; t += (int64_t)g.tiles_m * g.tiles_n; }
-    launch_tiles(d, tiles, type, st, s, flops);
+    const int64_t nt = set_tiles(d, tile);
+    launch_tiles(d, nt, type, st, s, flops, tile);
   }
   if (ce0) {
     HIP_CHECK(hipEventRecord(ce1, s));

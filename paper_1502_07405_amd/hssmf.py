@@ -45,7 +45,8 @@ class Opts(ctypes.Structure):
                 ("d0", ctypes.c_int32), ("dd", ctypes.c_int32), ("p", ctypes.c_int32), ("d_max", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("gemm_prec", ctypes.c_int32), ("outer", ctypes.c_int32),
                 ("restart", ctypes.c_int32), ("tol", ctypes.c_double), ("max_it", ctypes.c_int32),
-                ("id_kernel", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("id_kernel", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("gemm_tile", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

@@ -104,7 +104,7 @@ def test_rejects_separator_violation(lib, small):
 
 def test_rejects_bad_options(lib, small):
     A, o = small
-    for field, val in (("leaf_size", 0), ("d0", 0), ("dd", 0), ("restart", 0), ("gemm_prec", 7), ("rel_tol", -1.0), ("id_kernel", 5), ("use_graph", 2)):
+    for field, val in (("leaf_size", 0), ("d0", 0), ("dd", 0), ("restart", 0), ("gemm_prec", 7), ("rel_tol", -1.0), ("id_kernel", 5), ("use_graph", 2), ("gemm_tile", 96)):
         opts = H.default_opts(**{field: val})
         assert _call_factor(A.rowptr, A.colind, A.val, o.perm, o.sep_ptr, o.parent, A.n, opts) == H.HSSMF_EINVAL
 

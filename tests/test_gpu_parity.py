@@ -151,6 +151,26 @@ def test_graph_replay_matches_eager_sweeps():
     fe.close()
 
 
+@pytest.mark.parametrize("case", ["p3d20_tightd", "dense_p3d16"])
+def test_gemm_tile_choice_is_bitwise_neutral(case):
+    """The 64 x 64 and 128 x 128 FP64 GEMM kernels accumulate every output
+    in the same order, so forcing either (or letting the autotuner choose)
+    gives bitwise the same factorization."""
+    if case == "dense_p3d16":
+        A, o = P.poisson3d(16), P.geometric_nd((16, 16, 16), 2)
+        kw = {}
+    else:
+        mk, kw = HSS_CASES[case]
+        A, o = mk()
+    b = _t(np.random.default_rng(13).standard_normal(A.n))
+    ys = []
+    for tile in (64, 128, 0):
+        fac = H.Factorization(A, o, gemm_tile=tile, **kw)
+        ys.append(fac.apply(b))
+        fac.close()
+    assert torch.equal(ys[0], ys[1]) and torch.equal(ys[0], ys[2])
+
+
 def test_exact_recovery_as_tolerance_vanishes():
     """eps -> 0: the HSS-multifrontal factorization is a direct solver."""
     A, o = P.convdiff2d(40, 12.0, 9.0), P.geometric_nd((40, 40), 4)
