@@ -175,6 +175,37 @@ def fv_diffusion3d(n, kappa):
     return _coo_to_csr(N, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
 
 
+def fv_diffusion3d_values(n, kappa):
+    """The CSR values of :func:`fv_diffusion3d` (same order) as a function of
+    ``kappa`` written with torch operations, so that a loss computed from the
+    solution can be differentiated with respect to the coefficients by
+    automatic differentiation through the assembly (the chain rule from
+    dL/dval to dL/dkappa)."""
+    import torch
+    N = n ** 3
+    idx = np.arange(N)
+    coords = [idx % n, (idx // n) % n, idx // (n * n)]
+    stride = (1, n, n * n)
+    dev = kappa.device
+    diag = torch.zeros(N, dtype=kappa.dtype, device=dev)
+    rows, cols, vals = [], [], []
+    for ax in range(3):
+        for sign in (-1, 1):
+            ok = (coords[ax] + sign >= 0) & (coords[ax] + sign < n)
+            a = idx[ok]
+            nb = a + sign * stride[ax]
+            ta = torch.as_tensor(a, device=dev)
+            kc, kn = kappa[ta], kappa[torch.as_tensor(nb, device=dev)]
+            t = 2.0 * kc * kn / (kc + kn)
+            rows.append(a); cols.append(nb); vals.append(-t)
+            diag = diag.index_add(0, ta, t)
+            bd = torch.as_tensor(idx[~ok], device=dev)
+            diag = diag.index_add(0, bd, 2.0 * kappa[bd])
+    rows.append(idx); cols.append(idx); vals.append(diag)
+    order = np.lexsort((np.concatenate(cols), np.concatenate(rows)))
+    return torch.cat(vals)[torch.as_tensor(order, device=dev)]
+
+
 # ---------------------------------------------------------------------------
 # geometric nested dissection
 # ---------------------------------------------------------------------------
