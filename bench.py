@@ -84,6 +84,22 @@ KERNEL_NAME = {"id": "id_step_kernel (pivot steps of the column-pivoted QR behin
 BOUND = {"id": ("alu", FP64_PEAK_TFLOPS), "gemm64": ("mfma", FP64_PEAK_TFLOPS),
          "gemmlp": ("mfma", None), "lupanel": ("alu", FP64_PEAK_TFLOPS)}
 LP_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
+# HBM bytes per launch of the pivot-step kernel on this workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; each scaled by its reading for
+# a 256 MiB device copy): profiles/id_step_hbm_traffic_poisson3d_64.md.  Valid
+# only for the kernel source those counters were taken on.
+TRAFFIC = {"id": (28.14e6, "paper_1502_07405_amd/csrc/k_id.hip", "0898907207216ea3")}
+
+
+def traffic_for(cls):
+    import hashlib
+    if cls not in TRAFFIC:
+        return None
+    nbytes, src, digest = TRAFFIC[cls]
+    with open(os.path.join(ROOT, src), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest()[:16] != digest:
+            return None   # the kernel changed since the counters were taken
+    return nbytes
 
 
 def main():
@@ -96,6 +112,9 @@ def main():
     ap.add_argument("--no-dense", action="store_true", help="skip the all-dense multifrontal comparison")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 attempt")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="program for the HBM counter runs: a 256 MiB device copy (calibration), then one "
+                         "factorization and one refactorization of the headline workload; prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this solver path runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -106,6 +125,16 @@ def main():
 
     w = P.WORKLOADS["poisson3d_64"]
     A, order, b = P.workload(**w)
+    if args.traffic_probe:
+        xc = torch.ones(32 << 20, dtype=torch.float64, device="cuda:0")
+        torch.empty_like(xc).copy_(xc)
+        torch.cuda.synchronize()
+        fp = H.Factorization(A, order, **hss_opts(args.prec))
+        fp.refactor(A.val)
+        torch.cuda.synchronize()
+        fp.close()
+        print("traffic probe done", flush=True)
+        return
     S = A.to_scipy()
     dev = torch.device("cuda:0")
     bt = torch.tensor(b, device=dev)
@@ -144,7 +173,7 @@ def main():
     if peak is None:
         peak = LP_PEAK_TFLOPS[args.prec]
     roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": None, "kernel": KERNEL_NAME[dom], "avg_launch_ms": avg_ms, "launches": launches,
+            "traffic": traffic_for(dom), "traffic_unit": "bytes per launch (HBM)", "kernel": KERNEL_NAME[dom], "avg_launch_ms": avg_ms, "launches": launches,
             "time_share": ms / (sec_hooked * 1e3 * args.steps)}
     extra = {"step_s_with_timing_hooks": sec_hooked, "iterations": infos[-1][0], "rel_residual": relres(x), "max_rank": st["max_rank"],
              "max_d": st["max_d"], "growth_rounds": st["growth_rounds"],
