@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "factor+solve sec @1e-10 residual, 64^3 Poisson: mixed vs FP64 HSS; % roofline"
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 (vector and matrix cores)
+HBM_PEAK_BPS = 8.0e12     # MI355X HBM3E
 
 
 def hss_opts(prec):
@@ -172,8 +173,11 @@ def main():
     bound, peak = BOUND[dom]
     if peak is None:
         peak = LP_PEAK_TFLOPS[args.prec]
+    traffic = traffic_for(dom)
     roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": traffic_for(dom), "traffic_unit": "bytes per launch (HBM)", "kernel": KERNEL_NAME[dom], "avg_launch_ms": avg_ms, "launches": launches,
+            "traffic": traffic, "traffic_unit": "bytes per launch (HBM)",
+            "hbm_GBps_from_traffic": (traffic / (avg_ms * 1e-3) / 1e9) if traffic and avg_ms > 0 else None,
+            "hbm_frac_from_traffic": (traffic / (avg_ms * 1e-3) / HBM_PEAK_BPS) if traffic and avg_ms > 0 else None, "kernel": KERNEL_NAME[dom], "avg_launch_ms": avg_ms, "launches": launches,
             "time_share": ms / (sec_hooked * 1e3 * args.steps)}
     extra = {"step_s_with_timing_hooks": sec_hooked, "iterations": infos[-1][0], "rel_residual": relres(x), "max_rank": st["max_rank"],
              "max_d": st["max_d"], "growth_rounds": st["growth_rounds"],

@@ -139,6 +139,8 @@ void end(int token, hipStream_t s);
 // one timed kernel: events for hipExtLaunchKernelGGL, which stamps them with
 // that kernel's own start and end (nullptr events and -1 when off)
 int ext(int kclass, double flops, hipEvent_t* start, hipEvent_t* stop);
+// waits for a class's recorded events; summed ms, launches and work; resets
+int read(int kclass, double* ms, int64_t* launches, double* flops);
 }  // namespace prof
 
 }  // namespace hssmf

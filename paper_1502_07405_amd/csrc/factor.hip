@@ -11,6 +11,7 @@
 // F22 - Theta^* Phi for the parent.  Only ranks and pivot orders of the IDs
 // come back to the host (one synchronization per HSS level).
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 
@@ -1030,9 +1031,19 @@ static void debug_fronts(Handle& h, std::vector<HFront*>& fs) {
 // -------------------------------------------------------- numeric ---------
 void numeric_factor(Handle& h) {
   const Plan& P = h.P;
+  // diagnostics: HSSMF_LEVEL_TIMES=1 prints the time of the dense and the
+  // HSS part of every elimination-tree level (synchronizing between them)
+  static const bool level_times = std::getenv("HSSMF_LEVEL_TIMES") != nullptr;
+  auto wall = []() { return std::chrono::duration<double, std::milli>(
+                         std::chrono::steady_clock::now().time_since_epoch()).count(); };
   HIP_CHECK(hipMemsetAsync(h.d_info, 0, sizeof(int), h.st));
   for (size_t lev = 0; lev < P.levels.size(); ++lev) {
     const std::vector<int>& ids = P.levels[lev];
+    double tl0 = 0.0, tl1 = 0.0;
+    if (level_times) {
+      HIP_CHECK(hipStreamSynchronize(h.st));
+      tl0 = wall();
+    }
     // dense fronts
     std::vector<LUFront> lu;
     int64_t total = 0;
@@ -1069,6 +1080,10 @@ void numeric_factor(Handle& h) {
       }
       blocked_lu(h, lu);
     }
+    if (level_times) {
+      HIP_CHECK(hipStreamSynchronize(h.st));
+      tl1 = wall();
+    }
     // HSS fronts
     std::vector<HFront*> fs;
     for (int f : ids)
@@ -1099,9 +1114,35 @@ void numeric_factor(Handle& h) {
           launch_copy(h.stager.put_vec(cv, h.st), (int)cv.size(), mx, 1, h.st);
         }
       }
+      double tp[4] = {0, 0, 0, 0};
+      auto mark = [&](int i) {
+        if (!level_times) return;
+        HIP_CHECK(hipStreamSynchronize(h.st));
+        tp[i] = wall();
+      };
+      mark(0);
       compress_level(h, fs, fops, d_iota);
+      mark(1);
       ulv_level(h, fs, d_iota);
+      mark(2);
       schur_level(h, fs);
+      mark(3);
+      if (level_times && prof::enabled()) {
+        double ms[3];
+        int64_t nl[3];
+        for (int c = 0; c < 3; ++c) prof::read(c, &ms[c], &nl[c], nullptr);
+        std::fprintf(stderr, "   kernel classes: ID steps %.2f ms (%lld launches)  GEMM64 %.2f ms (%lld)  GEMMLP %.2f ms\n",
+                     ms[0], (long long)nl[0], ms[1], (long long)nl[1], ms[2]);
+      }
+      if (level_times) {
+        int rounds = 0, maxr = 0;
+        for (HFront* F : fs) {
+          rounds = std::max(rounds, F->rounds);
+          for (auto& nd : F->nd) maxr = std::max(maxr, std::max(nd.r, nd.c));
+        }
+        std::fprintf(stderr, "   hss phases: compress %8.2f ms (rounds %d, max rank %d)  ulv %8.2f ms  schur %8.2f ms\n",
+                     tp[1] - tp[0], rounds, maxr, tp[2] - tp[1], tp[3] - tp[2]);
+      }
       if (std::getenv("HSSMF_DEBUG")) debug_fronts(h, fs);
     }
     // check for zero pivots after each level
@@ -1113,6 +1154,9 @@ void numeric_factor(Handle& h) {
       h.failed_front = info - 1;
       throw Error(HSSMF_ESINGULAR, "zero pivot in front " + std::to_string(info - 1), info - 1);
     }
+    if (level_times)
+      std::fprintf(stderr, "level %2zu: %5zu fronts (%zu HSS)  dense %8.2f ms  hss %8.2f ms\n", lev, ids.size(),
+                   fs.size(), tl1 - tl0, wall() - tl1);
   }
 }
 
