@@ -171,6 +171,38 @@ def test_gemm_tile_choice_is_bitwise_neutral(case):
     assert torch.equal(ys[0], ys[1]) and torch.equal(ys[0], ys[2])
 
 
+def test_mixed_precision_sampling():
+    """Sampling products in FP32 (FP32 accumulation) with FP64 rank
+    decisions, ULV and refinement: the preconditioner stays within 1e-4 of
+    the FP64 one at eps = 1e-6 (FP32 sample noise ~1e-7 of the sampled block,
+    below eps), ranks stay within 4 of FP64 per front, and refinement still
+    reaches 1e-10.  BF16 products (noise ~2^-9) cannot resolve eps = 1e-6:
+    adaptive sampling reaches d_max (ERANK); with eps = 1e-2, above that
+    floor, the BF16 preconditioner converges."""
+    A, o = P.poisson3d(20), P.geometric_nd((20, 20, 20), 4)
+    kw = dict(min_sep_hss=100, leaf_size=40, d0=16, dd=16, p=6, d_max=400, max_it=200)
+    b = _t(np.random.default_rng(4).standard_normal(A.n))
+    S = A.to_scipy()
+    f64 = H.Factorization(A, o, rel_tol=1e-6, gemm_prec="fp64", **kw)
+    f32 = H.Factorization(A, o, rel_tol=1e-6, gemm_prec="fp32", **kw)
+    y64, y32 = f64.apply(b), f32.apply(b)
+    assert float(torch.linalg.norm(y32 - y64) / torch.linalg.norm(y64)) <= 1e-4
+    for r64, r32 in zip(f64.hss_ranks(), f32.hss_ranks()):
+        assert r64[0] == r32[0] and abs(r64[1] - r32[1]) <= 4, (r64, r32)
+    x, info = f32.solve(b)
+    bh = b.cpu().numpy()
+    assert np.linalg.norm(bh - S @ x.cpu().numpy()) <= 1e-10 * np.linalg.norm(bh)
+    f64.close()
+    f32.close()
+    with pytest.raises(H.HssmfError) as e:
+        H.Factorization(A, o, rel_tol=1e-6, gemm_prec="bf16", **kw)
+    assert e.value.code == H.HSSMF_ERANK
+    fb = H.Factorization(A, o, rel_tol=1e-2, gemm_prec="bf16", **kw)
+    x, info = fb.solve(b)
+    assert np.linalg.norm(bh - S @ x.cpu().numpy()) <= 1e-10 * np.linalg.norm(bh)
+    fb.close()
+
+
 def test_exact_recovery_as_tolerance_vanishes():
     """eps -> 0: the HSS-multifrontal factorization is a direct solver."""
     A, o = P.convdiff2d(40, 12.0, 9.0), P.geometric_nd((40, 40), 4)
