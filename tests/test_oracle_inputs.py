@@ -176,3 +176,17 @@ def test_fv_assembly_values_and_their_gradient():
     km[c] -= h
     fd = (P.fv_diffusion3d(n, kp).val - P.fv_diffusion3d(n, km).val) @ w / (2 * h)
     assert abs(kt.grad[c].item() - fd) <= 1e-7 * max(1.0, abs(fd))
+
+
+def test_convdiff_batch_recipe():
+    """The 256-system convection-diffusion batch: sides in [48, 160], speeds
+    in [0, 20], total unknowns 3,100,693 and 140,346 fronts with 8^2 leaves;
+    every system is its own elimination tree (one root)."""
+    systems = P.convdiff_batch()
+    assert len(systems) == 256
+    sides = [int(round(np.sqrt(A.n))) for A, _, _ in systems]
+    assert min(sides) >= 48 and max(sides) <= 160
+    assert sum(A.n for A, _, _ in systems) == 3100693
+    assert sum(len(o.parent) for _, o, _ in systems) == 140346
+    for A, o, b in systems[:8]:
+        assert int((o.parent == -1).sum()) == 1 and b.shape == (A.n,)
