@@ -97,10 +97,11 @@ typedef struct {
                           are captured once per factorization as a HIP graph
                           (on a private stream) and replayed on the handle's
                           stream; 0: launched one by one */
-  int32_t gemm_tile;   /* FP64 matrix-core GEMM tile side: 0 = chosen per
+  int32_t gemm_tile;   /* FP64 matrix-core GEMM kernel: 0 = chosen per
                           shape class by the built-in autotuner (timed once
-                          per process), 64 or 128 = forced; the results do
-                          not depend on it */
+                          per process); forced: 64 (64 x 64 tiles, k-tiles of
+                          16), 65 (64 x 64, k-tiles of 32), 128 (128 x 128);
+                          the results do not depend on it */
 } hssmf_opts;
 
 /* id_kernel: STEPWISE (default) = one launch per pivot step for each batch

@@ -416,7 +416,7 @@ bool opts_ok(const hssmf_opts* o) {
   return !(o->leaf_size < 1 || o->d0 < 1 || o->dd < 1 || o->p < 0 || o->d_max < o->d0 || !(o->rel_tol >= 0.0) ||
            o->restart < 1 || o->max_it < 0 || o->gemm_prec < 0 || o->gemm_prec > 2 || o->id_kernel < 0 ||
            o->id_kernel > 1 || o->use_graph < 0 || o->use_graph > 1 ||
-           !(o->gemm_tile == 0 || o->gemm_tile == 64 || o->gemm_tile == 128));
+           !(o->gemm_tile == 0 || o->gemm_tile == 64 || o->gemm_tile == 65 || o->gemm_tile == 128));
 }
 
 int factor_impl(const hssmf_csr* A, const hssmf_ordering* ord, const hssmf_opts* opts, void* stream, void** out,

@@ -50,11 +50,13 @@ __device__ __forceinline__ T load_b(const GemmDesc& g, int kk, int j) {
 }
 
 // ---------------------------------------------------------------- FP64 -----
-// k-tiles of 16 double-buffered in LDS: while the matrix cores work on tile
-// k0, every thread already holds its share of tile k0+16 in registers and
-// stores it into the other buffer afterwards (one barrier per k-tile).
+// k-tiles of TK (16 or 32) double-buffered in LDS: while the matrix cores
+// work on tile k0, every thread already holds its share of tile k0+TK in
+// registers and stores it into the other buffer afterwards (one barrier per
+// k-tile).  Each output accumulates over k in the same order for either TK.
+template <int TK>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restrict__ descs, int nd) {
-  constexpr int TK = 16, PER = TM * TK / 256;   // elements of A (and of B) per thread per k-tile
+  constexpr int PER = TM * TK / 256;   // elements of A (and of B) per thread per k-tile
   __shared__ double As[2][TK][TM + 1];
   __shared__ double Bs[2][TK][TN + 1];
   const int di = find_desc(descs, nd, blockIdx.x);
@@ -357,7 +359,8 @@ void launch_tiles(const std::vector<GemmDesc>& d, int64_t tiles, GemmType type, 
   switch (type) {
     case GEMM_F64:
       if (tile == 128) { HSSMF_GEMM_LAUNCH(gemm_f64_128_kernel) }
-      else { HSSMF_GEMM_LAUNCH(gemm_f64_kernel) }
+      else if (tile == 65) { HSSMF_GEMM_LAUNCH(gemm_f64_kernel<32>) }
+      else { HSSMF_GEMM_LAUNCH(gemm_f64_kernel<16>) }
       break;
     case GEMM_F32: HSSMF_GEMM_LAUNCH((gemm_lp_kernel<float, float>)) break;
     case GEMM_F32_D: HSSMF_GEMM_LAUNCH((gemm_lp_kernel<float, double>)) break;
@@ -370,6 +373,7 @@ void launch_tiles(const std::vector<GemmDesc>& d, int64_t tiles, GemmType type, 
 
 // tile counts and prefix offsets of a batch for square tiles of side T
 int64_t set_tiles(std::vector<GemmDesc>& d, int T) {
+  if (T == 65) T = 64;   // 64 x 64 tiles, k-tiles of 32
   int64_t t = 0;
   for (auto& g : d) {
     g.tiles_m = (g.m + T - 1) / T;
@@ -382,9 +386,10 @@ int64_t set_tiles(std::vector<GemmDesc>& d, int T) {
 
 // Tile autotuner: the first time an FP64 batch of a given shape class (log2
 // of its largest k, log2 of its 64 x 64 tile count) is large enough to
-// matter, both tile sizes are timed on the same operands with the products
-// written to the workspace, and the faster one is kept for that class for
-// the rest of the process.  The results do not depend on the choice.
+// matter, the three kernel variants (64 x 64 tiles with k-tiles of 16 or 32,
+// 128 x 128 tiles) are timed on the same operands with the products written
+// to the workspace, and the fastest is kept for that class for the rest of
+// the process.  The results do not depend on the choice.
 std::mutex g_tune_mu;
 std::map<std::pair<int, int>, int>& tune_table() {
   static std::map<std::pair<int, int>, int> t;
@@ -414,21 +419,26 @@ int tuned_tile(const std::vector<GemmDesc>& d, int64_t tiles64, int64_t kmax, do
       g.beta = 0.0;
       off += (int64_t)g.m * g.n;
     }
-    hipEvent_t ev[5];
+    // variants: 64 x 64 with k-tiles of 16 (64), of 32 (65), 128 x 128 (128);
+    // two rounds, the second one timed
+    const int var[3] = {64, 65, 128};
+    hipEvent_t ev[7];
     for (auto& e : ev) HIP_CHECK(hipEventCreate(&e));
     HIP_CHECK(hipEventRecord(ev[0], s));
     for (int rep = 0; rep < 2; ++rep)
-      for (int T : {64, 128}) {
-        const int64_t nt = set_tiles(tr, T);
-        launch_tiles(tr, nt, GEMM_F64, st, s, 0.0, T);
-        HIP_CHECK(hipEventRecord(ev[1 + 2 * rep + (T == 128)], s));
+      for (int vi = 0; vi < 3; ++vi) {
+        const int64_t nt = set_tiles(tr, var[vi]);
+        launch_tiles(tr, nt, GEMM_F64, st, s, 0.0, var[vi]);
+        HIP_CHECK(hipEventRecord(ev[1 + 3 * rep + vi], s));
       }
-    HIP_CHECK(hipEventSynchronize(ev[4]));
-    float t64 = 0, t128 = 0;
-    HIP_CHECK(hipEventElapsedTime(&t64, ev[2], ev[3]));    // second round, 64
-    HIP_CHECK(hipEventElapsedTime(&t128, ev[3], ev[4]));   // second round, 128
+    HIP_CHECK(hipEventSynchronize(ev[6]));
+    float best = 0.0f;
+    for (int vi = 0; vi < 3; ++vi) {
+      float ms = 0.0f;
+      HIP_CHECK(hipEventElapsedTime(&ms, ev[3 + vi], ev[4 + vi]));
+      if (vi == 0 || ms < best) { best = ms; choice = var[vi]; }
+    }
     for (auto& e : ev) (void)hipEventDestroy(e);
-    choice = t128 < t64 ? 128 : 64;
   }
   std::lock_guard<std::mutex> g(g_tune_mu);
   tune_table()[key] = choice;
@@ -511,7 +521,7 @@ void gemm_batched(const std::vector<GemmDesc>& in, GemmType type, Stager& st, hi
   // decision above uses the 64 x 64 tile count either way)
   int tile = 64;
   if (type == GEMM_F64) {
-    if (tile_pref == 64 || tile_pref == 128) tile = tile_pref;
+    if (tile_pref == 64 || tile_pref == 65 || tile_pref == 128) tile = tile_pref;
     else if (!split) tile = tuned_tile(d, tiles, kmax, flops, st, s);
   }
   if (split) {
