@@ -91,6 +91,7 @@ enum GemmType {
   GEMM_F32_D = 2,   // float x float -> double C
   GEMM_BF16 = 3,    // bf16 x bf16 -> float (FP32 accumulation)
   GEMM_BF16_D = 4,  // bf16 x bf16 -> double C
+  GEMM_D_F32 = 5,   // double operands rounded to float on load, FP32 MFMA, double C
 };
 
 // launch a batch of GEMMs (descriptors in host memory; staged to the device)

@@ -984,12 +984,12 @@ void schur_level(Handle& h, std::vector<HFront*>& fs) {
       e2.push_back(G(b.Ubig, b.m(), 0, tb, std::max(b.r, 1), 0, F->Upd + ob + (int64_t)oa * F->u, F->u, b.m(),
                      a.m(), b.r, 1.0, 0.0));
     }
-  run_gemm(h, e1);
-  run_gemm(h, e2);
+  run_gemm(h, e1, h.gs());
+  run_gemm(h, e2, h.gs());
   std::vector<GemmDesc> s;
   for (HFront* F : wu)
     s.push_back(G(F->ThT, F->mk, 1, F->Phi, F->mk, 0, F->Upd, F->u, F->u, F->u, F->mk, -1.0, 1.0));
-  run_gemm(h, s);
+  run_gemm(h, s, h.gs());
 }
 
 }  // namespace

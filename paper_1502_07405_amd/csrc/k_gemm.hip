@@ -271,7 +271,7 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(const GemmDesc* __restrict
       Bs[kk][j] = (float)load_b<TIn>(g, k0 + kk, col0 + j);
     }
     __syncthreads();
-    if constexpr (sizeof(TIn) == 4) {
+    if constexpr (sizeof(TIn) != 2) {   // FP32 inputs, or FP64 inputs rounded to FP32
 #pragma unroll
       for (int ks = 0; ks < TK; ks += 4) {
         const int kk = ks + (lane >> 4);
@@ -344,7 +344,9 @@ __global__ void splitk_reduce_kernel(const SplitRed* __restrict__ rs) {
 
 namespace {
 // element size of the A / B operands of a GEMM type
-size_t in_bytes(GemmType t) { return t == GEMM_F64 ? 8 : (t == GEMM_F32 || t == GEMM_F32_D) ? 4 : 2; }
+size_t in_bytes(GemmType t) {
+  return (t == GEMM_F64 || t == GEMM_D_F32) ? 8 : (t == GEMM_F32 || t == GEMM_F32_D) ? 4 : 2;
+}
 
 void launch_tiles(const std::vector<GemmDesc>& d, int64_t tiles, GemmType type, Stager& st, hipStream_t s,
                   double flops, int tile) {
@@ -364,6 +366,7 @@ void launch_tiles(const std::vector<GemmDesc>& d, int64_t tiles, GemmType type, 
       break;
     case GEMM_F32: HSSMF_GEMM_LAUNCH((gemm_lp_kernel<float, float>)) break;
     case GEMM_F32_D: HSSMF_GEMM_LAUNCH((gemm_lp_kernel<float, double>)) break;
+    case GEMM_D_F32: HSSMF_GEMM_LAUNCH((gemm_lp_kernel<double, double>)) break;
     case GEMM_BF16: HSSMF_GEMM_LAUNCH((gemm_lp_kernel<__bf16, float>)) break;
     case GEMM_BF16_D: HSSMF_GEMM_LAUNCH((gemm_lp_kernel<__bf16, double>)) break;
   }

@@ -173,6 +173,10 @@ struct Handle {
   }
   hssmf_stats stats{};
   GemmType gt() const;
+  // products of the low-rank Schur update and of its dense expansion:
+  // FP64 operands rounded to FP32 on the matrix cores in the low-precision
+  // modes, FP64 otherwise
+  GemmType gs() const { return o.gemm_prec == HSSMF_PREC_FP64 ? GEMM_F64 : GEMM_D_F32; }
 };
 
 void numeric_factor(Handle& h);

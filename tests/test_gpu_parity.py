@@ -173,11 +173,11 @@ def test_gemm_tile_choice_is_bitwise_neutral(case):
 
 
 def test_mixed_precision_sampling():
-    """Sampling products in FP32 (FP32 accumulation) with FP64 rank
-    decisions, ULV and refinement: the preconditioner stays within 1e-4 of
-    the FP64 one at eps = 1e-6 (FP32 sample noise ~1e-7 of the sampled block,
-    below eps), ranks stay within 4 of FP64 per front, and refinement still
-    reaches 1e-10.  BF16 products (noise ~2^-9) cannot resolve eps = 1e-6:
+    """Sampling and Schur-expansion products in FP32 (FP32 accumulation) with
+    FP64 rank decisions, ULV factors and refinement: the preconditioner stays
+    within 1e-4 of the FP64 one at eps = 1e-6 (FP32 rounding perturbs the
+    sampled blocks at ~1e-7, below eps), ranks near the threshold move by at
+    most max(4, 10%) per front, and refinement still reaches 1e-10.  BF16 products (noise ~2^-9) cannot resolve eps = 1e-6:
     adaptive sampling reaches d_max (ERANK); with eps = 1e-2, above that
     floor, the BF16 preconditioner converges."""
     A, o = P.poisson3d(20), P.geometric_nd((20, 20, 20), 4)
@@ -189,7 +189,7 @@ def test_mixed_precision_sampling():
     y64, y32 = f64.apply(b), f32.apply(b)
     assert float(torch.linalg.norm(y32 - y64) / torch.linalg.norm(y64)) <= 1e-4
     for r64, r32 in zip(f64.hss_ranks(), f32.hss_ranks()):
-        assert r64[0] == r32[0] and abs(r64[1] - r32[1]) <= 4, (r64, r32)
+        assert r64[0] == r32[0] and abs(r64[1] - r32[1]) <= max(4, r64[1] // 10), (r64, r32)
     x, info = f32.solve(b)
     bh = b.cpu().numpy()
     assert np.linalg.norm(bh - S @ x.cpu().numpy()) <= 1e-10 * np.linalg.norm(bh)
