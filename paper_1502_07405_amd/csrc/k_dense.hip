@@ -324,23 +324,25 @@ void launch_trsm_u12(const LUFront* fr, int nf, int jb, int nb, int max_n, hipSt
 }
 
 // -------------------------------------------------------------- solves ---
-// batched GEMV: each workgroup owns 64 outputs (non-transposed) or 4
-// outputs (transposed: one wavefront per column dot product)
+// batched GEMV: each workgroup owns 16 outputs (non-transposed: 16 column
+// phases per row, eight loads in flight per thread, partial sums added in
+// phase order) or 4 outputs (transposed: one wavefront per column dot
+// product)
 __global__ __launch_bounds__(256) void gemv_kernel(const GemvDesc* __restrict__ descs) {
   const GemvDesc d = descs[blockIdx.y];
   const int tid = threadIdx.x;
   if (!d.trans) {
-    const int r = blockIdx.x * 64 + (tid & 63);
-    const int ph = tid >> 6;
-    __shared__ double red[4][64];
+    if (blockIdx.x * 16 >= d.rows) return;
+    const int r = blockIdx.x * 16 + (tid & 15);
+    const int ph = tid >> 4;
+    __shared__ double red[16][17];
     double acc = 0.0;
     if (r < d.rows && d.alpha != 0.0) {
-      // eight columns' loads in flight per step; the sum keeps column order
-      for (int j0 = ph; j0 < d.cols; j0 += 32) {
+      for (int j0 = ph; j0 < d.cols; j0 += 128) {
         double mv[8], xv[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          const int j = j0 + 4 * u;
+          const int j = j0 + 16 * u;
           mv[u] = 0.0;
           xv[u] = 0.0;
           if (j < d.cols) {
@@ -351,15 +353,15 @@ __global__ __launch_bounds__(256) void gemv_kernel(const GemvDesc* __restrict__ 
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-          if (j0 + 4 * u < d.cols) acc += mv[u] * xv[u];
+          if (j0 + 16 * u < d.cols) acc += mv[u] * xv[u];
       }
     }
-    if (blockIdx.x * 64 >= d.rows) return;
-    red[ph][tid & 63] = acc;
+    red[ph][tid & 15] = acc;
     __syncthreads();
     if (ph == 0 && r < d.rows) {
-      double v = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-      int yr = d.ymap ? d.ymap[r] : r;
+      double v = 0.0;
+      for (int q = 0; q < 16; ++q) v += red[q][tid];
+      const int yr = d.ymap ? d.ymap[r] : r;
       d.y[yr] = d.overwrite ? d.alpha * v : d.y[yr] + d.alpha * v;
     }
   } else {
@@ -394,11 +396,10 @@ __global__ __launch_bounds__(256) void gemv_kernel(const GemvDesc* __restrict__ 
   }
 }
 
-void launch_gemv(const GemvDesc* d, int nd, int max_out, hipStream_t s) {
-  if (nd <= 0 || max_out <= 0) return;
-  // grid.x covers the larger of the two layouts; workgroups past a
-  // descriptor's extent return immediately
-  int gx = (max_out + 3) / 4;
+// gx: workgroups along x, the largest of ceil(rows / 16) (non-transposed)
+// and ceil(cols / 4) (transposed) over the batch
+void launch_gemv(const GemvDesc* d, int nd, int gx, hipStream_t s) {
+  if (nd <= 0 || gx <= 0) return;
   hipLaunchKernelGGL(gemv_kernel, dim3(gx, nd), dim3(256), 0, s, d);
   HIP_CHECK(hipGetLastError());
 }

@@ -68,7 +68,9 @@ void launch_lu_panel_split(const LUFront* fr, int nf, int jb, int nb, int max_m1
                            double flops = 0.0);
 void launch_laswp(const LUFront* fr, int nf, int jb, int nb, int max_n, hipStream_t s);
 void launch_trsm_u12(const LUFront* fr, int nf, int jb, int nb, int max_n, hipStream_t s);
-void launch_gemv(const GemvDesc* d, int nd, int max_rows, hipStream_t s);
+// gx: workgroups along x (ceil(rows / 16) non-transposed, ceil(cols / 4)
+// transposed, the largest over the batch)
+void launch_gemv(const GemvDesc* d, int nd, int gx, hipStream_t s);
 // kind: 0 = L^{-1} P (unit lower, pivots first), 1 = U^{-1} (upper),
 // 2 = U^{-T}, 3 = P^T L^{-T} (unit, pivots last), 4 = L^{-1} (non-unit
 // lower), 5 = L^{-T} (non-unit lower, transposed)

@@ -39,7 +39,7 @@ struct Rec {
     for (auto& g : v)
       if (g.rows > 0 && g.cols > 0) {
         w.push_back(g);
-        mx = std::max<int64_t>(mx, g.trans ? g.cols : g.rows);
+        mx = std::max<int64_t>(mx, g.trans ? (g.cols + 3) / 4 : (g.rows + 15) / 16);
       } else if (g.overwrite && (g.trans ? g.cols : g.rows) > 0) {
         // an empty product still has to clear its output
         GemvDesc z = g;
@@ -47,7 +47,7 @@ struct Rec {
         z.cols = std::max(z.cols, 1);
         z.rows = std::max(z.rows, 1);
         w.push_back(z);
-        mx = std::max<int64_t>(mx, z.trans ? z.cols : z.rows);
+        mx = std::max<int64_t>(mx, z.trans ? (z.cols + 3) / 4 : (z.rows + 15) / 16);
       }
     if (!w.empty()) ops.push_back({OP_GEMV, upload(h, w), (int)w.size(), mx});
   }
