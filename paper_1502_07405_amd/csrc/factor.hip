@@ -54,7 +54,7 @@ void run_copy(Handle& h, const std::vector<CopyDesc>& v) {
   std::vector<CopyDesc> w;
   int64_t mx = 0;
   for (auto& c : v)
-    if (c.m > 0 && c.n > 0) { w.push_back(c); mx = std::max<int64_t>(mx, (int64_t)c.m * c.n); }
+    if (c.m > 0 && c.n > 0) { w.push_back(c); mx = std::max<int64_t>(mx, copy_tiles(c)); }
   if (w.empty()) return;
   launch_copy(h.stager.put_vec(w, h.st), (int)w.size(), mx, 0, h.st);
 }
@@ -1000,7 +1000,7 @@ static void launch_copy_bf16(Handle& h, const double* U, int ldu, void* dst, int
   CopyDesc c{};
   c.src = U; c.dst = tmp; c.m = u; c.n = u; c.lds = ldu; c.ldd = u; c.alpha = 1.0;
   CopyDesc* dc = static_cast<CopyDesc*>(h.stager.put(&c, sizeof(c), h.st));
-  launch_copy(dc, 1, (int64_t)u * u, 0, h.st);
+  launch_copy(dc, 1, copy_tiles(c), 0, h.st);
   launch_convert(tmp, dst, (int64_t)u * u, 1, h.st);
 }
 
@@ -1110,7 +1110,7 @@ void numeric_factor(Handle& h) {
           }
         if (!cv.empty()) {
           int64_t mx = 0;
-          for (auto& c : cv) mx = std::max<int64_t>(mx, (int64_t)c.m * c.n);
+          for (auto& c : cv) mx = std::max<int64_t>(mx, copy_tiles(c));
           launch_copy(h.stager.put_vec(cv, h.st), (int)cv.size(), mx, 1, h.st);
         }
       }

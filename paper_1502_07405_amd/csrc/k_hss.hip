@@ -71,27 +71,103 @@ void launch_spmm(const SpmmDesc* d, int nd, int max_rows, int max_cols, hipStrea
 }
 
 // ---------------------------------------------------------------- copy ---
-template <class TD>
-__global__ void copy_kernel(const CopyDesc* __restrict__ descs) {
-  const CopyDesc d = descs[blockIdx.y];
-  const int64_t total = (int64_t)d.m * d.n;
-  const double* S = static_cast<const double*>(d.src);
-  TD* D = static_cast<TD*>(d.dst);
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    int i = (int)(e % d.m), j = (int)(e / d.m);
-    int si = d.rmap ? d.rmap[i] : i;
-    int sj = d.cmap ? d.cmap[j] : j;
-    double v = d.trans ? S[sj + (int64_t)si * d.lds] : S[si + (int64_t)sj * d.lds];
-    v *= d.alpha;
-    TD* o = D + i + (int64_t)j * d.ldd;
-    if (d.accumulate) *o = (TD)((double)*o + v); else *o = (TD)v;
+// dst(i, j) [+]= alpha * src(rmap(i), cmap(j)) (trans: src(cmap(j), rmap(i))).
+// A plain copy runs over tiles of copy_tile_rows(m) rows, one destination row
+// per thread and eight columns per thread; a transposed one over 64 x 64 tiles read along
+// the source's contiguous dimension and turned around in LDS, so both sides
+// stay coalesced.  Column indices past the edge are clamped to the last
+// column, so every load is unconditional and a thread's loads are in flight
+// together.  A clamped lane holds exactly the value of the last column; an
+// overwriting copy stores it there again (the same value twice), an
+// accumulating one skips it.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+
+template <class TD, int U>
+__device__ inline void store_batch(gptr<TD> D, int64_t ldd, int i, const int* j, int n, const double* v, int acc) {
+  if (acc) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (j[u] < n) D[i + (int64_t)j[u] * ldd] = (TD)((double)D[i + (int64_t)j[u] * ldd] + v[u]);
+  } else {
+#pragma unroll
+    for (int u = 0; u < U; ++u) D[i + (int64_t)min(j[u], n - 1) * ldd] = (TD)v[u];
   }
 }
 
-void launch_copy(const CopyDesc* d, int nd, int64_t max_elems, int f32, hipStream_t s) {
-  if (nd <= 0 || max_elems <= 0) return;
-  int64_t blocks = (max_elems + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
+template <class TD>
+__global__ __launch_bounds__(256) void copy_kernel(const CopyDesc* __restrict__ descs) {
+  __shared__ double tile[64][65];
+  const CopyDesc d = descs[blockIdx.y];
+  if (d.m <= 0 || d.n <= 0) return;
+  const auto S = (gptr<const double>)d.src;
+  const auto D = (gptr<TD>)d.dst;
+  const auto rmap = (gptr<const int>)d.rmap;
+  const auto cmap = (gptr<const int>)d.cmap;
+  if (!d.trans) {
+    const int TR = copy_tile_rows(d.m), G = 256 / TR, TC = 8 * G;
+    const int r = (int)threadIdx.x % TR, c0 = (int)threadIdx.x / TR, cs = G;
+    const int tm = (d.m + TR - 1) / TR, tn = (d.n + TC - 1) / TC;
+    for (int t = blockIdx.x; t < tm * tn; t += gridDim.x) {
+      const int i = (t % tm) * TR + r, jb = (t / tm) * TC + c0;
+      if (i >= d.m) continue;
+      const int si = rmap ? rmap[i] : i;
+      int jj[8], sj[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        jj[u] = jb + u * cs;
+        sj[u] = min(jj[u], d.n - 1);
+      }
+      if (cmap) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sj[u] = cmap[sj[u]];
+      }
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = d.alpha * S[si + (int64_t)sj[u] * d.lds];
+      store_batch<TD, 8>(D, d.ldd, i, jj, d.n, v, d.accumulate);
+    }
+    return;
+  }
+  const int tm = (d.m + 63) / 64, tn = (d.n + 63) / 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int t = blockIdx.x; t < tm * tn; t += gridDim.x) {
+    const int i0 = (t % tm) * 64, j0 = (t / tm) * 64;
+    // read src(cmap(j), rmap(i)) with j along the lanes; rows past the edge
+    // are clamped as well (they are never stored)
+    const int jr = min(j0 + tx, d.n - 1);
+    const int sj = cmap ? cmap[jr] : jr;
+    int si[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) si[u] = min(i0 + ty + 4 * u, d.m - 1);
+    if (rmap) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) si[u] = rmap[si[u]];
+    }
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = S[sj + (int64_t)si[u] * d.lds];
+    __syncthreads();   // the previous tile has been read out
+#pragma unroll
+    for (int u = 0; u < 16; ++u) tile[ty + 4 * u][tx] = v[u];
+    __syncthreads();
+    const int i = i0 + tx;
+    if (i < d.m) {
+      int jj[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        jj[u] = j0 + ty + 4 * u;
+        v[u] = d.alpha * tile[tx][ty + 4 * u];
+      }
+      store_batch<TD, 16>(D, d.ldd, i, jj, d.n, v, d.accumulate);
+    }
+  }
+}
+
+void launch_copy(const CopyDesc* d, int nd, int64_t max_tiles, int f32, hipStream_t s) {
+  if (nd <= 0 || max_tiles <= 0) return;
+  // one workgroup per tile of the largest copy (grid-stride beyond)
+  const int64_t blocks = max_tiles < 4096 ? max_tiles : 4096;
   if (f32)
     hipLaunchKernelGGL(copy_kernel<float>, dim3((unsigned)blocks, nd), dim3(256), 0, s, d);
   else

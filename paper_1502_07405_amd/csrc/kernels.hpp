@@ -110,6 +110,20 @@ struct CopyDesc {
   double alpha;
 };
 
+// tile of one plain copy: TR rows (one per thread of a 256-thread group,
+// 256 / TR column groups) by TC = 8 * 256 / TR columns, so a column segment
+// of up to 2 KB is read and written as one stretch; a transposed copy uses
+// 64 x 64 tiles
+__host__ __device__ inline int copy_tile_rows(int m) { return m > 128 ? 256 : (m > 64 ? 128 : 64); }
+
+// workgroups one copy descriptor can keep busy
+inline int64_t copy_tiles(const CopyDesc& c) {
+  if (c.m <= 0 || c.n <= 0) return 0;
+  if (c.trans) return (int64_t)((c.m + 63) / 64) * ((c.n + 63) / 64);
+  const int tr = copy_tile_rows(c.m), tc = 8 * 256 / tr;
+  return (int64_t)((c.m + tr - 1) / tr) * ((c.n + tc - 1) / tc);
+}
+
 // what element extraction needs to know about a front F_i = A_i (+) U_kids
 struct FrontOpDev {
   SpFront A;
@@ -137,7 +151,8 @@ struct TrsmDesc {
 
 void launch_rng(double* R, int ldr, const int* orig, int nrows, int c0, int nc, uint64_t seed, hipStream_t s);
 void launch_spmm(const SpmmDesc* d, int nd, int max_rows, int max_cols, hipStream_t s);
-void launch_copy(const CopyDesc* d, int nd, int64_t max_elems, int f32, hipStream_t s);
+// max_tiles: largest copy_tiles() over the descriptors
+void launch_copy(const CopyDesc* d, int nd, int64_t max_tiles, int f32, hipStream_t s);
 void launch_extract(const ExtractDesc* d, int nd, const FrontOpDev* fops, int64_t max_elems, hipStream_t s);
 // dst (m x k, ld ldd) = Pi [I; E]: dst[perm[i], :] = row i of [I; E]
 struct InterpDesc {

@@ -55,7 +55,7 @@ struct Rec {
     std::vector<CopyDesc> w;
     int64_t mx = 0;
     for (auto& c : v)
-      if (c.m > 0 && c.n > 0) { w.push_back(c); mx = std::max<int64_t>(mx, (int64_t)c.m * c.n); }
+      if (c.m > 0 && c.n > 0) { w.push_back(c); mx = std::max<int64_t>(mx, copy_tiles(c)); }
     if (!w.empty()) ops.push_back({OP_COPY, upload(h, w), (int)w.size(), mx});
   }
   void trsv(const std::vector<TrsvDesc>& v, int kind) {
