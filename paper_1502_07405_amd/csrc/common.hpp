@@ -14,6 +14,12 @@
 
 namespace hssmf {
 
+// pointer into device global memory: descriptor fields are generic pointers,
+// and a kernel that casts them to this keeps its memory operations off the
+// flat path (whose completion is counted together with LDS traffic)
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+
 struct Error : std::runtime_error {
   int code;
   int front;

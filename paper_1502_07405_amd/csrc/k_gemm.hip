@@ -31,22 +31,136 @@ __device__ __forceinline__ int find_desc(const GemmDesc* __restrict__ d, int nd,
   return lo;
 }
 
-template <class T>
-__device__ __forceinline__ T load_a(const GemmDesc& g, int i, int kk) {
-  const T* A = static_cast<const T*>(g.A);
-  if (i >= g.m || kk >= g.k) return T(0);
-  if (g.transA) return A[kk + (int64_t)i * g.lda];
-  int r = g.amap ? g.amap[i] : i;
-  return A[r + (int64_t)kk * g.lda];
-}
+// Operand loads of one thread for the k-tiles of one product.  Element q of
+// a k-tile is e = tid + 256 q: (i, kk) of op(A) and (kk, j) of op(B), ordered
+// so that consecutive threads read consecutive addresses.  Indices past the
+// edge are clamped to the last row / column / k and the value is zeroed when
+// it is stored to LDS, so no load sits behind a branch and all of a thread's
+// loads are in flight together.  A's row map does not depend on k and is
+// resolved once; the entries of B's row map for the next k-tile are loaded
+// together with the current tile, so no tile waits on a map lookup.
+template <class T, int PER, int TK, int BM, int BN>
+struct TileLoader {
+  int64_t abase[PER], bbase[PER];
+  int bnx[PER];
+  unsigned arow_ok, bcol_ok, am, bm;
+  T ra[PER], rb[PER];
+  int tid;
+  bool tA, tB;
 
-template <class T>
-__device__ __forceinline__ T load_b(const GemmDesc& g, int kk, int j) {
-  const T* B = static_cast<const T*>(g.B);
-  if (j >= g.n || kk >= g.k) return T(0);
-  if (g.transB) return B[j + (int64_t)kk * g.ldb];
-  int r = g.bmap ? g.bmap[kk] : kk;
-  return B[r + (int64_t)j * g.ldb];
+  __device__ __forceinline__ void a_idx(int q, int& i, int& kk) const {
+    const int e = tid + 256 * q;
+    if (tA) { kk = e % TK; i = e / TK; } else { i = e % BM; kk = e / BM; }
+  }
+  __device__ __forceinline__ void b_idx(int q, int& kk, int& j) const {
+    const int e = tid + 256 * q;
+    if (tB) { j = e % BN; kk = e / BN; } else { kk = e % TK; j = e / TK; }
+  }
+  __device__ __forceinline__ void map_ahead(const GemmDesc& g, int k0) {
+    const auto bmap = (gptr<const int>)g.bmap;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      int kk, j;
+      b_idx(q, kk, j);
+      bnx[q] = bmap[min(k0 + kk, g.k - 1)];
+    }
+  }
+  __device__ __forceinline__ void init(const GemmDesc& g, int row0, int col0) {
+    tid = threadIdx.x;
+    tA = g.transA;
+    tB = g.transB;
+    arow_ok = bcol_ok = 0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      int i, kk, j, kb;
+      a_idx(q, i, kk);
+      b_idx(q, kb, j);
+      const int ig = row0 + i, jg = col0 + j;
+      arow_ok |= (unsigned)(ig < g.m) << q;
+      bcol_ok |= (unsigned)(jg < g.n) << q;
+      const int ic = min(ig, g.m - 1), jc = min(jg, g.n - 1);
+      abase[q] = tA ? (int64_t)ic * g.lda : (int64_t)ic;
+      bbase[q] = tB ? (int64_t)jc : (int64_t)jc * g.ldb;
+    }
+    if (!tA && g.amap) {
+      const auto amap = (gptr<const int>)g.amap;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) abase[q] = amap[(int)abase[q]];
+    }
+    if (!tB && g.bmap) map_ahead(g, 0);
+  }
+  // tile k0 into registers; B's map entries of tile knext behind it
+  __device__ __forceinline__ void fetch(const GemmDesc& g, int k0, int knext) {
+    const auto A = (gptr<const T>)g.A;
+    const auto B = (gptr<const T>)g.B;
+    const bool bmapped = !tB && g.bmap;
+    am = bm = 0;
+    int64_t ao[PER], bo[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      int i, kk, j, kb;
+      a_idx(q, i, kk);
+      b_idx(q, kb, j);
+      const int ka = k0 + kk, kca = min(ka, g.k - 1);
+      const int kb2 = k0 + kb, kcb = min(kb2, g.k - 1);
+      am |= (unsigned)(ka < g.k) << q;
+      bm |= (unsigned)(kb2 < g.k) << q;
+      ao[q] = abase[q] + (tA ? (int64_t)kca : (int64_t)kca * g.lda);
+      bo[q] = bbase[q] + (tB ? (int64_t)kcb * g.ldb : (int64_t)(bmapped ? bnx[q] : kcb));
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) ra[q] = A[ao[q]];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) rb[q] = B[bo[q]];
+    if (bmapped && knext < g.k) map_ahead(g, knext);
+  }
+  template <class TO>
+  __device__ __forceinline__ TO a(int q) const { return ((am & arow_ok) >> q & 1u) ? (TO)ra[q] : TO(0); }
+  template <class TO>
+  __device__ __forceinline__ TO b(int q) const { return ((bm & bcol_ok) >> q & 1u) ? (TO)rb[q] : TO(0); }
+};
+
+// C(cmap(i), j) = alpha * acc + beta * C(cmap(i), j) for the NR x NC values a
+// thread holds (rows r[], columns c[]); map entries and old values of C are
+// loaded in one batch each before any store.  TA is the accumulator type.
+template <class TC, class TA, int NR, int NC>
+__device__ __forceinline__ void store_c(const GemmDesc& g, const int* r, const int* c, const TA (*acc)[NC]) {
+  const auto C = (gptr<TC>)g.C;
+  int rr[NR], cc[NC];
+#pragma unroll
+  for (int x = 0; x < NR; ++x) rr[x] = min(r[x], g.m - 1);
+#pragma unroll
+  for (int y = 0; y < NC; ++y) cc[y] = min(c[y], g.n - 1);
+  if (g.cmap) {
+    const auto cmap = (gptr<const int>)g.cmap;
+#pragma unroll
+    for (int x = 0; x < NR; ++x) rr[x] = cmap[rr[x]];
+  }
+  TC val[NR][NC];
+#pragma unroll
+  for (int x = 0; x < NR; ++x)
+#pragma unroll
+    for (int y = 0; y < NC; ++y) val[x][y] = (TC)(g.alpha * (double)acc[x][y]);
+  if (g.beta != 0.0) {
+    TC old[NR][NC];
+#pragma unroll
+    for (int x = 0; x < NR; ++x)
+#pragma unroll
+      for (int y = 0; y < NC; ++y) old[x][y] = C[rr[x] + (int64_t)cc[y] * g.ldc];
+#pragma unroll
+    for (int x = 0; x < NR; ++x)
+#pragma unroll
+      for (int y = 0; y < NC; ++y) {
+        // pin the loads here, ahead of the guarded stores below
+        asm volatile("" : "+v"(old[x][y]));
+        val[x][y] = (TC)(val[x][y] + (TC)g.beta * old[x][y]);
+      }
+  }
+#pragma unroll
+  for (int x = 0; x < NR; ++x)
+#pragma unroll
+    for (int y = 0; y < NC; ++y)
+      if (r[x] < g.m && c[y] < g.n) C[rr[x] + (int64_t)cc[y] * g.ldc] = val[x][y];
 }
 
 // ---------------------------------------------------------------- FP64 -----
@@ -68,35 +182,16 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restric
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
-  // element e = tid + 256 q of a k-tile: (i, kk) of A and (kk, j) of B,
-  // ordered so that consecutive threads read consecutive addresses
-  auto a_idx = [&](int q, int& i, int& kk) {
-    const int e = tid + 256 * q;
-    if (g.transA) { kk = e % TK; i = e / TK; } else { i = e % TM; kk = e / TM; }
-  };
-  auto b_idx = [&](int q, int& kk, int& j) {
-    const int e = tid + 256 * q;
-    if (g.transB) { j = e % TN; kk = e / TN; } else { kk = e % TK; j = e / TK; }
-  };
-  double ra[PER], rb[PER];
-  auto fetch = [&](int k0) {
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      int i, kk, j, kb;
-      a_idx(q, i, kk);
-      ra[q] = load_a<double>(g, row0 + i, k0 + kk);
-      b_idx(q, kb, j);
-      rb[q] = load_b<double>(g, k0 + kb, col0 + j);
-    }
-  };
+  TileLoader<double, PER, TK, TM, TN> ld;
+  ld.init(g, row0, col0);
   auto store = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       int i, kk, j, kb;
-      a_idx(q, i, kk);
-      As[buf][kk][i] = ra[q];
-      b_idx(q, kb, j);
-      Bs[buf][kb][j] = rb[q];
+      ld.a_idx(q, i, kk);
+      As[buf][kk][i] = ld.template a<double>(q);
+      ld.b_idx(q, kb, j);
+      Bs[buf][kb][j] = ld.template b<double>(q);
     }
   };
   dbl4 acc[2][2];
@@ -104,13 +199,13 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restric
     for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0, 0, 0, 0};
   int buf = 0;
   if (g.k > 0) {
-    fetch(0);
+    ld.fetch(g, 0, TK);
     store(0);
   }
   __syncthreads();
   for (int k0 = 0; k0 < g.k; k0 += TK) {
     const bool more = k0 + TK < g.k;
-    if (more) fetch(k0 + TK);   // in flight while the matrix cores run
+    if (more) ld.fetch(g, k0 + TK, k0 + 2 * TK);   // in flight while the matrix cores run
 #pragma unroll
     for (int ks = 0; ks < TK; ks += 4) {
       const int kk = ks + (lane >> 4);
@@ -128,19 +223,19 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restric
     buf ^= 1;
   }
   // FP64 16x16x4 result layout: lane l, slot v holds (row l/16 + 4v, col l%16)
-  double* C = static_cast<double*>(g.C);
+  int r[8], c[2];
+  double out[8][2];
+#pragma unroll
   for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b)
-      for (int v = 0; v < 4; ++v) {
-        int i = row0 + wr + a * 16 + (lane >> 4) + 4 * v;
-        int j = col0 + wc + b * 16 + (lane & 15);
-        if (i < g.m && j < g.n) {
-          int r = g.cmap ? g.cmap[i] : i;
-          double* c = C + r + (int64_t)j * g.ldc;
-          double val = g.alpha * acc[a][b][v];
-          *c = (g.beta == 0.0) ? val : val + g.beta * (*c);
-        }
-      }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      r[4 * a + v] = row0 + wr + a * 16 + (lane >> 4) + 4 * v;
+#pragma unroll
+      for (int b = 0; b < 2; ++b) out[4 * a + v][b] = acc[a][b][v];
+    }
+#pragma unroll
+  for (int b = 0; b < 2; ++b) c[b] = col0 + wc + b * 16 + (lane & 15);
+  store_c<double, double, 8, 2>(g, r, c, out);
 }
 
 // 128 x 128 tiles for large products: four wavefronts each own a 64 x 64
@@ -160,33 +255,16 @@ __global__ __launch_bounds__(256) void gemm_f64_128_kernel(const GemmDesc* __res
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = (wave & 1) * 64, wc = (wave >> 1) * 64;
-  auto a_idx = [&](int q, int& i, int& kk) {
-    const int e = tid + 256 * q;
-    if (g.transA) { kk = e % TK; i = e / TK; } else { i = e % BM; kk = e / BM; }
-  };
-  auto b_idx = [&](int q, int& kk, int& j) {
-    const int e = tid + 256 * q;
-    if (g.transB) { j = e % BN; kk = e / BN; } else { kk = e % TK; j = e / TK; }
-  };
-  double ra[PER], rb[PER];
-  auto fetch = [&](int k0) {
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      int i, kk, j, kb;
-      a_idx(q, i, kk);
-      ra[q] = load_a<double>(g, row0 + i, k0 + kk);
-      b_idx(q, kb, j);
-      rb[q] = load_b<double>(g, k0 + kb, col0 + j);
-    }
-  };
+  TileLoader<double, PER, TK, BM, BN> ld;
+  ld.init(g, row0, col0);
   auto store = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       int i, kk, j, kb;
-      a_idx(q, i, kk);
-      As[buf][kk][i] = ra[q];
-      b_idx(q, kb, j);
-      Bs[buf][kb][j] = rb[q];
+      ld.a_idx(q, i, kk);
+      As[buf][kk][i] = ld.template a<double>(q);
+      ld.b_idx(q, kb, j);
+      Bs[buf][kb][j] = ld.template b<double>(q);
     }
   };
   dbl4 acc[4][4];
@@ -196,13 +274,13 @@ __global__ __launch_bounds__(256) void gemm_f64_128_kernel(const GemmDesc* __res
     for (int b = 0; b < 4; ++b) acc[a][b] = dbl4{0, 0, 0, 0};
   int buf = 0;
   if (g.k > 0) {
-    fetch(0);
+    ld.fetch(g, 0, TK);
     store(0);
   }
   __syncthreads();
   for (int k0 = 0; k0 < g.k; k0 += TK) {
     const bool more = k0 + TK < g.k;
-    if (more) fetch(k0 + TK);
+    if (more) ld.fetch(g, k0 + TK, k0 + 2 * TK);
 #pragma unroll
     for (int ks = 0; ks < TK; ks += 4) {
       const int kk = ks + (lane >> 4);
@@ -220,22 +298,24 @@ __global__ __launch_bounds__(256) void gemm_f64_128_kernel(const GemmDesc* __res
     __syncthreads();
     buf ^= 1;
   }
-  double* C = static_cast<double*>(g.C);
+  // two passes of 32 values keep the epilogue's registers in bounds
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int h = 0; h < 2; ++h) {
+    int r[8], c[4];
+    double out[8][4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int a2 = 0; a2 < 2; ++a2)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = row0 + wr + a * 16 + (lane >> 4) + 4 * v;
-        const int j = col0 + wc + b * 16 + (lane & 15);
-        if (i < g.m && j < g.n) {
-          const int r = g.cmap ? g.cmap[i] : i;
-          double* c = C + r + (int64_t)j * g.ldc;
-          const double val = g.alpha * acc[a][b][v];
-          *c = (g.beta == 0.0) ? val : val + g.beta * (*c);
-        }
+        const int a = 2 * h + a2;
+        r[4 * a2 + v] = row0 + wr + a * 16 + (lane >> 4) + 4 * v;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) out[4 * a2 + v][b] = acc[a][b][v];
       }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) c[b] = col0 + wc + b * 16 + (lane & 15);
+    store_c<double, double, 8, 4>(g, r, c, out);
+  }
 }
 
 // ------------------------------------------------- FP32 / BF16 inputs -----
@@ -245,8 +325,9 @@ __global__ __launch_bounds__(256) void gemm_f64_128_kernel(const GemmDesc* __res
 template <class TIn, class TOut>
 __global__ __launch_bounds__(256) void gemm_lp_kernel(const GemmDesc* __restrict__ descs, int nd) {
   constexpr int TK = 32;
-  __shared__ float As[TK][TM + 1];
-  __shared__ float Bs[TK][TN + 1];
+  constexpr int PER = TM * TK / 256;
+  __shared__ float As[2][TK][TM + 1];
+  __shared__ float Bs[2][TK][TN + 1];
   const int di = find_desc(descs, nd, blockIdx.x);
   const GemmDesc g = descs[di];
   const int64_t t = blockIdx.x - g.tile_base;
@@ -256,27 +337,36 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(const GemmDesc* __restrict
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  TileLoader<TIn, PER, TK, TM, TN> ld;
+  ld.init(g, row0, col0);
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      int i, kk, j, kb;
+      ld.a_idx(q, i, kk);
+      As[buf][kk][i] = ld.template a<float>(q);
+      ld.b_idx(q, kb, j);
+      Bs[buf][kb][j] = ld.template b<float>(q);
+    }
+  };
   flt4 acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = flt4{0, 0, 0, 0};
+  int buf = 0;
+  if (g.k > 0) {
+    ld.fetch(g, 0, TK);
+    store(0);
+  }
+  __syncthreads();
   for (int k0 = 0; k0 < g.k; k0 += TK) {
-    for (int e = tid; e < TM * TK; e += 256) {
-      int i, kk;
-      if (g.transA) { kk = e % TK; i = e / TK; } else { i = e % TM; kk = e / TM; }
-      As[kk][i] = (float)load_a<TIn>(g, row0 + i, k0 + kk);
-    }
-    for (int e = tid; e < TN * TK; e += 256) {
-      int j, kk;
-      if (g.transB) { j = e % TN; kk = e / TN; } else { kk = e % TK; j = e / TK; }
-      Bs[kk][j] = (float)load_b<TIn>(g, k0 + kk, col0 + j);
-    }
-    __syncthreads();
+    const bool more = k0 + TK < g.k;
+    if (more) ld.fetch(g, k0 + TK, k0 + 2 * TK);   // in flight while the matrix cores run
     if constexpr (sizeof(TIn) != 2) {   // FP32 inputs, or FP64 inputs rounded to FP32
 #pragma unroll
       for (int ks = 0; ks < TK; ks += 4) {
         const int kk = ks + (lane >> 4);
-        float a0 = As[kk][wr + (lane & 15)], a1 = As[kk][wr + 16 + (lane & 15)];
-        float b0 = Bs[kk][wc + (lane & 15)], b1 = Bs[kk][wc + 16 + (lane & 15)];
+        float a0 = As[buf][kk][wr + (lane & 15)], a1 = As[buf][kk][wr + 16 + (lane & 15)];
+        float b0 = Bs[buf][kk][wc + (lane & 15)], b1 = Bs[buf][kk][wc + 16 + (lane & 15)];
         acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
         acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
         acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
@@ -288,32 +378,34 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(const GemmDesc* __restrict
       const int kb = 8 * (lane >> 4);
 #pragma unroll
       for (int v = 0; v < 8; ++v) {
-        a0[v] = (__bf16)As[kb + v][wr + (lane & 15)];
-        a1[v] = (__bf16)As[kb + v][wr + 16 + (lane & 15)];
-        b0[v] = (__bf16)Bs[kb + v][wc + (lane & 15)];
-        b1[v] = (__bf16)Bs[kb + v][wc + 16 + (lane & 15)];
+        a0[v] = (__bf16)As[buf][kb + v][wr + (lane & 15)];
+        a1[v] = (__bf16)As[buf][kb + v][wr + 16 + (lane & 15)];
+        b0[v] = (__bf16)Bs[buf][kb + v][wc + (lane & 15)];
+        b1[v] = (__bf16)Bs[buf][kb + v][wc + 16 + (lane & 15)];
       }
       acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
       acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
       acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
       acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
     }
+    if (more) store(buf ^ 1);   // the other buffer was last read before the previous barrier
     __syncthreads();
+    buf ^= 1;
   }
   // FP32 16x16 result layout: lane l, slot v holds (row 4(l/16) + v, col l%16)
-  TOut* C = static_cast<TOut*>(g.C);
+  int r[8], c[2];
+  float out[8][2];
+#pragma unroll
   for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b)
-      for (int v = 0; v < 4; ++v) {
-        int i = row0 + wr + a * 16 + 4 * (lane >> 4) + v;
-        int j = col0 + wc + b * 16 + (lane & 15);
-        if (i < g.m && j < g.n) {
-          int r = g.cmap ? g.cmap[i] : i;
-          TOut* c = C + r + (int64_t)j * g.ldc;
-          TOut val = (TOut)(g.alpha * (double)acc[a][b][v]);
-          *c = (g.beta == 0.0) ? val : (TOut)(val + (TOut)g.beta * (*c));
-        }
-      }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      r[4 * a + v] = row0 + wr + a * 16 + 4 * (lane >> 4) + v;
+#pragma unroll
+      for (int b = 0; b < 2; ++b) out[4 * a + v][b] = acc[a][b][v];
+    }
+#pragma unroll
+  for (int b = 0; b < 2; ++b) c[b] = col0 + wc + b * 16 + (lane & 15);
+  store_c<TOut, float, 8, 2>(g, r, c, out);
 }
 
 // C(cmap(i), j) = alpha * sum_c P_c(i, j) + beta * C(cmap(i), j): the

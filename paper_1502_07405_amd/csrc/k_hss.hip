@@ -80,9 +80,6 @@ void launch_spmm(const SpmmDesc* d, int nd, int max_rows, int max_cols, hipStrea
 // together.  A clamped lane holds exactly the value of the last column; an
 // overwriting copy stores it there again (the same value twice), an
 // accumulating one skips it.
-template <class T>
-using gptr = __attribute__((address_space(1))) T*;
-
 template <class TD, int U>
 __device__ inline void store_batch(gptr<TD> D, int64_t ldd, int i, const int* j, int n, const double* v, int acc) {
   if (acc) {
