@@ -4,6 +4,8 @@
 // restricted to F11, and the per-front triangular solves / products of the
 // forward and backward sweeps.  All fronts of one elimination-tree level go
 // through each launch together.
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace hssmf {
@@ -200,16 +202,30 @@ __global__ __launch_bounds__(256) void lu_panel21_kernel(const LUFront* __restri
   double* F = f.F;
   const int64_t ld = f.ld;
   if ((int64_t)blockIdx.x * 256 >= f.n - f.s) return;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int r = e % NB, c = e / NB;
-    U[r][c] = (r < w && c < w) ? F[(jb + r) + (int64_t)(jb + c) * ld] : 0.0;
+  // loads with indices clamped into the panel are unconditional, so all of
+  // a thread's loads are in flight together; entries past w are zeroed in
+  // U and never used in x
+  const auto G = (gptr<const double>)F;
+  {
+    constexpr int Q = NB * NB / 256;
+    double uv[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = tid + 256 * q, r = e % NB, c = e / NB;
+      uv[q] = G[(jb + min(r, w - 1)) + (int64_t)(jb + min(c, w - 1)) * ld];
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = tid + 256 * q, r = e % NB, c = e / NB;
+      U[r][c] = (r < w && c < w) ? uv[q] : 0.0;
+    }
   }
   __syncthreads();
   const int i = f.s + blockIdx.x * 256 + tid;
   if (i >= f.n) return;
   double x[NB];
 #pragma unroll
-  for (int c = 0; c < NB; ++c) x[c] = (c < w) ? F[i + (int64_t)(jb + c) * ld] : 0.0;
+  for (int c = 0; c < NB; ++c) x[c] = G[i + (int64_t)(jb + min(c, w - 1)) * ld];
 #pragma unroll
   for (int c = 0; c < NB; ++c) {
     if (c < w) {
@@ -297,10 +313,23 @@ __global__ __launch_bounds__(256) void trsm_u12_kernel(const LUFront* __restrict
   if (jb >= f.s) return;
   const int w = min(nb, f.s - jb);
   __shared__ double Lp[64][65];
-  for (int e = threadIdx.x; e < w * w; e += 256) {
-    int i = e % w, j = e / w;
-    Lp[i][j] = f.F[(jb + i) + (int64_t)(jb + j) * f.ld];
-  }
+  // the diagonal block: unconditional loads (indices clamped into the
+  // block) in flight together, then stored to LDS; a 32 x 32 footprint for
+  // panels up to 32 wide, 64 x 64 beyond
+  auto stage = [&](auto tw) {
+    constexpr int TW = decltype(tw)::value, U = TW * TW / 256;
+    const auto F = (gptr<const double>)f.F;
+    const int i = threadIdx.x % TW, j0 = threadIdx.x / TW;
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      v[u] = F[(jb + min(i, w - 1)) + (int64_t)(jb + min(j0 + (256 / TW) * u, w - 1)) * f.ld];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i < w && j0 + (256 / TW) * u < w) Lp[i][j0 + (256 / TW) * u] = v[u];
+  };
+  if (w <= 32) stage(std::integral_constant<int, 32>{});
+  else stage(std::integral_constant<int, 64>{});
   __syncthreads();
   // one wavefront per column, lane i holding row jb + i (unit lower solve)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -338,18 +367,25 @@ __global__ __launch_bounds__(256) void gemv_kernel(const GemvDesc* __restrict__ 
     __shared__ double red[16][17];
     double acc = 0.0;
     if (r < d.rows && d.alpha != 0.0) {
+      // indices clamped into the matrix, so every load is unconditional:
+      // the map entries of a round go out together, then all matrix and
+      // vector entries; only the accumulation is guarded
+      const auto M = (gptr<const double>)d.M;
+      const auto X = (gptr<const double>)d.x;
       for (int j0 = ph; j0 < d.cols; j0 += 128) {
+        int jc[8], xj[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) jc[u] = xj[u] = min(j0 + 16 * u, d.cols - 1);
+        if (d.xmap) {
+          const auto xmap = (gptr<const int>)d.xmap;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) xj[u] = xmap[jc[u]];
+        }
         double mv[8], xv[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          const int j = j0 + 16 * u;
-          mv[u] = 0.0;
-          xv[u] = 0.0;
-          if (j < d.cols) {
-            const int xj = d.xmap ? d.xmap[j] : j;
-            mv[u] = d.M[r + (int64_t)j * d.ld];
-            xv[u] = d.x[xj];
-          }
+          mv[u] = M[r + (int64_t)jc[u] * d.ld];
+          xv[u] = X[xj[u]];
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u)
@@ -369,20 +405,23 @@ __global__ __launch_bounds__(256) void gemv_kernel(const GemvDesc* __restrict__ 
     const int lane = tid & 63;
     if (c >= d.cols) return;
     double acc = 0.0;
-    const double* col = d.M + (int64_t)c * d.ld;
+    const auto col = (gptr<const double>)d.M + (int64_t)c * d.ld;
+    const auto X = (gptr<const double>)d.x;
     if (d.alpha != 0.0)
       for (int i0 = lane; i0 < d.rows; i0 += 512) {
+        int ic[8], xi[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) ic[u] = xi[u] = min(i0 + 64 * u, d.rows - 1);
+        if (d.xmap) {
+          const auto xmap = (gptr<const int>)d.xmap;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) xi[u] = xmap[ic[u]];
+        }
         double mv[8], xv[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          const int i = i0 + 64 * u;
-          mv[u] = 0.0;
-          xv[u] = 0.0;
-          if (i < d.rows) {
-            const int xi = d.xmap ? d.xmap[i] : i;
-            mv[u] = col[i];
-            xv[u] = d.x[xi];
-          }
+          mv[u] = col[ic[u]];
+          xv[u] = X[xi[u]];
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u)

@@ -314,10 +314,27 @@ __global__ __launch_bounds__(256) void trsm_block_kernel(const TrsmDesc* __restr
   const TrsmDesc d = descs[blockIdx.y];
   __shared__ double Tb[64][65];
   const int bs = d.bs;
-  for (int e = threadIdx.x; e < bs * bs; e += 256) {
-    int i = e % bs, j = e / bs;
-    int gi = d.b0 + i, gj = d.b0 + j;
-    Tb[i][j] = TRANS ? d.T[gj + (int64_t)gi * d.ldt] : d.T[gi + (int64_t)gj * d.ldt];
+  if (bs <= 0) return;
+  {
+    // the diagonal block, read along the stored columns: all sixteen loads
+    // of a thread unconditional (indices clamped into the block) and in
+    // flight together, then stored to LDS where they belong to the block
+    const auto T = (gptr<const double>)d.T;
+    const int fast = threadIdx.x & 63, slow0 = threadIdx.x >> 6;
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int f = d.b0 + min(fast, bs - 1), sl = d.b0 + min(slow0 + 4 * u, bs - 1);
+      v[u] = T[f + (int64_t)sl * d.ldt];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int sl = slow0 + 4 * u;
+      if (fast < bs && sl < bs) {
+        if (TRANS) Tb[sl][fast] = v[u];   // T(gi, gj) = stored (gj, gi)
+        else Tb[fast][sl] = v[u];
+      }
+    }
   }
   __syncthreads();
   const int lane = threadIdx.x & 63;
