@@ -56,7 +56,7 @@ void run_copy(Handle& h, const std::vector<CopyDesc>& v) {
   for (auto& c : v)
     if (c.m > 0 && c.n > 0) { w.push_back(c); mx = std::max<int64_t>(mx, copy_tiles(c)); }
   if (w.empty()) return;
-  launch_copy(h.stager.put_vec(w, h.st), (int)w.size(), mx, 0, h.st);
+  launch_copy(make_batch<CopyDesc, 32>(w, h.stager, h.st), (int)w.size(), mx, 0, h.st);
 }
 
 void run_extract(Handle& h, const std::vector<ExtractDesc>& v, const FrontOpDev* fops) {
@@ -123,9 +123,9 @@ void tri_solve_many(Handle& h, const double* T, int ldt, int n, double* X, int l
                     bool unit, bool trans) {
   if (n <= 0 || ncols <= 0) return;
   auto run_block = [&](int b0, int bs) {
-    TrsmDesc td{T, X, n, ncols, ldt, ldx, b0, bs};
-    TrsmDesc* dd = static_cast<TrsmDesc*>(h.stager.put(&td, sizeof(td), h.st));
-    launch_trsm_block(dd, 1, lower, unit, trans, ncols, h.st);
+    TrsmBatch tb{};
+    tb.inl[0] = TrsmDesc{T, X, n, ncols, ldt, ldx, b0, bs};
+    launch_trsm_block(tb, 1, lower, unit, trans, ncols, h.st);
   };
   // logical T(i,j) = trans ? T[j,i] : T[i,j]; the block (rows R, cols C)
   // of the logical matrix as a GEMM operand
@@ -166,7 +166,7 @@ void tri_solve_upper_batched(Handle& h, const std::vector<TriProb>& ps) {
         g.push_back(G(p.T + (int64_t)b0 * p.ldt, p.ldt, 0, p.X + b0, p.ldx, 0, p.X, p.ldx, b0, p.ncols, bs, -1.0, 1.0));
     }
     if (td.empty()) continue;
-    launch_trsm_block(h.stager.put_vec(td, h.st), (int)td.size(), 0, 0, 0, cmax, h.st);
+    launch_trsm_block(make_batch<TrsmDesc, 48>(td, h.stager, h.st), (int)td.size(), 0, 0, 0, cmax, h.st);
     run_gemm(h, g);
   }
 }
@@ -999,8 +999,9 @@ static void launch_copy_bf16(Handle& h, const double* U, int ldu, void* dst, int
   double* tmp = h.cur->get<double>((size_t)u * u);
   CopyDesc c{};
   c.src = U; c.dst = tmp; c.m = u; c.n = u; c.lds = ldu; c.ldd = u; c.alpha = 1.0;
-  CopyDesc* dc = static_cast<CopyDesc*>(h.stager.put(&c, sizeof(c), h.st));
-  launch_copy(dc, 1, copy_tiles(c), 0, h.st);
+  CopyBatch cb{};
+  cb.inl[0] = c;
+  launch_copy(cb, 1, copy_tiles(c), 0, h.st);
   launch_convert(tmp, dst, (int64_t)u * u, 1, h.st);
 }
 
@@ -1111,7 +1112,7 @@ void numeric_factor(Handle& h) {
         if (!cv.empty()) {
           int64_t mx = 0;
           for (auto& c : cv) mx = std::max<int64_t>(mx, copy_tiles(c));
-          launch_copy(h.stager.put_vec(cv, h.st), (int)cv.size(), mx, 1, h.st);
+          launch_copy(make_batch<CopyDesc, 32>(cv, h.stager, h.st), (int)cv.size(), mx, 1, h.st);
         }
       }
       double tp[4] = {0, 0, 0, 0};

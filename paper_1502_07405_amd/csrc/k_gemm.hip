@@ -8,6 +8,7 @@
 // FP32 with v_mfma_f32_16x16x4_f32 / v_mfma_f32_16x16x32_bf16.
 // Optional row maps fuse the gathers / scatters of the multifrontal
 // extend-add into the product.
+#include <algorithm>
 #include <cstdlib>
 #include <map>
 #include <mutex>
@@ -29,6 +30,28 @@ __device__ __forceinline__ int find_desc(const GemmDesc* __restrict__ d, int nd,
     if (d[mid].tile_base <= tile) lo = mid; else hi = mid - 1;
   }
   return lo;
+}
+
+// The descriptors of one launch.  A batch of up to kGemmInline products
+// travels in the kernel arguments themselves, so launching it costs no
+// upload; larger batches are staged in device memory.
+constexpr int kGemmInline = 24;
+struct GemmBatch {
+  const GemmDesc* descs;   // staged array, or nullptr: the inline copies
+  int nd, pad;
+  GemmDesc inl[kGemmInline];
+};
+
+__device__ __forceinline__ GemmDesc batch_desc(const GemmBatch& b, int64_t tile) {
+  GemmDesc g = b.descs ? b.descs[find_desc(b.descs, b.nd, tile)] : b.inl[find_desc(b.inl, b.nd, tile)];
+  // the descriptor is uniform: keep it in scalar registers
+  static_assert(sizeof(GemmDesc) % 4 == 0, "descriptor of whole words");
+  int w[sizeof(GemmDesc) / 4];
+  __builtin_memcpy(w, &g, sizeof(g));
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(GemmDesc) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  __builtin_memcpy(&g, w, sizeof(g));
+  return g;
 }
 
 // Operand loads of one thread for the k-tiles of one product.  Element q of
@@ -169,12 +192,11 @@ __device__ __forceinline__ void store_c(const GemmDesc& g, const int* r, const i
 // registers and stores it into the other buffer afterwards (one barrier per
 // k-tile).  Each output accumulates over k in the same order for either TK.
 template <int TK>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restrict__ descs, int nd) {
+__global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmBatch batch) {
   constexpr int PER = TM * TK / 256;   // elements of A (and of B) per thread per k-tile
   __shared__ double As[2][TK][TM + 1];
   __shared__ double Bs[2][TK][TN + 1];
-  const int di = find_desc(descs, nd, blockIdx.x);
-  const GemmDesc g = descs[di];
+  const GemmDesc g = batch_desc(batch, blockIdx.x);
   const int64_t t = blockIdx.x - g.tile_base;
   if (t >= (int64_t)g.tiles_m * g.tiles_n) return;
   const int row0 = (int)(t % g.tiles_m) * TM;
@@ -242,12 +264,11 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restric
 // quadrant (4 x 4 MFMA blocks).  Every output accumulates over k in the same
 // order as gemm_f64_kernel (k-tiles of 16, one 16x16x4 MFMA per 4), so the
 // two kernels give identical results; the choice between them is speed only.
-__global__ __launch_bounds__(256) void gemm_f64_128_kernel(const GemmDesc* __restrict__ descs, int nd) {
+__global__ __launch_bounds__(256) void gemm_f64_128_kernel(const GemmBatch batch) {
   constexpr int BM = 128, BN = 128, TK = 16, PER = BM * TK / 256;
   __shared__ double As[2][TK][BM + 1];
   __shared__ double Bs[2][TK][BN + 1];
-  const int di = find_desc(descs, nd, blockIdx.x);
-  const GemmDesc g = descs[di];
+  const GemmDesc g = batch_desc(batch, blockIdx.x);
   const int64_t t = blockIdx.x - g.tile_base;
   if (t >= (int64_t)g.tiles_m * g.tiles_n) return;
   const int row0 = (int)(t % g.tiles_m) * BM;
@@ -323,13 +344,12 @@ __global__ __launch_bounds__(256) void gemm_f64_128_kernel(const GemmDesc* __res
 // accumulate in FP32; C is stored as TOut (float, or double when a low
 // precision product is added into an FP64 result).
 template <class TIn, class TOut>
-__global__ __launch_bounds__(256) void gemm_lp_kernel(const GemmDesc* __restrict__ descs, int nd) {
+__global__ __launch_bounds__(256) void gemm_lp_kernel(const GemmBatch batch) {
   constexpr int TK = 32;
   constexpr int PER = TM * TK / 256;
   __shared__ float As[2][TK][TM + 1];
   __shared__ float Bs[2][TK][TN + 1];
-  const int di = find_desc(descs, nd, blockIdx.x);
-  const GemmDesc g = descs[di];
+  const GemmDesc g = batch_desc(batch, blockIdx.x);
   const int64_t t = blockIdx.x - g.tile_base;
   if (t >= (int64_t)g.tiles_m * g.tiles_n) return;
   const int row0 = (int)(t % g.tiles_m) * TM;
@@ -442,14 +462,21 @@ size_t in_bytes(GemmType t) {
 
 void launch_tiles(const std::vector<GemmDesc>& d, int64_t tiles, GemmType type, Stager& st, hipStream_t s,
                   double flops, int tile) {
-  GemmDesc* dd = st.put_vec(d, s);
+  GemmBatch b;
+  b.nd = (int)d.size();
+  b.pad = 0;
+  if (d.size() <= (size_t)kGemmInline) {
+    b.descs = nullptr;
+    std::copy(d.begin(), d.end(), b.inl);
+  } else {
+    b.descs = st.put_vec(d, s);
+  }
   dim3 grid((unsigned)tiles), blk(256);
-  const int n = (int)d.size();
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (prof::enabled()) prof::ext(type == GEMM_F64 ? 1 : 2, flops, &e0, &e1);   // timing hook
 #define HSSMF_GEMM_LAUNCH(K)                                                      \
-  if (e0) hipExtLaunchKernelGGL(K, grid, blk, 0, s, e0, e1, 0, dd, n);            \
-  else hipLaunchKernelGGL(K, grid, blk, 0, s, dd, n);
+  if (e0) hipExtLaunchKernelGGL(K, grid, blk, 0, s, e0, e1, 0, b);                \
+  else hipLaunchKernelGGL(K, grid, blk, 0, s, b);
   switch (type) {
     case GEMM_F64:
       if (tile == 128) { HSSMF_GEMM_LAUNCH(gemm_f64_128_kernel) }

@@ -93,9 +93,9 @@ __device__ inline void store_batch(gptr<TD> D, int64_t ldd, int i, const int* j,
 }
 
 template <class TD>
-__global__ __launch_bounds__(256) void copy_kernel(const CopyDesc* __restrict__ descs) {
+__global__ __launch_bounds__(256) void copy_kernel(const CopyBatch batch) {
   __shared__ double tile[64][65];
-  const CopyDesc d = descs[blockIdx.y];
+  const CopyDesc d = batch_get(batch, blockIdx.y);
   if (d.m <= 0 || d.n <= 0) return;
   const auto S = (gptr<const double>)d.src;
   const auto D = (gptr<TD>)d.dst;
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(256) void copy_kernel(const CopyDesc* __restrict__ 
   }
 }
 
-void launch_copy(const CopyDesc* d, int nd, int64_t max_tiles, int f32, hipStream_t s) {
+void launch_copy(const CopyBatch& d, int nd, int64_t max_tiles, int f32, hipStream_t s) {
   if (nd <= 0 || max_tiles <= 0) return;
   // one workgroup per tile of the largest copy (grid-stride beyond)
   const int64_t blocks = max_tiles < 4096 ? max_tiles : 4096;
@@ -310,8 +310,8 @@ void launch_pivots(double* M, int ld, int ncols, const int* ipiv, int k, int rev
 // substitution carried out with lane shuffles; the caller applies the
 // off-diagonal updates with GEMMs between blocks
 template <int LOWER, int UNIT, int TRANS>
-__global__ __launch_bounds__(256) void trsm_block_kernel(const TrsmDesc* __restrict__ descs) {
-  const TrsmDesc d = descs[blockIdx.y];
+__global__ __launch_bounds__(256) void trsm_block_kernel(const TrsmBatch batch) {
+  const TrsmDesc d = batch_get(batch, blockIdx.y);
   __shared__ double Tb[64][65];
   const int bs = d.bs;
   if (bs <= 0) return;
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(256) void trsm_block_kernel(const TrsmDesc* __restr
   }
 }
 
-void launch_trsm_block(const TrsmDesc* d, int nd, int lower, int unit, int trans, int max_cols, hipStream_t s) {
+void launch_trsm_block(const TrsmBatch& d, int nd, int lower, int unit, int trans, int max_cols, hipStream_t s) {
   if (nd <= 0 || max_cols <= 0) return;
   int gx = (max_cols + 3) / 4;
   if (gx > 512) gx = 512;

@@ -6,6 +6,47 @@
 
 namespace hssmf {
 
+// The descriptors of one launch.  Up to N of them travel in the kernel
+// arguments themselves, so a small batch costs no upload; a larger one (or
+// one recorded for replay) is an array in device memory that descs points
+// to.
+template <class D, int N>
+struct DescBatch {
+  const D* descs;   // device array, or nullptr: the inline copies
+  D inl[N];
+};
+
+// descriptor i of a batch; the fields are uniform across the workgroup and
+// are kept in scalar registers
+template <class D, int N>
+__device__ __forceinline__ D batch_get(const DescBatch<D, N>& b, int i) {
+  D d = b.descs ? b.descs[i] : b.inl[i];
+  static_assert(sizeof(D) % 4 == 0, "descriptor of whole words");
+  int w[sizeof(D) / 4];
+  __builtin_memcpy(w, &d, sizeof(d));
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(D) / 4); ++k) w[k] = __builtin_amdgcn_readfirstlane(w[k]);
+  __builtin_memcpy(&d, w, sizeof(d));
+  return d;
+}
+
+// host side: inline when the batch fits, else staged through the ring
+template <class D, int N>
+DescBatch<D, N> make_batch(const std::vector<D>& v, Stager& st, hipStream_t s) {
+  DescBatch<D, N> b{};
+  if (v.size() <= (size_t)N) std::copy(v.begin(), v.end(), b.inl);
+  else b.descs = st.put_vec(v, s);
+  return b;
+}
+
+// an array already in device memory
+template <class D, int N>
+DescBatch<D, N> device_batch(const D* p) {
+  DescBatch<D, N> b{};
+  b.descs = p;
+  return b;
+}
+
 // A dense front (or any square matrix factored by the batched blocked LU):
 // F is n x n column major (ld = ld); pivoting is restricted to rows [0, s).
 struct LUFront {
@@ -116,6 +157,8 @@ struct CopyDesc {
 // 64 x 64 tiles
 __host__ __device__ inline int copy_tile_rows(int m) { return m > 128 ? 256 : (m > 64 ? 128 : 64); }
 
+using CopyBatch = DescBatch<CopyDesc, 32>;
+
 // workgroups one copy descriptor can keep busy
 inline int64_t copy_tiles(const CopyDesc& c) {
   if (c.m <= 0 || c.n <= 0) return 0;
@@ -148,11 +191,12 @@ struct TrsmDesc {
   int n, ncols, ldt, ldx;
   int b0, bs;
 };
+using TrsmBatch = DescBatch<TrsmDesc, 48>;
 
 void launch_rng(double* R, int ldr, const int* orig, int nrows, int c0, int nc, uint64_t seed, hipStream_t s);
 void launch_spmm(const SpmmDesc* d, int nd, int max_rows, int max_cols, hipStream_t s);
 // max_tiles: largest copy_tiles() over the descriptors
-void launch_copy(const CopyDesc* d, int nd, int64_t max_tiles, int f32, hipStream_t s);
+void launch_copy(const CopyBatch& d, int nd, int64_t max_tiles, int f32, hipStream_t s);
 void launch_extract(const ExtractDesc* d, int nd, const FrontOpDev* fops, int64_t max_elems, hipStream_t s);
 // dst (m x k, ld ldd) = Pi [I; E]: dst[perm[i], :] = row i of [I; E]
 struct InterpDesc {
@@ -166,7 +210,7 @@ void launch_interp_dense(const InterpDesc* d, int nd, int64_t max_elems, hipStre
 // perm_ws: k ints of device workspace
 void launch_pivots(double* M, int ld, int ncols, const int* ipiv, int k, int reverse, int* perm_ws, hipStream_t s);
 // logical T(i,j) = trans ? T[j + i ld] : T[i + j ld]; solve rows [b0, b0+bs) in place
-void launch_trsm_block(const TrsmDesc* d, int nd, int lower, int unit, int trans, int max_cols, hipStream_t s);
+void launch_trsm_block(const TrsmBatch& d, int nd, int lower, int unit, int trans, int max_cols, hipStream_t s);
 void launch_convert(const double* src, void* dst, int64_t n, int to_bf16, hipStream_t s);
 // round x to the low precision in place and write the low-precision copy
 void launch_round_lp(double* x, void* lp, int64_t n, int to_bf16, hipStream_t s);

@@ -455,7 +455,7 @@ void run_ops(Handle& h, const std::vector<Op>& ops) {
   for (const Op& o : ops) {
     switch (o.kind) {
       case OP_GEMV: launch_gemv((const GemvDesc*)o.d, o.n, (int)o.p0, h.st); break;
-      case OP_COPY: launch_copy((const CopyDesc*)o.d, o.n, o.p0, 0, h.st); break;
+      case OP_COPY: launch_copy(device_batch<CopyDesc, 32>((const CopyDesc*)o.d), o.n, o.p0, 0, h.st); break;
       case OP_TRSV: launch_trsv((const TrsvDesc*)o.d, o.n, (int)(o.p0 % 16), (int)(o.p0 / 16), h.st); break;
       case OP_RHS: launch_rhs_gather((const RhsDesc*)o.d, o.n, (int)o.p0, h.st); break;
     }
