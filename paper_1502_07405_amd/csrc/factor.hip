@@ -80,7 +80,16 @@ void run_interp(Handle& h, const std::vector<InterpDesc>& v) {
 }  // namespace
 
 // ------------------------------------------------------- blocked LU -------
+// Partial LU of a batch of fronts (pivoting inside F11).  Block columns of
+// KB = 128 are factored panel by panel (NB = 32 wide: panel kernel, then
+// the interchanges, the U12 rows and the update restricted to the block
+// column); the block's interchanges then go to the columns outside it, its
+// U12 rows are solved against the 128 x 128 unit-lower diagonal block (two
+// 64-row halves), and the trailing matrix takes one update with k = 128.
+// This is the usual two-level blocking of a right-looking LU: the trailing
+// matrix is read and written once per 128 columns instead of once per 32.
 constexpr int NB = 32;
+constexpr int KB = 128;
 
 void blocked_lu(Handle& h, const std::vector<LUFront>& fronts) {
   if (fronts.empty()) return;
@@ -88,30 +97,60 @@ void blocked_lu(Handle& h, const std::vector<LUFront>& fronts) {
   int maxs = 0, maxn = 0;
   for (auto& f : fronts) { maxs = std::max(maxs, f.s); maxn = std::max(maxn, f.n); }
   const int nf = (int)fronts.size();
-  for (int jb = 0; jb < maxs; jb += NB) {
-    double pfl = 0.0;   // panel flops: w columns of height m = n - jb, m w^2 - w^3 / 3
-    if (prof::enabled())
+  for (int jb = 0; jb < maxs; jb += KB) {
+    // the block column, panel by panel
+    for (int jp = jb; jp < std::min(jb + KB, maxs); jp += NB) {
+      double pfl = 0.0;   // panel flops: w columns of height m = n - jp, m w^2 - w^3 / 3
+      if (prof::enabled())
+        for (auto& f : fronts)
+          if (jp < f.s) {
+            const double w = std::min(NB, f.s - jp), m = f.n - jp;
+            pfl += m * w * w - w * w * w / 3.0;
+          }
+      int m1 = 0, mu = 0;
       for (auto& f : fronts)
-        if (jb < f.s) {
-          const double w = std::min(NB, f.s - jb), m = f.n - jb;
-          pfl += m * w * w - w * w * w / 3.0;
-        }
-    int m1 = 0, mu = 0;
-    for (auto& f : fronts)
-      if (jb < f.s) { m1 = std::max(m1, f.s - jb); mu = std::max(mu, f.n - f.s); }
-    if (lu_panel_split_fits(m1, NB)) launch_lu_panel_split(d, nf, jb, NB, m1, mu, h.d_info, h.st, pfl);
-    else launch_lu_panel(d, nf, jb, NB, h.d_info, h.st, pfl);
-    launch_laswp(d, nf, jb, NB, maxn, h.st);
-    launch_trsm_u12(d, nf, jb, NB, maxn, h.st);
+        if (jp < f.s) { m1 = std::max(m1, f.s - jp); mu = std::max(mu, f.n - f.s); }
+      if (lu_panel_split_fits(m1, NB)) launch_lu_panel_split(d, nf, jp, NB, m1, mu, h.d_info, h.st, pfl);
+      else launch_lu_panel(d, nf, jp, NB, h.d_info, h.st, pfl);
+      launch_laswp(d, nf, jp, NB, jb, jb + KB, maxn, h.st);
+      launch_trsm_u12(d, nf, jp, NB, -1, jb + KB, maxn, h.st);
+      std::vector<GemmDesc> g;
+      for (auto& f : fronts) {
+        if (jp >= f.s) continue;
+        const int w = std::min(NB, f.s - jp);
+        const int nc = std::min(jb + KB, f.s) - (jp + w);
+        const int m2 = f.n - jp - w;
+        if (nc <= 0 || m2 <= 0) continue;
+        const int64_t ld = f.ld;
+        g.push_back(G(f.F + (jp + w) + jp * ld, f.ld, 0, f.F + jp + (jp + w) * ld, f.ld, 0,
+                      f.F + (jp + w) + (jp + w) * ld, f.ld, m2, nc, w, -1.0, 1.0));
+      }
+      run_gemm(h, g);
+    }
+    // the block's interchanges on the columns outside it
+    launch_laswp(d, nf, jb, KB, 0, -1, maxn, h.st);
+    // its U12 rows against the unit-lower diagonal block, 64 rows at a time
+    launch_trsm_u12(d, nf, jb, 64, jb + KB, -1, maxn, h.st);
     std::vector<GemmDesc> g;
     for (auto& f : fronts) {
       if (jb >= f.s) continue;
-      int w = std::min(NB, f.s - jb);
-      int m2 = f.n - jb - w;
+      const int kb = std::min(KB, f.s - jb), nc = f.n - jb - kb;
+      if (kb <= 64 || nc <= 0) continue;
+      const int64_t ld = f.ld;
+      g.push_back(G(f.F + (jb + 64) + jb * ld, f.ld, 0, f.F + jb + (jb + kb) * ld, f.ld, 0,
+                    f.F + (jb + 64) + (jb + kb) * ld, f.ld, kb - 64, nc, 64, -1.0, 1.0));
+    }
+    run_gemm(h, g);
+    launch_trsm_u12(d, nf, jb + 64, 64, jb + KB, -1, maxn, h.st);
+    // the trailing update, k = the block width
+    g.clear();
+    for (auto& f : fronts) {
+      if (jb >= f.s) continue;
+      const int kb = std::min(KB, f.s - jb), m2 = f.n - jb - kb;
       if (m2 <= 0) continue;
       const int64_t ld = f.ld;
-      g.push_back(G(f.F + (jb + w) + jb * ld, f.ld, 0, f.F + jb + (jb + w) * ld, f.ld, 0,
-                    f.F + (jb + w) + (jb + w) * ld, f.ld, m2, m2, w, -1.0, 1.0));
+      g.push_back(G(f.F + (jb + kb) + jb * ld, f.ld, 0, f.F + jb + (jb + kb) * ld, f.ld, 0,
+                    f.F + (jb + kb) + (jb + kb) * ld, f.ld, m2, m2, kb, -1.0, 1.0));
     }
     run_gemm(h, g);
   }

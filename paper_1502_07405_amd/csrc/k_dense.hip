@@ -288,30 +288,41 @@ void launch_lu_panel(const LUFront* fr, int nf, int jb, int nb, int* info, hipSt
 }
 
 // apply the panel's interchanges to the columns outside the panel
-__global__ void laswp_kernel(const LUFront* __restrict__ fr, int jb, int nb) {
+// The interchanges (p0 + t, ipiv[p0 + t]), t < w = min(np, s - p0), in order,
+// applied to the columns [c0, c1) of each front (c1 < 0: up to n; else
+// clamped to s) other than the pivot columns [p0, p0 + w) themselves.
+__global__ void laswp_kernel(const LUFront* __restrict__ fr, int p0, int np, int c0, int c1) {
   const LUFront f = fr[blockIdx.y];
-  if (jb >= f.s) return;
-  const int w = min(nb, f.s - jb);
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= f.n || (col >= jb && col < jb + w)) return;
+  if (p0 >= f.s) return;
+  const int w = min(np, f.s - p0);
+  const int cend = c1 < 0 ? f.n : min(c1, f.s);
+  const int col = c0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= cend || (col >= p0 && col < p0 + w)) return;
   double* c = f.F + (int64_t)col * f.ld;
   for (int t = 0; t < w; ++t) {
-    int r1 = jb + t, r2 = f.ipiv[r1];
+    int r1 = p0 + t, r2 = f.ipiv[r1];
     if (r1 != r2) { double x = c[r1]; c[r1] = c[r2]; c[r2] = x; }
   }
 }
 
-void launch_laswp(const LUFront* fr, int nf, int jb, int nb, int max_n, hipStream_t s) {
-  if (nf <= 0 || max_n <= 0) return;
-  hipLaunchKernelGGL(laswp_kernel, dim3((max_n + 255) / 256, nf), dim3(256), 0, s, fr, jb, nb);
+void launch_laswp(const LUFront* fr, int nf, int p0, int np, int c0, int c1, int max_n, hipStream_t s) {
+  const int span = (c1 < 0 ? max_n : std::min(c1, max_n)) - c0;
+  if (nf <= 0 || span <= 0) return;
+  hipLaunchKernelGGL(laswp_kernel, dim3((span + 255) / 256, nf), dim3(256), 0, s, fr, p0, np, c0, c1);
   HIP_CHECK(hipGetLastError());
 }
 
-// U12 block row: X = L_pp^{-1} X for rows [jb, jb+w), columns [jb+w, n)
-__global__ __launch_bounds__(256) void trsm_u12_kernel(const LUFront* __restrict__ fr, int jb, int nb) {
+// U12 block row: X = L_pp^{-1} X for rows [jb, jb+w), w = min(nb, s - jb)
+// <= 64, and the columns [c0, c1) (c0 < 0: from jb + w; c1 < 0: up to n;
+// explicit bounds clamped to s)
+__global__ __launch_bounds__(256) void trsm_u12_kernel(const LUFront* __restrict__ fr, int jb, int nb, int c0,
+                                                       int c1) {
   const LUFront f = fr[blockIdx.y];
   if (jb >= f.s) return;
   const int w = min(nb, f.s - jb);
+  const int cbeg = c0 < 0 ? jb + w : min(c0, f.s);
+  const int cend = c1 < 0 ? f.n : min(c1, f.s);
+  if (cbeg >= cend) return;
   __shared__ double Lp[64][65];
   // the diagonal block: unconditional loads (indices clamped into the
   // block) in flight together, then stored to LDS; a 32 x 32 footprint for
@@ -333,7 +344,7 @@ __global__ __launch_bounds__(256) void trsm_u12_kernel(const LUFront* __restrict
   __syncthreads();
   // one wavefront per column, lane i holding row jb + i (unit lower solve)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int col = jb + w + blockIdx.x * 4 + wave; col < f.n; col += gridDim.x * 4) {
+  for (int col = cbeg + blockIdx.x * 4 + wave; col < cend; col += gridDim.x * 4) {
     double* c = f.F + (int64_t)col * f.ld + jb;
     double v = (lane < w) ? c[lane] : 0.0;
     for (int j = 0; j < w; ++j) {
@@ -344,11 +355,12 @@ __global__ __launch_bounds__(256) void trsm_u12_kernel(const LUFront* __restrict
   }
 }
 
-void launch_trsm_u12(const LUFront* fr, int nf, int jb, int nb, int max_n, hipStream_t s) {
+void launch_trsm_u12(const LUFront* fr, int nf, int jb, int nb, int c0, int c1, int max_n, hipStream_t s) {
   if (nf <= 0 || max_n <= 0) return;
+  REQUIRE(nb <= 64, HSSMF_EINVAL, "U12 solve: more than 64 rows at once");
   int gx = (max_n + 3) / 4;
   if (gx > 256) gx = 256;
-  hipLaunchKernelGGL(trsm_u12_kernel, dim3(gx, nf), dim3(256), 0, s, fr, jb, nb);
+  hipLaunchKernelGGL(trsm_u12_kernel, dim3(gx, nf), dim3(256), 0, s, fr, jb, nb, c0, c1);
   HIP_CHECK(hipGetLastError());
 }
 

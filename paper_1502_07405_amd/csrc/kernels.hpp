@@ -107,8 +107,13 @@ void launch_lu_panel(const LUFront* fr, int nf, int jb, int nb, int* info, hipSt
 bool lu_panel_split_fits(int max_m1, int nb);
 void launch_lu_panel_split(const LUFront* fr, int nf, int jb, int nb, int max_m1, int max_u, int* info, hipStream_t s,
                            double flops = 0.0);
-void launch_laswp(const LUFront* fr, int nf, int jb, int nb, int max_n, hipStream_t s);
-void launch_trsm_u12(const LUFront* fr, int nf, int jb, int nb, int max_n, hipStream_t s);
+// interchanges p0 .. p0 + np - 1 (clamped to s) on the columns [c0, c1)
+// (c1 < 0: up to n, else clamped to s), the pivot columns excepted
+void launch_laswp(const LUFront* fr, int nf, int p0, int np, int c0, int c1, int max_n, hipStream_t s);
+// rows [jb, jb + min(nb, s - jb)) of U12 (nb <= 64) on the columns [c0, c1)
+// (c0 < 0: from the end of those rows' diagonal block; c1 < 0: up to n;
+// explicit bounds clamped to s)
+void launch_trsm_u12(const LUFront* fr, int nf, int jb, int nb, int c0, int c1, int max_n, hipStream_t s);
 // gx: workgroups along x (ceil(rows / 16) non-transposed, ceil(cols / 4)
 // transposed, the largest over the batch)
 void launch_gemv(const GemvDesc* d, int nd, int gx, hipStream_t s);

@@ -177,7 +177,10 @@ def test_mixed_precision_sampling():
     FP64 rank decisions, ULV factors and refinement: the preconditioner stays
     within 1e-4 of the FP64 one at eps = 1e-6 (FP32 rounding perturbs the
     sampled blocks at ~1e-7, below eps), ranks near the threshold move by at
-    most max(4, 10%) per front, and refinement still reaches 1e-10.  BF16 products (noise ~2^-9) cannot resolve eps = 1e-6:
+    most max(4, 10%) per front plus the difference in sample count when the
+    two modes needed a different number of growth rounds (d samples can
+    reveal at most d directions, Sec. 2.2 and the stopping rule of Sec. 5.3),
+    and refinement still reaches 1e-10.  BF16 products (noise ~2^-9) cannot resolve eps = 1e-6:
     adaptive sampling reaches d_max (ERANK); with eps = 1e-2, above that
     floor, the BF16 preconditioner converges."""
     A, o = P.poisson3d(20), P.geometric_nd((20, 20, 20), 4)
@@ -189,7 +192,8 @@ def test_mixed_precision_sampling():
     y64, y32 = f64.apply(b), f32.apply(b)
     assert float(torch.linalg.norm(y32 - y64) / torch.linalg.norm(y64)) <= 1e-4
     for r64, r32 in zip(f64.hss_ranks(), f32.hss_ranks()):
-        assert r64[0] == r32[0] and abs(r64[1] - r32[1]) <= max(4, r64[1] // 10), (r64, r32)
+        allowance = max(4, r64[1] // 10) + abs(r64[3] - r32[3])
+        assert r64[0] == r32[0] and abs(r64[1] - r32[1]) <= allowance, (r64, r32)
     x, info = f32.solve(b)
     bh = b.cpu().numpy()
     assert np.linalg.norm(bh - S @ x.cpu().numpy()) <= 1e-10 * np.linalg.norm(bh)
