@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <map>
+#include <type_traits>
 #include <mutex>
 
 #include "common.hpp"
@@ -372,6 +373,14 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(const GemmBatch batch) {
   flt4 acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = flt4{0, 0, 0, 0};
+  // FP32 products with an FP64 result: each k-tile's FP32 sum (32 terms)
+  // is added into FP64 accumulators, so the accumulated rounding stays at
+  // the level of one 32-term FP32 sum instead of growing with k
+  constexpr bool acc64 = sizeof(TOut) == 8 && sizeof(TIn) != 2;
+  double acc_d[2][2][4];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int v = 0; v < 4; ++v) acc_d[a][b][v] = 0.0;
   int buf = 0;
   if (g.k > 0) {
     ld.fetch(g, 0, TK);
@@ -408,24 +417,38 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(const GemmBatch batch) {
       acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
       acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
     }
+    if constexpr (acc64) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc_d[a][b][v] += (double)acc[a][b][v];
+          acc[a][b] = flt4{0, 0, 0, 0};
+        }
+    }
     if (more) store(buf ^ 1);   // the other buffer was last read before the previous barrier
     __syncthreads();
     buf ^= 1;
   }
   // FP32 16x16 result layout: lane l, slot v holds (row 4(l/16) + v, col l%16)
   int r[8], c[2];
-  float out[8][2];
+  using TAcc = std::conditional_t<acc64, double, float>;
+  TAcc out[8][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       r[4 * a + v] = row0 + wr + a * 16 + 4 * (lane >> 4) + v;
 #pragma unroll
-      for (int b = 0; b < 2; ++b) out[4 * a + v][b] = acc[a][b][v];
+      for (int b = 0; b < 2; ++b) {
+        if constexpr (acc64) out[4 * a + v][b] = acc_d[a][b][v];
+        else out[4 * a + v][b] = acc[a][b][v];
+      }
     }
 #pragma unroll
   for (int b = 0; b < 2; ++b) c[b] = col0 + wc + b * 16 + (lane & 15);
-  store_c<TOut, float, 8, 2>(g, r, c, out);
+  store_c<TOut, TAcc, 8, 2>(g, r, c, out);
 }
 
 // C(cmap(i), j) = alpha * sum_c P_c(i, j) + beta * C(cmap(i), j): the
