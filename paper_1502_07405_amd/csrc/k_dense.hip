@@ -459,19 +459,19 @@ void launch_gemv(const GemvDesc* d, int nd, int gx, hipStream_t s) {
 // right-hand side staged in LDS.  Blocks of 64: the diagonal block is staged
 // in LDS with coalesced loads, one wavefront solves it with lane shuffles,
 // then all threads update the rest of the right-hand side.
-template <int KIND, bool STAGE>
-__global__ __launch_bounds__(256) void trsv_kernel(const TrsvDesc* __restrict__ descs) {
+template <int KIND, bool STAGE, int NT>
+__global__ __launch_bounds__(NT) void trsv_kernel(const TrsvDesc* __restrict__ descs) {
   extern __shared__ double xs[];   // s entries, then (STAGE) the 64 x 65 block
   const TrsvDesc d = descs[blockIdx.x];
   double (*Tb)[65] = reinterpret_cast<double (*)[65]>(xs + ((d.s + 1) & ~1));
   const int s = d.s, tid = threadIdx.x, lane = tid & 63;
   const int64_t ld = d.ld;
   __shared__ int pv[256];   // pivot indices, staged 256 at a time for the sequential swaps
-  for (int i = tid; i < s; i += 256) xs[i] = d.x[i];
+  for (int i = tid; i < s; i += NT) xs[i] = d.x[i];
   __syncthreads();
   if (KIND == 0 && d.ipiv)
     for (int c0 = 0; c0 < s; c0 += 256) {
-      if (c0 + tid < s) pv[tid] = d.ipiv[c0 + tid];
+      if (tid < 256 && c0 + tid < s) pv[tid] = d.ipiv[c0 + tid];
       __syncthreads();
       if (tid == 0)
         for (int i = c0; i < min(s, c0 + 256); ++i) {
@@ -489,7 +489,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(const TrsvDesc* __restrict__ 
   // Tb[r][c] = T(b0 + r, b0 + c) for r, c < bs, read along the stored columns
   auto stage = [&](int b0, int bs) {
     if (!STAGE) return;
-    for (int e = tid; e < 64 * 64; e += 256) {
+    for (int e = tid; e < 64 * 64; e += NT) {
       const int fast = e & 63, slow = e >> 6;
       const int r = trans ? slow : fast, c = trans ? fast : slow;
       if (r < bs && c < bs) Tb[r][c] = T(b0 + r, b0 + c);
@@ -526,7 +526,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(const TrsvDesc* __restrict__ 
         if (lane < bs) xs[b0 + lane] = v;
       }
       __syncthreads();
-      for (int i = b0 + bs + tid; i < s; i += 256) xs[i] -= row_dot(i, b0, bs);
+      for (int i = b0 + bs + tid; i < s; i += NT) xs[i] -= row_dot(i, b0, bs);
       __syncthreads();
     }
   } else {
@@ -544,7 +544,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(const TrsvDesc* __restrict__ 
         if (lane < bs) xs[b0 + lane] = v;
       }
       __syncthreads();
-      for (int i = tid; i < b0; i += 256) xs[i] -= row_dot(i, b0, bs);
+      for (int i = tid; i < b0; i += NT) xs[i] -= row_dot(i, b0, bs);
       __syncthreads();
     }
   }
@@ -552,7 +552,7 @@ __global__ __launch_bounds__(256) void trsv_kernel(const TrsvDesc* __restrict__ 
     for (int c1 = s; c1 > 0; c1 -= 256) {
       const int c0 = max(0, c1 - 256);
       __syncthreads();
-      if (c0 + tid < c1) pv[tid] = d.ipiv[c0 + tid];
+      if (tid < 256 && c0 + tid < c1) pv[tid] = d.ipiv[c0 + tid];
       __syncthreads();
       if (tid == 0)
         for (int i = c1 - 1; i >= c0; --i) {
@@ -561,22 +561,30 @@ __global__ __launch_bounds__(256) void trsv_kernel(const TrsvDesc* __restrict__ 
         }
     }
   __syncthreads();
-  for (int i = tid; i < s; i += 256) d.x[i] = xs[i];
+  for (int i = tid; i < s; i += NT) d.x[i] = xs[i];
 }
 
 void launch_trsv(const TrsvDesc* d, int nd, int kind, int max_s, hipStream_t s) {
   if (nd <= 0) return;
   // LDS holds the whole right-hand side and, when it fits, the 64 x 64
-  // diagonal block being solved
+  // diagonal block being solved.  A batch of few fronts (each on its own
+  // CU) takes 1024 threads per front, so the row updates keep four times as
+  // many loads in flight.
   const size_t xs = (size_t)(std::max(max_s, 1) + 1) / 2 * 2 * sizeof(double);
   const size_t blk = 64 * 65 * sizeof(double);
-  const size_t budget = lds_budget(256);
+  const size_t budget = lds_budget(256 * sizeof(int));
   REQUIRE(xs <= budget, HSSMF_EINVAL, "triangular solve: right-hand side too long for LDS");
   const bool stage = xs + blk <= budget;
   const size_t lds = stage ? xs + blk : xs;
-#define HSSMF_TRSV(K)                                                                              \
-  if (stage) hipLaunchKernelGGL((trsv_kernel<K, true>), dim3(nd), dim3(256), lds, s, d);           \
-  else hipLaunchKernelGGL((trsv_kernel<K, false>), dim3(nd), dim3(256), lds, s, d);
+  const bool wide = nd <= 128 && max_s >= 256;
+#define HSSMF_TRSV(K)                                                                                     \
+  if (wide) {                                                                                             \
+    if (stage) hipLaunchKernelGGL((trsv_kernel<K, true, 1024>), dim3(nd), dim3(1024), lds, s, d);         \
+    else hipLaunchKernelGGL((trsv_kernel<K, false, 1024>), dim3(nd), dim3(1024), lds, s, d);              \
+  } else {                                                                                                \
+    if (stage) hipLaunchKernelGGL((trsv_kernel<K, true, 256>), dim3(nd), dim3(256), lds, s, d);           \
+    else hipLaunchKernelGGL((trsv_kernel<K, false, 256>), dim3(nd), dim3(256), lds, s, d);                \
+  }
   switch (kind) {
     case 0: HSSMF_TRSV(0) break;
     case 1: HSSMF_TRSV(1) break;
