@@ -66,54 +66,89 @@ void launch_extend_add(const EADesc* d, int nd, int max_u, hipStream_t s) {
 // over rows [col, s) only (partial pivoting inside F11, Sec. 3.2).  Rows
 // below s are eliminated with the same multipliers, which yields
 // L21 = F21 U11^{-1}.
-__global__ __launch_bounds__(256) void lu_panel_kernel(const LUFront* __restrict__ fr, int jb, int nb, int* info) {
+// Panel of a front whose F11 rows do not fit in LDS, worked on in place in
+// global memory by one workgroup of NT threads per front: for each column,
+// the pivot search (largest |value| over the remaining F11 rows, ties to
+// the lowest row), the interchange inside the panel, and the scaling and
+// rank-1 update of every row below.  A thread's loads are issued together
+// (indices clamped into the front, values past the edge unused); the row
+// update loads a row's panel entries before storing any, and it also takes
+// each thread's running maximum for the next column's pivot search from
+// the values it has just computed, so a column costs two dependent rounds
+// of memory traffic (the interchange, the update) instead of four.
+template <int NT>
+__global__ __launch_bounds__(NT) void lu_panel_kernel(const LUFront* __restrict__ fr, int jb, int nb, int* info) {
+  constexpr int NW = NT / 64;
   const LUFront f = fr[blockIdx.x];
   if (jb >= f.s) return;
-  const int w = min(nb, f.s - jb);
-  const int tid = threadIdx.x;
-  __shared__ double rv[256];
-  __shared__ int ri[256];
-  __shared__ double prow[64];
-  double* F = f.F;
+  const int w = min(nb, f.s - jb);   // <= 32
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double wv[NW];
+  __shared__ int wi[NW];
+  __shared__ double prow[32];
+  const auto F = (gptr<double>)f.F;
   const int64_t ld = f.ld;
+  // this thread's candidate for the first column's pivot
+  double best = -1.0;
+  int bi = jb;
+  for (int i0 = jb + tid; i0 < f.s; i0 += 4 * NT) {
+    double a[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] = fabs(F[min(i0 + NT * u, f.s - 1) + jb * ld]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i0 + NT * u < f.s && a[u] > best) { best = a[u]; bi = i0 + NT * u; }
+  }
   for (int c = 0; c < w; ++c) {
     const int col = jb + c;
-    double best = -1.0;
-    int bi = col;
-    for (int i = col + tid; i < f.s; i += 256) {
-      double a = fabs(F[i + col * ld]);
-      if (a > best) { best = a; bi = i; }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bi, off);
+      if (o > best || (o == best && oi < bi)) { best = o; bi = oi; }
     }
-    rv[tid] = best;
-    ri[tid] = bi;
+    if (lane == 0) { wv[wave] = best; wi[wave] = bi; }
     __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-      if (tid < off) {
-        double o = rv[tid + off];
-        int oi = ri[tid + off];
-        if (o > rv[tid] || (o == rv[tid] && oi < ri[tid])) { rv[tid] = o; ri[tid] = oi; }
-      }
-      __syncthreads();
-    }
-    const int p = ri[0];
+    best = wv[0];
+    bi = wi[0];
+#pragma unroll
+    for (int k = 1; k < NW; ++k)
+      if (wv[k] > best || (wv[k] == best && wi[k] < bi)) { best = wv[k]; bi = wi[k]; }
+    const int p = bi;
     if (tid == 0) {
       f.ipiv[col] = p;
-      if (rv[0] == 0.0) atomicCAS(info, 0, f.id + 1);
+      if (best == 0.0) atomicCAS(info, 0, f.id + 1);
     }
-    if (p != col && tid < w) {
-      double* a = F + col + (int64_t)(jb + tid) * ld;
-      double* b = F + p + (int64_t)(jb + tid) * ld;
-      double t = *a; *a = *b; *b = t;
+    // the interchange inside the panel; the pivot row goes to LDS directly
+    if (tid < w) {
+      const double a = F[col + (int64_t)(jb + tid) * ld];
+      const double b = F[p + (int64_t)(jb + tid) * ld];
+      if (p != col) {
+        F[col + (int64_t)(jb + tid) * ld] = b;
+        F[p + (int64_t)(jb + tid) * ld] = a;
+      }
+      prow[tid] = (p != col) ? b : a;
     }
-    __syncthreads();
-    if (tid < w) prow[tid] = F[col + (int64_t)(jb + tid) * ld];
     __syncthreads();
     const double piv = prow[c];
     const double rp = (piv != 0.0) ? 1.0 / piv : 0.0;
-    for (int i = col + 1 + tid; i < f.n; i += 256) {
-      double l = F[i + col * ld] * rp;
+    best = -1.0;
+    bi = col + 1;
+    for (int i = col + 1 + tid; i < f.n; i += NT) {
+      const double lraw = F[i + col * ld];
+      double v[32];
+#pragma unroll
+      for (int cc = 0; cc < 32; ++cc) v[cc] = F[i + (int64_t)(jb + min(cc, w - 1)) * ld];
+      const double l = lraw * rp;
       F[i + col * ld] = l;
-      for (int cc = c + 1; cc < w; ++cc) F[i + (int64_t)(jb + cc) * ld] -= l * prow[cc];
+      double nxt = 0.0;
+#pragma unroll
+      for (int cc = 0; cc < 32; ++cc)
+        if (cc > c && cc < w) {
+          const double y = v[cc] - l * prow[cc];
+          F[i + (int64_t)(jb + cc) * ld] = y;
+          if (cc == c + 1) nxt = y;
+        }
+      if (c + 1 < w && i < f.s && fabs(nxt) > best) { best = fabs(nxt); bi = i; }
     }
     __syncthreads();
   }
@@ -279,11 +314,12 @@ void launch_lu_panel_split(const LUFront* fr, int nf, int jb, int nb, int max_m1
 
 void launch_lu_panel(const LUFront* fr, int nf, int jb, int nb, int* info, hipStream_t s, double flops) {
   if (nf <= 0) return;
-  REQUIRE(nb <= 64, HSSMF_EINVAL, "panel width");
+  REQUIRE(nb <= 32, HSSMF_EINVAL, "panel width");
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (prof::enabled()) prof::ext(3, flops, &e0, &e1);   // timing hook
-  if (e0) hipExtLaunchKernelGGL(lu_panel_kernel, dim3(nf), dim3(256), 0, s, e0, e1, 0, fr, jb, nb, info);
-  else hipLaunchKernelGGL(lu_panel_kernel, dim3(nf), dim3(256), 0, s, fr, jb, nb, info);
+  // fronts this tall are few: one 512-thread workgroup each
+  if (e0) hipExtLaunchKernelGGL(lu_panel_kernel<512>, dim3(nf), dim3(512), 0, s, e0, e1, 0, fr, jb, nb, info);
+  else hipLaunchKernelGGL(lu_panel_kernel<512>, dim3(nf), dim3(512), 0, s, fr, jb, nb, info);
   HIP_CHECK(hipGetLastError());
 }
 
