@@ -16,8 +16,12 @@ __device__ __forceinline__ double wsum(double v) {
 // for the column loop and written back; false: the loop works on global
 // memory (panels too tall for LDS).  The Gram matrix Y^T Y is accumulated
 // from 64-row chunks by all threads, and T column by column in parallel.
-template <bool LDS>
-__global__ __launch_bounds__(256) void qr_panel_kernel(const PanelDesc* __restrict__ descs) {
+// NT threads: each trailing column of a step is one wavefront's work, so
+// wider workgroups (for batches of few panels, one per CU) take more
+// columns at once; every sum keeps its order whatever NT is.
+template <bool LDS, int NT>
+__global__ __launch_bounds__(NT) void qr_panel_kernel(const PanelDesc* __restrict__ descs) {
+  constexpr int NW = NT / 64;
   extern __shared__ double Pl[];
   __shared__ double tau[kPanel], v0s[kPanel], G[kPanel][kPanel + 1], Ts[kPanel][kPanel + 1];
   __shared__ double Yc[64][kPanel + 1];
@@ -32,7 +36,7 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const PanelDesc* __restri
     return C[i + (int64_t)(j0 + l) * m];
   };
   if (LDS) {
-    for (int64_t e = tid; e < (int64_t)mp * nb; e += 256) {
+    for (int64_t e = tid; e < (int64_t)mp * nb; e += NT) {
       const int r = (int)(e % mp), l = (int)(e / mp);
       Pl[e] = C[(j0 + r) + (int64_t)(j0 + l) * m];
     }
@@ -62,7 +66,7 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const PanelDesc* __restri
     __syncthreads();
     const double tv = bc[0], v0 = bc[1];
     // apply H_t to the remaining panel columns
-    for (int c = l + 1 + wave; c < nb; c += 4) {
+    for (int c = l + 1 + wave; c < nb; c += NW) {
       double dot = 0.0;
       for (int i = t + lane; i < m; i += 64) dot += ((i == t) ? v0 : el(l, i)) * el(c, i);
       dot = wsum(dot) * tv;
@@ -83,21 +87,23 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const PanelDesc* __restri
     if (i == t) return v0s[l];
     return el(l, i);
   };
-  for (int64_t e = tid; e < (int64_t)m * nb; e += 256) {
+  for (int64_t e = tid; e < (int64_t)m * nb; e += NT) {
     const int i = (int)(e % m), l = (int)(e / m);
     pd.Y[i + (int64_t)l * m] = (i < j0) ? 0.0 : yv(i, l);
   }
   if (LDS) {
-    for (int64_t e = tid; e < (int64_t)mp * nb; e += 256) {
+    for (int64_t e = tid; e < (int64_t)mp * nb; e += NT) {
       const int r = (int)(e % mp), l = (int)(e / mp);
       C[(j0 + r) + (int64_t)(j0 + l) * m] = Pl[e];
     }
   }
-  // Gram matrix G = Y^T Y over rows j0..m-1 (pairs a <= b, up to 3 per thread)
-  double g[3] = {0.0, 0.0, 0.0};
-  int pa[3], pb[3];
-  for (int q = 0; q < 3; ++q) {
-    int p = tid + 256 * q, a = 0;
+  // Gram matrix G = Y^T Y over rows j0..m-1 (pairs a <= b, Q per thread)
+  constexpr int Q = (kPanel * (kPanel + 1) / 2 + NT - 1) / NT;
+  double g[Q];
+  int pa[Q], pb[Q];
+  for (int q = 0; q < Q; ++q) {
+    g[q] = 0.0;
+    int p = tid + NT * q, a = 0;
     if (p >= kPanel * (kPanel + 1) / 2) {   // no pair for this slot
       pa[q] = pb[q] = kPanel;
       continue;
@@ -108,19 +114,19 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const PanelDesc* __restri
   }
   for (int r0 = j0; r0 < m; r0 += 64) {
     __syncthreads();
-    for (int e = tid; e < 64 * kPanel; e += 256) {
+    for (int e = tid; e < 64 * kPanel; e += NT) {
       const int r = e % 64, l = e / 64;
       Yc[r][l] = (r0 + r < m && l < nb) ? yv(r0 + r, l) : 0.0;
     }
     __syncthreads();
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < Q; ++q) {
       if (pa[q] >= nb || pb[q] >= nb) continue;
       double acc = 0.0;
       for (int r = 0; r < 64; ++r) acc += Yc[r][pa[q]] * Yc[r][pb[q]];
       g[q] += acc;
     }
   }
-  for (int q = 0; q < 3; ++q)
+  for (int q = 0; q < Q; ++q)
     if (pa[q] < nb && pb[q] < nb) G[pa[q]][pb[q]] = g[q];
   __syncthreads();
   // T: T(i,i) = tau_i, T(0:i, i) = -tau_i T(0:i, 0:i) G(0:i, i)
@@ -134,7 +140,7 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const PanelDesc* __restri
     }
     __syncthreads();
   }
-  for (int e = tid; e < kPanel * kPanel; e += 256) {
+  for (int e = tid; e < kPanel * kPanel; e += NT) {
     const int r = e % kPanel, i = e / kPanel;
     pd.T[r + i * kPanel] = (r <= i && i < nb) ? Ts[r][i] : 0.0;
   }
@@ -155,10 +161,15 @@ size_t qr_panel_lds_budget() {
 void launch_qr_panel(const PanelDesc* d, int nd, int max_mp, hipStream_t s) {
   if (nd <= 0) return;
   const size_t lds = (size_t)std::max(max_mp, 1) * kPanel * sizeof(double);
-  if (lds <= qr_panel_lds_budget())
-    hipLaunchKernelGGL(qr_panel_kernel<true>, dim3(nd), dim3(256), lds, s, d);
-  else
-    hipLaunchKernelGGL(qr_panel_kernel<false>, dim3(nd), dim3(256), 0, s, d);
+  // a batch of few panels has a CU per panel: 1024 threads each
+  const bool wide = nd <= 128;
+  if (lds <= qr_panel_lds_budget()) {
+    if (wide) hipLaunchKernelGGL((qr_panel_kernel<true, 1024>), dim3(nd), dim3(1024), lds, s, d);
+    else hipLaunchKernelGGL((qr_panel_kernel<true, 256>), dim3(nd), dim3(256), lds, s, d);
+  } else {
+    if (wide) hipLaunchKernelGGL((qr_panel_kernel<false, 1024>), dim3(nd), dim3(1024), 0, s, d);
+    else hipLaunchKernelGGL((qr_panel_kernel<false, 256>), dim3(nd), dim3(256), 0, s, d);
+  }
   HIP_CHECK(hipGetLastError());
 }
 
