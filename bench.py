@@ -88,18 +88,21 @@ LP_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
 # HBM bytes per launch of the pivot-step kernel on this workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; each scaled by its reading for
 # a 256 MiB device copy): profiles/id_step_hbm_traffic_poisson3d_64.md.  Valid
-# only for the kernel source those counters were taken on.
-TRAFFIC = {"id": (28.14e6, "paper_1502_07405_amd/csrc/k_id.hip", "0898907207216ea3")}
+# only for the kernel source those counters were taken on and for the same
+# mix of launches: the launches per factorization must agree within 1%.
+TRAFFIC = {"id": (28.14e6, "paper_1502_07405_amd/csrc/k_id.hip", "0898907207216ea3", 18627)}
 
 
-def traffic_for(cls):
+def traffic_for(cls, launches_per_factorization):
     import hashlib
     if cls not in TRAFFIC:
         return None
-    nbytes, src, digest = TRAFFIC[cls]
+    nbytes, src, digest, launches = TRAFFIC[cls]
     with open(os.path.join(ROOT, src), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest()[:16] != digest:
             return None   # the kernel changed since the counters were taken
+    if abs(launches_per_factorization - launches) > 0.01 * launches:
+        return None       # a different mix of pivot steps than the one measured
     return nbytes
 
 
@@ -173,7 +176,7 @@ def main():
     bound, peak = BOUND[dom]
     if peak is None:
         peak = LP_PEAK_TFLOPS[args.prec]
-    traffic = traffic_for(dom)
+    traffic = traffic_for(dom, launches / args.steps)
     roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
             "traffic": traffic, "traffic_unit": "bytes per launch (HBM)",
             "hbm_GBps_from_traffic": (traffic / (avg_ms * 1e-3) / 1e9) if traffic and avg_ms > 0 else None,

@@ -145,6 +145,7 @@ def factor(A, ordering, opts, stop_after=None):
     fronts = analyse(Ap, ordering.sep_ptr, ordering.parent)
     updates = {}
     factors = []
+    hss_d = {}   # final sample count of each HSS front
     for f in fronts:
         if stop_after is not None and f.id > stop_after:
             break
@@ -156,8 +157,12 @@ def factor(A, ordering, opts, stop_after=None):
             def rand(c0, nc, orig=orig):
                 return gaussian(opts.seed, orig, nc, c0)
 
+            # R_i reuses the random columns of its HSS children (Eq. (Rmerge),
+            # Sec. 4.3): it starts with as many as they ended with, at least d0
+            d_init = max([opts.d0] + [hss_d[c] for c in f.children if c in hss_d])
             H, F, k, q, Theta, Phi = hs.build_hss_front(
-                op, f.s, f.u, opts.leaf_size, rand, opts.rel_tol, opts.d0, opts.dd, opts.p, opts.d_max)
+                op, f.s, f.u, opts.leaf_size, rand, opts.rel_tol, d_init, opts.dd, opts.p, opts.d_max)
+            hss_d[f.id] = H.stats["d"]
             data = dict(H=H, ulv=F, k=k, q=q)
             if q >= 0:
                 data["ops"] = hs.Front11Ops(H, k, q)

@@ -414,17 +414,28 @@ FrontOpDev* front_ops(Handle& h, const std::vector<HFront*>& fs) {
 
 void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops, const int* iota) {
   const hssmf_opts& o = h.o;
-  // initial samples
+  // initial samples.  A front starts with as many random columns as its
+  // HSS children ended with (at least d0): its random matrix reuses their
+  // columns (Eq. (Rmerge), Sec. 4.3), so fewer than that cannot resolve
+  // what they already needed.
   h.larena.release();
   h.sarena.release();
   {
-    std::vector<int> c0;
+    std::vector<int> dinit;
     for (HFront* F : fs) {
+      int d = o.d0;
+      for (int c : h.P.fr[F->f].kids)
+        if (h.P.fr[c].hss) d = std::max(d, h.hf[h.fr[c].hidx].d);
+      dinit.push_back(d);
+    }
+    std::vector<int> c0;
+    for (size_t fi = 0; fi < fs.size(); ++fi) {
+      HFront* F = fs[fi];
       F->d = 0;
       F->dcap = 0;
       F->R = F->Sr = F->Sc = nullptr;
-      grow_samples(h, *F, o.d0);
-      F->d = o.d0;
+      grow_samples(h, *F, dinit[fi]);
+      F->d = dinit[fi];
       F->rounds = 0;
       F->finished = false;
       F->refresh = false;
@@ -443,7 +454,17 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
       gen_random(h, *F, 0, F->d);
       c0.push_back(0);
     }
-    sample(h, fs, c0, o.d0);
+    // one sampling pass per distinct starting width
+    std::vector<int> widths(dinit);
+    std::sort(widths.begin(), widths.end());
+    widths.erase(std::unique(widths.begin(), widths.end()), widths.end());
+    for (int wd : widths) {
+      std::vector<HFront*> grp;
+      std::vector<int> gc0;
+      for (size_t fi = 0; fi < fs.size(); ++fi)
+        if (dinit[fi] == wd) { grp.push_back(fs[fi]); gc0.push_back(0); }
+      sample(h, grp, gc0, wd);
+    }
   }
   int maxh = 0;
   for (HFront* F : fs) maxh = std::max(maxh, F->maxh);
