@@ -90,7 +90,7 @@ LP_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
 # a 256 MiB device copy): profiles/id_step_hbm_traffic_poisson3d_64.md.  Valid
 # only for the kernel source those counters were taken on and for the same
 # mix of launches: the launches per factorization must agree within 1%.
-TRAFFIC = {"id": (28.14e6, "paper_1502_07405_amd/csrc/k_id.hip", "0898907207216ea3", 18627)}
+TRAFFIC = {"id": (43.90e6, "paper_1502_07405_amd/csrc/k_id.hip", "0898907207216ea3", 15793)}
 
 
 def traffic_for(cls, launches_per_factorization):
