@@ -79,6 +79,28 @@ def test_rank_stays_flat_in_2d(rng):
     assert ranks[1] <= ranks[0] + 8
 
 
+def test_hss_front_starts_from_its_hss_childrens_samples():
+    """Eq. (Rmerge), Sec. 4.3: a front's random matrix reuses its HSS
+    children's random columns, so it starts with as many as they ended with
+    (at least d0) and grows by dd from there; its final d is never below a
+    child's, and its growth rounds count from that start."""
+    A, o = P.poisson2d(48), P.geometric_nd((48, 48), 4)
+    d0, dd = 8, 8
+    fac = mf.factor(A, o, mf.Options(min_sep_hss=12, leaf_size=8, rel_tol=1e-6, d0=d0, dd=dd, p=4))
+    info = {r[0]: r for r in mf.hss_ranks(fac)}
+    kids = {}
+    for f, par in enumerate(o.parent):
+        if par >= 0:
+            kids.setdefault(int(par), []).append(f)
+    checked = 0
+    for f, (_, _, _, d, rounds) in info.items():
+        hk = [info[c][3] for c in kids.get(f, []) if c in info]
+        start = max([d0] + hk)
+        assert d >= start and d == start + rounds * dd, (f, d, rounds, start)
+        checked += bool(hk) and max(hk) > d0
+    assert checked > 0   # the case the rule is about occurs here
+
+
 def test_adjoint_matches_dense(rng):
     """lambda = A^{-T} g, dL/db = lambda, dL/dA_ij = -lambda_i x_j on the
     pattern; checked against dense solves and central differences."""
