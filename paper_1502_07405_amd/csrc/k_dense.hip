@@ -170,9 +170,19 @@ __global__ __launch_bounds__(256) void lu_panel11_kernel(const LUFront* __restri
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double* F = f.F;
   const int64_t ld = f.ld;
-  for (int e = tid; e < m1 * w; e += 256) {
-    const int r = e % m1, c = e / m1;
-    P[e] = F[(jb + r) + (int64_t)(jb + c) * ld];
+  {
+    // stage the panel: a thread takes one row per 256-row chunk and loads
+    // its 32 panel entries at once (column indices clamped to the panel),
+    // so the loads are in flight together rather than one per round trip
+    const auto G = (gptr<const double>)F;
+    for (int r = tid; r < m1; r += 256) {
+      double v[32];
+#pragma unroll
+      for (int c = 0; c < 32; ++c) v[c] = G[(jb + r) + (int64_t)(jb + min(c, w - 1)) * ld];
+#pragma unroll
+      for (int c = 0; c < 32; ++c)
+        if (c < w) P[r + c * m1] = v[c];
+    }
   }
   __syncthreads();
   for (int c = 0; c < w; ++c) {

@@ -36,9 +36,17 @@ __global__ __launch_bounds__(NT) void qr_panel_kernel(const PanelDesc* __restric
     return C[i + (int64_t)(j0 + l) * m];
   };
   if (LDS) {
-    for (int64_t e = tid; e < (int64_t)mp * nb; e += NT) {
-      const int r = (int)(e % mp), l = (int)(e / mp);
-      Pl[e] = C[(j0 + r) + (int64_t)(j0 + l) * m];
+    // stage the panel: a thread takes one row per NT-row chunk and loads its
+    // kPanel entries at once (column indices clamped to the panel), so the
+    // loads are in flight together rather than one per round trip
+    const auto G = (gptr<const double>)C;
+    for (int r = tid; r < mp; r += NT) {
+      double v[kPanel];
+#pragma unroll
+      for (int l = 0; l < kPanel; ++l) v[l] = G[(j0 + r) + (int64_t)(j0 + min(l, nb - 1)) * m];
+#pragma unroll
+      for (int l = 0; l < kPanel; ++l)
+        if (l < nb) Pl[r + (int64_t)l * mp] = v[l];
     }
     __syncthreads();
   }
