@@ -85,6 +85,9 @@ KERNEL_NAME = {"id": "id_step_kernel (pivot steps of the column-pivoted QR behin
 BOUND = {"id": ("alu", FP64_PEAK_TFLOPS), "gemm64": ("mfma", FP64_PEAK_TFLOPS),
          "gemmlp": ("mfma", None), "lupanel": ("alu", FP64_PEAK_TFLOPS)}
 LP_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
+# the library's probe (hssmf_measure_peaks) that checks each published peak
+# on the device at hand: FP64 FMA loop, FP64 matrix-core loop
+MEASURED_KEY = {"id": "fp64_valu_TFLOPs", "gemm64": "fp64_mfma_TFLOPs", "gemmlp": None, "lupanel": "fp64_valu_TFLOPs"}
 # HBM bytes per launch of the pivot-step kernel on this workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; each scaled by its reading for
 # a 256 MiB device copy): profiles/id_step_hbm_traffic_poisson3d_64.md.  Valid
@@ -182,7 +185,15 @@ def main():
             "hbm_GBps_from_traffic": (traffic / (avg_ms * 1e-3) / 1e9) if traffic and avg_ms > 0 else None,
             "hbm_frac_from_traffic": (traffic / (avg_ms * 1e-3) / HBM_PEAK_BPS) if traffic and avg_ms > 0 else None, "kernel": KERNEL_NAME[dom], "avg_launch_ms": avg_ms, "launches": launches,
             "time_share": ms / (sec_hooked * 1e3 * args.steps)}
-    extra = {"step_s_with_timing_hooks": sec_hooked, "iterations": infos[-1][0], "rel_residual": relres(x), "max_rank": st["max_rank"],
+    # the published peaks checked on this device: copy, FMA and matrix-core loops
+    pk = H.measure_peaks()
+    mkey = MEASURED_KEY[dom]
+    roof["measured_peak"] = pk[mkey] if mkey else None
+    roof["frac_vs_measured"] = achieved / pk[mkey] if mkey and pk[mkey] > 0 else None
+    roof["hbm_measured_GBps"] = pk["hbm_GBps"]
+    if roof["hbm_GBps_from_traffic"] is not None and pk["hbm_GBps"] > 0:
+        roof["hbm_frac_vs_measured"] = roof["hbm_GBps_from_traffic"] / pk["hbm_GBps"]
+    extra = {"measured_peaks": pk, "step_s_with_timing_hooks": sec_hooked, "iterations": infos[-1][0], "rel_residual": relres(x), "max_rank": st["max_rank"],
              "max_d": st["max_d"], "growth_rounds": st["growth_rounds"],
              "kernel_ms_per_step": {k: prof[k][0] / args.steps for k in KCLASSES},
              "kernel_launches_per_step": {k: prof[k][1] / args.steps for k in KCLASSES},

@@ -212,6 +212,24 @@ int hssmf_last_failed_front(void* h);
 int hssmf_profile_enable(int32_t on);
 int hssmf_profile_read(int32_t kclass, double* ms, int64_t* launches, double* flops);
 
+/* Machine-peak probes, so that roofline fractions can be quoted against the
+ * device as measured as well as against its published figures.  Runs, on
+ * the given stream (NULL = the default stream) and the current device:
+ * a copy of 512 MiB between two device buffers (hbm_GBps = bytes read plus
+ * written per second / 1e9); a loop of independent FP64 fused
+ * multiply-adds (fp64_valu_TFLOPs, two flops each); a loop of FP64
+ * matrix-core 16 x 16 x 4 products (fp64_mfma_TFLOPs, 2048 flops per
+ * wavefront instruction).  Each figure is the best of five timed runs.
+ * Allocates and frees 1 GiB of device memory and synchronizes the stream;
+ * not for use under graph capture.  HSSMF_EINVAL for out == NULL,
+ * HSSMF_EDEVICE when a HIP call fails. */
+typedef struct {
+  double hbm_GBps;
+  double fp64_valu_TFLOPs;
+  double fp64_mfma_TFLOPs;
+} hssmf_peaks;
+int hssmf_measure_peaks(void* stream, hssmf_peaks* out);
+
 void hssmf_destroy(void* h);
 
 const char* hssmf_strerror(int code);

@@ -592,6 +592,13 @@ int hssmf_hss_ranks(void* hv, int32_t* out, int32_t cap) {
   return i;
 }
 
+int hssmf_measure_peaks(void* stream, hssmf_peaks* out) {
+  if (!out) return HSSMF_EINVAL;
+  return guard_impl(nullptr, [&]() {
+    measure_peaks(static_cast<hipStream_t>(stream), &out->hbm_GBps, &out->fp64_valu_TFLOPs, &out->fp64_mfma_TFLOPs);
+  });
+}
+
 int hssmf_last_failed_front(void* hv) {
   Handle* h = static_cast<Handle*>(hv);
   return h ? h->failed_front : g_failed_front;

@@ -250,6 +250,9 @@ void launch_id_init(const IDProb* p, int np, int total_wg, int max_d, hipStream_
 // wgmap[w] = (problem, workgroup within the problem) of grid workgroup w
 void launch_id_step(const IDProb* p, const int2* wgmap, int total_wg, int t, int max_d, hipStream_t s);
 void launch_id_finish(const IDProb* p, int np, int max_m, hipStream_t s);
+
+// Copy (HBM GB/s), FP64 FMA loop and FP64 matrix-core loop (TFLOP/s) rates.
+void measure_peaks(hipStream_t s, double* hbm_gbps, double* valu_tflops, double* mfma_tflops);
 // Cooperative variant: every pivot step of the listed problems in one launch
 // whose workgroups are all resident (hipLaunchCooperativeKernel), with the
 // candidates kept in registers and a per-problem barrier between steps.

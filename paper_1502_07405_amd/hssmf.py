@@ -19,7 +19,7 @@ OUTER = {"ir": 0, "gmres": 1}
 EXPORTS = ["hssmf_default_opts", "hssmf_factor", "hssmf_refactor", "hssmf_apply", "hssmf_solve",
            "hssmf_solve_transpose", "hssmf_adjoint", "hssmf_stats_get", "hssmf_hss_ranks",
            "hssmf_last_failed_front", "hssmf_destroy", "hssmf_strerror", "hssmf_profile_enable",
-           "hssmf_profile_read", "hssmf_factor_batch", "hssmf_systems"]
+           "hssmf_profile_read", "hssmf_factor_batch", "hssmf_systems", "hssmf_measure_peaks"]
 KCLASS = {"id": 0, "gemm64": 1, "gemmlp": 2, "lupanel": 3}
 
 
@@ -52,6 +52,11 @@ class Opts(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("rel_residual", ctypes.c_double),
                 ("failed_front", ctypes.c_int32)]
+
+
+class Peaks(ctypes.Structure):
+    _fields_ = [("hbm_GBps", ctypes.c_double), ("fp64_valu_TFLOPs", ctypes.c_double),
+                ("fp64_mfma_TFLOPs", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -91,6 +96,7 @@ def load():
                                          ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
         L.hssmf_systems.argtypes = [vp, vp, i32]
         L.hssmf_profile_enable.argtypes = [i32]
+        L.hssmf_measure_peaks.argtypes = [vp, ctypes.POINTER(Peaks)]
         L.hssmf_profile_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(ctypes.c_double)]
         _lib = L
@@ -111,6 +117,16 @@ def profile_read(kclass):
     if rc != HSSMF_OK:
         raise HssmfError(rc, "hssmf_profile_read")
     return ms.value, n.value, fl.value
+
+
+def measure_peaks(stream=None):
+    """Measured device rates: {"hbm_GBps", "fp64_valu_TFLOPs", "fp64_mfma_TFLOPs"}
+    from the library's copy, FMA-loop and matrix-core-loop probes."""
+    out = Peaks()
+    rc = load().hssmf_measure_peaks(stream, ctypes.byref(out))
+    if rc != HSSMF_OK:
+        raise HssmfError(rc, "hssmf_measure_peaks")
+    return {k: getattr(out, k) for k, _ in Peaks._fields_}
 
 
 def strerror(code):

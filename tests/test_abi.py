@@ -43,6 +43,10 @@ def test_default_options_and_strerror(lib):
     assert H.strerror(0) == "ok" and H.strerror(H.HSSMF_ERANK) == "HSS rank exceeds d_max"
 
 
+def test_measure_peaks_rejects_null_output(lib):
+    assert lib.hssmf_measure_peaks(None, None) == H.HSSMF_EINVAL
+
+
 def _call_factor(A_rowptr, A_col, A_val, perm, sep, par, n, opts=None):
     L = H.load()
     rp = np.ascontiguousarray(A_rowptr, dtype=np.int64)

@@ -402,3 +402,12 @@ def test_repeatable_bitwise():
     y2 = fac.apply(b).cpu().numpy()
     assert np.array_equal(y1, y2)
     fac.close()
+
+
+def test_measured_peaks_are_plausible():
+    """The library's peak probes (copy, FP64 FMA loop, FP64 matrix-core loop)
+    land between a quarter of MI355X's published figures (8 TB/s HBM, 78.6
+    TFLOP/s FP64 vector and matrix) and 10% above them."""
+    pk = H.measure_peaks()
+    for key, pub in (("hbm_GBps", 8000.0), ("fp64_valu_TFLOPs", 78.6), ("fp64_mfma_TFLOPs", 78.6)):
+        assert 0.25 * pub <= pk[key] <= 1.1 * pub, (key, pk[key])
