@@ -586,6 +586,16 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
           flush();
           launch_id_finish(dq, np, maxm, h.st);
         } else {
+        // done flags that the host reads without a copy back: each problem's
+        // stop step sets its flag in mapped host memory
+        IdPoll& ip = h.idpoll;
+        ip.reserve(np);
+        ip.reset();
+        volatile int* hd = ip.host;
+        for (int pi = 0; pi < np; ++pi) {
+          hd[pi] = (q[pi].m == 0 || q[pi].d == 0) ? 1 : 0;   // no pivot step to take
+          q[pi].hdone = ip.dev + pi;
+        }
         IDProb* dq = upload(h, q);
         // grid of the live problems' workgroups: rebuilt at every check so
         // that finished problems stop taking workgroups
@@ -601,20 +611,23 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
         int nwg = 0;
         const int2* dwgm = wgmap(live, nwg);
         launch_id_init(dq, np, wg, maxd, h.st);
-        std::vector<int> st(4 * cand.size());
+        // The stream never drains: every 4 steps the host drops the problems
+        // whose flag is set (rebuilding the grid at most every 16 steps) and
+        // stops once all are set, while the event ring keeps it at most a
+        // few tens of steps ahead of the device.
+        int remap = 0;
         for (int t = 0; t <= tmax; ++t) {
           launch_id_step(dq, dwgm, nwg, t, maxd, h.st);
-          if ((t & 63) == 63 && t < tmax) {  // stop early once every problem has its rank
-            HIP_CHECK(hipMemcpyAsync(st.data(), sbuf, st.size() * sizeof(int), hipMemcpyDeviceToHost, h.st));
-            HIP_CHECK(hipStreamSynchronize(h.st));
-            h.stager.sync();
+          ip.pace(t, h.st);
+          if ((t & 3) == 3 && t < tmax) {
             std::vector<int> nl;
             for (int pi : live)
-              if (!st[2 * pi]) nl.push_back(pi);
+              if (!hd[pi]) nl.push_back(pi);
             if (nl.empty()) break;
-            if (nl.size() < live.size()) {
+            if (nl.size() < live.size() && t - remap >= 16) {
               live.swap(nl);
               dwgm = wgmap(live, nwg);
+              remap = t;
             }
           }
         }

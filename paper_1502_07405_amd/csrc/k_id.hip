@@ -195,6 +195,8 @@ __global__ __launch_bounds__(256) void id_step_kernel(const IDProb* __restrict__
     if (b == 0 && tid == 0) {
       q.state[1] = (t == 0 && best <= 0.0) ? 0 : t;
       q.state[0] = 1;
+      // tell the host without a copy back: a plain store, visible system-wide
+      if (q.hdone) __hip_atomic_store(q.hdone, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
     return;
   }

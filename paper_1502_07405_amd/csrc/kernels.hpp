@@ -240,6 +240,7 @@ struct IDProb {
   double* first;        // first pivot norm
   unsigned char* active;
   double* cand;         // 2 (parity) x P x d: each workgroup's best candidate column (cooperative path)
+  int* hdone;           // null, or a flag in mapped host memory that the stop step sets (stepwise path)
   int m, d, lds, P;     // P workgroups of kIDCols candidates each
   int wg0, pad;         // first workgroup of this problem in the launch grid
   double eps;

@@ -123,6 +123,49 @@ struct FrontRT {
   int64_t asm_off = 0, asm_cnt = 0;  // range in the assembly map arrays
 };
 
+// Progress of the stepwise interpolative decompositions as the host sees it
+// without synchronizing: the stop step of every problem sets that problem's
+// flag in mapped, coherent pinned memory, and a ring of stream events (one
+// recorded every kEvery pivot steps) bounds how far the host runs ahead of
+// the device.
+struct IdPoll {
+  static constexpr int kEvery = 8;   // pivot steps per recorded event
+  static constexpr int kRing = 2;    // events in the ring: the host leads by < kRing * kEvery + kEvery steps
+  int* host = nullptr;               // flags as the host reads them
+  int* dev = nullptr;                // the same flags as the device writes them
+  size_t cap = 0;
+  hipEvent_t ev[kRing] = {};
+  bool armed[kRing] = {};
+  void reserve(size_t n) {
+    if (!ev[0])
+      for (auto& e : ev) HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    if (n <= cap) return;
+    if (host) HIP_CHECK(hipHostFree(host));
+    host = dev = nullptr;
+    cap = 0;
+    HIP_CHECK(hipHostMalloc((void**)&host, n * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent));
+    HIP_CHECK(hipHostGetDevicePointer((void**)&dev, host, 0));
+    cap = n;
+  }
+  // after pivot step t has been enqueued: every kEvery steps, wait for the
+  // event recorded kRing * kEvery steps ago, then record a new one
+  void pace(int t, hipStream_t s) {
+    if (t % kEvery != kEvery - 1) return;
+    const int k = (t / kEvery) % kRing;
+    if (armed[k]) HIP_CHECK(hipEventSynchronize(ev[k]));
+    HIP_CHECK(hipEventRecord(ev[k], s));
+    armed[k] = true;
+  }
+  void reset() {
+    for (auto& a : armed) a = false;
+  }
+  ~IdPoll() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (host) (void)hipHostFree(host);
+  }
+};
+
 struct Handle {
   Plan P;
   hssmf_opts o{};
@@ -133,6 +176,7 @@ struct Handle {
   Arena sarena;      // temporaries of one batched pass (stream ordered reuse)
   Arena* cur = &arena;
   Stager stager;
+  IdPoll idpoll;
   std::vector<Op> sops[2][2];  // [trans][0 = forward, 1 = backward]
   double* yws = nullptr;       // n, the right-hand side in the new ordering
   int* d_iperm = nullptr;
