@@ -88,25 +88,29 @@ LP_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
 # the library's probe (hssmf_measure_peaks) that checks each published peak
 # on the device at hand: FP64 FMA loop, FP64 matrix-core loop
 MEASURED_KEY = {"id": "fp64_valu_TFLOPs", "gemm64": "fp64_mfma_TFLOPs", "gemmlp": None, "lupanel": "fp64_valu_TFLOPs"}
-# HBM bytes per launch of the pivot-step kernel on this workload, from two
-# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; each scaled by its reading for
-# a 256 MiB device copy): profiles/id_step_hbm_traffic_poisson3d_64.md.  Valid
-# only for the kernel source those counters were taken on and for the same
-# mix of launches: the launches per factorization must agree within 1%.
-TRAFFIC = {"id": (43.90e6, "paper_1502_07405_amd/csrc/k_id.hip", "0898907207216ea3", 15793)}
+# HBM bytes per factorization moved by the pivot-step kernel on this
+# workload, from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; each scaled
+# by its reading for a 256 MiB device copy):
+# profiles/id_step_hbm_traffic_poisson3d_64.md.  Valid only for the kernel
+# source those counters were taken on.  The number of launches varies a
+# little from run to run (how far the host has run ahead when the last
+# problem of a pass stops), and the extra launches exit at once and move
+# nothing, so the per-launch figure is this total over the run's own
+# launches.
+TRAFFIC = {"id": (6.8842e11, "paper_1502_07405_amd/csrc/k_id.hip", "39790950b6cabba7")}
 
 
 def traffic_for(cls, launches_per_factorization):
+    """HBM bytes per launch of kernel class cls, or None when not measured for
+    the current source."""
     import hashlib
-    if cls not in TRAFFIC:
+    if cls not in TRAFFIC or launches_per_factorization <= 0:
         return None
-    nbytes, src, digest, launches = TRAFFIC[cls]
+    nbytes, src, digest = TRAFFIC[cls]
     with open(os.path.join(ROOT, src), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest()[:16] != digest:
             return None   # the kernel changed since the counters were taken
-    if abs(launches_per_factorization - launches) > 0.01 * launches:
-        return None       # a different mix of pivot steps than the one measured
-    return nbytes
+    return nbytes / launches_per_factorization
 
 
 def main():
