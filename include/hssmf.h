@@ -96,7 +96,7 @@ typedef struct {
   int32_t use_graph;   /* 1: the preconditioner's forward and backward sweeps
                           are captured once per factorization as a HIP graph
                           (on a private stream) and replayed on the handle's
-                          stream; 0: launched one by one */
+                          stream; 0 (default): launched one by one */
   int32_t gemm_tile;   /* FP64 matrix-core GEMM kernel: 0 = chosen per
                           shape class by the built-in autotuner (timed once
                           per process); forced: 64 (64 x 64 tiles, k-tiles of

@@ -404,7 +404,7 @@ int hssmf_default_opts(hssmf_opts* o) {
   o->tol = 1e-10;
   o->max_it = 50;
   o->id_kernel = HSSMF_ID_STEPWISE;
-  o->use_graph = 1;
+  o->use_graph = 0;   // capture after every factorization costs more than replay saves
   return HSSMF_OK;
 }
 
