@@ -164,6 +164,13 @@ int hssmf_systems(void* h, int64_t* off, int32_t cap);
  * matrix given to hssmf_factor; val has rowptr[n] entries, host memory). */
 int hssmf_refactor(void* h, const double* val);
 
+/* hssmf_refactor with the new values already in device memory: val_dev has
+ * rowptr[n] entries in the CSR order given to hssmf_factor, is read on the
+ * handle's stream (copied into the handle there) and stays owned by the
+ * caller.  HSSMF_EINVAL for a null handle or pointer; otherwise as
+ * hssmf_refactor. */
+int hssmf_refactor_device(void* h, const double* val_dev);
+
 /* One application of the factorization, y = M^{-1} x (trans = 0) or
  * y = M^{-T} x (trans = 1): the multifrontal forward sweep bottom-up and the
  * backward sweep top-down (Sec. 3.3), with ULV solves on HSS fronts.  x, y:

@@ -531,6 +531,15 @@ int hssmf_refactor(void* hv, const double* val) {
   });
 }
 
+int hssmf_refactor_device(void* hv, const double* val_dev) {
+  Handle* h = static_cast<Handle*>(hv);
+  if (!h || !val_dev) return HSSMF_EINVAL;
+  return guard_impl(h, [&]() {
+    HIP_CHECK(hipMemcpyAsync(h->d_val, val_dev, sizeof(double) * h->P.nnz, hipMemcpyDeviceToDevice, h->st));
+    numeric(*h);
+  });
+}
+
 int hssmf_apply(void* hv, int32_t trans, const double* x, double* y) {
   Handle* h = static_cast<Handle*>(hv);
   if (!h || !x || !y || (trans != 0 && trans != 1)) return HSSMF_EINVAL;

@@ -19,7 +19,8 @@ OUTER = {"ir": 0, "gmres": 1}
 EXPORTS = ["hssmf_default_opts", "hssmf_factor", "hssmf_refactor", "hssmf_apply", "hssmf_solve",
            "hssmf_solve_transpose", "hssmf_adjoint", "hssmf_stats_get", "hssmf_hss_ranks",
            "hssmf_last_failed_front", "hssmf_destroy", "hssmf_strerror", "hssmf_profile_enable",
-           "hssmf_profile_read", "hssmf_factor_batch", "hssmf_systems", "hssmf_measure_peaks"]
+           "hssmf_profile_read", "hssmf_factor_batch", "hssmf_systems", "hssmf_measure_peaks",
+           "hssmf_refactor_device"]
 KCLASS = {"id": 0, "gemm64": 1, "gemmlp": 2, "lupanel": 3}
 
 
@@ -81,6 +82,7 @@ def load():
         L.hssmf_factor.argtypes = [ctypes.POINTER(CSRArg), ctypes.POINTER(OrderingArg), ctypes.POINTER(Opts), vp,
                                    ctypes.POINTER(vp)]
         L.hssmf_refactor.argtypes = [vp, vp]
+        L.hssmf_refactor_device.argtypes = [vp, vp]
         L.hssmf_apply.argtypes = [vp, i32, vp, vp]
         L.hssmf_solve.argtypes = [vp, vp, vp, ctypes.POINTER(Info)]
         L.hssmf_solve_transpose.argtypes = [vp, vp, vp, ctypes.POINTER(Info)]
@@ -200,6 +202,13 @@ class Factorization:
         raise HssmfError(rc, what, self.lib.hssmf_last_failed_front(self.h))
 
     def refactor(self, val):
+        """New values, same pattern: a float64 CUDA tensor (read in place,
+        hssmf_refactor_device) or host values (hssmf_refactor)."""
+        torch = self._torch
+        if torch is not None and isinstance(val, torch.Tensor) and val.is_cuda:
+            _dev_f64(val, self.nnz, torch)
+            self._check(self.lib.hssmf_refactor_device(self.h, _ptr(val)), "hssmf_refactor_device")
+            return
         v = np.ascontiguousarray(val, dtype=np.float64)
         assert v.size == self.nnz
         self._check(self.lib.hssmf_refactor(self.h, v.ctypes.data), "hssmf_refactor")

@@ -47,6 +47,10 @@ def test_measure_peaks_rejects_null_output(lib):
     assert lib.hssmf_measure_peaks(None, None) == H.HSSMF_EINVAL
 
 
+def test_refactor_device_rejects_null_arguments(lib):
+    assert lib.hssmf_refactor_device(None, None) == H.HSSMF_EINVAL
+
+
 def _call_factor(A_rowptr, A_col, A_val, perm, sep, par, n, opts=None):
     L = H.load()
     rp = np.ascontiguousarray(A_rowptr, dtype=np.int64)

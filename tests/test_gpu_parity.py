@@ -98,6 +98,23 @@ def test_hss_multifrontal_matches_oracle(case, idk):
     fac.close()
 
 
+def test_refactor_from_device_values_matches_host_values():
+    """hssmf_refactor_device (values already in device memory) and
+    hssmf_refactor (host values) give bitwise the same factorization."""
+    mk, kw = HSS_CASES["cd2d48"]
+    A, o = mk()
+    b = _t(np.random.default_rng(9).standard_normal(A.n))
+    val2 = A.val * 1.5   # new values, same pattern
+    out = []
+    for dev in (False, True):
+        fac = H.Factorization(A, o, **kw)
+        fac.refactor(_t(val2) if dev else val2)
+        out.append((fac.hss_ranks(), fac.apply(b).cpu()))
+        fac.close()
+    assert out[0][0] == out[1][0]
+    assert torch.equal(out[0][1], out[1][1])
+
+
 def test_batch_of_systems_matches_oracle():
     """Independent conv-diff systems of uneven sizes in one batched
     factorization: per system, the HSS ranks equal the oracle's factorization
