@@ -101,7 +101,7 @@ MEASURED_KEY = {"id": "fp64_valu_TFLOPs", "gemm64": "fp64_mfma_TFLOPs", "gemmlp"
 # problem of a pass stops), and the extra launches exit at once and move
 # nothing, so the per-launch figure is this total over the run's own
 # launches.
-TRAFFIC = {"id": (6.8842e11, "paper_1502_07405_amd/csrc/k_id.hip", "39790950b6cabba7")}
+TRAFFIC = {"id": (5.4816e11, "paper_1502_07405_amd/csrc/k_id.hip", "21a6834ad2086791")}
 
 
 def traffic_for(cls, launches_per_factorization):

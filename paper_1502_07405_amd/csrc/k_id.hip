@@ -164,18 +164,20 @@ __global__ __launch_bounds__(256) void id_step_kernel(const IDProb* __restrict__
       if (vw > sv || (vw == sv && cw < sc)) { sv = vw; sc = cw; }
     }
   }
+  // own columns: only the active ones are read (a pivoted column is never
+  // touched again); these loads wait for the flags, as the pivot column's
+  // load waits for the partial maxima, so the chain gets no longer
+  const bool acta = ja < m && q.active[ja];
+  const bool actb = jb < m && q.active[jb];
   double ra[NR], rb[NR];
-  const bool hasa = ja < m, hasb = jb < m;
   const double* ca = q.W + (int64_t)ja * d + t;
   const double* cb = q.W + (int64_t)jb * d + t;
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const int i = lane + 64 * r;
-    ra[r] = (hasa && i < len) ? ca[i] : 0.0;
-    rb[r] = (hasb && i < len) ? cb[i] : 0.0;
+    ra[r] = (acta && i < len) ? ca[i] : 0.0;
+    rb[r] = (actb && i < len) ? cb[i] : 0.0;
   }
-  const bool acta = hasa && q.active[ja];
-  const bool actb = hasb && q.active[jb];
   if (done) return;
   // pivot: largest partial maximum, ties to the lowest candidate index
   if (wave == 0) {
