@@ -183,16 +183,22 @@ def test_compression_known_ranks(rng):
 
 
 def test_adaptive_rank_growth(rng):
-    """Block of rank 40 with d0 = 8, dd = 8: d grows until d >= rank + p and
-    the final compression is accurate (Sec. 2.2.1)."""
+    """Growth-round count in closed form (Sec. 2.2.1).  The off-diagonal
+    blocks of A = (rank 40) + 30 I have rank 40 at the two 60-row nodes and
+    the 30-row leaves are full rank.  With d0 = dd = 8, p = 4, a leaf passes
+    through k = m once d >= 30 + p.  A 60-row node needs its ID rank 40 <= d - p,
+    so d = 8 + 8j >= 44 first holds at d = 48: five growth rounds.  The
+    compression is then accurate, and d_max = 47 (one below) is refused."""
     n = 120
     A = (rng.standard_normal((n, 40)) @ rng.standard_normal((40, n))) + 30 * np.eye(n)
     nodes, k, q = hss_tree(60, 60, 30)
     hs = H.compress(DenseOp(A), nodes, len(nodes) - 1, _rand_fn(n), 1e-12, 8, 8, 4, 10000)
-    assert hs.stats["rounds"] >= 4 and hs.stats["d"] >= 44
+    assert hs.stats["d"] == 48 and hs.stats["rounds"] == 5
     assert np.linalg.norm(H.hss_dense(hs, hs.root) - A) <= 1e-9 * np.linalg.norm(A)
-    with pytest.raises(H.RankError):
-        H.compress(DenseOp(A), nodes, len(nodes) - 1, _rand_fn(n), 1e-12, 8, 8, 4, 24)
+    assert H.compress(DenseOp(A), nodes, len(nodes) - 1, _rand_fn(n), 1e-12, 8, 8, 4, 48).stats["d"] == 48
+    for d_max in (47, 24):
+        with pytest.raises(H.RankError):
+            H.compress(DenseOp(A), nodes, len(nodes) - 1, _rand_fn(n), 1e-12, 8, 8, 4, d_max)
 
 
 @pytest.mark.parametrize("s,u,leaf", [(64, 40, 8), (50, 0, 7), (33, 20, 40)])
