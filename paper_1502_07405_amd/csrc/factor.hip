@@ -597,8 +597,8 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
           q[pi].hdone = ip.dev + pi;
         }
         IDProb* dq = upload(h, q);
-        // grid of the live problems' workgroups: rebuilt at every check so
-        // that finished problems stop taking workgroups
+        // grid of the live problems' workgroups, rebuilt as problems finish
+        // so that they stop taking workgroups
         auto wgmap = [&](const std::vector<int>& live, int& nwg) {
           std::vector<int2> wgm;
           for (int pi : live)
