@@ -129,7 +129,7 @@ typedef struct {
 /* Fill *o with defaults: rel_tol 1e-6, leaf_size 64, min_sep_hss INT32_MAX
  * (pure multifrontal), d0 128, dd 128, p 10, d_max 4096, seed 0, FP64,
  * iterative refinement, restart 30, tol 1e-10, max_it 50, stepwise ID
- * kernel, graph replay of the sweeps. */
+ * kernel, sweeps launched one by one (no graph), autotuned GEMM tiles. */
 int hssmf_default_opts(hssmf_opts* o);
 
 /* Symbolic analysis, upload and numeric factorization (Sec. 3.2, Sec. 4).
