@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from oracle import adjoint as oadj
-from oracle import krylov, mf
+from oracle import dense, krylov, mf
 from paper_1502_07405_amd import problems as P
 
 
@@ -28,6 +28,38 @@ def test_dense_mf_equals_dense_lu(kind, rng):
         x = mf.apply_inverse(fac, b, trans=tr)
         xr = np.linalg.solve(Ad.T if tr else Ad, b)
         assert np.linalg.norm(x - xr) <= 1e-13 * np.linalg.norm(xr)
+
+
+@pytest.mark.parametrize("s,u", [(12, 7), (9, 0), (5, 11)])
+def test_partial_lu_block_identities(rng, s, u):
+    """Partial LU of one front (Sec. 3.2) against the block-elimination
+    identities: P F11 = L11 U11 with |L11| <= 1 (partial pivoting),
+    L11 U12 = P F12, L21 U11 = F21, and the update matrix is the Schur
+    complement F22 - F21 F11^{-1} F12, formed here by a plain solve."""
+    n = s + u
+    F = rng.standard_normal((n, n)) + 0.5 * np.eye(n)
+    f = dense.partial_lu(F, s)
+    L11 = np.tril(f["lu"], -1) + np.eye(s)
+    U11 = np.triu(f["lu"])
+    PF = F[f["P"]]
+    assert sorted(f["P"]) == list(range(s))
+    assert np.abs(L11).max() <= 1.0 + 1e-15
+    tol = 1e-12 * np.linalg.norm(F)
+    assert np.linalg.norm(L11 @ U11 - PF[:s, :s]) <= tol
+    assert np.linalg.norm(L11 @ f["U12"] - PF[:s, s:]) <= tol
+    assert np.linalg.norm(f["L21"] @ U11 - F[s:, :s]) <= tol
+    schur = F[s:, s:] - F[s:, :s] @ np.linalg.solve(F[:s, :s], F[:s, s:])
+    assert np.linalg.norm(f["U"] - schur) <= 1e-10 * max(1.0, np.linalg.norm(schur))
+
+
+@pytest.mark.filterwarnings("ignore:Diagonal number")
+def test_partial_lu_reports_a_singular_front():
+    """An exactly singular F11 (a zero column) is reported with its front."""
+    F = np.eye(6)
+    F[:, 2] = 0.0
+    with pytest.raises(dense.SingularFront) as e:
+        dense.partial_lu(F, 4, front_id=17)
+    assert e.value.front == 17
 
 
 def test_exact_solution_of_ones_rhs():
