@@ -155,6 +155,39 @@ def test_compression_exact_recovery(rng):
     assert np.linalg.norm(H.hss_dense(hs, hs.root) - A) <= 1e-12 * np.linalg.norm(A)
 
 
+def test_nested_bases_reproduce_offdiagonal_block_rows(rng):
+    """Interpolative property of the nested bases (Sec. 2.2, Eq. nestedUV):
+    at every non-root node, the off-diagonal block row is its skeleton rows
+    mapped through the expanded row basis, A(I, I^c) = U^big A(J^r, I^c),
+    and likewise for columns, A(I^c, I) = A(I^c, J^c) (V^big)^T.  The
+    transposed product big_t agrees with the expanded basis.  Rows and
+    columns are scaled differently so that the row and column bases differ
+    (with U in place of V the check misses by ~0.7)."""
+    n = 96
+    A = _hss_matrix(rng, n, 0)
+    A = np.exp(rng.standard_normal(n))[:, None] * A * np.exp(rng.standard_normal(n))[None, :]
+    nodes, k, q = hss_tree(n, 0, 12)
+    root = len(nodes) - 1
+    hs = H.compress(DenseOp(A), nodes, root, _rand_fn(n), 1e-10, 48, 16, 8, 10000)
+    X = rng.standard_normal((n, 3))
+    checked = 0
+    for t, nd in enumerate(hs.nodes):
+        if t == root:
+            continue
+        g = hs.gen[t]
+        rows = np.arange(nd.lo, nd.hi)
+        comp = np.setdiff1d(np.arange(n), rows)
+        Ub = H.down_expand(hs, t, np.eye(g.r), "U")
+        Vb = H.down_expand(hs, t, np.eye(g.c), "V")
+        blk_r, blk_c = A[np.ix_(rows, comp)], A[np.ix_(comp, rows)]
+        assert np.linalg.norm(blk_r - Ub @ A[np.ix_(g.Ir, comp)]) <= 1e-6 * np.linalg.norm(blk_r)
+        assert np.linalg.norm(blk_c - A[np.ix_(comp, g.Ic)] @ Vb.T) <= 1e-6 * np.linalg.norm(blk_c)
+        for which, G in (("U", Ub), ("V", Vb)):
+            assert np.allclose(H.big_t(hs, t, X[rows], which), G.T @ X[rows], rtol=0, atol=1e-12 * np.abs(X).max() * max(1.0, np.abs(G).max()) * len(rows))
+        checked += 1
+    assert checked == root
+
+
 def test_compression_b_blocks_are_submatrices(rng):
     """B_{nu1,nu2} = A(I^r_nu1, I^c_nu2) bit-exactly (Sec. 2.2)."""
     n = 80
