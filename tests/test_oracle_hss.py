@@ -234,6 +234,53 @@ def test_adaptive_rank_growth(rng):
             H.compress(DenseOp(A), nodes, len(nodes) - 1, _rand_fn(n), 1e-12, 8, 8, 4, d_max)
 
 
+@pytest.mark.parametrize("transpose", [False, True])
+def test_growth_rule_binds_on_each_side(transpose):
+    """The success test k <= d - p (Sec. 2.2.1) holds separately for row and
+    column IDs.  A rank-40 off-diagonal block row of leaf 0 (two rank-20
+    blocks with independent row spaces, in the sibling leaf and in the other
+    half) is seen only by that leaf's row ID: every column ID, and every
+    other row ID, meets rank <= 20.  So the row rule alone demands d - 4 >=
+    40, i.e. d = 48 after five rounds from d0 = dd = 8, where a rule without
+    p would stop at 40.  The transposed matrix puts the same demand on the
+    column rule."""
+    rg = np.random.default_rng(7)
+    n = 240
+    A = 30 * np.eye(n)
+    A[0:60, 60:120] += rg.standard_normal((60, 20)) @ rg.standard_normal((20, 60))
+    A[0:60, 120:180] += rg.standard_normal((60, 20)) @ rg.standard_normal((20, 60))
+    if transpose:
+        A = A.T.copy()
+    nodes, k, q = hss_tree(n, 0, 60)
+    hs = H.compress(DenseOp(A), nodes, len(nodes) - 1, _rand_fn(n), 1e-12, 8, 8, 4, 10000)
+    side = [(hs.gen[t].c, hs.gen[t].r) if transpose else (hs.gen[t].r, hs.gen[t].c) for t in range(len(nodes) - 1)]
+    assert side[0] == (40, 0) and max(max(r, c) for r, c in side[1:]) == 20 and max(c for _, c in side) == 20
+    assert hs.stats["d"] == 48 and hs.stats["rounds"] == 5
+    assert np.linalg.norm(H.hss_dense(hs, hs.root) - A) <= 1e-12 * np.linalg.norm(A)
+
+
+def test_full_rank_node_succeeds_with_all_its_rows():
+    """The other half of the success test (Sec. 2.2.1): a node whose rank
+    equals its number of rows succeeds once every row is a skeleton row,
+    k = m, without the p extra samples.  Sibling leaves of 30 rows are
+    coupled by full-rank blocks, and the two halves by rank-8 blocks.  So the
+    leaves bind at k = m = 30 <= d, giving d = 32 after three rounds from
+    d0 = dd = 8; without the k = m clause they would need d - 4 >= 30, i.e. 40."""
+    rg = np.random.default_rng(11)
+    n = 120
+    A = 30 * np.eye(n)
+    for r0, c0 in ((0, 30), (30, 0), (60, 90), (90, 60)):
+        A[r0:r0 + 30, c0:c0 + 30] += rg.standard_normal((30, 30))
+    A[0:60, 60:120] += rg.standard_normal((60, 8)) @ rg.standard_normal((8, 60))
+    A[60:120, 0:60] += rg.standard_normal((60, 8)) @ rg.standard_normal((8, 60))
+    nodes, k, q = hss_tree(n, 0, 30)
+    hs = H.compress(DenseOp(A), nodes, len(nodes) - 1, _rand_fn(n), 1e-12, 8, 8, 4, 10000)
+    ranks = [(hs.gen[t].r, hs.gen[t].c) for t in range(len(nodes) - 1)]
+    assert ranks == [(30, 30), (30, 30), (8, 8), (30, 30), (30, 30), (8, 8)]
+    assert hs.stats["d"] == 32 and hs.stats["rounds"] == 3
+    assert np.linalg.norm(H.hss_dense(hs, hs.root) - A) <= 1e-12 * np.linalg.norm(A)
+
+
 @pytest.mark.parametrize("s,u,leaf", [(64, 40, 8), (50, 0, 7), (33, 20, 40)])
 def test_ulv_equals_dense_solve(rng, s, u, leaf):
     """ULV solves (and transposed solves) of the compressed F11 equal dense LU
