@@ -62,6 +62,31 @@ def test_partial_lu_reports_a_singular_front():
     assert e.value.front == 17
 
 
+def test_front_samples_equal_the_assembled_front_times_r():
+    """Sampling by skinny extend-add (Eq. FtimesR, Sec. 4.3) equals the
+    assembled front times R, and its column samples equal F^T R.  The front is
+    assembled through element extraction (Sec. 4.5), a separate code path.
+    The children's update matrices are random and nonsymmetric, so a column
+    sample taken through U instead of U^T shows."""
+    A, o = P.convdiff2d(14, 5.0, 3.0), P.geometric_nd((14, 14), 3)
+    Ap = mf.permute_csr(A, np.asarray(o.perm, dtype=np.int64))
+    fronts = mf.analyse(Ap, o.sep_ptr, o.parent)
+    rg = np.random.default_rng(21)
+    updates = {f.id: mf.DenseUpdate(rg.standard_normal((len(f.upd), len(f.upd)))) for f in fronts}
+    tested = 0
+    for f in fronts:
+        if len(f.children) < 2:
+            continue
+        op = mf.FrontOp(Ap, f, fronts, updates)
+        F = op.extract(np.arange(op.n), np.arange(op.n))
+        R = rg.standard_normal((op.n, 5))
+        Sr, Sc = op.sample(R)
+        assert np.allclose(Sr, F @ R, rtol=0, atol=1e-12 * np.abs(F).sum())
+        assert np.allclose(Sc, F.T @ R, rtol=0, atol=1e-12 * np.abs(F).sum())
+        tested += 1
+    assert tested >= 3
+
+
 def test_exact_solution_of_ones_rhs():
     """The paper's right-hand side A [1 ... 1]^T (Sec. 6.1) has solution 1."""
     A, o = P.poisson2d(30), P.geometric_nd((30, 30), 4)
