@@ -87,6 +87,22 @@ def test_front_samples_equal_the_assembled_front_times_r():
     assert tested >= 3
 
 
+def test_restarted_gmres_reaches_the_solution():
+    """GMRES(m) with restarts (Sec. 6.1 uses GMRES(30)): with m = 5 the
+    solve needs several cycles, and each restart continues from the previous
+    cycle's iterate.  The result matches the dense solve at the requested
+    residual, and the iteration count exceeds one cycle."""
+    rg = np.random.default_rng(3)
+    n = 60
+    A = np.eye(n) + 0.45 * rg.standard_normal((n, n)) / np.sqrt(n)
+    b = rg.standard_normal(n)
+    x, its, hist = krylov.gmres(lambda v: A @ v, lambda v: v, b, 1e-10, restart=5, max_it=400)
+    xr = np.linalg.solve(A, b)
+    assert its > 5 and len(hist) >= 3
+    assert np.linalg.norm(b - A @ x) <= 1e-10 * np.linalg.norm(b)
+    assert np.linalg.norm(x - xr) <= 1e-8 * np.linalg.norm(xr)
+
+
 def test_exact_solution_of_ones_rhs():
     """The paper's right-hand side A [1 ... 1]^T (Sec. 6.1) has solution 1."""
     A, o = P.poisson2d(30), P.geometric_nd((30, 30), 4)
