@@ -13,15 +13,27 @@ def _dense(A):
     return A.to_scipy().toarray()
 
 
-@pytest.mark.parametrize("kind", ["p2d", "p3d", "cd2d"])
+@pytest.mark.parametrize("kind", ["p2d", "p3d", "cd2d", "indefinite2d"])
 def test_dense_mf_equals_dense_lu(kind, rng):
+    """Dense multifrontal factorization (Sec. 3.2) equals a dense solve, and
+    so does its transposed solve.  The indefinite case (5-point Laplacian
+    shifted by -2.1) makes partial pivoting interchange rows inside the
+    fronts, which the diagonally dominant cases never do."""
     if kind == "p2d":
         A, o = P.poisson2d(16), P.geometric_nd((16, 16), 4)
     elif kind == "p3d":
         A, o = P.poisson3d(8), P.geometric_nd((8, 8, 8), 2)
-    else:
+    elif kind == "cd2d":
         A, o = P.convdiff2d(14, 18.0, -6.0), P.geometric_nd((14, 14), 3)
+    else:
+        A, o = P.poisson2d(16), P.geometric_nd((16, 16), 4)
+        rows = np.repeat(np.arange(A.n), np.diff(A.rowptr))
+        A.val = A.val.copy()
+        A.val[rows == A.colind] -= 2.1
     fac = mf.factor(A, o, mf.Options())
+    if kind == "indefinite2d":
+        moved = [np.any(fa.data["P"] != np.arange(len(fa.data["P"]))) for fa in fac.factors if fa.kind == "dense"]
+        assert sum(moved) >= len(moved) // 2
     b = rng.standard_normal((A.n, 2))
     Ad = _dense(A)
     for tr in (False, True):

@@ -1,0 +1,39 @@
+"""GPU dense fronts with real row interchanges (not collected by pytest: run
+it by naming the file).  The dense-front parity cases are M-matrices, whose
+fronts never pivot; here the 5-point and 7-point Laplacians shifted to be
+indefinite make partial pivoting interchange rows in most fronts, including
+fronts larger than one 128-column block of the blocked LU."""
+import numpy as np
+import pytest
+
+from oracle import mf
+from paper_1502_07405_amd import hssmf as H
+from paper_1502_07405_amd import problems as P
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _shifted(A, shift):
+    rows = np.repeat(np.arange(A.n), np.diff(A.rowptr))
+    A.val = A.val.copy()
+    A.val[rows == A.colind] -= shift
+    return A
+
+
+@pytest.mark.parametrize("case", ["2d", "3d"])
+def test_dense_fronts_with_row_interchanges_match_the_oracle(case):
+    if case == "2d":
+        A, o = _shifted(P.poisson2d(40), 2.1), P.geometric_nd((40, 40), 4)
+    else:
+        A, o = _shifted(P.poisson3d(14), 6.3), P.geometric_nd((14, 14, 14), 2)
+    ofac = mf.factor(A, o, mf.Options())
+    moved = [np.any(fa.data["P"] != np.arange(len(fa.data["P"]))) for fa in ofac.factors if fa.kind == "dense"]
+    assert sum(moved) >= len(moved) // 2
+    fac = H.Factorization(A, o)
+    b = np.random.default_rng(5).standard_normal(A.n)
+    for tr in (False, True):
+        y = fac.apply(torch.tensor(b, device="cuda:0"), trans=tr).cpu().numpy()
+        yo = mf.apply_inverse(ofac, b, trans=tr)
+        assert np.linalg.norm(y - yo) <= 1e-11 * np.linalg.norm(yo), (case, tr)
+    fac.close()
