@@ -186,6 +186,34 @@ def test_hss_front_starts_from_its_hss_childrens_samples():
     assert checked > 0   # the case the rule is about occurs here
 
 
+def test_adjoint_of_a_nonsymmetric_system(rng):
+    """The adjoint solves with A^T.  On a convection-diffusion matrix, where
+    A^T differs from A, lambda equals the dense A^{-T} g and the gradient
+    with respect to b is lambda."""
+    A, o = P.convdiff2d(20, 25.0, -15.0), P.geometric_nd((20, 20), 4)
+    fac = mf.factor(A, o, mf.Options(min_sep_hss=12, leaf_size=8, rel_tol=1e-8, d0=16, dd=16, p=5))
+    b = rng.standard_normal(A.n)
+    g = rng.standard_normal(A.n)
+    x, lam, dval = oadj.solve_and_adjoint(A, fac, b, lambda x: g, tol=1e-13)
+    Ad = _dense(A)
+    assert np.linalg.norm(Ad - Ad.T) > 0.1 * np.linalg.norm(Ad)
+    lam_ref = np.linalg.solve(Ad.T, g)
+    assert np.linalg.norm(lam - lam_ref) <= 1e-10 * np.linalg.norm(lam_ref)
+    rows = np.repeat(np.arange(A.n), np.diff(A.rowptr))
+    assert np.allclose(dval, -lam_ref[rows] * x[A.colind], rtol=0, atol=1e-9 * np.abs(lam_ref).max() * np.abs(x).max())
+
+
+def test_refinement_starts_from_the_preconditioned_rhs():
+    """Iterative refinement starts from x0 = M^{-1} b: with an exact
+    factorization (dense multifrontal) it returns at iteration 0."""
+    A, o = P.poisson2d(16), P.geometric_nd((16, 16), 4)
+    fac = mf.factor(A, o, mf.Options())
+    b = A.matvec(np.ones(A.n))
+    x, its, hist = krylov.refine(A.matvec, lambda v: mf.apply_inverse(fac, v), b, 1e-12)
+    assert its == 0 and len(hist) == 1
+    assert np.abs(x - 1).max() < 1e-12
+
+
 def test_adjoint_matches_dense(rng):
     """lambda = A^{-T} g, dL/db = lambda, dL/dA_ij = -lambda_i x_j on the
     pattern; checked against dense solves and central differences."""
