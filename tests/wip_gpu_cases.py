@@ -4,12 +4,13 @@ cases are M-matrices, whose fronts never pivot, so here the 5-point and
 7-point Laplacians are shifted to be indefinite, which makes partial
 pivoting interchange rows in most fronts, including fronts larger than one
 128-column block of the blocked LU.  The adjoint on a nonsymmetric
-matrix, where A^T differs from A."""
+matrix, where A^T differs from A.  GMRES(2), so that the restart update runs
+(the GMRES(30) parity case converges within one cycle)."""
 import numpy as np
 import pytest
 
 from oracle import adjoint as oadj
-from oracle import mf
+from oracle import krylov, mf
 from paper_1502_07405_amd import hssmf as H
 from paper_1502_07405_amd import problems as P
 
@@ -55,4 +56,21 @@ def test_adjoint_of_a_nonsymmetric_system_matches_the_oracle():
     db, dval, _ = fac.adjoint(x, torch.tensor(g, device="cuda:0"))
     assert np.linalg.norm(db.cpu().numpy() - lamo) <= 1e-8 * np.linalg.norm(lamo)
     assert np.linalg.norm(dval.cpu().numpy() - dvalo) <= 1e-8 * np.linalg.norm(dvalo)
+    fac.close()
+
+
+def test_gmres_with_restarts_matches_the_oracle():
+    w = P.WORKLOADS["poisson2d_100"]
+    A, o, b = P.workload(**w)
+    kw = dict(min_sep_hss=64, leaf_size=16, rel_tol=1e-2, d0=32, dd=16, p=10)
+    S = A.to_scipy()
+    ofac = mf.factor(A, o, mf.Options(**kw))
+    xo, its, hist = krylov.gmres(lambda v: S @ v, lambda v: mf.apply_inverse(ofac, v), b, 1e-12, restart=2, max_it=200)
+    assert len(hist) >= 3   # several cycles
+    fac = H.Factorization(A, o, outer="gmres", restart=2, tol=1e-12, max_it=200, **kw)
+    x, info = fac.solve(torch.tensor(b, device="cuda:0"))
+    x = x.cpu().numpy()
+    assert np.linalg.norm(b - S @ x) <= 1e-12 * np.linalg.norm(b) * 1.0001
+    assert np.linalg.norm(x - xo) <= 1e-8 * np.linalg.norm(xo)
+    assert abs(info.iterations - its) <= 2
     fac.close()
