@@ -184,19 +184,47 @@ void setup(Handle& h, const hssmf_csr* A) {
 void numeric(Handle& h) {
   HIP_CHECK(hipStreamSynchronize(h.st));
   h.stager.sync();
+  // the old factors and the solve operations recorded over them go first,
+  // so that nothing refers to released memory if this factorization fails
+  h.factor_status = HSSMF_EINVAL;
+  for (auto& tr : h.sops)
+    for (auto& sw : tr) sw.clear();
+  h.drop_graphs();   // the sweeps change with the factors
   h.narena.release();
   h.cur = &h.narena;
   double t0 = now_ms();
-  h.drop_graphs();   // the sweeps change with the factors
-  numeric_factor(h);
-  build_solve_ops(h);
-  HIP_CHECK(hipStreamSynchronize(h.st));
+  try {
+    numeric_factor(h);
+    build_solve_ops(h);
+    HIP_CHECK(hipStreamSynchronize(h.st));
+  } catch (...) {
+    // drain what was enqueued before giving the arenas back; the handle
+    // keeps the error, and its solve entry points return it
+    (void)hipStreamSynchronize(h.st);
+    h.stager.sync();
+    for (auto& tr : h.sops)
+      for (auto& sw : tr) sw.clear();
+    h.larena.release();
+    h.sarena.release();
+    h.cur = &h.arena;
+    try {
+      throw;
+    } catch (const Error& e) {
+      h.factor_status = e.code;
+    } catch (const std::bad_alloc&) {
+      h.factor_status = HSSMF_ENOMEM;
+    } catch (...) {
+      h.factor_status = HSSMF_EDEVICE;
+    }
+    throw;
+  }
   h.stager.sync();
   h.larena.release();
   h.sarena.release();
   gemm_census_print();
   h.stats.t_factor_ms = now_ms() - t0;
   h.cur = &h.arena;
+  h.factor_status = HSSMF_OK;
   // statistics
   int maxr = 0, maxd = 0, rounds = 0;
   for (auto& F : h.hf) {
@@ -543,6 +571,7 @@ int hssmf_refactor_device(void* hv, const double* val_dev) {
 int hssmf_apply(void* hv, int32_t trans, const double* x, double* y) {
   Handle* h = static_cast<Handle*>(hv);
   if (!h || !x || !y || (trans != 0 && trans != 1)) return HSSMF_EINVAL;
+  if (h->factor_status != HSSMF_OK) return h->factor_status;
   return guard_impl(h, [&]() {
     apply_inverse(*h, trans, x, y);
     HIP_CHECK(hipStreamSynchronize(h->st));
@@ -553,6 +582,7 @@ int hssmf_apply(void* hv, int32_t trans, const double* x, double* y) {
 int hssmf_solve(void* hv, const double* b, double* x, hssmf_info* info) {
   Handle* h = static_cast<Handle*>(hv);
   if (!h || !b || !x) return HSSMF_EINVAL;
+  if (h->factor_status != HSSMF_OK) return h->factor_status;
   int out = HSSMF_OK;
   int rc = guard_impl(h, [&]() { out = outer(*h, 0, b, x, info); });
   return rc != HSSMF_OK ? rc : out;
@@ -561,6 +591,7 @@ int hssmf_solve(void* hv, const double* b, double* x, hssmf_info* info) {
 int hssmf_solve_transpose(void* hv, const double* g, double* lam, hssmf_info* info) {
   Handle* h = static_cast<Handle*>(hv);
   if (!h || !g || !lam) return HSSMF_EINVAL;
+  if (h->factor_status != HSSMF_OK) return h->factor_status;
   int out = HSSMF_OK;
   int rc = guard_impl(h, [&]() { out = outer(*h, 1, g, lam, info); });
   return rc != HSSMF_OK ? rc : out;
@@ -569,6 +600,7 @@ int hssmf_solve_transpose(void* hv, const double* g, double* lam, hssmf_info* in
 int hssmf_adjoint(void* hv, const double* x, const double* g, double* dl_db, double* dl_dval, hssmf_info* info) {
   Handle* h = static_cast<Handle*>(hv);
   if (!h || !x || !g || !dl_db || !dl_dval) return HSSMF_EINVAL;
+  if (h->factor_status != HSSMF_OK) return h->factor_status;
   int out = HSSMF_OK;
   int rc = guard_impl(h, [&]() {
     out = outer(*h, 1, g, dl_db, info);

@@ -557,6 +557,15 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
         }
       }
       int* derr = nullptr;
+      // diagnostics: HSSMF_ID_CENSUS=1 prints one line per ID pass (problem
+      // shapes, ranks, pivot-step launches and the pass's wall time)
+      static const bool id_census = std::getenv("HSSMF_ID_CENSUS") != nullptr;
+      int census_steps = 0;
+      double census_t0 = 0.0;
+      if (id_census) {
+        HIP_CHECK(hipStreamSynchronize(h.st));
+        census_t0 = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+      }
       if (!q.empty()) {
         const int np = (int)q.size();
         int maxp = 0;
@@ -618,6 +627,7 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
         int remap = 0;
         for (int t = 0; t <= tmax; ++t) {
           launch_id_step(dq, dwgm, nwg, t, maxd, h.st);
+          census_steps = t + 1;
           ip.pace(t, h.st);
           if ((t & 3) == 3 && t < tmax) {
             std::vector<int> nl;
@@ -645,6 +655,26 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
       HIP_CHECK(hipStreamSynchronize(h.st));
       h.stager.sync();
       REQUIRE(herr == 0, HSSMF_EDEVICE, "interpolative decomposition: a workgroup barrier timed out");
+      if (id_census && !cand.empty()) {
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count() - census_t0;
+        int mlo = 1 << 30, mhi = 0, dlo = 1 << 30, dhi = 0, kmx = 0, fails = 0;
+        double work = 0.0;
+        for (size_t i = 0; i < cand.size(); ++i) {
+          const int d = cand[i].F->d;
+          const int ms2[2] = {cand[i].n().mr, cand[i].n().mc};
+          for (int sd = 0; sd < 2; ++sd) {
+            const int k = sh[4 * i + 1 + 2 * sd], m = ms2[sd];
+            mlo = std::min(mlo, m); mhi = std::max(mhi, m);
+            dlo = std::min(dlo, d); dhi = std::max(dhi, d);
+            kmx = std::max(kmx, k);
+            if (!(k <= d - o.p || k == m)) ++fails;
+            work += (double)m * d;
+          }
+        }
+        std::fprintf(stderr, "id pass: height %d  problems %zu  m %d..%d  d %d..%d  kmax %d  failed %d  "
+                     "steps %d  words %.3g  %.3f ms\n", hh, 2 * cand.size(), mlo, mhi, dlo, dhi, kmx, fails,
+                     census_steps, work, ms);
+      }
       if (prof::enabled()) {
         // algorithmic flops of the pivot steps: Householder QR of the d x m
         // matrix truncated at k columns, 4dmk - 2k^2(d+m) + 4/3 k^3 per side

@@ -178,6 +178,10 @@ struct Handle {
   Stager stager;
   IdPoll idpoll;
   std::vector<Op> sops[2][2];  // [trans][0 = forward, 1 = backward]
+  // status of the last numeric factorization: HSSMF_OK when the factors and
+  // the recorded solve operations are valid, else the error it ended with
+  // (the solve entry points return it and launch nothing)
+  int factor_status = HSSMF_EINVAL;
   double* yws = nullptr;       // n, the right-hand side in the new ordering
   int* d_iperm = nullptr;
   int *d_row = nullptr, *d_col = nullptr;  // CSR entry coordinates (adjoint)

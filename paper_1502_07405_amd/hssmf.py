@@ -195,6 +195,17 @@ class Factorization:
             raise HssmfError(rc, "hssmf_factor", self.lib.hssmf_last_failed_front(None))
         self.h = h
         self.offsets = [0, self.n]
+        self._vals_host = np.array(A.val, dtype=np.float64, copy=True)
+        self._vals_dev = None
+
+    def factored_values(self, device):
+        """The matrix values of the current factorization, as a float64 tensor
+        on device."""
+        torch = self._torch
+        if self._vals_dev is None or self._vals_dev.device != torch.device(device):
+            src = self._vals_dev if self._vals_dev is not None else torch.from_numpy(self._vals_host)
+            self._vals_dev = src.to(device=device, dtype=torch.float64)
+        return self._vals_dev
 
     def _check(self, rc, what, allow_noconv=False):
         if rc == HSSMF_OK or (allow_noconv and rc == HSSMF_ENOCONV):
@@ -207,11 +218,15 @@ class Factorization:
         torch = self._torch
         if torch is not None and isinstance(val, torch.Tensor) and val.is_cuda:
             _dev_f64(val, self.nnz, torch)
+            self._vals_dev = self._vals_host = None
             self._check(self.lib.hssmf_refactor_device(self.h, _ptr(val)), "hssmf_refactor_device")
+            self._vals_dev = val.detach().clone()
             return
         v = np.ascontiguousarray(val, dtype=np.float64)
         assert v.size == self.nnz
+        self._vals_dev = self._vals_host = None
         self._check(self.lib.hssmf_refactor(self.h, v.ctypes.data), "hssmf_refactor")
+        self._vals_host = v.copy()
 
     def apply(self, x, trans=False):
         torch = self._torch
@@ -301,6 +316,8 @@ class BatchFactorization(Factorization):
         off = np.zeros(ns + 1, dtype=np.int64)
         self.lib.hssmf_systems(h, off.ctypes.data, ns + 1)
         self.offsets = [int(v) for v in off]
+        self._vals_host = np.concatenate([np.asarray(A.val, dtype=np.float64) for A, _ in systems])
+        self._vals_dev = None
 
     def split(self, x):
         return [x[a:b] for a, b in zip(self.offsets[:-1], self.offsets[1:])]
@@ -318,7 +335,9 @@ class BatchFactorization(Factorization):
 class LinearSolve:
     """x = A(val)^{-1} b as a torch.autograd.Function whose backward is the
     hand-written adjoint: one transposed solve with the same factors gives
-    dL/db = lambda and dL/dval = -lambda_i x_j on the pattern."""
+    dL/db = lambda and dL/dval = -lambda_i x_j on the pattern.  forward
+    refactors (hssmf_refactor_device, same pattern and plan) whenever val
+    differs from the values the handle holds factors of."""
 
     @staticmethod
     def make(fact):
@@ -327,6 +346,11 @@ class LinearSolve:
         class _Fn(torch.autograd.Function):
             @staticmethod
             def forward(ctx, val, b):
+                v = val.detach().to(dtype=torch.float64).contiguous()
+                if fact.h is None:
+                    raise HssmfError(HSSMF_EINVAL, "LinearSolve on a closed factorization")
+                if not torch.equal(fact.factored_values(v.device), v):
+                    fact.refactor(v)
                 x, _ = fact.solve(b.contiguous())
                 ctx.save_for_backward(x)
                 return x

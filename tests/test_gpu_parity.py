@@ -333,9 +333,10 @@ def test_fv96_gradient_matches_central_differences():
     stream, HSS on separators >= 512 (leaf 64, eps 1e-6, d0 = dd = 128),
     FP32 sampling products, refinement to 1e-13.  L = ||x - x*||^2; dL/dkappa
     through the adjoint (LinearSolve) and the differentiable assembly is
-    checked against central differences on cells drawn from default_rng(5):
-    step 1e-3 kappa_c, each side by a difference solve refined to 1e-13;
-    relative error <= 1e-5."""
+    checked against central differences on all 20 cells drawn from
+    default_rng(5) without replacement: step 1e-3 kappa_c, each side by a
+    difference solve refined to 1e-13 after a refactorization with the
+    perturbed kappa; relative error <= 1e-5."""
     n = 96
     kap, rng = P.smoothed_log_kappa(n, seed=3)
     A = P.fv_diffusion3d(n, kap)
@@ -353,7 +354,7 @@ def test_fv96_gradient_matches_central_differences():
     grad = kt.grad.cpu().numpy()
     x0 = x.detach()
     bt = _t(b)
-    for c in np.random.default_rng(5).choice(A.n, 20, replace=False)[:2]:
+    for c in np.random.default_rng(5).choice(A.n, 20, replace=False):
         dlt = 1e-3 * kap[c]
         dx = []
         for sg in (1, -1):
@@ -384,6 +385,16 @@ def test_autograd_function_uses_the_adjoint():
     assert np.allclose(b.grad.cpu().numpy(), lam, rtol=1e-8, atol=1e-10)
     rows = np.repeat(np.arange(A.n), np.diff(A.rowptr))
     assert np.allclose(val.grad.cpu().numpy(), -lam[rows] * xr[A.colind], rtol=1e-7, atol=1e-10)
+    # values other than the factored ones: forward refactors first, so x and
+    # both gradients belong to the matrix of those values
+    val2 = _t(A.val * (1.0 + 0.5 * np.random.default_rng(8).random(len(A.val)))).requires_grad_(True)
+    x2 = solve(val2, b)
+    (x2 ** 2).sum().backward()
+    A2 = P.CSR(A.n, A.rowptr, A.colind, val2.detach().cpu().numpy()).to_scipy().toarray()
+    xr2 = np.linalg.solve(A2, b.detach().cpu().numpy())
+    lam2 = np.linalg.solve(A2.T, 2 * xr2)
+    assert np.allclose(x2.detach().cpu().numpy(), xr2, rtol=1e-9, atol=1e-12)
+    assert np.allclose(val2.grad.cpu().numpy(), -lam2[rows] * xr2[A.colind], rtol=1e-7, atol=1e-10)
     fac.close()
 
 
@@ -400,6 +411,23 @@ def test_error_paths():
     with pytest.raises(H.HssmfError) as e:
         H.Factorization(B, o)
     assert e.value.code == H.HSSMF_ESINGULAR and e.value.front >= 0
+    # a failed refactorization leaves no stale factors behind: the solve
+    # entry points return its error and launch nothing, and a later good
+    # refactorization restores the handle
+    fac = H.Factorization(A, o, min_sep_hss=40, leaf_size=16, rel_tol=1e-8, d0=16, dd=16, p=4)
+    bt = _t(np.random.default_rng(2).standard_normal(A.n))
+    y0 = fac.apply(bt)
+    with pytest.raises(H.HssmfError) as e:
+        fac.refactor(val)
+    assert e.value.code == H.HSSMF_ESINGULAR
+    for call in (lambda: fac.apply(bt), lambda: fac.solve(bt), lambda: fac.solve_transpose(bt),
+                 lambda: fac.adjoint(bt, bt)):
+        with pytest.raises(H.HssmfError) as e:
+            call()
+        assert e.value.code == H.HSSMF_ESINGULAR
+    fac.refactor(A.val)
+    assert torch.equal(fac.apply(bt), y0)
+    fac.close()
     # no convergence within max_it keeps the best iterate
     fac = H.Factorization(A, o, min_sep_hss=40, leaf_size=16, rel_tol=0.5, d0=8, dd=8, p=2, max_it=1, tol=1e-14)
     x, info = fac.solve(_t(np.ones(A.n)), allow_noconv=True)

@@ -1,5 +1,5 @@
-"""GPU cases not yet run on a GPU (not collected by pytest: run the file by
-name).  Dense fronts with real row interchanges: the dense-front parity
+"""GPU parity cases beyond the M-matrix workloads.  Dense fronts with real
+row interchanges: the dense-front parity
 cases are M-matrices, whose fronts never pivot, so here the 5-point and
 7-point Laplacians are shifted to be indefinite, which makes partial
 pivoting interchange rows in most fronts, including fronts larger than one

@@ -110,21 +110,27 @@ def test_cpqr_matches_library_on_well_separated_columns(rng):
     assert np.allclose(np.abs(np.diag(R[:6, :6])), np.abs(np.diag(R2[:6, :6])), rtol=1e-10)
 
 
-@pytest.mark.parametrize("eps", [1e-2, 1e-5, 1e-9])
+@pytest.mark.parametrize("eps", [1e-3, 1e-7, 1e-11])
 def test_epsilon_rank_rule(rng, eps):
-    """Rank stops at the first i with |R_{i+1,i+1}| / |R_11| <= eps (Sec. 5.3);
-    with prescribed, well separated singular values the ranks are known."""
+    """Rank stops at the first i with |R_{i+1,i+1}| / |R_11| <= eps (Sec. 5.3).
+    The prescribed singular values lie two decades apart and eps sits half
+    way between two of them, so the rank is known exactly: the column
+    pivoted diagonal follows the singular values within a factor of ~7 here
+    (over 200 seeds), well inside the decade of margin on either side.  Both
+    sides of the rule are checked: the k-th diagonal entry is above
+    eps |R_11| and the (k+1)-th (the one that stopped the loop) is not."""
     n = 60
-    sv = 10.0 ** -np.arange(0, 12, 1.0)
+    sv = 10.0 ** -np.arange(0, 24, 2.0)
     U, _ = np.linalg.qr(rng.standard_normal((n, 12)))
     V, _ = np.linalg.qr(rng.standard_normal((n, 12)))
     Y = (U * sv) @ V.T
     _, R, k = H.cpqr_eps(Y, eps)
-    expect = int(np.sum(sv > eps * 1.0000001))
-    assert abs(k - expect) <= 1
-    if k < 12:
-        assert k == 0 or True
-    assert np.all(np.abs(np.diag(R[:k, :k])) / abs(R[0, 0]) > eps)
+    expect = int(np.sum(sv > eps))
+    assert k == expect
+    _, Rf, _ = H.cpqr_eps(Y, 0.0)
+    dg = np.abs(np.diag(Rf)) / abs(Rf[0, 0])
+    assert dg[k - 1] > eps
+    assert dg[k] <= eps
 
 
 def test_omega_annihilates_interpolative_basis(rng):
