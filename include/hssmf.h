@@ -12,10 +12,15 @@
  * Conventions
  *  - Every function returns HSSMF_OK (0) or a negative status code; no C++
  *    exception crosses this boundary.  hssmf_strerror() names a code.
- *  - Matrix and ordering arrays are HOST arrays owned by the caller; they are
- *    read during the call only (copied / uploaded).
- *  - Vector arguments of the solve functions are DEVICE pointers (HIP global
- *    memory on the current device), owned by the caller.
+ *  - Matrix and ordering arrays are owned by the caller and read during the
+ *    call only (copied / uploaded).  Ordering arrays are host memory; the
+ *    CSR arrays are host or device memory as hssmf_csr.mem says.
+ *  - Vector arguments of hssmf_apply and hssmf_adjoint are DEVICE pointers
+ *    (HIP global memory on the current device).  hssmf_solve,
+ *    hssmf_solve_transpose and hssmf_solve_batch take host or device
+ *    vectors: the library asks the HIP runtime (hipPointerGetAttributes)
+ *    which one each pointer is, and stages host vectors through device
+ *    memory.  All vectors are owned by the caller.
  *  - A handle owns all device memory of a factorization until
  *    hssmf_destroy().  A handle is not thread-safe; calls on one handle must
  *    not overlap.  All device work is enqueued on the stream given to
@@ -50,14 +55,23 @@ extern "C" {
 #define HSSMF_OUTER_IR 0
 #define HSSMF_OUTER_GMRES 1
 
-/* Sparse matrix A (n x n) in CSR form, host memory.  rowptr has n+1 entries
+/* where the arrays of an hssmf_csr live */
+#define HSSMF_MEM_HOST 0
+#define HSSMF_MEM_DEVICE 1
+
+/* Sparse matrix A (n x n) in CSR form: a general non-symmetric,
+ * non-singular matrix (Sec. 1, Sec. 3).  rowptr has n+1 entries
  * (rowptr[0] = 0, non-decreasing), colind/val have rowptr[n] entries; column
- * indices lie in [0, n) and are unique within a row. */
+ * indices lie in [0, n) and are unique within a row.  mem: HSSMF_MEM_HOST
+ * (0) when rowptr / colind / val are host memory, HSSMF_MEM_DEVICE (1) when
+ * they are device memory of the current device (they are then copied to the
+ * host for the symbolic analysis, and the values also device to device). */
 typedef struct {
   int32_t n;
   const int64_t* rowptr;
   const int32_t* colind;
   const double* val;
+  int32_t mem;
 } hssmf_csr;
 
 /* Fill-reducing nested-dissection ordering (Sec. 3.1) with its separator
@@ -102,16 +116,25 @@ typedef struct {
                           per process); forced: 64 (64 x 64 tiles, k-tiles of
                           16), 65 (64 x 64, k-tiles of 32), 128 (128 x 128);
                           the results do not depend on it */
+  double abs_tol;      /* absolute HSS compression tolerance: the rank of an
+                          ID stops at |R_{i+1,i+1}| <= max(rel_tol |R_11|,
+                          abs_tol) (Sec. 5.3 gives the relative rule; 0, the
+                          default, keeps it alone) */
 } hssmf_opts;
 
-/* id_kernel: STEPWISE (default) = one launch per pivot step for each batch
- * of IDs; COOPERATIVE = when every workgroup of a batch fits on the device
- * at once, one cooperative launch that keeps the candidates in registers and
- * passes the partial maxima and the pivot column between workgroups through
- * agent-coherent memory (one launch per step otherwise).  Both take the
- * same pivot rule; they differ only in the order of floating-point sums. */
+/* id_kernel: STEPWISE = one launch per pivot step for each batch of IDs;
+ * COOPERATIVE = when every workgroup of a batch fits on the device at once,
+ * one cooperative launch that keeps the candidates in registers and passes
+ * the partial maxima and the pivot column between workgroups through
+ * agent-coherent memory (one launch per step otherwise); RESIDENT = every
+ * pivot step of a batch in one launch with each problem's candidates in the
+ * registers of as few 512-thread workgroups as hold them (one workgroup,
+ * and no exchange between workgroups, for the problems that fit; up to 2560
+ * samples).  All take the same pivot rule; they differ only in the order of
+ * floating-point sums. */
 #define HSSMF_ID_STEPWISE 0
 #define HSSMF_ID_COOPERATIVE 1
+#define HSSMF_ID_RESIDENT 2
 
 typedef struct {
   int32_t iterations;    /* refinement steps or GMRES iterations */
@@ -129,7 +152,8 @@ typedef struct {
 /* Fill *o with defaults: rel_tol 1e-6, leaf_size 64, min_sep_hss INT32_MAX
  * (pure multifrontal), d0 128, dd 128, p 10, d_max 4096, seed 0, FP64,
  * iterative refinement, restart 30, tol 1e-10, max_it 50, stepwise ID
- * kernel, sweeps launched one by one (no graph), autotuned GEMM tiles. */
+ * kernel, sweeps launched one by one (no graph), autotuned GEMM tiles,
+ * abs_tol 0. */
 int hssmf_default_opts(hssmf_opts* o);
 
 /* Symbolic analysis, upload and numeric factorization (Sec. 3.2, Sec. 4).
@@ -177,13 +201,30 @@ int hssmf_refactor_device(void* h, const double* val_dev);
  * device arrays of n doubles (may alias). */
 int hssmf_apply(void* h, int32_t trans, const double* x, double* y);
 
-/* Solve A x = b with the outer solver of the options (Sec. 4.6): b, x are
- * device arrays of n doubles.  ENOCONV still writes the best x and fills
- * info. */
-int hssmf_solve(void* h, const double* b, double* x, hssmf_info* info);
+/* Solve A x = b with the outer solver of the options, iterative refinement
+ * or restarted GMRES with modified Gram-Schmidt preconditioned by the
+ * factorization (Sec. 4.6, Sec. 6.1), stopping on the true residual
+ * ||b - A x||_2 / ||b||_2 <= tol.  b, x: n x nrhs column-major (column j at
+ * offset j n), host or device memory (each pointer's kind is looked up);
+ * the right-hand sides are solved one after another.  info: NULL or an
+ * array of nrhs records.  Returns the worst status over the right-hand
+ * sides: ENOCONV still writes the best x of every column and fills info.
+ * EINVAL for nrhs < 0 or null pointers (nrhs = 0 does nothing). */
+int hssmf_solve(void* h, int32_t nrhs, const double* b, double* x, hssmf_info* info);
 
-/* Solve A^T lambda = g with the same factors (transposed sweeps). */
-int hssmf_solve_transpose(void* h, const double* g, double* lambda, hssmf_info* info);
+/* Solve A^T lambda = g with the same factors: the multifrontal and ULV
+ * sweeps transposed (Sec. 3.3, Sec. 2.3), inside the same outer solver with
+ * A^T products.  Arguments as hssmf_solve. */
+int hssmf_solve_transpose(void* h, int32_t nrhs, const double* g, double* lambda, hssmf_info* info);
+
+/* Solve every system of an hssmf_factor_batch handle: b[s] and x[s] point to
+ * system s's right-hand side and solution (off[s+1] - off[s] doubles each,
+ * see hssmf_systems), each host or device memory.  The systems are solved
+ * together (their vectors are packed back to back on the device) and the
+ * outer solver stops when every system reaches its own tolerance.  info:
+ * NULL or one record (worst system).  A single-system handle takes nsys = 1
+ * arrays.  EINVAL for null arrays or entries. */
+int hssmf_solve_batch(void* h, const double* const* b, double* const* x, hssmf_info* info);
 
 /* Adjoint of x = A^{-1} b for a scalar loss L with gradient g = dL/dx:
  * lambda = A^{-T} g, dl_db = lambda, dl_dval[e] = -lambda[row(e)] x[col(e)]

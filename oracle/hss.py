@@ -25,13 +25,15 @@ class RankError(RuntimeError):
 # interpolative decomposition (Sec. 2.2, Eq. for ID; stopping rule Sec. 5.3)
 # ---------------------------------------------------------------------------
 
-def cpqr_eps(Y, eps):
+def cpqr_eps(Y, eps, atol=0.0):
     """Householder QR with column pivoting of Y (d x m), stopped at the
     numerical rank.  At every step the pivot is the column whose remaining
     part has the largest 2-norm, recomputed from the updated column (ties go
     to the lowest index).  The factorization stops before step i+1 when that
     norm is <= eps times the first pivot's norm, i.e. |R_{i+1,i+1}| <= eps
-    |R_11| (the modified geqp3 of Sec. 5.3).  A zero matrix has rank 0.
+    |R_11| (the modified geqp3 of Sec. 5.3), or <= the absolute tolerance
+    atol (0: the relative rule alone).  It stops before the first step when
+    the largest column norm is <= atol, so a zero matrix has rank 0.
 
     Returns (perm, R, k): Y[:, perm] = Q R with R (min(d,m) x m) upper
     trapezoidal in its first k rows; only R[:k] is meaningful."""
@@ -47,9 +49,9 @@ def cpqr_eps(Y, eps):
         nrm = norms[p - j]
         if first is None:
             first = nrm
-            if first == 0.0:
+            if first <= atol:
                 break
-        elif nrm <= eps * first:
+        elif nrm <= max(eps * first, atol):
             break
         if p != j:
             W[:, [j, p]] = W[:, [p, j]]
@@ -67,11 +69,11 @@ def cpqr_eps(Y, eps):
     return perm, W[:kmax], k
 
 
-def interp_decomp(Y, eps):
+def interp_decomp(Y, eps, atol=0.0):
     """[X, J] = ID(Y, eps): Y ~= Y[:, J] X with X = [I, R1^{-1} R2] Pi^{-1}
     (Sec. 2.2).  Returns (perm, E, k) where J = perm[:k] and
     E = (R1^{-1} R2)^T, so that Y^T ~= Pi [I; E] Y[:, J]^T."""
-    perm, R, k = cpqr_eps(Y, eps)
+    perm, R, k = cpqr_eps(Y, eps, atol)
     m = Y.shape[1]
     if k == 0:
         return perm, np.zeros((m, 0)), 0
@@ -133,7 +135,7 @@ class HSS:
 # randomized compression (Alg. 1) with adaptive rank (Sec. 2.2.1, Sec. 4.3)
 # ---------------------------------------------------------------------------
 
-def compress(op, nodes, root, rand, eps, d0, dd, p, d_max):
+def compress(op, nodes, root, rand, eps, d0, dd, p, d_max, atol=0.0):
     """Alg. 1 applied to a matrix known through ``op``:
     op.sample(R) -> (F R, F^T R) for a block of random columns and
     op.extract(I, J) -> F[I][:, J].  ``rand(c0, nc)`` returns columns
@@ -156,6 +158,10 @@ def compress(op, nodes, root, rand, eps, d0, dd, p, d_max):
     R = rand(0, d)
     Sr, Sc = op.sample(R)
     rounds = 0
+    # record of the work done, for the algorithmic operation counts only
+    # (oracle.work): columns sampled per pass, and per ID attempt the node,
+    # side, samples d, rows m and rank k
+    log = dict(sampled=[d], ids=[], node_cols=[])
 
     def node_samples(t, cols):
         """Unreduced S^r_tau, S^c_tau on columns ``cols`` (Alg. 1, leaf and
@@ -207,8 +213,9 @@ def compress(op, nodes, root, rand, eps, d0, dd, p, d_max):
                 done[t] = True
                 continue
             sr, sc = node_samples(t, allc)
-            pu, Eu, kr = interp_decomp(sr.T, eps)
-            pv, Ev, kc = interp_decomp(sc.T, eps)
+            pu, Eu, kr = interp_decomp(sr.T, eps, atol)
+            pv, Ev, kc = interp_decomp(sc.T, eps, atol)
+            log["ids"].append((t, d, sr.shape[0], kr, sc.shape[0], kc))
             ok_r = kr <= d - p or kr == sr.shape[0]
             ok_c = kc <= d - p or kc == sc.shape[0]
             if not (ok_r and ok_c):
@@ -223,6 +230,7 @@ def compress(op, nodes, root, rand, eps, d0, dd, p, d_max):
             g.Ir = base_r[pu[:kr]]
             g.Ic = base_c[pv[:kc]]
             Sr_red[t], Sc_red[t], Rr_red[t], Rc_red[t] = reduce_node(t, sr, sc, allc)
+            log["node_cols"].append((t, d))
             done[t] = True
         if done[root]:
             break
@@ -230,6 +238,7 @@ def compress(op, nodes, root, rand, eps, d0, dd, p, d_max):
             raise RankError(f"HSS compression needs more than d_max={d_max} samples")
         Rn = rand(d, dd)
         Srn, Scn = op.sample(Rn)
+        log["sampled"].append(dd)
         R = np.hstack([R, Rn])
         Sr = np.hstack([Sr, Srn])
         Sc = np.hstack([Sc, Scn])
@@ -240,11 +249,12 @@ def compress(op, nodes, root, rand, eps, d0, dd, p, d_max):
             if done[t] and t != root:
                 sr, sc = node_samples(t, newc)
                 a1, a2, a3, a4 = reduce_node(t, sr, sc, newc)
+                log["node_cols"].append((t, dd))
                 Sr_red[t] = np.hstack([Sr_red[t], a1])
                 Sc_red[t] = np.hstack([Sc_red[t], a2])
                 Rr_red[t] = np.hstack([Rr_red[t], a3])
                 Rc_red[t] = np.hstack([Rc_red[t], a4])
-    return HSS(nodes, gen, root, dict(d=d, rounds=rounds))
+    return HSS(nodes, gen, root, dict(d=d, rounds=rounds, log=log))
 
 
 # ---------------------------------------------------------------------------
@@ -656,12 +666,12 @@ class Front11Ops:
         return down_expand(self.H, self.k, self.B_qk.T @ self._vt(self.q, x, "U"), "V")
 
 
-def build_hss_front(op, s, u, leaf_size, rand, eps, d0, dd, p, d_max):
+def build_hss_front(op, s, u, leaf_size, rand, eps, d0, dd, p, d_max, atol=0.0):
     """Compress a front of size s+u (Alg. 1), then ULV-factor its F11 part and
     form Theta^*, Phi.  Returns (H, ULV, k, q, Theta, Phi)."""
     nodes, k, q = hss_tree(s, u, leaf_size)
     root = len(nodes) - 1
-    H = compress(op, nodes, root, rand, eps, d0, dd, p, d_max)
+    H = compress(op, nodes, root, rand, eps, d0, dd, p, d_max, atol)
     F = ulv_factor(H, k)
     Theta = Phi = None
     if q >= 0:

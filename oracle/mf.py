@@ -30,6 +30,7 @@ class Options:
     p: int = 10
     d_max: int = 1 << 20
     seed: int = 0
+    abs_tol: float = 0.0
 
 
 class DenseUpdate:
@@ -161,7 +162,8 @@ def factor(A, ordering, opts, stop_after=None):
             # Sec. 4.3): it starts with as many as they ended with, at least d0
             d_init = max([opts.d0] + [hss_d[c] for c in f.children if c in hss_d])
             H, F, k, q, Theta, Phi = hs.build_hss_front(
-                op, f.s, f.u, opts.leaf_size, rand, opts.rel_tol, d_init, opts.dd, opts.p, opts.d_max)
+                op, f.s, f.u, opts.leaf_size, rand, opts.rel_tol, d_init, opts.dd, opts.p, opts.d_max,
+                opts.abs_tol)
             hss_d[f.id] = H.stats["d"]
             data = dict(H=H, ulv=F, k=k, q=q)
             if q >= 0:

@@ -286,22 +286,49 @@ double max_rel(Handle& h, const double* r, const std::vector<double>& nb) {
   return rel;
 }
 
+// Device vectors of one outer solve: carved from a caller-provided block
+// (the no-allocation entry point's static scratch) or taken from the
+// handle's arena and given back when the solve ends.
+struct Ws {
+  Handle& h;
+  double* base;
+  size_t cap, off = 0;
+  Arena::Mark mk;
+  Ws(Handle& hh, double* b = nullptr, size_t c = 0) : h(hh), base(b), cap(c), mk(hh.arena.mark()) {}
+  ~Ws() {
+    if (!base) h.arena.reset(mk);
+  }
+  double* get(size_t n) {
+    if (!base) return h.arena.get<double>(n);
+    const size_t need = (n + 31) & ~size_t(31);   // 256-byte aligned pieces
+    REQUIRE(off + need <= cap, HSSMF_EINVAL, "outer solver: workspace too small");
+    double* p = base + off;
+    off += need;
+    return p;
+  }
+};
+
+// doubles of workspace the outer solver of the options takes for n unknowns
+size_t outer_ws_doubles(const hssmf_opts& o, int64_t n) {
+  const size_t nn = ((size_t)std::max<int64_t>(n, 1) + 31) & ~size_t(31);
+  if (o.outer == HSSMF_OUTER_GMRES) return nn * (size_t)(std::max(1, std::min(o.restart, 200)) + 3);
+  return 2 * nn;
+}
+
 // restarted, left-preconditioned GMRES(m) with modified Gram-Schmidt on the
 // device and Givens rotations on the host; x0 = 0; stops on the true
 // relative residual
-int gmres(Handle& h, int trans, const double* b, double* x, hssmf_info* info) {
+int gmres(Handle& h, int trans, const double* b, double* x, hssmf_info* info, Ws& ws, bool graph) {
   const int n = h.P.n, m = std::max(1, std::min(h.o.restart, 200));
-  Arena::Mark mk = h.arena.mark();
-  double* V = h.arena.get<double>((size_t)n * (m + 1));
-  double* w = h.arena.get<double>(n);
-  double* r = h.arena.get<double>(n);
+  double* V = ws.get((size_t)n * (m + 1));
+  double* w = ws.get(n);
+  double* r = ws.get(n);
   double* hcol = h.d_scal;  // m+2 device scalars
   const std::vector<double> nbs = sys_norms(h, b);
   const double nb = dnrm2(h, b, n);
-  HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * n, h.st));
+  launch_fill(x, n, 0.0, h.st);
   if (nb == 0.0) {
     if (info) { info->iterations = 0; info->rel_residual = 0; }
-    h.arena.reset(mk);
     return HSSMF_OK;
   }
   int its = 0;
@@ -316,7 +343,7 @@ int gmres(Handle& h, int trans, const double* b, double* x, hssmf_info* info) {
     // r = M^{-1} (b - A x)
     spmv(h, trans, x, r, -1.0, 0.0);
     launch_axpy(r, b, n, nullptr, 1.0, 0, h.st);
-    apply_inverse(h, trans, r, w);
+    apply_inverse(h, trans, r, w, graph);
     double beta = dnrm2(h, w, n);
     if (beta0 < 0) beta0 = beta;
     if (beta == 0.0) break;
@@ -329,7 +356,7 @@ int gmres(Handle& h, int trans, const double* b, double* x, hssmf_info* info) {
     for (int j = 0; j < m && its < h.o.max_it; ++j) {
       double* vj = V + (size_t)j * n;
       spmv(h, trans, vj, r, 1.0, 0.0);
-      apply_inverse(h, trans, r, w);
+      apply_inverse(h, trans, r, w, graph);
       for (int i = 0; i <= j; ++i) {
         launch_dot(w, V + (size_t)i * n, n, h.d_part, hcol + i, 0, h.st);
         launch_axpy(w, V + (size_t)i * n, n, hcol + i, -1.0, 0, h.st);
@@ -378,18 +405,16 @@ int gmres(Handle& h, int trans, const double* b, double* x, hssmf_info* info) {
     if (done) break;
   }
   HIP_CHECK(hipStreamSynchronize(h.st));
-  h.arena.reset(mk);
   if (info) { info->iterations = its; info->rel_residual = rel; }
   return rel <= h.o.tol ? HSSMF_OK : HSSMF_ENOCONV;
 }
 
-int refine(Handle& h, int trans, const double* b, double* x, hssmf_info* info) {
+int refine(Handle& h, int trans, const double* b, double* x, hssmf_info* info, Ws& ws, bool graph) {
   const int n = h.P.n;
-  Arena::Mark mk = h.arena.mark();
-  double* r = h.arena.get<double>(n);
-  double* z = h.arena.get<double>(n);
+  double* r = ws.get(n);
+  double* z = ws.get(n);
   const std::vector<double> nbs = sys_norms(h, b);
-  apply_inverse(h, trans, b, x);
+  apply_inverse(h, trans, b, x, graph);
   double rel = 0.0;
   int it = 0;
   for (;; ++it) {
@@ -397,18 +422,84 @@ int refine(Handle& h, int trans, const double* b, double* x, hssmf_info* info) {
     launch_axpy(r, b, n, nullptr, 1.0, 0, h.st);
     rel = max_rel(h, r, nbs);
     if (rel <= h.o.tol || it >= h.o.max_it) break;
-    apply_inverse(h, trans, r, z);
+    apply_inverse(h, trans, r, z, graph);
     launch_axpy(x, z, n, nullptr, 1.0, 0, h.st);
   }
   HIP_CHECK(hipStreamSynchronize(h.st));
-  h.arena.reset(mk);
   if (info) { info->iterations = it; info->rel_residual = rel; info->failed_front = -1; }
   return rel <= h.o.tol ? HSSMF_OK : HSSMF_ENOCONV;
 }
 
-int outer(Handle& h, int trans, const double* b, double* x, hssmf_info* info) {
+// one right-hand side; ws null: work vectors from the handle's arena
+int outer(Handle& h, int trans, const double* b, double* x, hssmf_info* info, double* wsbase = nullptr,
+          size_t wscap = 0) {
   if (info) { info->iterations = 0; info->rel_residual = 0; info->failed_front = -1; }
-  return h.o.outer == HSSMF_OUTER_GMRES ? gmres(h, trans, b, x, info) : refine(h, trans, b, x, info);
+  Ws ws(h, wsbase, wscap);
+  const bool graph = wsbase == nullptr;   // capturing a graph allocates
+  return h.o.outer == HSSMF_OUTER_GMRES ? gmres(h, trans, b, x, info, ws, graph)
+                                        : refine(h, trans, b, x, info, ws, graph);
+}
+
+}  // namespace
+
+namespace hssmf {
+int outer_solve(Handle& h, int trans, const double* b, double* x, hssmf_info* info, double* ws, size_t wscap) {
+  return outer(h, trans, b, x, info, ws, wscap);
+}
+size_t outer_workspace(const hssmf_opts& o, int64_t n) { return outer_ws_doubles(o, n); }
+}  // namespace hssmf
+
+namespace {
+
+// whether p is device memory (else host memory, pinned or pageable)
+bool on_device(const void* p) {
+  hipPointerAttribute_t a{};
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();   // pageable host memory is unknown to the runtime
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+// status precedence when several right-hand sides end differently: any hard
+// error first, then ENOCONV, then OK
+int worse(int a, int b) {
+  if (a == HSSMF_OK) return b;
+  if (b == HSSMF_OK) return a;
+  if (a == HSSMF_ENOCONV) return b;
+  return a;
+}
+
+// nrhs right-hand sides, host or device, one after another
+int outer_many(Handle& h, int trans, int nrhs, const double* b, double* x, hssmf_info* info) {
+  const int64_t n = h.P.n;
+  const bool bd = on_device(b), xd = on_device(x);
+  Arena::Mark mk = h.arena.mark();
+  double* bs = bd ? nullptr : h.arena.get<double>((size_t)n);
+  double* xs = xd ? nullptr : h.arena.get<double>((size_t)n);
+  int st = HSSMF_OK;
+  try {
+    for (int j = 0; j < nrhs; ++j) {
+      const double* bj = b + (size_t)j * n;
+      double* xj = x + (size_t)j * n;
+      if (!bd) {
+        HIP_CHECK(hipMemcpyAsync(bs, bj, sizeof(double) * n, hipMemcpyHostToDevice, h.st));
+        bj = bs;
+      }
+      double* xo = xd ? xj : xs;
+      st = worse(st, outer(h, trans, bj, xo, info ? info + j : nullptr));
+      if (!xd) {
+        HIP_CHECK(hipMemcpyAsync(xj, xs, sizeof(double) * n, hipMemcpyDeviceToHost, h.st));
+        HIP_CHECK(hipStreamSynchronize(h.st));
+      }
+    }
+  } catch (...) {
+    (void)hipStreamSynchronize(h.st);
+    h.arena.reset(mk);
+    throw;
+  }
+  h.arena.reset(mk);
+  return st;
 }
 
 }  // namespace
@@ -443,8 +534,40 @@ namespace {
 bool opts_ok(const hssmf_opts* o) {
   return !(o->leaf_size < 1 || o->d0 < 1 || o->dd < 1 || o->p < 0 || o->d_max < o->d0 || !(o->rel_tol >= 0.0) ||
            o->restart < 1 || o->max_it < 0 || o->gemm_prec < 0 || o->gemm_prec > 2 || o->id_kernel < 0 ||
-           o->id_kernel > 1 || o->use_graph < 0 || o->use_graph > 1 ||
-           !(o->gemm_tile == 0 || o->gemm_tile == 64 || o->gemm_tile == 65 || o->gemm_tile == 128));
+           o->id_kernel > 2 || o->use_graph < 0 || o->use_graph > 1 ||
+           !(o->gemm_tile == 0 || o->gemm_tile == 64 || o->gemm_tile == 65 || o->gemm_tile == 128) ||
+           !(o->abs_tol >= 0.0));
+}
+
+// a CSR matrix in host memory: the caller's arrays when they are host
+// memory, else copies of its device arrays
+struct HostCSR {
+  hssmf_csr a{};
+  std::vector<int64_t> rp;
+  std::vector<int32_t> ci;
+  std::vector<double> v;
+};
+int to_host(const hssmf_csr* A, HostCSR& out) {
+  out.a = *A;
+  out.a.mem = HSSMF_MEM_HOST;
+  if (A->mem == HSSMF_MEM_HOST) return HSSMF_OK;
+  if (A->mem != HSSMF_MEM_DEVICE || A->n < 0 || !A->rowptr) return HSSMF_EINVAL;
+  return guard_impl(nullptr, [&]() {
+    out.rp.resize((size_t)A->n + 1);
+    HIP_CHECK(hipMemcpy(out.rp.data(), A->rowptr, sizeof(int64_t) * out.rp.size(), hipMemcpyDeviceToHost));
+    const int64_t nnz = out.rp[A->n] - out.rp[0];
+    REQUIRE(out.rp[0] >= 0 && nnz >= 0, HSSMF_EINVAL, "device CSR: bad rowptr");
+    REQUIRE(nnz == 0 || (A->colind && A->val), HSSMF_EINVAL, "device CSR: null arrays");
+    out.ci.resize((size_t)out.rp[A->n]);
+    out.v.resize((size_t)out.rp[A->n]);
+    if (!out.ci.empty()) {
+      HIP_CHECK(hipMemcpy(out.ci.data(), A->colind, sizeof(int32_t) * out.ci.size(), hipMemcpyDeviceToHost));
+      HIP_CHECK(hipMemcpy(out.v.data(), A->val, sizeof(double) * out.v.size(), hipMemcpyDeviceToHost));
+    }
+    out.a.rowptr = out.rp.data();
+    out.a.colind = out.ci.data();
+    out.a.val = out.v.data();
+  });
 }
 
 int factor_impl(const hssmf_csr* A, const hssmf_ordering* ord, const hssmf_opts* opts, void* stream, void** out,
@@ -493,7 +616,10 @@ int hssmf_factor(const hssmf_csr* A, const hssmf_ordering* ord, const hssmf_opts
   if (!out || !A || !ord || !opts) return HSSMF_EINVAL;
   *out = nullptr;
   if (!opts_ok(opts)) return HSSMF_EINVAL;
-  return factor_impl(A, ord, opts, stream, out, {0, (int64_t)std::max(A->n, 0)});
+  HostCSR hc;
+  int rc = to_host(A, hc);
+  if (rc != HSSMF_OK) return rc;
+  return factor_impl(&hc.a, ord, opts, stream, out, {0, (int64_t)std::max(A->n, 0)});
 }
 
 int hssmf_factor_batch(int32_t nsys, const hssmf_csr* A, const hssmf_ordering* ord, const hssmf_opts* opts,
@@ -503,6 +629,14 @@ int hssmf_factor_batch(int32_t nsys, const hssmf_csr* A, const hssmf_ordering* o
   if (!opts_ok(opts)) return HSSMF_EINVAL;
   // one block-diagonal matrix whose elimination forest has one tree per
   // system, numbered system by system (each system's postorder kept)
+  std::vector<HostCSR> hcs(nsys);
+  for (int s = 0; s < nsys; ++s) {
+    int rc = to_host(A + s, hcs[s]);
+    if (rc != HSSMF_OK) return rc;
+  }
+  std::vector<hssmf_csr> Ah(nsys);
+  for (int s = 0; s < nsys; ++s) Ah[s] = hcs[s].a;
+  A = Ah.data();
   int64_t n = 0, nnz = 0, nf = 0;
   for (int s = 0; s < nsys; ++s) {
     if (A[s].n < 0 || !A[s].rowptr || (A[s].n > 0 && (!A[s].colind || !A[s].val)) || ord[s].nfront < 0 ||
@@ -537,7 +671,7 @@ int hssmf_factor_batch(int32_t nsys, const hssmf_csr* A, const hssmf_ordering* o
     f0 += o.nfront;
     off[s + 1] = r0;
   }
-  hssmf_csr ca{(int32_t)n, rowptr.data(), col.data(), val.data()};
+  hssmf_csr ca{(int32_t)n, rowptr.data(), col.data(), val.data(), HSSMF_MEM_HOST};
   hssmf_ordering co{perm.data(), (int32_t)nf, sep.data(), par.data()};
   return factor_impl(&ca, &co, opts, stream, out, off);
 }
@@ -579,21 +713,57 @@ int hssmf_apply(void* hv, int32_t trans, const double* x, double* y) {
   });
 }
 
-int hssmf_solve(void* hv, const double* b, double* x, hssmf_info* info) {
+int hssmf_solve(void* hv, int32_t nrhs, const double* b, double* x, hssmf_info* info) {
   Handle* h = static_cast<Handle*>(hv);
-  if (!h || !b || !x) return HSSMF_EINVAL;
+  if (!h || nrhs < 0 || (nrhs > 0 && (!b || !x))) return HSSMF_EINVAL;
   if (h->factor_status != HSSMF_OK) return h->factor_status;
   int out = HSSMF_OK;
-  int rc = guard_impl(h, [&]() { out = outer(*h, 0, b, x, info); });
+  int rc = guard_impl(h, [&]() { out = outer_many(*h, 0, nrhs, b, x, info); });
   return rc != HSSMF_OK ? rc : out;
 }
 
-int hssmf_solve_transpose(void* hv, const double* g, double* lam, hssmf_info* info) {
+int hssmf_solve_transpose(void* hv, int32_t nrhs, const double* g, double* lam, hssmf_info* info) {
   Handle* h = static_cast<Handle*>(hv);
-  if (!h || !g || !lam) return HSSMF_EINVAL;
+  if (!h || nrhs < 0 || (nrhs > 0 && (!g || !lam))) return HSSMF_EINVAL;
   if (h->factor_status != HSSMF_OK) return h->factor_status;
   int out = HSSMF_OK;
-  int rc = guard_impl(h, [&]() { out = outer(*h, 1, g, lam, info); });
+  int rc = guard_impl(h, [&]() { out = outer_many(*h, 1, nrhs, g, lam, info); });
+  return rc != HSSMF_OK ? rc : out;
+}
+
+int hssmf_solve_batch(void* hv, const double* const* b, double* const* x, hssmf_info* info) {
+  Handle* h = static_cast<Handle*>(hv);
+  if (!h || !b || !x) return HSSMF_EINVAL;
+  const int ns = (int)h->sys_off.size() - 1;
+  for (int s = 0; s < ns; ++s)
+    if (h->sys_off[s + 1] > h->sys_off[s] && (!b[s] || !x[s])) return HSSMF_EINVAL;
+  if (h->factor_status != HSSMF_OK) return h->factor_status;
+  int out = HSSMF_OK;
+  int rc = guard_impl(h, [&]() {
+    // pack the systems' right-hand sides back to back, solve once, unpack
+    const int64_t n = h->P.n;
+    Arena::Mark mk = h->arena.mark();
+    double* bb = h->arena.get<double>((size_t)n);
+    double* xx = h->arena.get<double>((size_t)n);
+    auto seg = [&](int s) { return (size_t)(h->sys_off[s + 1] - h->sys_off[s]); };
+    try {
+      for (int s = 0; s < ns; ++s)
+        if (seg(s))
+          HIP_CHECK(hipMemcpyAsync(bb + h->sys_off[s], b[s], sizeof(double) * seg(s),
+                                   on_device(b[s]) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->st));
+      out = outer(*h, 0, bb, xx, info);
+      for (int s = 0; s < ns; ++s)
+        if (seg(s))
+          HIP_CHECK(hipMemcpyAsync(x[s], xx + h->sys_off[s], sizeof(double) * seg(s),
+                                   on_device(x[s]) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->st));
+      HIP_CHECK(hipStreamSynchronize(h->st));
+    } catch (...) {
+      (void)hipStreamSynchronize(h->st);
+      h->arena.reset(mk);
+      throw;
+    }
+    h->arena.reset(mk);
+  });
   return rc != HSSMF_OK ? rc : out;
 }
 

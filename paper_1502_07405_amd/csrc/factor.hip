@@ -549,6 +549,7 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
           pr.d = d;
           pr.wg0 = wg;
           pr.eps = o.rel_tol;
+          pr.atol = o.abs_tol;
           wg += pr.P;
           q.push_back(pr);
           maxm = std::max(maxm, m);
@@ -566,7 +567,64 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
         HIP_CHECK(hipStreamSynchronize(h.st));
         census_t0 = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
       }
-      if (!q.empty()) {
+      const int res_c = o.id_kernel == HSSMF_ID_RESIDENT ? id_res_candidates(maxd) : 0;
+      if (!q.empty() && res_c > 0) {
+        // every pivot step of a problem in one launch, candidates resident
+        // in registers: problems of at most res_c candidates on one
+        // workgroup (ordinary launch), larger ones on several workgroups of
+        // a cooperative launch (all resident, bounded waits)
+        const int np = (int)q.size();
+        const int cap = id_res_capacity(maxd);
+        std::vector<int> single, multi;
+        for (int pi = 0; pi < np; ++pi) {
+          q[pi].P = std::max(1, (q[pi].m + res_c - 1) / res_c);
+          (q[pi].P > 1 ? multi : single).push_back(pi);
+        }
+        int wgm = 0;
+        for (int pi : multi) wgm += q[pi].P;
+        REQUIRE(multi.empty() || cap > 0, HSSMF_EDEVICE, "interpolative decomposition: no cooperative launch");
+        double* slots = nullptr;
+        if (!multi.empty()) {
+          derr = sialloc(h, 1);
+          slots = salloc(h, 8 * (int64_t)wgm);   // per problem 2 x P x (norm, index, step tag, pad)
+          int o8 = 0;
+          for (int pi : multi) {
+            REQUIRE(q[pi].P <= cap, HSSMF_ERANK, "interpolative decomposition: problem wider than the device");
+            q[pi].cand = salloc(h, 2 * (int64_t)q[pi].P * q[pi].d);
+            q[pi].slots = slots + o8;
+            o8 += 8 * q[pi].P;
+          }
+          launch_fill(slots, 8 * (int64_t)wgm, -1.0, h.st);   // step tags start at -1
+          HIP_CHECK(hipMemsetAsync(derr, 0, sizeof(int), h.st));
+        }
+        IDProb* dq = upload(h, q);
+        std::vector<int2> wgs;
+        // one cooperative launch for everything when it all fits at once,
+        // else the single-workgroup problems in one ordinary launch and the
+        // wider ones in cooperative launches of at most cap workgroups
+        int total = wgm + (int)single.size();
+        if (!multi.empty() && total <= cap) {
+          for (int pi = 0; pi < np; ++pi)
+            for (int w = 0; w < q[pi].P; ++w) wgs.push_back(make_int2(pi, w));
+          launch_id_res(dq, upload(h, wgs), (int)wgs.size(), maxd, true, derr, h.st);
+        } else {
+          for (int pi : single) wgs.push_back(make_int2(pi, 0));
+          if (!wgs.empty()) launch_id_res(dq, upload(h, wgs), (int)wgs.size(), maxd, false, derr, h.st);
+          wgs.clear();
+          auto flush = [&]() {
+            if (wgs.empty()) return;
+            launch_id_res(dq, upload(h, wgs), (int)wgs.size(), maxd, true, derr, h.st);
+            wgs.clear();
+          };
+          for (int pi : multi) {
+            if ((int)wgs.size() + q[pi].P > cap) flush();
+            for (int w = 0; w < q[pi].P; ++w) wgs.push_back(make_int2(pi, w));
+          }
+          flush();
+        }
+        census_steps = -1;
+        launch_id_finish(dq, np, maxm, h.st);
+      } else if (!q.empty()) {
         const int np = (int)q.size();
         int maxp = 0;
         for (auto& pr : q) maxp = std::max(maxp, pr.P);

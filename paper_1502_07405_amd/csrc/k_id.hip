@@ -192,7 +192,7 @@ __global__ __launch_bounds__(256) void id_step_kernel(const IDProb* __restrict__
   const double best = wred[0];
   const int p = wredi[0];
   if (t == 0) first = best;
-  const bool stop = (t >= kmax) || (t == 0 ? best <= 0.0 : best <= q.eps * first);
+  const bool stop = (t >= kmax) || (t == 0 ? best <= q.atol : best <= fmax(q.eps * first, q.atol));
   if (stop) {
     if (b == 0 && tid == 0) {
       q.state[1] = (t == 0 && best <= 0.0) ? 0 : t;
@@ -431,7 +431,7 @@ __global__ __launch_bounds__(256) void id_coop_kernel(const IDProb* __restrict__
     const double best = pbest;
     const int p = pidx;
     if (t == 0) first = best;
-    const bool stop = (t >= kmax) || (t == 0 ? best <= 0.0 : best <= q.eps * first);
+    const bool stop = (t >= kmax) || (t == 0 ? best <= q.atol : best <= fmax(q.eps * first, q.atol));
     if (stop) {
       if (b == 0 && tid == 0) {
         q.first[0] = first;

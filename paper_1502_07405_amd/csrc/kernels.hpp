@@ -243,7 +243,8 @@ struct IDProb {
   int* hdone;           // null, or a flag in mapped host memory that the stop step sets (stepwise path)
   int m, d, lds, P;     // P workgroups of kIDCols candidates each
   int wg0, pad;         // first workgroup of this problem in the launch grid
-  double eps;
+  double eps;           // relative stopping tolerance (Sec. 5.3)
+  double atol;          // absolute stopping tolerance (0: the relative rule alone)
 };
 constexpr int kIDCols = 8;
 
@@ -264,6 +265,19 @@ void measure_peaks(hipStream_t s, double* hbm_gbps, double* valu_tflops, double*
 // results are invalid.
 int id_coop_capacity(int max_d);
 void launch_id_coop(const IDProb* p, const int2* wgmap, int total_wg, int max_d, int* err, hipStream_t s);
+
+// Resident variant (k_idres.hip): every pivot step in one launch, the
+// candidates of a problem resident in the registers of P workgroups of
+// id_res_candidates(max_d) candidates each (0: max_d too large).  Problems
+// with P = 1 need no other workgroup; a launch holding any problem with
+// P > 1 must be cooperative (coop = true, at most id_res_capacity(max_d)
+// workgroups), with that problem's slots (2 x P x 4 doubles, step tags
+// preset to -1) and cand (2 x P x d) set and *err zero; *err != 0
+// afterwards means a wait gave up and the results are invalid.
+int id_res_candidates(int max_d);
+int id_res_capacity(int max_d);
+void launch_id_res(const IDProb* p, const int2* wgmap, int total_wg, int max_d, bool coop, int* err,
+                   hipStream_t s);
 
 }  // namespace hssmf
 

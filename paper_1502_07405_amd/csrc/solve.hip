@@ -465,8 +465,8 @@ void run_ops(Handle& h, const std::vector<Op>& ops) {
 // forward and backward sweeps on the handle's work vector, replayed as one
 // HIP graph when enabled (captured on first use after each factorization:
 // the sweeps only launch kernels on descriptors already on the device)
-void sweeps(Handle& h, int trans) {
-  if (!h.o.use_graph) {
+void sweeps(Handle& h, int trans, bool graph) {
+  if (!h.o.use_graph || !graph) {
     run_ops(h, h.sops[trans][0]);
     run_ops(h, h.sops[trans][1]);
     return;
@@ -495,10 +495,10 @@ void sweeps(Handle& h, int trans) {
   HIP_CHECK(hipGraphLaunch(h.gexec[trans], h.st));
 }
 
-void apply_inverse(Handle& h, int trans, const double* x, double* yout) {
+void apply_inverse(Handle& h, int trans, const double* x, double* yout, bool graph) {
   const int n = h.P.n;
   launch_gather(h.yws, x, h.d_perm, n, h.st);
-  sweeps(h, trans);
+  sweeps(h, trans, graph);
   launch_gather(yout, h.yws, h.d_iperm, n, h.st);
 }
 

@@ -228,8 +228,18 @@ struct Handle {
 };
 
 void numeric_factor(Handle& h);
-void apply_inverse(Handle& h, int trans, const double* x, double* y);
+// y = M^{-1} x or M^{-T} x; graph = false keeps the sweeps eager even when
+// use_graph is set (no capture, nothing allocated)
+void apply_inverse(Handle& h, int trans, const double* x, double* y, bool graph = true);
 void spmv(Handle& h, int trans, const double* x, double* y, double alpha, double beta);
+// the outer solver of the options on one right-hand side (device b, x):
+// work vectors from the handle's arena (ws null) or carved from ws (wscap
+// doubles; the sweeps then run eagerly); returns HSSMF_OK / HSSMF_ENOCONV,
+// throws Error otherwise
+int outer_solve(Handle& h, int trans, const double* b, double* x, hssmf_info* info, double* ws = nullptr,
+                size_t wscap = 0);
+// doubles of workspace outer_solve takes for n unknowns under options o
+size_t outer_workspace(const hssmf_opts& o, int64_t n);
 double dnrm2(Handle& h, const double* x, int n);
 
 // device helpers shared by factor and solve

@@ -20,7 +20,7 @@ EXPORTS = ["hssmf_default_opts", "hssmf_factor", "hssmf_refactor", "hssmf_apply"
            "hssmf_solve_transpose", "hssmf_adjoint", "hssmf_stats_get", "hssmf_hss_ranks",
            "hssmf_last_failed_front", "hssmf_destroy", "hssmf_strerror", "hssmf_profile_enable",
            "hssmf_profile_read", "hssmf_factor_batch", "hssmf_systems", "hssmf_measure_peaks",
-           "hssmf_refactor_device"]
+           "hssmf_refactor_device", "hssmf_solve_batch"]
 KCLASS = {"id": 0, "gemm64": 1, "gemmlp": 2, "lupanel": 3}
 
 
@@ -31,9 +31,12 @@ class HssmfError(RuntimeError):
         self.front = front
 
 
+MEM_HOST, MEM_DEVICE = 0, 1
+
+
 class CSRArg(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("rowptr", ctypes.c_void_p), ("colind", ctypes.c_void_p),
-                ("val", ctypes.c_void_p)]
+                ("val", ctypes.c_void_p), ("mem", ctypes.c_int32)]
 
 
 class OrderingArg(ctypes.Structure):
@@ -47,7 +50,7 @@ class Opts(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("gemm_prec", ctypes.c_int32), ("outer", ctypes.c_int32),
                 ("restart", ctypes.c_int32), ("tol", ctypes.c_double), ("max_it", ctypes.c_int32),
                 ("id_kernel", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("gemm_tile", ctypes.c_int32)]
+                ("gemm_tile", ctypes.c_int32), ("abs_tol", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -84,8 +87,9 @@ def load():
         L.hssmf_refactor.argtypes = [vp, vp]
         L.hssmf_refactor_device.argtypes = [vp, vp]
         L.hssmf_apply.argtypes = [vp, i32, vp, vp]
-        L.hssmf_solve.argtypes = [vp, vp, vp, ctypes.POINTER(Info)]
-        L.hssmf_solve_transpose.argtypes = [vp, vp, vp, ctypes.POINTER(Info)]
+        L.hssmf_solve.argtypes = [vp, i32, vp, vp, ctypes.POINTER(Info)]
+        L.hssmf_solve_transpose.argtypes = [vp, i32, vp, vp, ctypes.POINTER(Info)]
+        L.hssmf_solve_batch.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(Info)]
         L.hssmf_adjoint.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(Info)]
         L.hssmf_stats_get.argtypes = [vp, ctypes.POINTER(Stats)]
         L.hssmf_hss_ranks.argtypes = [vp, vp, i32]
@@ -144,7 +148,7 @@ def default_opts(**kw):
         if k == "outer" and isinstance(v, str):
             v = OUTER[v]
         if k == "id_kernel" and isinstance(v, str):
-            v = {"stepwise": 0, "cooperative": 1}[v]
+            v = {"stepwise": 0, "cooperative": 1, "resident": 2}[v]
         if not hasattr(o, k):
             raise KeyError(k)
         setattr(o, k, v)
@@ -169,14 +173,16 @@ def _args(A, ordering, keep):
             np.ascontiguousarray(ordering.parent, dtype=np.int32))
     keep.append(arrs)
     rp, ci, va, pe, sp, pa = arrs
-    return (CSRArg(int(A.n), rp.ctypes.data, ci.ctypes.data, va.ctypes.data),
+    return (CSRArg(int(A.n), rp.ctypes.data, ci.ctypes.data, va.ctypes.data, MEM_HOST),
             OrderingArg(pe.ctypes.data, len(pa), sp.ctypes.data, pa.ctypes.data))
 
 
 class Factorization:
-    """hssmf_factor on host CSR / ordering arrays; solves on CUDA tensors."""
+    """hssmf_factor on CSR / ordering arrays; solves on CUDA tensors or host
+    arrays.  device_csr=True hands the CSR arrays over in device memory
+    (hssmf_csr.mem = HSSMF_MEM_DEVICE)."""
 
-    def __init__(self, A, ordering, opts=None, stream=None, **kw):
+    def __init__(self, A, ordering, opts=None, stream=None, device_csr=False, **kw):
         import torch
         self._torch = torch
         self.lib = load()
@@ -184,6 +190,11 @@ class Factorization:
         self.nnz = int(A.rowptr[-1])
         self._keep = []
         csr, ordg = _args(A, ordering, self._keep)
+        if device_csr:
+            dev = [torch.tensor(np.asarray(a), device="cuda") for a in (A.rowptr, A.colind, A.val)]
+            dev = [dev[0].to(torch.int64), dev[1].to(torch.int32), dev[2].to(torch.float64)]
+            self._keep.append(dev)
+            csr = CSRArg(int(A.n), dev[0].data_ptr(), dev[1].data_ptr(), dev[2].data_ptr(), MEM_DEVICE)
         self.opts = opts if opts is not None else default_opts(**kw)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
@@ -235,23 +246,40 @@ class Factorization:
         self._check(self.lib.hssmf_apply(self.h, int(bool(trans)), _ptr(x), _ptr(y)), "hssmf_apply")
         return y
 
-    def solve(self, b, allow_noconv=False):
+    def _solve(self, fn, what, b, allow_noconv):
+        """b: float64 CUDA tensor or numpy array of n entries (one right-hand
+        side) or n x nrhs (columns = right-hand sides); the result has b's
+        kind and shape.  Returns (x, info) for one right-hand side and
+        (x, [info, ...]) for several."""
         torch = self._torch
-        _dev_f64(b, self.n, torch)
-        x = torch.empty_like(b)
-        info = Info()
-        rc = self.lib.hssmf_solve(self.h, _ptr(b), _ptr(x), ctypes.byref(info))
-        self._check(rc, "hssmf_solve", allow_noconv)
-        return x, info
+        if isinstance(b, torch.Tensor):
+            if not (b.dtype == torch.float64 and b.shape[0] == self.n and b.dim() in (1, 2)):
+                raise ValueError(f"expected float64 with {self.n} rows")
+            many = b.dim() == 2
+            bc = b.t().contiguous() if many else b.contiguous()   # columns back to back
+            xc = torch.empty_like(bc)
+            ptr_b, ptr_x = bc.data_ptr(), xc.data_ptr()
+        else:
+            b = np.asarray(b, dtype=np.float64)
+            if b.shape[0] != self.n or b.ndim not in (1, 2):
+                raise ValueError(f"expected {self.n} rows")
+            many = b.ndim == 2
+            bc = np.ascontiguousarray(b.T if many else b)
+            xc = np.empty_like(bc)
+            ptr_b, ptr_x = bc.ctypes.data, xc.ctypes.data
+        nrhs = bc.shape[0] if many else 1
+        infos = (Info * max(nrhs, 1))()
+        rc = fn(self.h, nrhs, ctypes.c_void_p(ptr_b), ctypes.c_void_p(ptr_x), infos)
+        self._check(rc, what, allow_noconv)
+        if many:
+            return xc.T, [infos[j] for j in range(nrhs)]
+        return xc, infos[0]
+
+    def solve(self, b, allow_noconv=False):
+        return self._solve(self.lib.hssmf_solve, "hssmf_solve", b, allow_noconv)
 
     def solve_transpose(self, g, allow_noconv=False):
-        torch = self._torch
-        _dev_f64(g, self.n, torch)
-        lam = torch.empty_like(g)
-        info = Info()
-        rc = self.lib.hssmf_solve_transpose(self.h, _ptr(g), _ptr(lam), ctypes.byref(info))
-        self._check(rc, "hssmf_solve_transpose", allow_noconv)
-        return lam, info
+        return self._solve(self.lib.hssmf_solve_transpose, "hssmf_solve_transpose", g, allow_noconv)
 
     def adjoint(self, x, g):
         torch = self._torch
@@ -321,6 +349,36 @@ class BatchFactorization(Factorization):
 
     def split(self, x):
         return [x[a:b] for a, b in zip(self.offsets[:-1], self.offsets[1:])]
+
+    def solve_batch(self, bs, allow_noconv=False):
+        """hssmf_solve_batch: bs = one right-hand side per system (float64
+        CUDA tensors or numpy arrays, each of the system's size); returns
+        ([x_s], info) with x_s of the same kind as b_s."""
+        torch = self._torch
+        sizes = [b - a for a, b in zip(self.offsets[:-1], self.offsets[1:])]
+        if len(bs) != len(sizes):
+            raise ValueError(f"expected {len(sizes)} right-hand sides")
+        keep, xs = [], []
+        for b, m in zip(bs, sizes):
+            if isinstance(b, torch.Tensor):
+                b = b.contiguous()
+                if b.dtype != torch.float64 or b.numel() != m:
+                    raise ValueError("bad right-hand side")
+                x = torch.empty_like(b)
+                keep.append((b, b.data_ptr(), x.data_ptr()))
+            else:
+                b = np.ascontiguousarray(b, dtype=np.float64)
+                if b.size != m:
+                    raise ValueError("bad right-hand side")
+                x = np.empty_like(b)
+                keep.append((b, b.ctypes.data, x.ctypes.data))
+            xs.append(x)
+        pb = (ctypes.c_void_p * len(keep))(*[k[1] for k in keep])
+        px = (ctypes.c_void_p * len(keep))(*[k[2] for k in keep])
+        info = Info()
+        rc = self.lib.hssmf_solve_batch(self.h, pb, px, ctypes.byref(info))
+        self._check(rc, "hssmf_solve_batch", allow_noconv)
+        return xs, info
 
     def hss_ranks_by_system(self):
         """hss_ranks() with the fronts renumbered per system:

@@ -51,7 +51,7 @@ def test_refactor_device_rejects_null_arguments(lib):
     assert lib.hssmf_refactor_device(None, None) == H.HSSMF_EINVAL
 
 
-def _call_factor(A_rowptr, A_col, A_val, perm, sep, par, n, opts=None):
+def _call_factor(A_rowptr, A_col, A_val, perm, sep, par, n, opts=None, mem=H.MEM_HOST):
     L = H.load()
     rp = np.ascontiguousarray(A_rowptr, dtype=np.int64)
     ci = np.ascontiguousarray(A_col, dtype=np.int32)
@@ -59,7 +59,7 @@ def _call_factor(A_rowptr, A_col, A_val, perm, sep, par, n, opts=None):
     pe = np.ascontiguousarray(perm, dtype=np.int32)
     sp = np.ascontiguousarray(sep, dtype=np.int32)
     pa = np.ascontiguousarray(par, dtype=np.int32)
-    csr = H.CSRArg(n, rp.ctypes.data, ci.ctypes.data, va.ctypes.data)
+    csr = H.CSRArg(n, rp.ctypes.data, ci.ctypes.data, va.ctypes.data, mem)
     od = H.OrderingArg(pe.ctypes.data, len(pa), sp.ctypes.data, pa.ctypes.data)
     o = opts if opts is not None else H.default_opts()
     h = ctypes.c_void_p()
@@ -112,7 +112,8 @@ def test_rejects_separator_violation(lib, small):
 
 def test_rejects_bad_options(lib, small):
     A, o = small
-    for field, val in (("leaf_size", 0), ("d0", 0), ("dd", 0), ("restart", 0), ("gemm_prec", 7), ("rel_tol", -1.0), ("id_kernel", 5), ("use_graph", 2), ("gemm_tile", 96)):
+    for field, val in (("leaf_size", 0), ("d0", 0), ("dd", 0), ("restart", 0), ("gemm_prec", 7), ("rel_tol", -1.0), ("id_kernel", 5), ("use_graph", 2), ("gemm_tile", 96),
+                       ("abs_tol", -1e-3)):
         opts = H.default_opts(**{field: val})
         assert _call_factor(A.rowptr, A.colind, A.val, o.perm, o.sep_ptr, o.parent, A.n, opts) == H.HSSMF_EINVAL
 
@@ -139,3 +140,20 @@ def test_batch_rejects_bad_input(lib, small):
         if h:
             L.hssmf_destroy(h)
         assert rc == H.HSSMF_EINVAL
+
+
+def test_rejects_unknown_memory_kind(lib, small):
+    """hssmf_csr.mem is HSSMF_MEM_HOST or HSSMF_MEM_DEVICE; anything else is
+    refused before the arrays are read."""
+    A, o = small
+    assert _call_factor(A.rowptr, A.colind, A.val, o.perm, o.sep_ptr, o.parent, A.n, mem=5) == H.HSSMF_EINVAL
+
+
+def test_solve_family_rejects_bad_arguments(lib):
+    """Null handles, negative right-hand-side counts and null vectors are
+    refused on the host."""
+    buf = np.zeros(4)
+    p = ctypes.c_void_p(buf.ctypes.data)
+    for fn in (lib.hssmf_solve, lib.hssmf_solve_transpose):
+        assert fn(None, 1, p, p, None) == H.HSSMF_EINVAL
+    assert lib.hssmf_solve_batch(None, None, None, None) == H.HSSMF_EINVAL

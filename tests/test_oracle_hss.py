@@ -133,6 +133,29 @@ def test_epsilon_rank_rule(rng, eps):
     assert dg[k] <= eps
 
 
+@pytest.mark.parametrize("atol", [3e-3, 3e-7, 3e-11])
+def test_absolute_rank_rule(rng, atol):
+    """The absolute tolerance: the rank stops at the first i with
+    |R_{i+1,i+1}| <= max(eps |R_11|, atol).  The columns here are orthogonal
+    with norms 10^0, 10^-2, ..., so column-pivoted QR takes them in order of
+    norm and |R_ii| equals the i-th norm (the projections change nothing): the
+    rank is exactly the number of norms above atol, with eps far below.  A
+    matrix whose largest column is at or below atol has rank 0."""
+    n = 40
+    nrm = 10.0 ** -np.arange(0, 24, 2.0)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, len(nrm))))
+    Y = Q * nrm
+    Y = Y[:, rng.permutation(len(nrm))]
+    _, R, k = H.cpqr_eps(Y, 1e-20, atol)
+    assert k == int(np.sum(nrm > atol))
+    assert np.allclose(np.abs(np.diag(R))[:k], nrm[:k], rtol=1e-12, atol=0)
+    _, _, k0 = H.cpqr_eps(Y * (atol / 2.0), 1e-20, atol)
+    assert k0 == 0
+    # the relative rule still binds when it is the larger of the two
+    _, _, k2 = H.cpqr_eps(Y, 3e-5, 3e-11)
+    assert k2 == 3
+
+
 def test_omega_annihilates_interpolative_basis(rng):
     """Omega U = [0; I] exactly for U = Pi [I; E] (Sec. 2.3)."""
     m, r = 11, 4

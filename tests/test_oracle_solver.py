@@ -241,3 +241,63 @@ def test_adjoint_matches_dense(rng):
             Lv.append(np.sum((xx - xs) ** 2))
         fd = (Lv[0] - Lv[1]) / (2 * h)
         assert abs(fd - dval[e]) <= 1e-5 * max(1.0, abs(fd))
+
+
+def test_work_counts_dense_fronts_follow_the_table2_model():
+    """The algorithmic flop count of an all-dense factorization equals the
+    geometric model that reproduces Table 2's multifrontal flops (the same
+    fronts, counted from box geometry only)."""
+    from oracle import work
+    from tests.test_oracle_inputs import _mf_flop_model
+    for dims, leaf in (((24, 24), 4), ((10, 9, 8), 2)):
+        A = P.poisson2d(*dims) if len(dims) == 2 else P.poisson3d(*dims)
+        o = P.geometric_nd(dims, leaf)
+        fac = mf.factor(A, o, mf.Options())
+        w = work.factorization_work(fac)
+        assert abs(w["dense_lu"]["flops"] / _mf_flop_model(dims, leaf) - 1) < 1e-12
+        assert w["sampling"]["flops"] == w["id"]["flops"] == 0.0
+
+
+def test_work_counts_id_closed_forms():
+    """The ID count 4dmk - 2k^2(d+m) + 4/3 k^3 + k^2(m-k) reduces to the
+    textbook Householder QR counts: 4/3 n^3 for a full-rank n x n block
+    (k = m = d), 2 d m^2 - 2/3 m^3 for k = m < d; and every attempt of the
+    adaptive loop is counted (a node that failed once contributes twice)."""
+    from oracle import hss as H
+    from oracle import work
+    from oracle.symbolic import hss_tree
+
+    class Op:
+        def __init__(self, M):
+            self.M = M
+
+        def sample(self, R):
+            return self.M @ R, self.M.T @ R
+
+        def extract(self, I, J):
+            return self.M[np.ix_(np.asarray(I, int), np.asarray(J, int))]
+
+    rng = np.random.default_rng(3)
+    n = 40
+    M = rng.standard_normal((n, n)) + n * np.eye(n)
+    nodes, k, q = hss_tree(n, 0, 20)
+    gen = np.random.default_rng(4)
+    Hs = H.compress(Op(M), nodes, len(nodes) - 1, lambda c0, nc: gen.standard_normal((n, nc)), 1e-14, 8, 8, 2, 200)
+    # closed forms: 4/3 n^3 for a full-rank square block, 2 d m^2 - 2/3 m^3
+    # for a full-column-rank d x m block, and the truncated count is the
+    # full one minus the columns it skips
+    assert work.id_flops(30, 30, 30) == pytest.approx(4 / 3 * 30 ** 3)
+    assert work.id_flops(50, 20, 20) == pytest.approx(2 * 50 * 20 ** 2 - 2 / 3 * 20 ** 3)
+    assert work.id_flops(50, 20, 0) == 0.0
+    seen = 0
+    for (t, d, mr, kr, mc, kc) in Hs.stats["log"]["ids"]:
+        for m, kk in ((mr, kr), (mc, kc)):
+            if kk == m < d:
+                seen += 1
+                assert work.id_flops(d, m, kk) == pytest.approx(2 * d * m * m - 2 / 3 * m ** 3)
+    assert seen > 0
+    # full-rank 20-row leaves start at d = 8: they fail (k = 8 > d - p) and are
+    # redone after each growth round until d >= 20 + p
+    ids = Hs.stats["log"]["ids"]
+    leaf_attempts = [e for e in ids if nodes[e[0]].leaf]
+    assert len(leaf_attempts) > 2 and Hs.stats["rounds"] >= 2
