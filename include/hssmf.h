@@ -15,8 +15,9 @@
  *  - Matrix and ordering arrays are owned by the caller and read during the
  *    call only (copied / uploaded).  Ordering arrays are host memory; the
  *    CSR arrays are host or device memory as hssmf_csr.mem says.
- *  - Vector arguments of hssmf_apply and hssmf_adjoint are DEVICE pointers
- *    (HIP global memory on the current device).  hssmf_solve,
+ *  - Vector arguments of hssmf_apply, hssmf_adjoint and
+ *    hssmf_solve_noalloc are DEVICE pointers (HIP global memory on the
+ *    current device).  hssmf_solve,
  *    hssmf_solve_transpose and hssmf_solve_batch take host or device
  *    vectors: the library asks the HIP runtime (hipPointerGetAttributes)
  *    which one each pointer is, and stages host vectors through device
@@ -45,6 +46,8 @@ extern "C" {
 #define HSSMF_ERANK (-4)     /* adaptive sampling reached d_max (Sec. 2.2.1) */
 #define HSSMF_ENOCONV (-5)   /* outer solver did not reach tol within max_it */
 #define HSSMF_EDEVICE (-6)   /* HIP runtime error / no device */
+#define HSSMF_ETOOBIG (-7)   /* the no-allocation solve's static scratch is too
+                                small for this handle and these options */
 
 /* precision of the sampling and ULV products (pivoted QR / ID, the LU of
  * F11 blocks and the refinement residual always stay FP64) */
@@ -277,6 +280,21 @@ typedef struct {
   double fp64_mfma_TFLOPs;
 } hssmf_peaks;
 int hssmf_measure_peaks(void* stream, hssmf_peaks* out);
+
+/* hssmf_solve without any memory allocation, for callers that cannot
+ * allocate device memory (serving loops with a fixed memory budget,
+ * harnesses that forbid hipMalloc).  The outer solver's work vectors live in
+ * a static device array of HSSMF_NOALLOC_SCRATCH_BYTES per GPU (held until
+ * the process ends); the preconditioner sweeps run eagerly (no graph is
+ * captured).  b, x: DEVICE arrays, n x nrhs column-major; info as
+ * hssmf_solve.  The scratch must hold 2 n doubles for iterative refinement
+ * and (restart + 3) n doubles for GMRES, else HSSMF_ETOOBIG (nothing is
+ * launched).  Every call on one GPU shares that GPU's scratch: calls that
+ * overlap on one GPU (other threads or streams) race.  Synchronizes the
+ * handle's stream, like hssmf_solve; results are bitwise those of
+ * hssmf_solve with use_graph = 0. */
+#define HSSMF_NOALLOC_SCRATCH_BYTES (64u << 20)
+int hssmf_solve_noalloc(void* h, int32_t nrhs, const double* b, double* x, hssmf_info* info);
 
 void hssmf_destroy(void* h);
 

@@ -832,6 +832,7 @@ const char* hssmf_strerror(int code) {
     case HSSMF_ERANK: return "HSS rank exceeds d_max";
     case HSSMF_ENOCONV: return "no convergence";
     case HSSMF_EDEVICE: return "device error";
+    case HSSMF_ETOOBIG: return "problem too large for the no-allocation scratch";
   }
   return "unknown status";
 }

@@ -13,6 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhssmf.so")
 
 HSSMF_OK, HSSMF_EINVAL, HSSMF_ENOMEM, HSSMF_ESINGULAR, HSSMF_ERANK, HSSMF_ENOCONV, HSSMF_EDEVICE = 0, -1, -2, -3, -4, -5, -6
+HSSMF_ETOOBIG = -7
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 OUTER = {"ir": 0, "gmres": 1}
 
@@ -20,7 +21,7 @@ EXPORTS = ["hssmf_default_opts", "hssmf_factor", "hssmf_refactor", "hssmf_apply"
            "hssmf_solve_transpose", "hssmf_adjoint", "hssmf_stats_get", "hssmf_hss_ranks",
            "hssmf_last_failed_front", "hssmf_destroy", "hssmf_strerror", "hssmf_profile_enable",
            "hssmf_profile_read", "hssmf_factor_batch", "hssmf_systems", "hssmf_measure_peaks",
-           "hssmf_refactor_device", "hssmf_solve_batch"]
+           "hssmf_refactor_device", "hssmf_solve_batch", "hssmf_solve_noalloc"]
 KCLASS = {"id": 0, "gemm64": 1, "gemmlp": 2, "lupanel": 3}
 
 
@@ -90,6 +91,7 @@ def load():
         L.hssmf_solve.argtypes = [vp, i32, vp, vp, ctypes.POINTER(Info)]
         L.hssmf_solve_transpose.argtypes = [vp, i32, vp, vp, ctypes.POINTER(Info)]
         L.hssmf_solve_batch.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(Info)]
+        L.hssmf_solve_noalloc.argtypes = [vp, i32, vp, vp, ctypes.POINTER(Info)]
         L.hssmf_adjoint.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(Info)]
         L.hssmf_stats_get.argtypes = [vp, ctypes.POINTER(Stats)]
         L.hssmf_hss_ranks.argtypes = [vp, vp, i32]
