@@ -34,12 +34,12 @@ def refine(matvec, prec, b, tol, max_it=50):
     raise NoConvergence(x, hist[-1], max_it)
 
 
-def gmres(matvec, prec, b, tol, restart=30, max_it=300):
+def gmres(matvec, prec, b, tol, restart=30, max_it=300, x0=None):
     """Left-preconditioned restarted GMRES(m) with modified Gram-Schmidt
-    Arnoldi and Givens rotations, x0 = 0."""
+    Arnoldi and Givens rotations, x0 = 0 unless given."""
     n = b.shape[0]
     nb = np.linalg.norm(b)
-    x = np.zeros(n)
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
     its = 0
     hist = []
     while its < max_it:
@@ -95,3 +95,35 @@ def gmres(matvec, prec, b, tol, restart=30, max_it=300):
         if converged:
             break
     raise NoConvergence(x, hist[-1] if hist else np.inf, its)
+
+
+def refine_or_gmres(matvec, prec, b, tol, max_it=50, restart=30):
+    """Iterative refinement that hands over to GMRES(restart) when it
+    stagnates: once the relative residual has failed to fall below 0.9 times
+    the previous one on two consecutive steps, GMRES continues from the
+    current iterate with the same preconditioner (a weak preconditioner,
+    e.g. an HSS factorization at a large tolerance, need not be a
+    contraction, which refinement requires, while GMRES only needs it to
+    cluster the spectrum; Sec. 4.6).  Returns (x, iterations, history,
+    switched): iterations counts refinement steps plus GMRES iterations."""
+    nb = np.linalg.norm(b)
+    x = prec(b)
+    hist = []
+    slow = 0
+    for it in range(max_it + 1):
+        r = b - matvec(x)
+        rel = np.linalg.norm(r) / nb
+        if hist and rel > 0.9 * hist[-1]:
+            slow += 1
+        else:
+            slow = 0
+        hist.append(rel)
+        if rel <= tol:
+            return x, it, hist, False
+        if slow >= 2 or it == max_it:
+            break
+        x = x + prec(r)
+    if slow < 2:
+        raise NoConvergence(x, hist[-1], max_it)
+    xg, its, gh = gmres(matvec, prec, b, tol, restart=restart, max_it=max_it, x0=x)
+    return xg, it + its, hist + gh, True

@@ -134,13 +134,16 @@ class Factorization:
     opts: Options
 
 
-def factor(A, ordering, opts, stop_after=None):
+def factor(A, ordering, opts, stop_after=None, record=None):
     """Numeric multifrontal factorization, fronts in postorder (Sec. 3.2).
     ``stop_after`` ends the loop after that front id (a bounded sample of the
     work for timing; the result is then not a usable factorization).
     Dense fronts: assembly, extend-add, partial LU.  HSS fronts: random
     matrix keyed by original row id, samples by skinny extend-add, Alg. 1
-    with adaptive rank, ULV of F11 and Theta^*, Phi (Sec. 4)."""
+    with adaptive rank, ULV of F11 and Theta^*, Phi (Sec. 4).
+    ``record``: None, or a dict that receives, per HSS front id, the front
+    operator, its random-matrix function, the HSS generators, Theta^*, Phi
+    and the update (for stage-by-stage comparisons)."""
     perm = np.asarray(ordering.perm, dtype=np.int64)
     Ap = permute_csr(A, perm)
     fronts = analyse(Ap, ordering.sep_ptr, ordering.parent)
@@ -169,6 +172,9 @@ def factor(A, ordering, opts, stop_after=None):
             if q >= 0:
                 data["ops"] = hs.Front11Ops(H, k, q)
                 updates[f.id] = HSSUpdate(H, q, Theta, Phi)
+            if record is not None:
+                record[f.id] = dict(op=op, rand=rand, H=H, d=H.stats["d"], Theta=Theta, Phi=Phi,
+                                    update=updates.get(f.id))
             factors.append(FrontFactor("hss", data))
         else:
             sub = Ap[idx][:, idx].toarray()

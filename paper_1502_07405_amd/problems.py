@@ -132,6 +132,44 @@ def convdiff2d(n, wx, wy):
     return _stencil((n, n), 4.0 + h * (abs(wx) + abs(wy)), coeff)
 
 
+def _velocity(dims, coords):
+    """The velocity fields of the paper's convection-diffusion problems
+    (Sec. 6.1): in 2D v = (x(1-x)(2y-1), y(1-y)(2x-1)); in 3D
+    v = (2x(1-x)(2y-1)z, -y(1-y)(2x-1), -(2x-1)(2y-1)z(1-z))."""
+    if len(dims) == 2:
+        x, y = coords
+        return [x * (1 - x) * (2 * y - 1), y * (1 - y) * (2 * x - 1)]
+    x, y, z = coords
+    return [2 * x * (1 - x) * (2 * y - 1) * z, -y * (1 - y) * (2 * x - 1), -(2 * x - 1) * (2 * y - 1) * z * (1 - z)]
+
+
+def convdiff_paper(n, ndim=2, nu=1e-4):
+    """The paper's C2D / C3D problems (Sec. 6.1): -nu Lap(u) + v.grad(u) = f on
+    the unit square / cube with homogeneous Dirichlet boundary, n interior
+    points per side (h = 1/(n+1), point i at (i+1) h), first-order upwind
+    differences for the convection and the (2 ndim + 1)-point Laplacian,
+    scaled by h^2: centre 2 ndim nu + h sum_a |v_a|, the upwind neighbour
+    along axis a -nu - h |v_a|, the downwind one -nu.  nu = 1e-4 as in the
+    paper, so convection dominates (cell Peclet numbers up to about 25 at
+    n = 100)."""
+    dims = (n,) * ndim
+    h = 1.0 / (n + 1)
+    N = n ** ndim
+    idx = np.arange(N)
+    coords = []
+    rem = idx.copy()
+    for _ in dims:
+        coords.append((rem % n + 1) * h)
+        rem = rem // n
+    v = _velocity(dims, coords)
+
+    def coeff(ax, sign):
+        up = (v[ax] >= 0) if sign < 0 else (v[ax] < 0)
+        return np.where(up, -nu - h * np.abs(v[ax]), -nu)
+
+    return _stencil(dims, 2 * ndim * nu + h * sum(np.abs(va) for va in v), coeff)
+
+
 def smoothed_log_kappa(n, seed=3, sigma=0.5):
     """log(kappa) iid N(0, sigma^2) from ``default_rng(seed)``, then a 3x3x3 box
     mean over the in-domain neighbours.  Returns (kappa, rng) so that the caller

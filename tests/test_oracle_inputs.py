@@ -190,3 +190,36 @@ def test_convdiff_batch_recipe():
     assert sum(len(o.parent) for _, o, _ in systems) == 140346
     for A, o, b in systems[:8]:
         assert int((o.parent == -1).sum()) == 1 and b.shape == (A.n,)
+
+
+@pytest.mark.parametrize("ndim,n", [(2, 23), (3, 9)])
+def test_paper_convection_diffusion_is_exact_on_linear_functions(ndim, n):
+    """C2D / C3D (Sec. 6.1): first-order upwind differences are exact on
+    linear functions, and the Laplacian vanishes on them, so at every point
+    whose neighbours are all interior, (A u)/h^2 = v_a for u = the a-th
+    coordinate; the matrix is a (weakly) diagonally dominant M-matrix."""
+    A = P.convdiff_paper(n, ndim)
+    S = A.to_scipy()
+    h = 1.0 / (n + 1)
+    N = n ** ndim
+    idx = np.arange(N)
+    coords, rem = [], idx.copy()
+    for _ in range(ndim):
+        coords.append(rem % n)
+        rem = rem // n
+    inner = np.all([(c > 0) & (c < n - 1) for c in coords], axis=0)
+    x = [(c + 1) * h for c in coords]
+    if ndim == 2:
+        v = [x[0] * (1 - x[0]) * (2 * x[1] - 1), x[1] * (1 - x[1]) * (2 * x[0] - 1)]
+    else:
+        v = [2 * x[0] * (1 - x[0]) * (2 * x[1] - 1) * x[2], -x[1] * (1 - x[1]) * (2 * x[0] - 1),
+             -(2 * x[0] - 1) * (2 * x[1] - 1) * x[2] * (1 - x[2])]
+    for a in range(ndim):
+        Au = S @ x[a] / h ** 2
+        assert np.allclose(Au[inner], v[a][inner], rtol=0, atol=1e-9)
+    import scipy.sparse as sp
+    D = S.diagonal()
+    C = S.tocoo()
+    assert np.all(C.data[C.row != C.col] <= 0) and np.all(D > 0)
+    assert np.all(D + np.asarray((S - sp.diags(D)).sum(axis=1)).ravel() >= -1e-15)
+    assert abs(S - S.T).max() > 0   # not symmetric

@@ -301,3 +301,24 @@ def test_work_counts_id_closed_forms():
     ids = Hs.stats["log"]["ids"]
     leaf_attempts = [e for e in ids if nodes[e[0]].leaf]
     assert len(leaf_attempts) > 2 and Hs.stats["rounds"] >= 2
+
+
+def test_refinement_hands_over_to_gmres_when_it_stagnates():
+    """Refinement x += M^-1 r diverges when M^-1 = 0.3 I on a 2D Laplacian
+    (|1 - 0.3 lambda_max| ~ 1.4 > 1): after two steps whose residual does not
+    fall below 0.9 times the previous one it hands over to GMRES(30), which
+    still reaches the dense solution.  With an exact preconditioner it
+    converges at once and never switches."""
+    A = P.poisson2d(8)
+    S = A.to_scipy()
+    Ad = S.toarray()
+    b = np.random.default_rng(11).standard_normal(A.n)
+    xr = np.linalg.solve(Ad, b)
+    x, its, hist, sw = krylov.refine_or_gmres(lambda v: S @ v, lambda r: 0.3 * r, b, 1e-12, max_it=400)
+    assert sw
+    k = next(i for i in range(2, len(hist)) if hist[i] > 0.9 * hist[i - 1] and hist[i - 1] > 0.9 * hist[i - 2])
+    assert np.linalg.norm(x - xr) <= 1e-10 * np.linalg.norm(xr)
+    assert np.linalg.norm(b - S @ x) <= 1e-12 * np.linalg.norm(b)
+    assert k == 2 and its > k
+    x2, its2, _, sw2 = krylov.refine_or_gmres(lambda v: S @ v, lambda r: np.linalg.solve(Ad, r), b, 1e-12)
+    assert not sw2 and its2 <= 1
