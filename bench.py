@@ -80,18 +80,54 @@ def cpu_baseline(A, order, opts):
                       f"(lower bound)"}
 
 
-KCLASSES = ("id", "gemm64", "gemmlp", "lupanel")
+KCLASSES = ("id", "gemm64", "gemmlp", "lupanel", "idres")
+FP32_MFMA_PEAK_TFLOPS = 157.3
+# stages whose products run on the FP32 matrix cores in the mixed mode (the
+# sampling products and the low-rank Schur update); the rest is FP64
+LP_STAGES = ("sampling", "schur")
+
+
+def step_roofline(work, prec, applies, spmvs, t_meas):
+    """Whole-step roofline from the oracle's algorithmic counts
+    (tests/golden/poisson3d_64_work.json): T_roof = sum over stages of
+    max(flops / peak of the stage's precision, bytes / HBM peak), with the
+    solve as `applies` applications of M^-1 and `spmvs` sparse products."""
+    stages = {}
+    t_roof = 0.0
+    flops = 0.0
+    for st, w in work["factorization"].items():
+        peak = (FP32_MFMA_PEAK_TFLOPS if (prec != "fp64" and st in LP_STAGES) else FP64_PEAK_TFLOPS) * 1e12
+        t = max(w["flops"] / peak, w["bytes"] / HBM_PEAK_BPS)
+        stages[st] = {"flops": w["flops"], "bytes": w["bytes"], "t_roof_ms": t * 1e3,
+                      "bound": "hbm" if w["bytes"] / HBM_PEAK_BPS > w["flops"] / peak else "flops"}
+        t_roof += t
+        flops += w["flops"]
+    ts = (applies * work["apply_bytes"] + spmvs * work["spmv_bytes"]) / HBM_PEAK_BPS
+    stages["solve"] = {"bytes": applies * work["apply_bytes"] + spmvs * work["spmv_bytes"], "t_roof_ms": ts * 1e3,
+                       "bound": "hbm"}
+    t_roof += ts
+    return {"t_roof_ms": t_roof * 1e3, "t_meas_ms": t_meas * 1e3, "frac": t_roof / t_meas,
+            "gflops": flops / t_meas / 1e9, "algorithmic_flops": flops, "stages": stages,
+            "counts": "oracle-counted algorithmic work of the FP64 factorization (tests/golden/poisson3d_64_work.json)"}
+
+
 KERNEL_NAME = {"id": "id_step_kernel (pivot steps of the column-pivoted QR behind the IDs)",
                "gemm64": "gemm_f64_kernel (batched FP64 MFMA GEMM)",
                "gemmlp": "gemm_lp_kernel (batched FP32/BF16 MFMA GEMM, FP32 accumulation)",
-               "lupanel": "lu_panel_kernel (dense LU panels)"}
-# what bounds each class, and the MI355X peak it is priced against (TFLOP/s)
+               "lupanel": "lu_panel_kernel (dense LU panels)",
+               "idres": "id_res_kernel (every pivot step of an ID pass in one launch, candidates in registers)"}
+# what bounds each class, and the MI355X peak it is priced against (TFLOP/s).
+# The pivot steps: every sample block is read once and its candidates stay in
+# registers (at least k/2 flops per byte), so the roofline class is the FP64
+# vector ALU; in practice each step is a chain of dependent reductions and
+# barriers, so the kernel runs far below that roof.
 BOUND = {"id": ("alu", FP64_PEAK_TFLOPS), "gemm64": ("mfma", FP64_PEAK_TFLOPS),
-         "gemmlp": ("mfma", None), "lupanel": ("alu", FP64_PEAK_TFLOPS)}
+         "gemmlp": ("mfma", None), "lupanel": ("alu", FP64_PEAK_TFLOPS), "idres": ("alu", FP64_PEAK_TFLOPS)}
 LP_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
 # the library's probe (hssmf_measure_peaks) that checks each published peak
 # on the device at hand: FP64 FMA loop, FP64 matrix-core loop
-MEASURED_KEY = {"id": "fp64_valu_TFLOPs", "gemm64": "fp64_mfma_TFLOPs", "gemmlp": None, "lupanel": "fp64_valu_TFLOPs"}
+MEASURED_KEY = {"id": "fp64_valu_TFLOPs", "gemm64": "fp64_mfma_TFLOPs", "gemmlp": None, "lupanel": "fp64_valu_TFLOPs",
+                "idres": "fp64_valu_TFLOPs"}
 # HBM bytes per factorization moved by the pivot-step kernel on this
 # workload, from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; each scaled
 # by its reading for a 256 MiB device copy):
@@ -183,6 +219,14 @@ def main():
     ranks = fac.hss_ranks()
     y = fac.apply(v).cpu().numpy()
     fac.close()
+    # against the FP64 oracle's stored results (same workload, same R):
+    # the preconditioner applied to v = default_rng(7), and the ranks
+    gold = os.path.join(ROOT, "tests", "golden")
+    vec = np.load(os.path.join(gold, "poisson3d_64_vectors.npz"))
+    with open(os.path.join(gold, "poisson3d_64_work.json")) as f:
+        work = json.load(f)
+    orc_ranks = [tuple(int(t) for t in ln.split()) for ln in open(os.path.join(gold, "poisson3d_64_hss_ranks.txt"))
+                 if ln.strip() and not ln.startswith("#")]
     # dominant timed kernel class and its roofline
     dom = max(prof, key=lambda k: prof[k][0])
     ms, launches, flops = prof[dom]
@@ -205,7 +249,12 @@ def main():
     roof["hbm_measured_GBps"] = pk["hbm_GBps"]
     if roof["hbm_GBps_from_traffic"] is not None and pk["hbm_GBps"] > 0:
         roof["hbm_frac_vs_measured"] = roof["hbm_GBps_from_traffic"] / pk["hbm_GBps"]
-    extra = {"measured_peaks": pk, "step_s_host_values": sec_host, "step_s_with_timing_hooks": sec_hooked, "iterations": infos[-1][0], "rel_residual": relres(x), "max_rank": st["max_rank"],
+    extra = {"vs_oracle": {
+                 "minv_v_rel_diff": float(np.linalg.norm(y - vec["minv_v"]) / np.linalg.norm(vec["minv_v"])),
+                 "rank_delta_per_front": [int(a[1] - c[1]) for a, c in zip(ranks, orc_ranks)],
+                 "final_d_delta_per_front": [int(a[3] - c[3]) for a, c in zip(ranks, orc_ranks)]},
+             "step_roofline": step_roofline(work, args.prec, infos[-1][0] + 1, infos[-1][0] + 1, sec),
+             "measured_peaks": pk, "step_s_host_values": sec_host, "step_s_with_timing_hooks": sec_hooked, "iterations": infos[-1][0], "rel_residual": relres(x), "max_rank": st["max_rank"],
              "max_d": st["max_d"], "growth_rounds": st["growth_rounds"],
              "kernel_ms_per_step": {k: prof[k][0] / args.steps for k in KCLASSES},
              "kernel_launches_per_step": {k: prof[k][1] / args.steps for k in KCLASSES},

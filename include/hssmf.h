@@ -123,6 +123,10 @@ typedef struct {
                           ID stops at |R_{i+1,i+1}| <= max(rel_tol |R_11|,
                           abs_tol) (Sec. 5.3 gives the relative rule; 0, the
                           default, keeps it alone) */
+  int32_t keep_stages; /* 1: every numeric factorization keeps copies of each
+                          HSS front's random matrix, samples and low-rank
+                          Schur factors for hssmf_front_data (device memory
+                          of O(n d + m_k u) per front); 0 (default): not */
 } hssmf_opts;
 
 /* id_kernel: STEPWISE = one launch per pivot step for each batch of IDs;
@@ -132,17 +136,23 @@ typedef struct {
  * agent-coherent memory (one launch per step otherwise); RESIDENT = every
  * pivot step of a batch in one launch with each problem's candidates in the
  * registers of as few 512-thread workgroups as hold them (one workgroup,
- * and no exchange between workgroups, for the problems that fit; up to 2560
- * samples).  All take the same pivot rule; they differ only in the order of
- * floating-point sums. */
+ * and no exchange between workgroups, for the problems that fit; passes
+ * with more than 640 samples, or with an ID of more than twice as many
+ * columns as the kernel holds sample rows per candidate, take the stepwise
+ * kernel).  All take the same
+ * pivot rule; they differ only in the order of floating-point sums. */
 #define HSSMF_ID_STEPWISE 0
 #define HSSMF_ID_COOPERATIVE 1
 #define HSSMF_ID_RESIDENT 2
 
 typedef struct {
-  int32_t iterations;    /* refinement steps or GMRES iterations */
-  double rel_residual;   /* final ||b - A x|| / ||b|| (FP64) */
-  int32_t failed_front;  /* front id for HSSMF_ESINGULAR, else -1 */
+  int32_t iterations;     /* refinement steps plus GMRES iterations */
+  double rel_residual;    /* final ||b - A x|| / ||b|| (FP64) */
+  int32_t failed_front;   /* front id for HSSMF_ESINGULAR, else -1 */
+  int32_t outer_switched; /* 1 when iterative refinement stagnated (two
+                             consecutive steps without the residual falling
+                             below 0.9 times the previous one) and handed
+                             over to GMRES(restart) from its iterate */
 } hssmf_info;
 
 typedef struct {
@@ -255,13 +265,40 @@ int hssmf_last_failed_front(void* h);
  * interpolative decompositions (one launch per step, work 4dmk - 2k^2(d+m)
  * + 4/3 k^3 per d x m problem truncated at k), 1 = FP64 batched GEMM
  * (matrix cores, 2mnk), 2 = low-precision batched GEMM (2mnk), 3 = panel
- * factorization of the blocked dense LU (m w^2 - w^3/3 per m x w panel). */
+ * factorization of the blocked dense LU (m w^2 - w^3/3 per m x w panel),
+ * 4 = the same pivot steps when every step of an ID pass runs in one
+ * launch (id_kernel = RESIDENT; the launch is bracketed by an event pair,
+ * work as for class 0). */
 #define HSSMF_KCLASS_ID 0
 #define HSSMF_KCLASS_GEMM64 1
 #define HSSMF_KCLASS_GEMMLP 2
 #define HSSMF_KCLASS_LUPANEL 3
+#define HSSMF_KCLASS_ID_RESIDENT 4
 int hssmf_profile_enable(int32_t on);
 int hssmf_profile_read(int32_t kclass, double* ms, int64_t* launches, double* flops);
+
+/* Intermediate results of one HSS front of the last numeric factorization,
+ * for checking each stage of the method on its own (diagnostics; the
+ * factorization must have been made with keep_stages = 1, except for
+ * HSSMF_STAGE_UPDATE).  Rows are the front's local indices: the separator
+ * in elimination order, then the update set in ascending new numbering.
+ *  RANDOM        R (n x d), the random matrix at the final d (Sec. 2.2.1);
+ *  SAMPLES_ROW   S^r = F R (n x d), SAMPLES_COL S^c = F^T R (Eq. FtimesR);
+ *  THETA_T       Theta^T (m_k x u) and PHI Phi (m_k x u) of the low-rank
+ *                Schur complement F21 F11^-1 F12 ~ Theta^* Phi (Sec. 4.4);
+ *  UPDATE        the update matrix F22 - Theta^* Phi (u x u) passed to the
+ *                parent.
+ * dims[0], dims[1] receive the shape; the column-major array is copied to
+ * host memory out when cap (entries) holds it, else only dims are set.
+ * EINVAL for a front that is not HSS, an unknown kind, or a kind that was
+ * not kept. */
+#define HSSMF_STAGE_RANDOM 0
+#define HSSMF_STAGE_SAMPLES_ROW 1
+#define HSSMF_STAGE_SAMPLES_COL 2
+#define HSSMF_STAGE_THETA_T 3
+#define HSSMF_STAGE_PHI 4
+#define HSSMF_STAGE_UPDATE 5
+int hssmf_front_data(void* h, int32_t front, int32_t what, double* out, int64_t cap, int32_t* dims);
 
 /* Machine-peak probes, so that roofline fractions can be quoted against the
  * device as measured as well as against its published figures.  Runs, on
@@ -287,13 +324,13 @@ int hssmf_measure_peaks(void* stream, hssmf_peaks* out);
  * a static device array of HSSMF_NOALLOC_SCRATCH_BYTES per GPU (held until
  * the process ends); the preconditioner sweeps run eagerly (no graph is
  * captured).  b, x: DEVICE arrays, n x nrhs column-major; info as
- * hssmf_solve.  The scratch must hold 2 n doubles for iterative refinement
- * and (restart + 3) n doubles for GMRES, else HSSMF_ETOOBIG (nothing is
+ * hssmf_solve.  The scratch must hold (restart + 3) n doubles (GMRES, and
+ * refinement, which may hand over to GMRES), else HSSMF_ETOOBIG (nothing is
  * launched).  Every call on one GPU shares that GPU's scratch: calls that
  * overlap on one GPU (other threads or streams) race.  Synchronizes the
  * handle's stream, like hssmf_solve; results are bitwise those of
  * hssmf_solve with use_graph = 0. */
-#define HSSMF_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define HSSMF_NOALLOC_SCRATCH_BYTES (256u << 20)
 int hssmf_solve_noalloc(void* h, int32_t nrhs, const double* b, double* x, hssmf_info* info);
 
 void hssmf_destroy(void* h);

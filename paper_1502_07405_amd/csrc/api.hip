@@ -309,16 +309,17 @@ struct Ws {
 };
 
 // doubles of workspace the outer solver of the options takes for n unknowns
+// (refinement may hand over to GMRES, which then reuses its vectors)
 size_t outer_ws_doubles(const hssmf_opts& o, int64_t n) {
   const size_t nn = ((size_t)std::max<int64_t>(n, 1) + 31) & ~size_t(31);
-  if (o.outer == HSSMF_OUTER_GMRES) return nn * (size_t)(std::max(1, std::min(o.restart, 200)) + 3);
-  return 2 * nn;
+  return nn * (size_t)(std::max(1, std::min(o.restart, 200)) + 3);
 }
 
 // restarted, left-preconditioned GMRES(m) with modified Gram-Schmidt on the
 // device and Givens rotations on the host; x0 = 0; stops on the true
 // relative residual
-int gmres(Handle& h, int trans, const double* b, double* x, hssmf_info* info, Ws& ws, bool graph) {
+int gmres(Handle& h, int trans, const double* b, double* x, hssmf_info* info, Ws& ws, bool graph,
+          bool from_x = false, int its0 = 0) {
   const int n = h.P.n, m = std::max(1, std::min(h.o.restart, 200));
   double* V = ws.get((size_t)n * (m + 1));
   double* w = ws.get(n);
@@ -326,7 +327,7 @@ int gmres(Handle& h, int trans, const double* b, double* x, hssmf_info* info, Ws
   double* hcol = h.d_scal;  // m+2 device scalars
   const std::vector<double> nbs = sys_norms(h, b);
   const double nb = dnrm2(h, b, n);
-  launch_fill(x, n, 0.0, h.st);
+  if (!from_x || nb == 0.0) launch_fill(x, n, 0.0, h.st);
   if (nb == 0.0) {
     if (info) { info->iterations = 0; info->rel_residual = 0; }
     return HSSMF_OK;
@@ -405,27 +406,42 @@ int gmres(Handle& h, int trans, const double* b, double* x, hssmf_info* info, Ws
     if (done) break;
   }
   HIP_CHECK(hipStreamSynchronize(h.st));
-  if (info) { info->iterations = its; info->rel_residual = rel; }
+  if (info) { info->iterations = its0 + its; info->rel_residual = rel; }
   return rel <= h.o.tol ? HSSMF_OK : HSSMF_ENOCONV;
 }
 
+// Iterative refinement; once the relative residual has failed to fall below
+// 0.9 times the previous one on two consecutive steps (the factorization is
+// then no contraction, e.g. an HSS preconditioner at a large tolerance), the
+// solve hands over to GMRES from the current iterate (Sec. 4.6)
 int refine(Handle& h, int trans, const double* b, double* x, hssmf_info* info, Ws& ws, bool graph) {
   const int n = h.P.n;
+  const size_t mark = ws.off;
+  const Arena::Mark amark = h.arena.mark();
   double* r = ws.get(n);
   double* z = ws.get(n);
   const std::vector<double> nbs = sys_norms(h, b);
   apply_inverse(h, trans, b, x, graph);
-  double rel = 0.0;
-  int it = 0;
+  double rel = 0.0, prev = 0.0;
+  int it = 0, slow = 0;
   for (;; ++it) {
     spmv(h, trans, x, r, -1.0, 0.0);
     launch_axpy(r, b, n, nullptr, 1.0, 0, h.st);
     rel = max_rel(h, r, nbs);
-    if (rel <= h.o.tol || it >= h.o.max_it) break;
+    slow = (it > 0 && rel > 0.9 * prev) ? slow + 1 : 0;
+    prev = rel;
+    if (rel <= h.o.tol || slow >= 2 || it >= h.o.max_it) break;
     apply_inverse(h, trans, r, z, graph);
     launch_axpy(x, z, n, nullptr, 1.0, 0, h.st);
   }
   HIP_CHECK(hipStreamSynchronize(h.st));
+  if (rel > h.o.tol && slow >= 2) {
+    // r and z are dead: GMRES takes their place in the workspace
+    ws.off = mark;
+    if (!ws.base) h.arena.reset(amark);
+    if (info) info->outer_switched = 1;
+    return gmres(h, trans, b, x, info, ws, graph, true, it);
+  }
   if (info) { info->iterations = it; info->rel_residual = rel; info->failed_front = -1; }
   return rel <= h.o.tol ? HSSMF_OK : HSSMF_ENOCONV;
 }
@@ -433,7 +449,7 @@ int refine(Handle& h, int trans, const double* b, double* x, hssmf_info* info, W
 // one right-hand side; ws null: work vectors from the handle's arena
 int outer(Handle& h, int trans, const double* b, double* x, hssmf_info* info, double* wsbase = nullptr,
           size_t wscap = 0) {
-  if (info) { info->iterations = 0; info->rel_residual = 0; info->failed_front = -1; }
+  if (info) { info->iterations = 0; info->rel_residual = 0; info->failed_front = -1; info->outer_switched = 0; }
   Ws ws(h, wsbase, wscap);
   const bool graph = wsbase == nullptr;   // capturing a graph allocates
   return h.o.outer == HSSMF_OUTER_GMRES ? gmres(h, trans, b, x, info, ws, graph)
@@ -536,7 +552,7 @@ bool opts_ok(const hssmf_opts* o) {
            o->restart < 1 || o->max_it < 0 || o->gemm_prec < 0 || o->gemm_prec > 2 || o->id_kernel < 0 ||
            o->id_kernel > 2 || o->use_graph < 0 || o->use_graph > 1 ||
            !(o->gemm_tile == 0 || o->gemm_tile == 64 || o->gemm_tile == 65 || o->gemm_tile == 128) ||
-           !(o->abs_tol >= 0.0));
+           !(o->abs_tol >= 0.0) || o->keep_stages < 0 || o->keep_stages > 1);
 }
 
 // a CSR matrix in host memory: the caller's arrays when they are host
@@ -801,6 +817,34 @@ int hssmf_hss_ranks(void* hv, int32_t* out, int32_t cap) {
     ++i;
   }
   return i;
+}
+
+int hssmf_front_data(void* hv, int32_t front, int32_t what, double* out, int64_t cap, int32_t* dims) {
+  Handle* h = static_cast<Handle*>(hv);
+  if (!h || !dims || (cap > 0 && !out)) return HSSMF_EINVAL;
+  if (h->factor_status != HSSMF_OK) return h->factor_status;
+  if (front < 0 || front >= h->P.nfront || h->fr[front].hidx < 0) return HSSMF_EINVAL;
+  const HFront& F = h->hf[h->fr[front].hidx];
+  const double* src = nullptr;
+  int rows = 0, cols = 0;
+  switch (what) {
+    case HSSMF_STAGE_RANDOM: src = F.kR; rows = F.n; cols = F.kd; break;
+    case HSSMF_STAGE_SAMPLES_ROW: src = F.kSr; rows = F.n; cols = F.kd; break;
+    case HSSMF_STAGE_SAMPLES_COL: src = F.kSc; rows = F.n; cols = F.kd; break;
+    case HSSMF_STAGE_THETA_T: src = F.kTh; rows = F.mk; cols = F.u; break;
+    case HSSMF_STAGE_PHI: src = F.kPhi; rows = F.mk; cols = F.u; break;
+    case HSSMF_STAGE_UPDATE: src = F.Upd; rows = F.u; cols = F.u; break;
+    default: return HSSMF_EINVAL;
+  }
+  if (!src && (int64_t)rows * cols > 0) return HSSMF_EINVAL;   // not kept (keep_stages off)
+  dims[0] = rows;
+  dims[1] = cols;
+  const int64_t nel = (int64_t)rows * cols;
+  if (cap < nel || nel == 0) return HSSMF_OK;
+  return guard_impl(h, [&]() {
+    HIP_CHECK(hipStreamSynchronize(h->st));
+    HIP_CHECK(hipMemcpy(out, src, sizeof(double) * (size_t)nel, hipMemcpyDeviceToHost));
+  });
 }
 
 int hssmf_measure_peaks(void* stream, hssmf_peaks* out) {

@@ -449,6 +449,8 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
       }
       F->Dk = nullptr; F->ipivk = nullptr; F->mk = 0;
       F->Vbark = F->ThT = F->Phi = F->Upd = nullptr;
+      F->kR = F->kSr = F->kSc = F->kTh = F->kPhi = nullptr;
+      F->kd = 0;
       F->UpdLP = nullptr;
       F->X = F->t1 = F->t2 = nullptr;
       gen_random(h, *F, 0, F->d);
@@ -567,7 +569,7 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
         HIP_CHECK(hipStreamSynchronize(h.st));
         census_t0 = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
       }
-      const int res_c = o.id_kernel == HSSMF_ID_RESIDENT ? id_res_candidates(maxd) : 0;
+      const int res_c = o.id_kernel == HSSMF_ID_RESIDENT ? id_res_candidates(maxd, maxm) : 0;
       if (!q.empty() && res_c > 0) {
         // every pivot step of a problem in one launch, candidates resident
         // in registers: problems of at most res_c candidates on one
@@ -745,7 +747,7 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
             fl += 4.0 * d * m * k - 2.0 * k * k * (d + m) + 4.0 / 3.0 * k * k * k;
           }
         }
-        prof::add_flops(0, fl);
+        prof::add_flops(res_c > 0 ? 4 : 0, fl);   // class 4: the resident kernel
       }
       std::vector<NRef> ok = refresh;
       std::vector<int> ivec;
@@ -853,6 +855,19 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
       F->refresh = true;
     }
     sample(h, grow, c0, o.dd);
+  }
+  if (o.keep_stages) {
+    // the random matrix and the samples at the final d, for inspection
+    for (HFront* F : fs) {
+      const size_t nd = (size_t)F->n * F->d;
+      F->kd = F->d;
+      F->kR = dalloc(h, (int64_t)nd);
+      F->kSr = dalloc(h, (int64_t)nd);
+      F->kSc = dalloc(h, (int64_t)nd);
+      HIP_CHECK(hipMemcpyAsync(F->kR, F->R, nd * sizeof(double), hipMemcpyDeviceToDevice, h.st));
+      HIP_CHECK(hipMemcpyAsync(F->kSr, F->Sr, nd * sizeof(double), hipMemcpyDeviceToDevice, h.st));
+      HIP_CHECK(hipMemcpyAsync(F->kSc, F->Sc, nd * sizeof(double), hipMemcpyDeviceToDevice, h.st));
+    }
   }
 }
 
@@ -1111,6 +1126,14 @@ void schur_level(Handle& h, std::vector<HFront*>& fs) {
     launch_pivots(F->Phi, F->mk, F->u, F->ipivk, F->mk, 0, sialloc(h, F->mk), h.st);
     tri_solve_many(h, F->Dk, F->mk, F->mk, F->Phi, F->mk, F->u, true, true, false);
   }
+  if (h.o.keep_stages)
+    for (HFront* F : wu) {
+      const size_t nb = sizeof(double) * (size_t)F->mk * F->u;
+      F->kTh = dalloc(h, (int64_t)F->mk * F->u);
+      F->kPhi = dalloc(h, (int64_t)F->mk * F->u);
+      HIP_CHECK(hipMemcpyAsync(F->kTh, F->ThT, nb, hipMemcpyDeviceToDevice, h.st));
+      HIP_CHECK(hipMemcpyAsync(F->kPhi, F->Phi, nb, hipMemcpyDeviceToDevice, h.st));
+    }
   // dense update matrix: expand F22 of the q-subtree, subtract Theta^* Phi
   for (HFront* F : wu) {
     F->Upd = dalloc(h, (int64_t)F->u * F->u);

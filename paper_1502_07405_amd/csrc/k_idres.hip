@@ -5,22 +5,29 @@
 // A problem is Y = S^T (d x m): its m candidates (rows of the node samples)
 // are the columns, each of length d.  A 512-thread workgroup (one per CU,
 // two wavefronts per SIMD, so each may hold 256 registers) holds C
-// candidates: each of its 8 wavefronts owns CW of them, and lane l keeps
-// rows l, l + 64, ..., l + 64 (NR - 1) of each in registers.  Problems of at
-// most C candidates (the leaves and most lower nodes) run on one workgroup,
-// so a pivot step costs two workgroup barriers: the remaining norms are
-// published in LDS and every wavefront takes the pivot (largest remaining
-// norm, ties to the lowest candidate index); the owner copies the pivot
-// column to LDS; every wavefront forms the reflector and applies it to its
-// active candidates, recomputing their remaining norms from the updated
-// entries (no downdating).  Larger problems are spread over P workgroups of
-// one cooperative launch (all resident at once): per step each workgroup
-// publishes its best candidate's column and then its (norm, index) with a
-// step tag through agent-coherent memory, waits (bounded) for the other
-// workgroups' tags of that step, and takes the pivot column from the
-// winner's published copy.  Columns never move: perm / ipos record the
-// interchanges a swapping QR would make, and the factored columns are
-// written back to W (d x m) at the end for the R1 / R2 gathers.
+// candidates.  Each candidate lives in one group of LPC = 16 lanes of a
+// wavefront (a DPP row), lane e of the group keeping rows
+// e, e + LPC, ..., so the sums over a candidate's rows (its dot product
+// with the reflector, its remaining norm) are butterflies inside the group:
+// data-parallel-primitive moves within a row, bitwise the same result in
+// every lane of the group (each level adds a and b in one lane and b and a
+// in its partner).  A wavefront holds SL candidates per group.
+//
+// Problems of at most C candidates (the leaves and most lower nodes) run on
+// one workgroup, with one workgroup barrier per pivot step: each wavefront
+// publishes its best remaining candidate (norm, index) and that candidate's
+// column, already in reflector form, in LDS; after the barrier every
+// wavefront takes the pivot (largest remaining norm, ties to the lowest
+// candidate index) and applies its reflector to its own candidates,
+// recomputing their remaining norms from the updated entries (no
+// downdating).  Larger problems are spread over P workgroups of one
+// cooperative launch (all resident at once): per step each workgroup also
+// publishes its best column and then its (norm, index) with a step tag
+// through agent-coherent memory, waits (bounded) for the other workgroups'
+// tags of that step, and takes the pivot column from the winner's published
+// copy.  Columns never move: perm / ipos record the interchanges a swapping
+// QR would make, and the factored columns are written back to W (d x m) at
+// the end for the R1 / R2 gathers.
 #include "kernels.hpp"
 
 namespace hssmf {
@@ -31,11 +38,6 @@ constexpr int kResThreads = 512;
 constexpr int kResWaves = kResThreads / 64;
 constexpr unsigned kResSpinLimit = 1u << 22;
 
-__device__ __forceinline__ double rsum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
-
 __device__ __forceinline__ void st_coh(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -43,37 +45,49 @@ __device__ __forceinline__ double ld_coh(const double* p) {
   return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ double rdlane(double v, int l) {
-  const long long u = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), l);
-  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+// a double moved between lanes of a 16-lane row by a data-parallel
+// primitive (CTRL: quad permutation, half-row mirror or row rotation)
+template <int CTRL>
+__device__ __forceinline__ double dpp(double x) {
+  const long long u = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffll), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xf, 0xf, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// Sums over the wavefront of N values per lane at once (N a power of two
-// up to 64).  The first log2(N) exchange levels halve the values each lane
-// carries (a lane keeps the half its offset bit selects and adds the
-// partner's copy of it), so they take N - 1 exchanges in all instead of
-// N log2(N); the remaining levels are plain butterflies.  Value c's sum
-// ends up in lanes (64 / N) c ..; it is returned to every lane (wave
-// uniform) in v[c].
-template <int N>
-__device__ __forceinline__ void msum(double (&v)[N], int lane) {
-#pragma unroll
-  for (int o = 32, cnt = N; cnt > 1; o >>= 1, cnt >>= 1) {
-    const bool up = (lane & o) != 0;
-#pragma unroll
-    for (int i = 0; i < cnt / 2; ++i) {
-      const double keep = up ? v[i + cnt / 2] : v[i];
-      const double send = up ? v[i] : v[i + cnt / 2];
-      v[i] = keep + __shfl_xor(send, o);
-    }
-  }
-#pragma unroll
-  for (int o = 32 / N; o > 0; o >>= 1) v[0] += __shfl_xor(v[0], o);
-  const double w = v[0];
-#pragma unroll
-  for (int c = 0; c < N; ++c) v[c] = rdlane(w, (64 / N) * c);
+// Sum over each group of 16 lanes (a row), the same bits in every lane of
+// the group: partners 1 and 2 apart (quad permutations), then the other
+// quad of the half-row (its mirror: all lanes of a quad already agree),
+// then the other half-row (rotation by 8).
+template <int LPC>
+__device__ __forceinline__ double gsum(double x) {
+  static_assert(LPC == 16, "a candidate spans one 16-lane row");
+  x += dpp<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += dpp<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += dpp<0x141>(x);  // row_half_mirror
+  x += dpp<0x128>(x);  // row_ror:8
+  return x;
+}
+
+// per-wavefront record of a pivot step: its best candidate's remaining norm
+// and index, and that column's entry in the pivot row
+struct alignas(16) WRec {
+  double v, x0;
+  int i, pad[3];
+};
+
+// (v, i) <- the larger of (v, i) and (o, oi), ties to the lower index, by
+// selects
+__device__ __forceinline__ void amax(double& v, int& i, double o, int oi) {
+  const bool tk = (o > v) | ((o == v) & (oi < i));
+  v = tk ? o : v;
+  i = tk ? oi : i;
+}
+
+// y * y rounded on its own (never fused into a following sum)
+__device__ __forceinline__ double sq_rn(double y) {
+#pragma clang fp contract(off)
+  return y * y;
 }
 
 // (value, index) maximum over the wavefront: larger value wins, ties to the
@@ -88,117 +102,213 @@ __device__ __forceinline__ void wargmax(double& v, int& i) {
 
 }  // namespace
 
-template <int NR, int CW>
+// LPC lanes per candidate, RL rows per lane (d <= LPC RL), SL candidates per
+// lane group
+template <int LPC, int RL, int SL>
 __global__ __launch_bounds__(kResThreads) void id_res_kernel(const IDProb* __restrict__ probs,
                                                              const int2* __restrict__ wgmap, int* err) {
-  constexpr int C = kResWaves * CW;          // candidates per workgroup
+  constexpr int G = 64 / LPC;                 // lane groups per wavefront
+  constexpr int CW = G * SL;                  // candidates per wavefront
+  constexpr int NW = kResWaves;
+  constexpr int C = NW * CW;                  // candidates per workgroup
   constexpr int TLD = 65;                     // staging tile: candidate-major, padded
   constexpr int kStage = C * TLD;
-  constexpr int kV = 64 * NR;
-  constexpr int kLds = kStage > kV ? kStage : kV;
-  __shared__ double sh[kLds];                 // staging tile, then the pivot column (absolute rows)
-  __shared__ double nrm[C];
-  __shared__ double gbest;
+  constexpr int kV = LPC * RL;
+  constexpr int kBuf = 2 * NW * kV + kV;      // per-wavefront columns by step parity, remote pivot
+  constexpr int kLds = kStage > kBuf ? kStage : kBuf;
+  constexpr int kMaxM = 2 * LPC * RL;         // a node's rows: at most twice the samples
+  constexpr int RPC = 64 / LPC;               // r-slots per 64-row staging chunk
+  constexpr int RB = RL % 8 == 0 ? 8 : RL;    // r-blocks per chunk of rows
+  constexpr int NCH = RL / RB;
+  __shared__ double sh[kLds];                 // staging tile, then the column buffers
+  __shared__ WRec wrec[2][NW];
+  __shared__ int lperm[kMaxM], lipos[kMaxM];  // pivot order (workgroup 0 of a problem)
+  __shared__ double lalpha[kV];               // R diagonal, written out at the end
+  __shared__ double gbest, gx0;
   __shared__ int gidx, gok;
-  double* v = sh;
 
   const int2 wm = wgmap[blockIdx.x];
-  const IDProb& q = probs[wm.x];
   const int b = wm.y;
+  // the problem's fields, read once: stores through the output pointers
+  // below must not make the compiler fetch them again
+  const IDProb& qr = probs[wm.x];
+  const double* __restrict__ S = qr.S;
+  double* __restrict__ W = qr.W;
+  double* __restrict__ alpha_out = qr.alpha;
+  double* __restrict__ slots = qr.slots;
+  double* __restrict__ cand = qr.cand;
+  int* __restrict__ perm_out = qr.perm;
+  int* __restrict__ ipos_out = qr.ipos;
+  int* __restrict__ state = qr.state;
+  double* __restrict__ first_out = qr.first;
+  const int m = qr.m, d = qr.d, P = qr.P, lds = qr.lds;
+  const double eps = qr.eps, atol = qr.atol;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m = q.m, d = q.d, P = q.P;
+  const int g = lane / LPC, e = lane % LPC;   // lane group, row offset in it
   const int kmax = min(m, d);
   const int j0 = b * C;
   const int jw = j0 + wave * CW;              // this wavefront's first candidate
+  const bool keeper = b == 0;                 // keeps the pivot order
+  const int dc = (d + LPC * RB - 1) / (LPC * RB);   // chunks holding rows < d
+  // candidate of slot s in this lane's group: jw + s G + g
 
   // stage the workgroup's candidates: rows j0.. of S (m x d, ld lds), 64
   // samples at a time, read coalesced along the candidates and turned
   // around in LDS
-  double col[CW][NR];
+  double col[SL][RL];
 #pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    if (64 * r < d) {
-      for (int e = tid; e < C * 64; e += kResThreads) {
-        const int jj = e % C, kk = e / C;
-        const int j = j0 + jj, k = 64 * r + kk;
-        sh[jj * TLD + kk] = (j < m && k < d) ? q.S[j + (int64_t)k * q.lds] : 0.0;
+  for (int k = 0; k < (RL + RPC - 1) / RPC; ++k) {
+    if (64 * k < d) {
+      for (int x = tid; x < C * 64; x += kResThreads) {
+        const int jj = x % C, kk = x / C;
+        const int j = j0 + jj, i = 64 * k + kk;
+        sh[jj * TLD + kk] = (j < m && i < d) ? S[j + (int64_t)i * lds] : 0.0;
       }
       __syncthreads();
 #pragma unroll
-      for (int c = 0; c < CW; ++c) col[c][r] = sh[(wave * CW + c) * TLD + lane];
+      for (int rr = 0; rr < RPC; ++rr) {
+        const int r = k * RPC + rr;
+        if (r < RL) {
+#pragma unroll
+          for (int s = 0; s < SL; ++s) col[s][r] = sh[(wave * CW + s * G + g) * TLD + e + LPC * rr];
+        }
+      }
       __syncthreads();
     } else {
 #pragma unroll
-      for (int c = 0; c < CW; ++c) col[c][r] = 0.0;
+      for (int rr = 0; rr < RPC; ++rr) {
+        const int r = k * RPC + rr;
+        if (r < RL) {
+#pragma unroll
+          for (int s = 0; s < SL; ++s) col[s][r] = 0.0;
+        }
+      }
     }
   }
-  // the pivot column buffer is zero past row d for the whole run
-  for (int i = d + tid; i < 64 * NR; i += kResThreads) v[i] = 0.0;
-  // active candidates of this wavefront (bit c: candidate jw + c), and
-  // their remaining norms in LDS (-1 once pivoted or past m)
-  unsigned act = 0;
-  {
-    double ss[CW];
-#pragma unroll
-    for (int c = 0; c < CW; ++c) {
-      if (jw + c < m) act |= 1u << c;
-      ss[c] = 0.0;
-#pragma unroll
-      for (int r = 0; r < NR; ++r) ss[c] += col[c][r] * col[c][r];
-    }
-    msum<CW>(ss, lane);
-#pragma unroll
-    for (int c = 0; c < CW; ++c)
-      if (lane == c) nrm[wave * CW + c] = (act >> c & 1u) ? sqrt(ss[c]) : -1.0;
-  }
-  if (b == 0) {   // the pivot order is kept by workgroup 0 alone
+  if (keeper)
     for (int j = tid; j < m; j += kResThreads) {
-      q.perm[j] = j;
-      q.ipos[j] = j;
+      lperm[j] = j;
+      lipos[j] = j;
     }
+  // active slots of this lane's group (bit s) and their remaining norms
+  // (the same in every lane of the group)
+  unsigned act = 0;
+  double nv[SL];
+#pragma unroll
+  for (int s = 0; s < SL; ++s) {
+    if (jw + s * G + g < m) act |= 1u << s;
+    double ss = 0.0;
+#pragma unroll
+    for (int r = 0; r < RL; ++r) ss += col[s][r] * col[s][r];
+    nv[s] = sqrt(gsum<LPC>(ss));
   }
   double first = 0.0;
   bool failed = false;
   int t = 0;
+  // One workgroup barrier per pivot step: every wavefront publishes its best
+  // remaining candidate (norm, index) and that candidate's column, already
+  // in reflector form for step t (rows below t zero, row t holding
+  // x0 - alpha), in its own buffer; after the barrier all wavefronts take
+  // the largest (ties to the lowest index) and apply that buffer.  Buffers
+  // alternate with the step's parity, so a wavefront that runs ahead to
+  // step t + 1 never overwrites what the others still read for step t.
   for (;; ++t) {
-    __syncthreads();
-    // this workgroup's best remaining candidate
+    const int par = t & 1;
+    const int tc = t / (LPC * RB);            // the chunk holding row t
+    // this wavefront's best active candidate (inactive slots never win)
     double bv = -1.0;
     int bi = 0x7fffffff;
-    for (int e = lane; e < C; e += 64) {
-      const double x = nrm[e];
-      if (x > bv) { bv = x; bi = j0 + e; }
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+      const bool on = (act >> s) & 1u;
+      amax(bv, bi, on ? nv[s] : -1.0, on ? jw + s * G + g : 0x7fffffff);
     }
-    wargmax(bv, bi);
-    double best = bv;
-    int p = bi;
-    bool local = true;
-    if (P > 1) {
-      // publish the best column (rows t..), then (norm, index), then the tag
-      const int bl = bi - j0;
-      if (bv >= 0.0 && bl / CW == wave) {
-        double* dst = q.cand + ((size_t)(t & 1) * P + b) * d;
 #pragma unroll
-        for (int c = 0; c < CW; ++c)
-          if (c == bl % CW) {
+    for (int off = LPC; off < 64; off <<= 1) {
+      const double o = __shfl_xor(bv, off);
+      const int oi = __shfl_xor(bi, off);
+      amax(bv, bi, o, oi);
+    }
+    // the lanes of the group holding it write its column, in reflector form
+    // for step t, to this wavefront's buffer (one uniform branch per chunk
+    // of rows; the slot is the same in every lane of the group)
+    if ((bv >= 0.0) & ((bi - jw) % G == g)) {
+      const int sb = __builtin_amdgcn_readfirstlane((bi - jw) / G);
+      double* dst = sh + (size_t)(par * NW + wave) * kV;
+      const double al = bv;
 #pragma unroll
-            for (int r = 0; r < NR; ++r) {
-              const int i = lane + 64 * r;
-              if (i >= t && i < d) st_coh(dst + i, col[c][r]);
+      for (int s = 0; s < SL; ++s) {
+        if (s != sb) continue;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+          if (ch < tc || ch >= dc) continue;
+          if (ch == tc) {
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr) {
+              const int r = ch * RB + rr;
+              const int i = e + LPC * r;
+              const double x = col[s][r];
+              double w = i > t ? x : 0.0;
+              if (i == t) {
+                w = x - ((x >= 0.0) ? -al : al);
+                wrec[par][wave].x0 = x;
+              }
+              dst[i] = w;
+            }
+          } else {
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr) {
+              const int r = ch * RB + rr;
+              dst[e + LPC * r] = col[s][r];
             }
           }
+        }
+      }
+    }
+    if (lane == 0) {
+      wrec[par][wave].v = bv;
+      wrec[par][wave].i = bi;
+    }
+    __syncthreads();
+    // the workgroup's best: all (norm, index) records read at once, then
+    // compared; the pivot-row entry of the winner's column after that
+    double rv[NW];
+    int ri[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      rv[w] = wrec[par][w].v;
+      ri[w] = wrec[par][w].i;
+    }
+    double best = rv[0];
+    int p = ri[0], pw = 0;
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+      const bool tk = (rv[w] > best) | ((rv[w] == best) & (ri[w] < p));
+      best = tk ? rv[w] : best;
+      p = tk ? ri[w] : p;
+      pw = tk ? w : pw;
+    }
+    double x0 = wrec[par][pw].x0;
+    const double* vp = sh + (size_t)(par * NW + pw) * kV;
+    bool local = true;
+    if (P > 1) {
+      // publish the workgroup's best column (rows t.., raw), then (norm,
+      // index), then the step tag; wait for the problem's other workgroups
+      if (best >= 0.0) {
+        double* dst = cand + ((size_t)par * P + b) * d;
+        for (int i = t + tid; i < d; i += kResThreads) st_coh(dst + i, i == t ? x0 : vp[i]);
       }
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
       if (tid == 0) {
-        double* sl = q.slots + ((size_t)(t & 1) * P + b) * 4;
-        st_coh(sl, bv);
-        st_coh(sl + 1, (double)bi);
+        double* sl = slots + ((size_t)par * P + b) * 4;
+        st_coh(sl, best);
+        st_coh(sl + 1, (double)p);
         __builtin_amdgcn_s_waitcnt(0);
         st_coh(sl + 2, (double)t);
       }
       if (wave == 0) {
-        const double* sl = q.slots + (size_t)(t & 1) * P * 4;
+        const double* sl = slots + (size_t)par * P * 4;
         double sv = -1.0;
         int sc = 0x7fffffff;
         bool ok = true;
@@ -235,112 +345,118 @@ __global__ __launch_bounds__(kResThreads) void id_res_kernel(const IDProb* __res
       best = gbest;
       p = gidx;
       local = p >= j0 && p < j0 + C;
+      if (local) {
+        pw = (p - j0) / CW;
+        vp = sh + (size_t)(par * NW + pw) * kV;
+        x0 = wrec[par][pw].x0;
+      } else if (best >= 0.0 && t < kmax) {
+        // another workgroup's column, rows from the chunk holding t
+        double* gv = sh + (size_t)2 * NW * kV;
+        const double* src = cand + ((size_t)par * P + p / C) * d;
+        const double al = best;
+        for (int i = tc * RB * LPC + tid; i < dc * RB * LPC; i += kResThreads) {
+          const double x = (i >= t && i < d) ? ld_coh(src + i) : 0.0;
+          double w = i > t ? x : 0.0;
+          if (i == t) {
+            w = x - ((x >= 0.0) ? -al : al);
+            gx0 = x;
+          }
+          gv[i] = w;
+        }
+        __syncthreads();
+        vp = gv;
+        x0 = gx0;
+      }
     }
     if (t == 0) first = best;
-    const bool stop = (t >= kmax) || (t == 0 ? best <= q.atol : best <= fmax(q.eps * first, q.atol));
+    const bool stop = (t >= kmax) || (t == 0 ? best <= atol : best <= fmax(eps * first, atol));
     if (stop) break;
-    // the pivot column, rows t.., into LDS
-    if (local) {
-      const int pl = p - j0;
-      if (pl / CW == wave) {
-#pragma unroll
-        for (int c = 0; c < CW; ++c)
-          if (c == pl % CW) {
-#pragma unroll
-            for (int r = 0; r < NR; ++r) {
-              const int i = lane + 64 * r;
-              if (i >= t && i < d) v[i] = col[c][r];
-            }
-            act &= ~(1u << c);
-          }
-      }
-    } else {
-      const double* src = q.cand + ((size_t)(t & 1) * P + p / C) * d;
-      for (int i = t + tid; i < d; i += kResThreads) v[i] = ld_coh(src + i);
-    }
-    __syncthreads();
-    const double x0 = v[t];
     const double alpha = (x0 >= 0.0) ? -best : best;
-    const double v0 = x0 - alpha;
+    const double v0 = x0 - alpha;   // row t of the reflector
     const double vtv = v0 * v0 + (best * best - x0 * x0);
     const double tau = (vtv > 0.0 && best > 0.0) ? 2.0 / vtv : 0.0;
-    if (b == 0 && tid == 0) {
-      const int qpos = q.ipos[p];
-      const int ct = q.perm[t];
-      q.perm[t] = p;
-      q.perm[qpos] = ct;
-      q.ipos[p] = t;
-      q.ipos[ct] = qpos;
-      q.alpha[t] = alpha;
+    if (local && wave == pw) {
+      const int q = p - jw;
+      act &= (q % G == g) ? ~(1u << (q / G)) : ~0u;
     }
-    // the reflector (v with v[t] = v0) on every candidate of the wavefront.
-    // Rows below t are finished: the reflector is zero there, so a block of
-    // 64 rows entirely below t is skipped, and only the block holding row t
-    // needs per-row masks (v is zero past d, as are the columns).  Pivoted
-    // candidates are updated too: their rows above their own pivot step (R
-    // entries) are left unchanged by every later reflector.
-    // Candidates go through in chunks of CH (fewer live registers); each
-    // chunk reads the reflector from LDS twice.
-    const int r0 = t >> 6;
-    constexpr int CH = (NR <= 4 ? 8 : 4) < CW ? (NR <= 4 ? 8 : 4) : CW;
+    if (keeper && tid == kResThreads - 1) {   // the interchange of step t
+      const int qpos = lipos[p];
+      const int ct = lperm[t];
+      lperm[t] = p;
+      lperm[qpos] = ct;
+      lipos[p] = t;
+      lipos[ct] = qpos;
+    }
+    if (tid == 0) lalpha[t] = alpha;
+    // the reflector on every candidate of the group.  Pivoted candidates
+    // are updated too: their rows above their own pivot step (R entries)
+    // are left unchanged by every later reflector.  Chunks below the one
+    // holding row t are finished and skipped, as are chunks past d (the
+    // reflector and the columns are zero there); the remaining norms leave
+    // out rows up to t, which only that chunk masks.
+    double dot[SL];
 #pragma unroll
-    for (int cb = 0; cb < CW; cb += CH) {
-      double dot[CH];
+    for (int s = 0; s < SL; ++s) dot[s] = 0.0;
 #pragma unroll
-      for (int c = 0; c < CH; ++c) dot[c] = 0.0;
+    for (int ch = 0; ch < NCH; ++ch) {
+      if (ch < tc || ch >= dc) continue;
 #pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        if (r < r0) continue;
-        const int i = lane + 64 * r;
-        double vi = v[i];
-        if (r == r0) vi = (i == t) ? v0 : (i > t ? vi : 0.0);
+      for (int rr = 0; rr < RB; ++rr) {
+        const int r = ch * RB + rr;
+        const double vi = vp[e + LPC * r];
 #pragma unroll
-        for (int c = 0; c < CH; ++c) dot[c] += vi * col[cb + c][r];
+        for (int s = 0; s < SL; ++s) dot[s] += vi * col[s][r];
       }
-      msum<CH>(dot, lane);
+    }
 #pragma unroll
-      for (int c = 0; c < CH; ++c) dot[c] *= tau;
-      double ss[CH];
+    for (int s = 0; s < SL; ++s) dot[s] = gsum<LPC>(dot[s]) * tau;
+    double ss[SL];
 #pragma unroll
-      for (int c = 0; c < CH; ++c) ss[c] = 0.0;
+    for (int s = 0; s < SL; ++s) ss[s] = 0.0;
 #pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        if (r < r0) continue;
-        const int i = lane + 64 * r;
-        double vi = v[i];
-        if (r == r0) vi = (i == t) ? v0 : (i > t ? vi : 0.0);
-        const double keep = (r == r0 && i <= t) ? 0.0 : 1.0;
+    for (int ch = 0; ch < NCH; ++ch) {
+      if (ch < tc || ch >= dc) continue;
+      const bool tchunk = ch == tc;
 #pragma unroll
-        for (int c = 0; c < CH; ++c) {
-          const double y = col[cb + c][r] - dot[c] * vi;
-          col[cb + c][r] = y;
-          ss[c] += keep * (y * y);
+      for (int rr = 0; rr < RB; ++rr) {
+        const int r = ch * RB + rr;
+        const int i = e + LPC * r;
+        const double vi = vp[i];
+        const bool keep = !tchunk || i > t;
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+          const double y = col[s][r] - dot[s] * vi;
+          col[s][r] = y;
+          ss[s] += keep ? sq_rn(y) : 0.0;
         }
       }
-      msum<CH>(ss, lane);
-      // lane c publishes candidate cb + c's remaining norm (v is next
-      // rewritten after the next step's first barrier, when every
-      // wavefront is done with it)
-#pragma unroll
-      for (int c = 0; c < CH; ++c)
-        if (lane == c) nrm[wave * CW + cb + c] = (act >> (cb + c) & 1u) ? sqrt(ss[c]) : -1.0;
     }
+#pragma unroll
+    for (int s = 0; s < SL; ++s) nv[s] = sqrt(gsum<LPC>(ss[s]));
   }
-  if (b == 0 && tid == 0) {
-    q.first[0] = first;
-    q.state[1] = failed ? 0 : t;
-    q.state[0] = 1;
+  __syncthreads();
+  if (keeper) {
+    for (int j = tid; j < m; j += kResThreads) {
+      perm_out[j] = lperm[j];
+      ipos_out[j] = lipos[j];
+    }
+    for (int j = tid; j < t; j += kResThreads) alpha_out[j] = lalpha[j];
+    if (tid == 0) {
+      first_out[0] = first;
+      state[1] = failed ? 0 : t;
+      state[0] = 1;
+    }
   }
   if (failed) return;
   // the factored columns (R in rows < k) for the R1 / R2 gathers
 #pragma unroll
-  for (int c = 0; c < CW; ++c) {
-    const int j = jw + c;
+  for (int s = 0; s < SL; ++s) {
+    const int j = jw + s * G + g;
     if (j < m) {
 #pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const int i = lane + 64 * r;
-        if (i < d) q.W[i + (int64_t)j * d] = col[c][r];
+      for (int r = 0; r < RL; ++r) {
+        const int i = e + LPC * r;
+        if (i < d) W[i + (int64_t)j * d] = col[s][r];
       }
     }
   }
@@ -348,41 +464,33 @@ __global__ __launch_bounds__(kResThreads) void id_res_kernel(const IDProb* __res
 
 namespace {
 
-// template for a pass whose largest sample count is max_d: rows per lane
-// and candidates per wavefront, at most 80 register-resident entries per
-// lane
+// template for a pass whose largest sample count is max_d: lanes per
+// candidate, rows per lane and candidates per lane group, at most 80
+// register-resident entries per lane
 struct ResShape {
-  int nr, cw;
+  int lpc, rl, sl;
 };
 ResShape res_shape(int max_d) {
-  if (max_d <= 128) return {2, 16};
-  if (max_d <= 256) return {4, 16};
-  if (max_d <= 640) return {10, 8};
-  if (max_d <= 1280) return {20, 4};
-  if (max_d <= 2560) return {40, 2};
-  return {0, 0};
-}
-
-template <int NR, int CW>
-const void* res_fn() {
-  return (const void*)id_res_kernel<NR, CW>;
+  if (max_d <= 128) return {16, 8, 4};
+  if (max_d <= 256) return {16, 16, 4};
+  if (max_d <= 640) return {16, 40, 2};
+  return {0, 0, 0};
 }
 
 const void* res_kernel(int max_d) {
   const ResShape s = res_shape(max_d);
-  if (s.nr == 2) return res_fn<2, 16>();
-  if (s.nr == 4) return res_fn<4, 16>();
-  if (s.nr == 10) return res_fn<10, 8>();
-  if (s.nr == 20) return res_fn<20, 4>();
-  if (s.nr == 40) return res_fn<40, 2>();
+  if (s.rl == 8) return (const void*)id_res_kernel<16, 8, 4>;
+  if (s.rl == 16) return (const void*)id_res_kernel<16, 16, 4>;
+  if (s.rl == 40) return (const void*)id_res_kernel<16, 40, 2>;
   return nullptr;
 }
 
 }  // namespace
 
-int id_res_candidates(int max_d) {
+int id_res_candidates(int max_d, int max_m) {
   const ResShape s = res_shape(max_d);
-  return s.nr ? kResWaves * s.cw : 0;
+  if (!s.lpc || max_m > 2 * s.lpc * s.rl) return 0;   // the pivot order is kept in LDS
+  return kResWaves * (64 / s.lpc) * s.sl;
 }
 
 int id_res_capacity(int max_d) {
@@ -401,9 +509,9 @@ void launch_id_res(const IDProb* p, const int2* wgmap, int total_wg, int max_d, 
                    hipStream_t s) {
   if (total_wg <= 0) return;
   const void* fn = res_kernel(max_d);
-  REQUIRE(fn != nullptr, HSSMF_ERANK, "interpolative decomposition: more than 2560 samples");
+  REQUIRE(fn != nullptr, HSSMF_ERANK, "interpolative decomposition: more than 640 samples");
   void* args[] = {(void*)&p, (void*)&wgmap, (void*)&err};
-  const int tok = prof::begin(0, s);   // timing hook (no-op when off)
+  const int tok = prof::begin(4, s);   // timing hook (no-op when off)
   if (coop) HIP_CHECK(hipLaunchCooperativeKernel(fn, dim3(total_wg), dim3(kResThreads), args, 0, s));
   else HIP_CHECK(hipLaunchKernel(fn, dim3(total_wg), dim3(kResThreads), args, 0, s));
   prof::end(tok, s);

@@ -268,13 +268,14 @@ void launch_id_coop(const IDProb* p, const int2* wgmap, int total_wg, int max_d,
 
 // Resident variant (k_idres.hip): every pivot step in one launch, the
 // candidates of a problem resident in the registers of P workgroups of
-// id_res_candidates(max_d) candidates each (0: max_d too large).  Problems
+// id_res_candidates(max_d, max_m) candidates each (0: max_d too large, or
+// more than 128 ceil(max_d / 64) candidates in a problem).  Problems
 // with P = 1 need no other workgroup; a launch holding any problem with
 // P > 1 must be cooperative (coop = true, at most id_res_capacity(max_d)
 // workgroups), with that problem's slots (2 x P x 4 doubles, step tags
 // preset to -1) and cand (2 x P x d) set and *err zero; *err != 0
 // afterwards means a wait gave up and the results are invalid.
-int id_res_candidates(int max_d);
+int id_res_candidates(int max_d, int max_m);
 int id_res_capacity(int max_d);
 void launch_id_res(const IDProb* p, const int2* wgmap, int total_wg, int max_d, bool coop, int* err,
                    hipStream_t s);

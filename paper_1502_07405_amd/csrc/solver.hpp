@@ -92,6 +92,10 @@ struct HFront {
   int mk = 0;
   double *Vbark = nullptr, *ThT = nullptr, *Phi = nullptr;
   double* Upd = nullptr;     // dense update matrix (u x u)
+  // copies kept for inspection when opts.keep_stages is set: R, S^r, S^c at
+  // the final d (n x kd each), Theta^T and Phi (mk x u each)
+  double *kR = nullptr, *kSr = nullptr, *kSc = nullptr, *kTh = nullptr, *kPhi = nullptr;
+  int kd = 0;
   void* UpdLP = nullptr;     // low-precision copy for sampling GEMMs
   double *X = nullptr, *t1 = nullptr, *t2 = nullptr;  // solve buffers
 };

@@ -21,8 +21,9 @@ EXPORTS = ["hssmf_default_opts", "hssmf_factor", "hssmf_refactor", "hssmf_apply"
            "hssmf_solve_transpose", "hssmf_adjoint", "hssmf_stats_get", "hssmf_hss_ranks",
            "hssmf_last_failed_front", "hssmf_destroy", "hssmf_strerror", "hssmf_profile_enable",
            "hssmf_profile_read", "hssmf_factor_batch", "hssmf_systems", "hssmf_measure_peaks",
-           "hssmf_refactor_device", "hssmf_solve_batch", "hssmf_solve_noalloc"]
-KCLASS = {"id": 0, "gemm64": 1, "gemmlp": 2, "lupanel": 3}
+           "hssmf_refactor_device", "hssmf_solve_batch", "hssmf_solve_noalloc",
+           "hssmf_front_data"]
+KCLASS = {"id": 0, "gemm64": 1, "gemmlp": 2, "lupanel": 3, "idres": 4}
 
 
 class HssmfError(RuntimeError):
@@ -51,12 +52,13 @@ class Opts(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("gemm_prec", ctypes.c_int32), ("outer", ctypes.c_int32),
                 ("restart", ctypes.c_int32), ("tol", ctypes.c_double), ("max_it", ctypes.c_int32),
                 ("id_kernel", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("gemm_tile", ctypes.c_int32), ("abs_tol", ctypes.c_double)]
+                ("gemm_tile", ctypes.c_int32), ("abs_tol", ctypes.c_double),
+                ("keep_stages", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("rel_residual", ctypes.c_double),
-                ("failed_front", ctypes.c_int32)]
+                ("failed_front", ctypes.c_int32), ("outer_switched", ctypes.c_int32)]
 
 
 class Peaks(ctypes.Structure):
@@ -92,6 +94,7 @@ def load():
         L.hssmf_solve_transpose.argtypes = [vp, i32, vp, vp, ctypes.POINTER(Info)]
         L.hssmf_solve_batch.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(Info)]
         L.hssmf_solve_noalloc.argtypes = [vp, i32, vp, vp, ctypes.POINTER(Info)]
+        L.hssmf_front_data.argtypes = [vp, i32, i32, vp, ctypes.c_int64, vp]
         L.hssmf_adjoint.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(Info)]
         L.hssmf_stats_get.argtypes = [vp, ctypes.POINTER(Stats)]
         L.hssmf_hss_ranks.argtypes = [vp, vp, i32]
@@ -298,6 +301,19 @@ class Factorization:
         s = Stats()
         self._check(self.lib.hssmf_stats_get(self.h, ctypes.byref(s)), "hssmf_stats_get")
         return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    STAGES = {"random": 0, "samples_row": 1, "samples_col": 2, "theta_t": 3, "phi": 4, "update": 5}
+
+    def front_data(self, front, what):
+        """hssmf_front_data: an intermediate array of HSS front ``front``
+        (``what`` in STAGES) as a numpy array."""
+        dims = np.zeros(2, dtype=np.int32)
+        w = self.STAGES[what]
+        self._check(self.lib.hssmf_front_data(self.h, int(front), w, None, 0, dims.ctypes.data), "hssmf_front_data")
+        out = np.zeros((int(dims[0]), int(dims[1])), dtype=np.float64, order="F")
+        self._check(self.lib.hssmf_front_data(self.h, int(front), w, out.ctypes.data, out.size, dims.ctypes.data),
+                    "hssmf_front_data")
+        return out
 
     def hss_ranks(self):
         nf = self.lib.hssmf_hss_ranks(self.h, None, 0)

@@ -64,9 +64,9 @@ def test_noalloc_solve_matches_solve(outer):
 
 
 def test_noalloc_refuses_too_large_a_workspace():
-    """GMRES(200) on 90,000 unknowns needs 203 x 90,000 doubles of scratch,
-    more than the 64 MiB array: HSSMF_ETOOBIG, and the output is untouched."""
-    A, o = P.poisson2d(300), P.geometric_nd((300, 300), 8)
+    """GMRES(200) on 176,400 unknowns needs 203 x 176,400 doubles of scratch,
+    more than the 256 MiB array: HSSMF_ETOOBIG, and the output is untouched."""
+    A, o = P.poisson2d(420), P.geometric_nd((420, 420), 8)
     fac = H.Factorization(A, o, outer="gmres", restart=200)
     b = torch.ones(A.n, dtype=torch.float64, device=DEV)
     x = torch.zeros_like(b)
