@@ -153,6 +153,49 @@ def traffic_for(cls, launches_per_factorization):
     return nbytes / launches_per_factorization
 
 
+def progress(msg):
+    """One line on stderr per finished phase (the JSON line is the only stdout)."""
+    print(f"bench.py: {msg}", file=sys.stderr, flush=True)
+
+
+def summarize(paths):
+    """Per-kernel totals of rocprofv3 CSV files: for counter_collection files
+    the dispatches and the sum and mean of each counter (as rocprofv3
+    reports it: per dispatch, summed over the device), for kernel_trace
+    files the dispatches and the total and mean duration."""
+    import csv
+    import re
+    for path in paths:
+        with open(path, newline="") as f:
+            rows = list(csv.DictReader(f))
+        if not rows:
+            continue
+        agg = {}
+        if "Counter_Name" in rows[0]:
+            for r in rows:
+                name = re.sub(r"\s+", " ", r["Kernel_Name"])[:110]
+                a = agg.setdefault((name, r["Counter_Name"]), {})
+                a.setdefault(r["Dispatch_Id"], 0.0)
+                a[r["Dispatch_Id"]] += float(r["Counter_Value"])
+            print(f"# {path}: counters per kernel (per-dispatch values summed over the device)")
+            print("| kernel | counter | dispatches | sum | mean per dispatch |")
+            print("|---|---|---:|---:|---:|")
+            for (name, cn), a in sorted(agg.items(), key=lambda kv: -sum(kv[1].values())):
+                tot = sum(a.values())
+                print(f"| {name} | {cn} | {len(a)} | {tot:.6g} | {tot / len(a):.6g} |")
+        else:
+            for r in rows:
+                name = re.sub(r"\s+", " ", r["Kernel_Name"])[:110]
+                a = agg.setdefault(name, [0, 0.0])
+                a[0] += 1
+                a[1] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6
+            print(f"# {path}: kernel durations")
+            print("| kernel | dispatches | total ms | mean us |")
+            print("|---|---:|---:|---:|")
+            for name, (n, ms) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+                print(f"| {name} | {n} | {ms:.3f} | {1000 * ms / n:.2f} |")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,10 +206,16 @@ def main():
     ap.add_argument("--no-dense", action="store_true", help="skip the all-dense multifrontal comparison")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 attempt")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--summarize", nargs="+", metavar="CSV",
+                    help="print per-kernel totals of rocprofv3 CSV output (counter_collection or kernel_trace "
+                         "files) and exit; no GPU is used")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="program for the HBM counter runs: a 256 MiB device copy (calibration), then one "
-                         "factorization and one refactorization of the headline workload; prints no JSON")
+                         "factorization, one refactorization and one solve of the headline workload; prints no JSON")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args.summarize)
+        return
     if args.gpus != 1:
         print(f"bench.py: this solver path runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
@@ -182,6 +231,7 @@ def main():
         torch.cuda.synchronize()
         fp = H.Factorization(A, order, **hss_opts(args.prec))
         fp.refactor(A.val)
+        fp.solve(torch.tensor(b, device="cuda:0"))
         torch.cuda.synchronize()
         fp.close()
         print("traffic probe done", flush=True)
@@ -206,6 +256,7 @@ def main():
     # kernel timing hooks on (roofline): event-stamped launches slow the
     # short pivot-step kernels' pipeline down, so they stay out of value
     sec, x, infos = time_steps(fac, vals, bt, args.steps, 0, torch)
+    progress(f"headline steps: {sec:.4f} s per step")
     H.profile_enable(True)
     for k in KCLASSES:
         H.profile_read(k)
@@ -215,6 +266,7 @@ def main():
     # the same step with the matrix values handed over in host memory
     # (hssmf_refactor): includes their upload, so it is reported beside value
     sec_host, _, _ = time_steps(fac, A.val, bt, args.steps, 0, torch)
+    progress("hooked and host-value steps done")
     st = fac.stats()
     ranks = fac.hss_ranks()
     y = fac.apply(v).cpu().numpy()
@@ -269,6 +321,7 @@ def main():
         r64 = f64.hss_ranks()
         f64.close()
         extra["fp64_hss_step_s"] = sec64
+        progress(f"FP64 HSS: {sec64:.4f} s per step")
         extra["fp64_iterations"] = inf64[-1][0]
         extra["fp64_rel_residual"] = relres(x64)
         extra["mixed_vs_fp64"] = {
@@ -292,6 +345,7 @@ def main():
         dsec, xd, dinf = time_steps(fd, vals, bt, max(1, args.steps), 1, torch)
         fd.close()
         extra["dense_mf_step_s"] = dsec
+        progress(f"dense multifrontal: {dsec:.4f} s per step")
         extra["dense_mf_rel_residual"] = relres(xd)
     line = {"metric": METRIC, "value": sec, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": sec * 1e3, "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
@@ -303,6 +357,7 @@ def main():
             "roofline": roof, "extra": extra}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(A, order, opts)
+        progress("oracle sample timed")
     print(json.dumps(line), flush=True)
 
 

@@ -137,9 +137,10 @@ typedef struct {
  * pivot step of a batch in one launch with each problem's candidates in the
  * registers of as few 512-thread workgroups as hold them (one workgroup,
  * and no exchange between workgroups, for the problems that fit; passes
- * with more than 640 samples, or with an ID of more than twice as many
- * columns as the kernel holds sample rows per candidate, take the stepwise
- * kernel).  All take the same
+ * with more than 640 samples, with an ID of more than twice as many
+ * columns as the kernel holds sample rows per candidate, or with a problem
+ * that needs more workgroups than one cooperative launch holds, take the
+ * stepwise kernel).  All take the same
  * pivot rule; they differ only in the order of floating-point sums. */
 #define HSSMF_ID_STEPWISE 0
 #define HSSMF_ID_COOPERATIVE 1
@@ -164,9 +165,9 @@ typedef struct {
 
 /* Fill *o with defaults: rel_tol 1e-6, leaf_size 64, min_sep_hss INT32_MAX
  * (pure multifrontal), d0 128, dd 128, p 10, d_max 4096, seed 0, FP64,
- * iterative refinement, restart 30, tol 1e-10, max_it 50, stepwise ID
- * kernel, sweeps launched one by one (no graph), autotuned GEMM tiles,
- * abs_tol 0. */
+ * iterative refinement, restart 30, tol 1e-10, max_it 50, resident ID
+ * kernel (the stepwise one where it does not apply), sweeps launched one by
+ * one (no graph), autotuned GEMM tiles, abs_tol 0. */
 int hssmf_default_opts(hssmf_opts* o);
 
 /* Symbolic analysis, upload and numeric factorization (Sec. 3.2, Sec. 4).

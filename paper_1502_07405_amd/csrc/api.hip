@@ -538,7 +538,7 @@ int hssmf_default_opts(hssmf_opts* o) {
   o->restart = 30;
   o->tol = 1e-10;
   o->max_it = 50;
-  o->id_kernel = HSSMF_ID_STEPWISE;
+  o->id_kernel = HSSMF_ID_RESIDENT;
   o->use_graph = 0;   // capture after every factorization costs more than replay saves
   return HSSMF_OK;
 }

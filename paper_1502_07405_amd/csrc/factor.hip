@@ -14,6 +14,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <limits>
 
 #include "solver.hpp"
 
@@ -569,14 +570,19 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
         HIP_CHECK(hipStreamSynchronize(h.st));
         census_t0 = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
       }
-      const int res_c = o.id_kernel == HSSMF_ID_RESIDENT ? id_res_candidates(maxd, maxm) : 0;
+      // the resident kernel where it applies: at most 640 samples, and a
+      // problem that needs several workgroups only with cooperative launches
+      // that can hold all of them; the stepwise kernel otherwise
+      int res_c = o.id_kernel == HSSMF_ID_RESIDENT ? id_res_candidates(maxd, maxm) : 0;
+      const int cap = res_c > 0 ? id_res_capacity(maxd, maxm) : 0;
+      for (size_t pi = 0; pi < q.size() && res_c > 0; ++pi)
+        if (q[pi].m > res_c && (q[pi].m + res_c - 1) / res_c > cap) res_c = 0;
       if (!q.empty() && res_c > 0) {
         // every pivot step of a problem in one launch, candidates resident
         // in registers: problems of at most res_c candidates on one
         // workgroup (ordinary launch), larger ones on several workgroups of
         // a cooperative launch (all resident, bounded waits)
         const int np = (int)q.size();
-        const int cap = id_res_capacity(maxd);
         std::vector<int> single, multi;
         for (int pi = 0; pi < np; ++pi) {
           q[pi].P = std::max(1, (q[pi].m + res_c - 1) / res_c);
@@ -584,19 +590,18 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
         }
         int wgm = 0;
         for (int pi : multi) wgm += q[pi].P;
-        REQUIRE(multi.empty() || cap > 0, HSSMF_EDEVICE, "interpolative decomposition: no cooperative launch");
         double* slots = nullptr;
         if (!multi.empty()) {
           derr = sialloc(h, 1);
-          slots = salloc(h, 8 * (int64_t)wgm);   // per problem 2 x P x (norm, index, step tag, pad)
-          int o8 = 0;
+          slots = salloc(h, 6 * (int64_t)wgm);   // per problem 3 x P x (norm, index)
+          int o6 = 0;
           for (int pi : multi) {
-            REQUIRE(q[pi].P <= cap, HSSMF_ERANK, "interpolative decomposition: problem wider than the device");
-            q[pi].cand = salloc(h, 2 * (int64_t)q[pi].P * q[pi].d);
-            q[pi].slots = slots + o8;
-            o8 += 8 * q[pi].P;
+            q[pi].cand = salloc(h, 3 * (int64_t)q[pi].P * q[pi].d);
+            q[pi].slots = slots + o6;
+            o6 += 6 * q[pi].P;
           }
-          launch_fill(slots, 8 * (int64_t)wgm, -1.0, h.st);   // step tags start at -1
+          // every exchange record starts empty
+          launch_fill(slots, 6 * (int64_t)wgm, std::numeric_limits<double>::quiet_NaN(), h.st);
           HIP_CHECK(hipMemsetAsync(derr, 0, sizeof(int), h.st));
         }
         IDProb* dq = upload(h, q);
@@ -608,16 +613,22 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
         if (!multi.empty() && total <= cap) {
           for (int pi = 0; pi < np; ++pi)
             for (int w = 0; w < q[pi].P; ++w) wgs.push_back(make_int2(pi, w));
-          launch_id_res(dq, upload(h, wgs), (int)wgs.size(), maxd, true, derr, h.st);
+          launch_id_res(dq, upload(h, wgs), (int)wgs.size(), maxd, maxm, true, derr, h.st);
         } else {
           for (int pi : single) wgs.push_back(make_int2(pi, 0));
-          if (!wgs.empty()) launch_id_res(dq, upload(h, wgs), (int)wgs.size(), maxd, false, derr, h.st);
+          if (!wgs.empty()) launch_id_res(dq, upload(h, wgs), (int)wgs.size(), maxd, maxm, false, derr, h.st);
           wgs.clear();
           auto flush = [&]() {
             if (wgs.empty()) return;
-            launch_id_res(dq, upload(h, wgs), (int)wgs.size(), maxd, true, derr, h.st);
+            launch_id_res(dq, upload(h, wgs), (int)wgs.size(), maxd, maxm, true, derr, h.st);
             wgs.clear();
           };
+          // launches run one after another, each as long as its longest
+          // problem: fill them in order of the most pivot steps a problem
+          // can take
+          std::stable_sort(multi.begin(), multi.end(), [&](int a, int b) {
+            return std::min(q[a].m, q[a].d) > std::min(q[b].m, q[b].d);
+          });
           for (int pi : multi) {
             if ((int)wgs.size() + q[pi].P > cap) flush();
             for (int w = 0; w < q[pi].P; ++w) wgs.push_back(make_int2(pi, w));

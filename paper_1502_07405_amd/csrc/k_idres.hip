@@ -22,10 +22,11 @@
 // recomputing their remaining norms from the updated entries (no
 // downdating).  Larger problems are spread over P workgroups of one
 // cooperative launch (all resident at once): per step each workgroup also
-// publishes its best column and then its (norm, index) with a step tag
-// through agent-coherent memory, waits (bounded) for the other workgroups'
-// tags of that step, and takes the pivot column from the winner's published
-// copy.  Columns never move: perm / ipos record the interchanges a swapping
+// publishes its best column and then its (norm, index) through
+// agent-coherent memory, in records that are empty (NaN) until written and
+// rotate over three buffers, waits (bounded) until the other workgroups'
+// records of that step are filled, and takes the pivot column from the
+// winner's published copy.  Columns never move: perm / ipos record the interchanges a swapping
 // QR would make, and the factored columns are written back to W (d x m) at
 // the end for the R1 / R2 gathers.
 #include "kernels.hpp"
@@ -37,6 +38,7 @@ namespace {
 constexpr int kResThreads = 512;
 constexpr int kResWaves = kResThreads / 64;
 constexpr unsigned kResSpinLimit = 1u << 22;
+constexpr double kEmpty = __builtin_nan("");   // an exchange record not yet written
 
 __device__ __forceinline__ void st_coh(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -292,32 +294,46 @@ __global__ __launch_bounds__(kResThreads) void id_res_kernel(const IDProb* __res
     const double* vp = sh + (size_t)(par * NW + pw) * kV;
     bool local = true;
     if (P > 1) {
-      // publish the workgroup's best column (rows t.., raw), then (norm,
-      // index), then the step tag; wait for the problem's other workgroups
+      // Exchange with the problem's other workgroups through three rotating
+      // buffers of agent-coherent records (norm, index), NaN when empty:
+      // publish this workgroup's best column (rows t.., raw) and clear its
+      // record for step t + 1 (last used at step t - 2, which every
+      // workgroup has finished reading: each has published step t - 1
+      // since); once those stores are complete, publish (norm, index) of
+      // step t, then wait (bounded) until every record of step t is filled.
+      const int u = t % 3;
       if (best >= 0.0) {
-        double* dst = cand + ((size_t)par * P + b) * d;
+        double* dst = cand + ((size_t)u * P + b) * d;
         for (int i = t + tid; i < d; i += kResThreads) st_coh(dst + i, i == t ? x0 : vp[i]);
+      }
+      if (tid == 0) {
+        double* nx = slots + ((size_t)((t + 1) % 3) * P + b) * 2;
+        st_coh(nx, kEmpty);
+        st_coh(nx + 1, kEmpty);
       }
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
       if (tid == 0) {
-        double* sl = slots + ((size_t)par * P + b) * 4;
+        double* sl = slots + ((size_t)u * P + b) * 2;
         st_coh(sl, best);
         st_coh(sl + 1, (double)p);
-        __builtin_amdgcn_s_waitcnt(0);
-        st_coh(sl + 2, (double)t);
       }
       if (wave == 0) {
-        const double* sl = slots + (size_t)par * P * 4;
+        const double* sl = slots + (size_t)u * P * 2;
         double sv = -1.0;
         int sc = 0x7fffffff;
         bool ok = true;
         for (int w0 = 0; w0 < P && ok; w0 += 64) {
           const int w = w0 + lane;
-          unsigned spins = 0;
+          double vw = -1.0, cw = 0.0;
           bool ready = w >= P;
+          unsigned spins = 0;
           while (true) {
-            if (!ready) ready = ld_coh(sl + 4 * w + 2) == (double)t;
+            if (!ready) {
+              vw = ld_coh(sl + 2 * w);
+              cw = ld_coh(sl + 2 * w + 1);
+              ready = !__builtin_isnan(vw) && !__builtin_isnan(cw);
+            }
             if (__all(ready)) break;
             if (++spins > kResSpinLimit ||
                 __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
@@ -326,11 +342,7 @@ __global__ __launch_bounds__(kResThreads) void id_res_kernel(const IDProb* __res
             }
             __builtin_amdgcn_s_sleep(1);
           }
-          if (ok && w < P) {
-            const double vw = ld_coh(sl + 4 * w);
-            const int cw = (int)ld_coh(sl + 4 * w + 1);
-            if (vw > sv || (vw == sv && cw < sc)) { sv = vw; sc = cw; }
-          }
+          if (ok && w < P) amax(sv, sc, vw, (int)cw);
         }
         wargmax(sv, sc);
         if (lane == 0) {
@@ -352,7 +364,7 @@ __global__ __launch_bounds__(kResThreads) void id_res_kernel(const IDProb* __res
       } else if (best >= 0.0 && t < kmax) {
         // another workgroup's column, rows from the chunk holding t
         double* gv = sh + (size_t)2 * NW * kV;
-        const double* src = cand + ((size_t)par * P + p / C) * d;
+        const double* src = cand + ((size_t)u * P + p / C) * d;
         const double al = best;
         for (int i = tc * RB * LPC + tid; i < dc * RB * LPC; i += kResThreads) {
           const double x = (i >= t && i < d) ? ld_coh(src + i) : 0.0;
@@ -422,12 +434,12 @@ __global__ __launch_bounds__(kResThreads) void id_res_kernel(const IDProb* __res
         const int r = ch * RB + rr;
         const int i = e + LPC * r;
         const double vi = vp[i];
-        const bool keep = !tchunk || i > t;
+        const double keep = (!tchunk || i > t) ? 1.0 : 0.0;
 #pragma unroll
         for (int s = 0; s < SL; ++s) {
           const double y = col[s][r] - dot[s] * vi;
           col[s][r] = y;
-          ss[s] += keep ? sq_rn(y) : 0.0;
+          ss[s] += keep * sq_rn(y);   // exactly ss + y^2 or ss
         }
       }
     }
@@ -464,56 +476,70 @@ __global__ __launch_bounds__(kResThreads) void id_res_kernel(const IDProb* __res
 
 namespace {
 
-// template for a pass whose largest sample count is max_d: lanes per
-// candidate, rows per lane and candidates per lane group, at most 80
-// register-resident entries per lane
+// Templates: lanes per candidate, rows per lane (samples up to 16 rl) and
+// candidates per lane group (32 sl candidates per workgroup), each without
+// register spills.  A launch takes the fewest rows per lane that hold its
+// largest sample count and then the fewest candidates per group that hold
+// its largest problem (every wavefront runs every slot, so spare slots cost
+// time), or the most if none does (fewest workgroups per problem).
 struct ResShape {
   int lpc, rl, sl;
+  const void* fn;
 };
-ResShape res_shape(int max_d) {
-  if (max_d <= 128) return {16, 8, 4};
-  if (max_d <= 256) return {16, 16, 4};
-  if (max_d <= 640) return {16, 40, 2};
-  return {0, 0, 0};
-}
+const ResShape kShapes[] = {
+    {16, 8, 2, (const void*)id_res_kernel<16, 8, 2>},   {16, 8, 4, (const void*)id_res_kernel<16, 8, 4>},
+    {16, 8, 8, (const void*)id_res_kernel<16, 8, 8>},   {16, 16, 2, (const void*)id_res_kernel<16, 16, 2>},
+    {16, 16, 4, (const void*)id_res_kernel<16, 16, 4>}, {16, 16, 5, (const void*)id_res_kernel<16, 16, 5>},
+    {16, 24, 2, (const void*)id_res_kernel<16, 24, 2>}, {16, 24, 3, (const void*)id_res_kernel<16, 24, 3>},
+    {16, 32, 2, (const void*)id_res_kernel<16, 32, 2>}, {16, 40, 2, (const void*)id_res_kernel<16, 40, 2>},
+};
 
-const void* res_kernel(int max_d) {
-  const ResShape s = res_shape(max_d);
-  if (s.rl == 8) return (const void*)id_res_kernel<16, 8, 4>;
-  if (s.rl == 16) return (const void*)id_res_kernel<16, 16, 4>;
-  if (s.rl == 40) return (const void*)id_res_kernel<16, 40, 2>;
-  return nullptr;
+const ResShape* res_shape(int max_d, int max_m) {
+  int rl = 0;
+  for (const ResShape& r : kShapes)
+    if (16 * r.rl >= max_d && (rl == 0 || r.rl < rl)) rl = r.rl;
+  if (rl == 0 || max_m > 2 * 16 * rl) return nullptr;   // the pivot order is kept in LDS
+  const ResShape* pick = nullptr;
+  for (const ResShape& r : kShapes) {
+    if (r.rl != rl) continue;
+    const int c = kResWaves * (64 / r.lpc) * r.sl;
+    if (c >= max_m) {
+      if (!pick || r.sl < pick->sl || kResWaves * (64 / pick->lpc) * pick->sl < max_m) pick = &r;
+    } else if (!pick || (kResWaves * (64 / pick->lpc) * pick->sl < max_m && r.sl > pick->sl)) {
+      pick = &r;
+    }
+  }
+  return pick;
 }
 
 }  // namespace
 
 int id_res_candidates(int max_d, int max_m) {
-  const ResShape s = res_shape(max_d);
-  if (!s.lpc || max_m > 2 * s.lpc * s.rl) return 0;   // the pivot order is kept in LDS
-  return kResWaves * (64 / s.lpc) * s.sl;
+  const ResShape* s = res_shape(max_d, max_m);
+  return s ? kResWaves * (64 / s->lpc) * s->sl : 0;
 }
 
-int id_res_capacity(int max_d) {
-  const void* fn = res_kernel(max_d);
-  if (!fn) return 0;
+int id_res_capacity(int max_d, int max_m) {
+  const ResShape* s = res_shape(max_d, max_m);
+  if (!s) return 0;
   int dev = 0, cus = 0, coop = 0, nb = 0;
   HIP_CHECK(hipGetDevice(&dev));
   HIP_CHECK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
   if (!coop) return 0;
   HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kResThreads, 0));
+  HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, s->fn, kResThreads, 0));
   return nb * cus;
 }
 
-void launch_id_res(const IDProb* p, const int2* wgmap, int total_wg, int max_d, bool coop, int* err,
+void launch_id_res(const IDProb* p, const int2* wgmap, int total_wg, int max_d, int max_m, bool coop, int* err,
                    hipStream_t s) {
   if (total_wg <= 0) return;
-  const void* fn = res_kernel(max_d);
-  REQUIRE(fn != nullptr, HSSMF_ERANK, "interpolative decomposition: more than 640 samples");
+  const ResShape* sh = res_shape(max_d, max_m);
+  REQUIRE(sh != nullptr, HSSMF_ERANK, "interpolative decomposition: more than 640 samples");
   void* args[] = {(void*)&p, (void*)&wgmap, (void*)&err};
   const int tok = prof::begin(4, s);   // timing hook (no-op when off)
-  if (coop) HIP_CHECK(hipLaunchCooperativeKernel(fn, dim3(total_wg), dim3(kResThreads), args, 0, s));
-  else HIP_CHECK(hipLaunchKernel(fn, dim3(total_wg), dim3(kResThreads), args, 0, s));
+  if (coop) HIP_CHECK(hipLaunchCooperativeKernel(sh->fn, dim3(total_wg), dim3(kResThreads), args, 0, s));
+  else HIP_CHECK(hipLaunchKernel(sh->fn, dim3(total_wg), dim3(kResThreads), args, 0, s));
   prof::end(tok, s);
 }
 

@@ -231,7 +231,7 @@ struct IDProb {
   double* W;            // d x m work, ld d
   double* norms;        // m
   double* alpha;        // min(m, d): R diagonal
-  double* slots;        // 2 (parity) x P x 2: partial (norm, column)
+  double* slots;        // exchange records between a problem's workgroups (layout per kernel)
   double* R1;           // k x k scratch (upper triangle, pivot order)
   double* W2;           // k x (m - k) scratch: R2, then X = R1^{-1} R2
   int* perm;            // output: position -> candidate
@@ -239,7 +239,7 @@ struct IDProb {
   int* state;           // [0] done, [1] rank
   double* first;        // first pivot norm
   unsigned char* active;
-  double* cand;         // 2 (parity) x P x d: each workgroup's best candidate column (cooperative path)
+  double* cand;         // per step buffer x P x d: each workgroup's best candidate column (layout per kernel)
   int* hdone;           // null, or a flag in mapped host memory that the stop step sets (stepwise path)
   int m, d, lds, P;     // P workgroups of kIDCols candidates each
   int wg0, pad;         // first workgroup of this problem in the launch grid
@@ -268,16 +268,18 @@ void launch_id_coop(const IDProb* p, const int2* wgmap, int total_wg, int max_d,
 
 // Resident variant (k_idres.hip): every pivot step in one launch, the
 // candidates of a problem resident in the registers of P workgroups of
-// id_res_candidates(max_d, max_m) candidates each (0: max_d too large, or
-// more than 128 ceil(max_d / 64) candidates in a problem).  Problems
-// with P = 1 need no other workgroup; a launch holding any problem with
-// P > 1 must be cooperative (coop = true, at most id_res_capacity(max_d)
-// workgroups), with that problem's slots (2 x P x 4 doubles, step tags
-// preset to -1) and cand (2 x P x d) set and *err zero; *err != 0
-// afterwards means a wait gave up and the results are invalid.
+// id_res_candidates(max_d, max_m) candidates each, for the template the
+// launch's largest sample count and largest problem select (0: max_d above
+// 640, or max_m above twice the rows the template holds).  Problems with
+// P = 1 need no other workgroup; a launch holding any problem with P > 1
+// must be cooperative (coop = true, at most id_res_capacity(max_d, max_m)
+// workgroups), with that problem's slots (3 x P x 2 doubles, all NaN) and
+// cand (3 x P x d) set and *err zero; *err != 0
+// afterwards means a wait gave up and the results are invalid.  Every
+// launch of one pass must take the same (max_d, max_m).
 int id_res_candidates(int max_d, int max_m);
-int id_res_capacity(int max_d);
-void launch_id_res(const IDProb* p, const int2* wgmap, int total_wg, int max_d, bool coop, int* err,
+int id_res_capacity(int max_d, int max_m);
+void launch_id_res(const IDProb* p, const int2* wgmap, int total_wg, int max_d, int max_m, bool coop, int* err,
                    hipStream_t s);
 
 }  // namespace hssmf

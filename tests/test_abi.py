@@ -39,7 +39,7 @@ def test_default_options_and_strerror(lib):
     o = H.default_opts()
     assert o.leaf_size == 64 and o.d0 == 128 and o.dd == 128 and o.p == 10 and o.restart == 30
     assert o.tol == 1e-10 and o.rel_tol == 1e-6 and o.min_sep_hss == 2 ** 31 - 1
-    assert o.id_kernel == 0 and o.use_graph == 0
+    assert o.id_kernel == 2 and o.use_graph == 0
     assert H.strerror(0) == "ok" and H.strerror(H.HSSMF_ERANK) == "HSS rank exceeds d_max"
 
 
