@@ -128,16 +128,13 @@ LP_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
 # on the device at hand: FP64 FMA loop, FP64 matrix-core loop
 MEASURED_KEY = {"id": "fp64_valu_TFLOPs", "gemm64": "fp64_mfma_TFLOPs", "gemmlp": None, "lupanel": "fp64_valu_TFLOPs",
                 "idres": "fp64_valu_TFLOPs"}
-# HBM bytes per factorization moved by the pivot-step kernel on this
-# workload, from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; each scaled
-# by its reading for a 256 MiB device copy):
-# profiles/id_step_hbm_traffic_poisson3d_64.md.  Valid only for the kernel
-# source those counters were taken on.  The number of launches varies a
-# little from run to run (how far the host has run ahead when the last
-# problem of a pass stops), and the extra launches exit at once and move
-# nothing, so the per-launch figure is this total over the run's own
-# launches.
-TRAFFIC = {"id": (5.4816e11, "paper_1502_07405_amd/csrc/k_id.hip", "21a6834ad2086791")}
+# HBM bytes per factorization moved by each ID kernel class on this
+# workload, from two rocprofv3 --pmc runs of `bench.py --traffic-probe`
+# (FETCH_SIZE, WRITE_SIZE; each scaled by its reading for a 256 MiB device
+# copy in the same run): profiles/id_res_hbm_traffic_poisson3d_64.md.  Valid
+# only for the kernel source those counters were taken on.  The bench divides
+# the total by its own launches per factorization.
+TRAFFIC = {"idres": (1.5822e10, "paper_1502_07405_amd/csrc/k_idres.hip", "24483633caefa2e3")}
 
 
 def traffic_for(cls, launches_per_factorization):
