@@ -106,7 +106,8 @@ typedef struct {
   uint64_t seed;       /* key of the counter-based Gaussian generator of R */
   int32_t gemm_prec;   /* HSSMF_PREC_*: sampling / ULV product precision */
   int32_t outer;       /* HSSMF_OUTER_IR or HSSMF_OUTER_GMRES */
-  int32_t restart;     /* GMRES restart length (30 in Sec. 6.1) */
+  int32_t restart;     /* GMRES restart length (30 in Sec. 6.1; at most 200
+                          are used) */
   double tol;          /* stop when ||b - A x||_2 / ||b||_2 <= tol */
   int32_t max_it;      /* max refinement steps / GMRES iterations */
   int32_t id_kernel;   /* HSSMF_ID_*: how the pivoted QR of the IDs runs */
@@ -128,6 +129,7 @@ typedef struct {
                           Schur factors for hssmf_front_data (device memory
                           of O(n d + m_k u) per front); 0 (default): not */
 } hssmf_opts;
+
 
 /* id_kernel: STEPWISE = one launch per pivot step for each batch of IDs;
  * COOPERATIVE = when every workgroup of a batch fits on the device at once,
@@ -217,7 +219,9 @@ int hssmf_apply(void* h, int32_t trans, const double* x, double* y);
 
 /* Solve A x = b with the outer solver of the options, iterative refinement
  * or restarted GMRES with modified Gram-Schmidt preconditioned by the
- * factorization (Sec. 4.6, Sec. 6.1), stopping on the true residual
+ * factorization (Sec. 4.6, Sec. 6.1; the Arnoldi steps and the Givens
+ * rotations run on the device, which reports each step's residual estimate
+ * to the host through mapped memory), stopping on the true residual
  * ||b - A x||_2 / ||b||_2 <= tol.  b, x: n x nrhs column-major (column j at
  * offset j n), host or device memory (each pointer's kind is looked up);
  * the right-hand sides are solved one after another.  info: NULL or an

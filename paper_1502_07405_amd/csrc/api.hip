@@ -84,6 +84,8 @@ void setup(Handle& h, const hssmf_csr* A) {
   h.d_iperm = upload_big(h, P.iperm);
   h.yws = h.arena.get<double>(n);
   h.d_scal = h.arena.get<double>(1024);
+  h.gm = gm_dev(h.arena.get<double>(kGmDevDoubles));
+  h.gmpoll.init();
   h.d_part = h.arena.get<double>(kDotParts);
   h.d_info = h.arena.get<int>(2);
   h.fr.assign(P.nfront, FrontRT());
@@ -312,19 +314,20 @@ struct Ws {
 // (refinement may hand over to GMRES, which then reuses its vectors)
 size_t outer_ws_doubles(const hssmf_opts& o, int64_t n) {
   const size_t nn = ((size_t)std::max<int64_t>(n, 1) + 31) & ~size_t(31);
-  return nn * (size_t)(std::max(1, std::min(o.restart, 200)) + 3);
+  return nn * (size_t)(std::max(1, std::min(o.restart, kGmMaxRestart)) + 3);
 }
 
-// restarted, left-preconditioned GMRES(m) with modified Gram-Schmidt on the
-// device and Givens rotations on the host; x0 = 0; stops on the true
-// relative residual
+// restarted, left-preconditioned GMRES(m) (Sec. 4.6) with the modified
+// Gram-Schmidt Arnoldi process and the Givens rotations on the device; x0 =
+// 0 (or the given iterate); stops on the true relative residual
 int gmres(Handle& h, int trans, const double* b, double* x, hssmf_info* info, Ws& ws, bool graph,
           bool from_x = false, int its0 = 0) {
-  const int n = h.P.n, m = std::max(1, std::min(h.o.restart, 200));
+  const int n = h.P.n, m = std::max(1, std::min(h.o.restart, kGmMaxRestart));
   double* V = ws.get((size_t)n * (m + 1));
   double* w = ws.get(n);
   double* r = ws.get(n);
-  double* hcol = h.d_scal;  // m+2 device scalars
+  const GmDev& gd = h.gm;
+  GmPoll& gp = h.gmpoll;
   const std::vector<double> nbs = sys_norms(h, b);
   const double nb = dnrm2(h, b, n);
   if (!from_x || nb == 0.0) launch_fill(x, n, 0.0, h.st);
@@ -334,7 +337,6 @@ int gmres(Handle& h, int trans, const double* b, double* x, hssmf_info* info, Ws
   }
   int its = 0;
   double rel = 1.0, beta0 = -1.0;
-  std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
   auto true_res = [&](const double* xx) {
     spmv(h, trans, xx, r, -1.0, 0.0);
     launch_axpy(r, b, n, nullptr, 1.0, 0, h.st);
@@ -348,52 +350,32 @@ int gmres(Handle& h, int trans, const double* b, double* x, hssmf_info* info, Ws
     double beta = dnrm2(h, w, n);
     if (beta0 < 0) beta0 = beta;
     if (beta == 0.0) break;
-    HIP_CHECK(hipMemcpyAsync(hcol, &beta, sizeof(double), hipMemcpyHostToDevice, h.st));
-    launch_axpy(V, w, n, hcol, 1.0, 1, h.st);  // v0 = w / beta
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int jd = 0;
+    launch_gm_start(V, w, n, beta, gd, m, h.st);  // v0 = w / beta, g = beta e1
     bool done = false;
+    // Arnoldi steps with the Gram-Schmidt sweep and the Givens rotations on
+    // the device; the host only waits for each step's residual estimate
+    // (mapped memory, no stream synchronization) to decide whether to go on
     for (int j = 0; j < m && its < h.o.max_it; ++j) {
       double* vj = V + (size_t)j * n;
       spmv(h, trans, vj, r, 1.0, 0.0);
       apply_inverse(h, trans, r, w, graph);
-      for (int i = 0; i <= j; ++i) {
-        launch_dot(w, V + (size_t)i * n, n, h.d_part, hcol + i, 0, h.st);
-        launch_axpy(w, V + (size_t)i * n, n, hcol + i, -1.0, 0, h.st);
-      }
-      launch_dot(w, w, n, h.d_part, hcol + j + 1, 1, h.st);
-      launch_axpy(V + (size_t)(j + 1) * n, w, n, hcol + j + 1, 1.0, 1, h.st);
-      std::vector<double> hc(j + 2);
-      HIP_CHECK(hipMemcpyAsync(hc.data(), hcol, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, h.st));
-      HIP_CHECK(hipStreamSynchronize(h.st));
-      h.stager.sync();
-      for (int i = 0; i < j; ++i) {
-        double t = cs[i] * hc[i] + sn[i] * hc[i + 1];
-        hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
-        hc[i] = t;
-      }
-      double den = std::hypot(hc[j], hc[j + 1]);
-      cs[j] = hc[j] / den;
-      sn[j] = hc[j + 1] / den;
-      hc[j] = den;
-      hc[j + 1] = 0.0;
-      for (int i = 0; i <= j; ++i) H[i + (size_t)j * (m + 1)] = hc[i];
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      ++its;
-      jd = j + 1;
-      bool est = std::fabs(g[j + 1]) <= h.o.tol * beta0;
-      if (est || its >= h.o.max_it || j == m - 1) {
-        // x_t = x + V y
-        for (int i = jd - 1; i >= 0; --i) {
-          double s = g[i];
-          for (int l = i + 1; l < jd; ++l) s -= H[i + (size_t)l * (m + 1)] * y[l];
-          y[i] = s / H[i + (size_t)i * (m + 1)];
+      const int tag = ++gp.tag;
+      if (n <= kArnoldiMaxN) {
+        launch_arnoldi(w, V, n, j, gd, gp.dev, tag, h.st);
+      } else {
+        for (int i = 0; i <= j; ++i) {
+          launch_dot(w, V + (size_t)i * n, n, h.d_part, gd.hcol + i, 0, h.st);
+          launch_axpy(w, V + (size_t)i * n, n, gd.hcol + i, -1.0, 0, h.st);
         }
-        HIP_CHECK(hipMemcpyAsync(w, x, sizeof(double) * n, hipMemcpyDeviceToDevice, h.st));
-        HIP_CHECK(hipMemcpyAsync(hcol + m + 2, y.data(), sizeof(double) * jd, hipMemcpyHostToDevice, h.st));
-        for (int i = 0; i < jd; ++i) launch_axpy(w, V + (size_t)i * n, n, hcol + m + 2 + i, 1.0, 0, h.st);
+        launch_dot(w, w, n, h.d_part, gd.hcol + j + 1, 1, h.st);
+        launch_axpy(V + (size_t)(j + 1) * n, w, n, gd.hcol + j + 1, 1.0, 1, h.st);
+        launch_givens(j, gd, gp.dev, tag, h.st);
+      }
+      const double est = gp.wait(tag);
+      ++its;
+      if (est <= h.o.tol * beta0 || its >= h.o.max_it || j == m - 1) {
+        // x_t = x + V y with y from the rotated Hessenberg system
+        launch_gm_update(w, x, V, n, j + 1, gd, h.st);
         rel = true_res(w);
         if (rel <= h.o.tol || j == m - 1 || its >= h.o.max_it) {
           HIP_CHECK(hipMemcpyAsync(x, w, sizeof(double) * n, hipMemcpyDeviceToDevice, h.st));
@@ -402,7 +384,6 @@ int gmres(Handle& h, int trans, const double* b, double* x, hssmf_info* info, Ws
         }
       }
     }
-    (void)jd;
     if (done) break;
   }
   HIP_CHECK(hipStreamSynchronize(h.st));

@@ -1,6 +1,8 @@
 // Vector kernels of the outer solvers: CSR sparse matrix-vector product,
 // dot products with device-resident results, axpy with device scalars, the
-// adjoint's entrywise gradient.
+// Arnoldi and Givens steps of GMRES, the adjoint's entrywise gradient.
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "vec.hpp"
 
@@ -84,6 +86,164 @@ __global__ void gather_kernel(double* y, const double* __restrict__ x, const int
 void launch_gather(double* y, const double* x, const int* map, int n, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(gather_kernel, dim3((n + 255) / 256), dim3(256), 0, s, y, x, map, n);
+  HIP_CHECK(hipGetLastError());
+}
+
+// ------------------------------------------------------------- GMRES ------
+
+GmDev gm_dev(double* base) {
+  GmDev d;
+  d.H = base;
+  base += (int64_t)(kGmMaxRestart + 1) * kGmMaxRestart;
+  d.cs = base;
+  base += kGmMaxRestart + 2;
+  d.sn = base;
+  base += kGmMaxRestart + 2;
+  d.g = base;
+  base += kGmMaxRestart + 2;
+  d.y = base;
+  base += kGmMaxRestart + 2;
+  d.hcol = base;
+  return d;
+}
+
+__global__ void gm_start_kernel(double* v0, const double* __restrict__ w, int n, double beta, GmDev d, int m) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v0[i] = w[i] / beta;
+  if (i <= m) d.g[i] = i == 0 ? beta : 0.0;
+}
+
+void launch_gm_start(double* v0, const double* w, int n, double beta, GmDev d, int m, hipStream_t s) {
+  const int cnt = std::max(n, m + 1);
+  hipLaunchKernelGGL(gm_start_kernel, dim3((cnt + 255) / 256), dim3(256), 0, s, v0, w, n, beta, d, m);
+  HIP_CHECK(hipGetLastError());
+}
+
+// the Givens step of GMRES for Hessenberg column j (h[0..j+1]): rotations
+// 0..j-1 applied in order, the new rotation zeroing h[j+1], the column stored
+// to H, g rotated; then the estimate |g[j+1]| and the tag to the host
+__device__ void givens_step(double* h, int j, GmDev d, GmStatus* status, int tag) {
+  for (int i = 0; i < j; ++i) {
+    const double t = d.cs[i] * h[i] + d.sn[i] * h[i + 1];
+    h[i + 1] = -d.sn[i] * h[i] + d.cs[i] * h[i + 1];
+    h[i] = t;
+  }
+  const double den = hypot(h[j], h[j + 1]);
+  d.cs[j] = h[j] / den;
+  d.sn[j] = h[j + 1] / den;
+  h[j] = den;
+  h[j + 1] = 0.0;
+  for (int i = 0; i <= j; ++i) d.H[i + (int64_t)j * (kGmMaxRestart + 1)] = h[i];
+  const double gj = d.g[j];
+  d.g[j + 1] = -d.sn[j] * gj;
+  d.g[j] = d.cs[j] * gj;
+  __hip_atomic_store(&status->est, fabs(d.g[j + 1]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(&status->tag, tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// sum over a 1024-thread workgroup, the same bits in every thread: butterfly
+// inside each wavefront, then every thread adds the 16 wavefront sums in
+// order.  red alternates between two buffers, so one barrier per call
+// suffices.
+__device__ double block_sum(double v, double (*red)[16], int& par) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if ((threadIdx.x & 63) == 0) red[par][threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < 16; ++w) s += red[par][w];
+  par ^= 1;
+  return s;
+}
+
+template <int PER>
+__global__ __launch_bounds__(1024) void arnoldi_kernel(const double* __restrict__ win, double* V, int n, int j,
+                                                        GmDev d, GmStatus* status, int tag) {
+  __shared__ double red[2][16];
+  __shared__ double hl[kGmMaxRestart + 2];
+  int par = 0;
+  const int tid = threadIdx.x;
+  double w[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int i = tid + 1024 * q;
+    w[q] = i < n ? win[i] : 0.0;
+  }
+  // modified Gram-Schmidt: h_i = <w, v_i>, then w -= h_i v_i, i = 0..j
+  for (int k = 0; k <= j; ++k) {
+    const double* vk = V + (int64_t)k * n;
+    double v[PER];
+    double p = 0.0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int i = tid + 1024 * q;
+      v[q] = i < n ? vk[i] : 0.0;
+      p += w[q] * v[q];
+    }
+    const double hk = block_sum(p, red, par);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) w[q] -= hk * v[q];
+    if (tid == 0) hl[k] = hk;
+  }
+  double p = 0.0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) p += w[q] * w[q];
+  const double hn = sqrt(block_sum(p, red, par));
+  double* vn = V + (int64_t)(j + 1) * n;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int i = tid + 1024 * q;
+    if (i < n) vn[i] = w[q] / hn;
+  }
+  if (tid == 0) {
+    hl[j + 1] = hn;
+    givens_step(hl, j, d, status, tag);
+  }
+}
+
+void launch_arnoldi(const double* w, double* V, int n, int j, GmDev d, GmStatus* status, int tag, hipStream_t s) {
+  REQUIRE(n <= kArnoldiMaxN && j < kGmMaxRestart, HSSMF_EINVAL, "arnoldi: problem too large for one workgroup");
+  const int per = (n + 1023) / 1024;
+  if (per <= 4) hipLaunchKernelGGL(arnoldi_kernel<4>, dim3(1), dim3(1024), 0, s, w, V, n, j, d, status, tag);
+  else if (per <= 8) hipLaunchKernelGGL(arnoldi_kernel<8>, dim3(1), dim3(1024), 0, s, w, V, n, j, d, status, tag);
+  else hipLaunchKernelGGL(arnoldi_kernel<16>, dim3(1), dim3(1024), 0, s, w, V, n, j, d, status, tag);
+  HIP_CHECK(hipGetLastError());
+}
+
+__global__ void givens_kernel(int j, GmDev d, GmStatus* status, int tag) {
+  if (threadIdx.x == 0) givens_step(d.hcol, j, d, status, tag);
+}
+
+void launch_givens(int j, GmDev d, GmStatus* status, int tag, hipStream_t s) {
+  REQUIRE(j < kGmMaxRestart, HSSMF_EINVAL, "givens: restart too large");
+  hipLaunchKernelGGL(givens_kernel, dim3(1), dim3(64), 0, s, j, d, status, tag);
+  HIP_CHECK(hipGetLastError());
+}
+
+// back substitution with the rotated Hessenberg matrix (one thread: k is at
+// most the restart length)
+__global__ void gm_solve_kernel(GmDev d, int k) {
+  if (threadIdx.x != 0) return;
+  for (int i = k - 1; i >= 0; --i) {
+    double s = d.g[i];
+    for (int l = i + 1; l < k; ++l) s -= d.H[i + (int64_t)l * (kGmMaxRestart + 1)] * d.y[l];
+    d.y[i] = s / d.H[i + (int64_t)i * (kGmMaxRestart + 1)];
+  }
+}
+
+// out = x + sum_l y_l V(:, l), terms added in order of l
+__global__ void gm_combine_kernel(double* out, const double* __restrict__ x, const double* __restrict__ V, int n, int k,
+                                  GmDev d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = x[i];
+  for (int l = 0; l < k; ++l) acc += d.y[l] * V[i + (int64_t)l * n];
+  out[i] = acc;
+}
+
+void launch_gm_update(double* out, const double* x, const double* V, int n, int k, GmDev d, hipStream_t s) {
+  hipLaunchKernelGGL(gm_solve_kernel, dim3(1), dim3(64), 0, s, d, k);
+  if (n > 0) hipLaunchKernelGGL(gm_combine_kernel, dim3((n + 255) / 256), dim3(256), 0, s, out, x, V, n, k, d);
   HIP_CHECK(hipGetLastError());
 }
 

@@ -1,10 +1,12 @@
 // Host-side structures of a factorization: symbolic plan, per-front device
 // storage, HSS node storage.
 #pragma once
+#include <chrono>
 #include <memory>
 #include <vector>
 
 #include "kernels.hpp"
+#include "vec.hpp"
 
 namespace hssmf {
 
@@ -170,6 +172,34 @@ struct IdPoll {
   }
 };
 
+// GMRES progress in mapped, coherent pinned host memory: the device's
+// Givens step stores each Arnoldi step's residual estimate and tag there,
+// and the host waits for the tag without draining the stream
+struct GmPoll {
+  GmStatus* host = nullptr;
+  GmStatus* dev = nullptr;
+  int tag = 0;
+  void init() {
+    if (host) return;
+    HIP_CHECK(hipHostMalloc((void**)&host, sizeof(GmStatus), hipHostMallocMapped | hipHostMallocCoherent));
+    HIP_CHECK(hipHostGetDevicePointer((void**)&dev, host, 0));
+    host->est = 0.0;
+    host->tag = 0;
+  }
+  // the estimate of the step tagged t, once the device has stored it
+  double wait(int t) {
+    const auto t0 = std::chrono::steady_clock::now();
+    for (unsigned spin = 0;; ++spin) {
+      if (__atomic_load_n(&host->tag, __ATOMIC_ACQUIRE) == t) return *(volatile double*)&host->est;
+      if ((spin & 1023) == 1023 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(120))
+        throw Error(HSSMF_EDEVICE, "GMRES: no Arnoldi step result from the device");
+    }
+  }
+  ~GmPoll() {
+    if (host) (void)hipHostFree(host);
+  }
+};
+
 struct Handle {
   Plan P;
   hssmf_opts o{};
@@ -181,6 +211,8 @@ struct Handle {
   Arena* cur = &arena;
   Stager stager;
   IdPoll idpoll;
+  GmPoll gmpoll;
+  GmDev gm{};                  // GMRES state on the device
   std::vector<Op> sops[2][2];  // [trans][0 = forward, 1 = backward]
   // status of the last numeric factorization: HSSMF_OK when the factors and
   // the recorded solve operations are valid, else the error it ended with

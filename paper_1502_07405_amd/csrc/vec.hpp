@@ -6,6 +6,43 @@ namespace hssmf {
 
 constexpr int kDotParts = 512;
 
+// Device state of GMRES(m) (Sec. 4.6): the Hessenberg matrix after the
+// Givens rotations (upper triangular, (kGmMaxRestart + 1) x kGmMaxRestart,
+// column-major), the rotations, the rotated right-hand side g and the
+// least-squares solution y.  One per handle.
+constexpr int kGmMaxRestart = 200;
+struct GmDev {
+  double* H;
+  double* cs;
+  double* sn;
+  double* g;
+  double* y;
+  double* hcol;   // the current Hessenberg column before rotation (j + 2 entries)
+};
+constexpr int64_t kGmDevDoubles = (int64_t)(kGmMaxRestart + 1) * kGmMaxRestart + 6 * (kGmMaxRestart + 2);
+GmDev gm_dev(double* base);   // carve a GmDev out of kGmDevDoubles doubles
+// what an Arnoldi step reports to the host through mapped memory: the
+// estimated residual |g[j+1]| and the step's tag, stored last
+struct GmStatus {
+  double est;
+  int tag;
+  int pad;
+};
+
+// g = (beta, 0, ..., 0) of length m + 1, v0 = w / beta
+void launch_gm_start(double* v0, const double* w, int n, double beta, GmDev d, int m, hipStream_t s);
+// One Arnoldi step j of GMRES on the device: modified Gram-Schmidt of w
+// against V[:, 0..j] (ld n), the new basis vector V[:, j+1] = w / ||w||, the
+// previous Givens rotations applied to the new Hessenberg column, the new
+// rotation, the updated g, and the estimate |g[j+1]| with `tag` stored to
+// *status.  n at most kArnoldiMaxN: one workgroup, w in registers.
+constexpr int kArnoldiMaxN = 16384;
+void launch_arnoldi(const double* w, double* V, int n, int j, GmDev d, GmStatus* status, int tag, hipStream_t s);
+// the rotation part alone, for a Hessenberg column already in d.hcol
+void launch_givens(int j, GmDev d, GmStatus* status, int tag, hipStream_t s);
+// y = H(0:k, 0:k)^{-1} g(0:k), then out = x + V(:, 0:k) y
+void launch_gm_update(double* out, const double* x, const double* V, int n, int k, GmDev d, hipStream_t s);
+
 void launch_spmv(const int64_t* rp, const int* ci, const double* v, const int64_t* vidx, const double* x, double* y,
                  int n, double alpha, double beta, hipStream_t s);
 void launch_dot(const double* a, const double* b, int n, double* part, double* out, int sqrt_out, hipStream_t s);
