@@ -33,9 +33,9 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 (vector and matrix cores)
 HBM_PEAK_BPS = 8.0e12     # MI355X HBM3E
 
 
-def hss_opts(prec):
+def hss_opts(prec, update="dense"):
     return dict(min_sep_hss=512, leaf_size=64, rel_tol=1e-6, d0=128, dd=128, p=10, tol=1e-10, max_it=50,
-                gemm_prec=prec)
+                gemm_prec=prec, hss_update=update)
 
 
 def time_steps(fac, vals, bt, steps, warmup, torch):
@@ -327,6 +327,18 @@ def main():
             "speedup": sec64 / sec}
     else:
         extra["fp64_hss_step_s"] = sec
+    # the other form of an HSS child's update matrix: expanded densely once
+    # (the headline keeps it in low-rank form, Sec. 4.4)
+    other = "dense" if opts["hss_update"] == "lowrank" else "lowrank"
+    fu = H.Factorization(A, order, **dict(opts, hss_update=other))
+    su, xu, iu = time_steps(fu, vals, bt, args.steps, args.warmup, torch)
+    stu = fu.stats()
+    fu.close()
+    extra["update_form"] = {"headline": opts["hss_update"],
+                            "headline_factor_bytes": st["factor_bytes"], "headline_peak_bytes": st["peak_bytes"],
+                            other: {"step_s": su, "iterations": iu[-1][0], "rel_residual": relres(xu),
+                                    "factor_bytes": stu["factor_bytes"], "peak_bytes": stu["peak_bytes"]}}
+    progress(f"update matrices {other}: {su:.4f} s per step")
     if args.prec == "fp32" and not args.no_bf16:
         # BF16 products: their rounding (2^-9) sits far above eps = 1e-6, so
         # the adaptive sampling keeps growing; capped at d = 1280

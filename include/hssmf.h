@@ -128,8 +128,18 @@ typedef struct {
                           HSS front's random matrix, samples and low-rank
                           Schur factors for hssmf_front_data (device memory
                           of O(n d + m_k u) per front); 0 (default): not */
+  int32_t hss_update;  /* HSSMF_UPDATE_*: how an HSS front's update matrix
+                          F22 - Theta^* Phi reaches an HSS parent */
 } hssmf_opts;
 
+/* hss_update: LOWRANK = kept as the HSS generators of F22 with Theta^* and
+ * Phi; the parent samples it by an HSS matrix-vector product minus
+ * Theta^* (Phi X) and takes its entries from the generators (Sec. 4.4,
+ * Sec. 4.5); DENSE = expanded once into a u x u matrix that the parent
+ * multiplies and reads.  A dense parent always receives the dense
+ * expansion. */
+#define HSSMF_UPDATE_LOWRANK 0
+#define HSSMF_UPDATE_DENSE 1
 
 /* id_kernel: STEPWISE = one launch per pivot step for each batch of IDs;
  * COOPERATIVE = when every workgroup of a batch fits on the device at once,
@@ -163,13 +173,17 @@ typedef struct {
   int64_t factor_bytes;     /* device bytes held by the factors */
   double t_plan_ms, t_factor_ms;     /* host planning + upload, numeric factor */
   double flops_factor;      /* algorithmic flops of the numeric factorization */
+  int64_t peak_bytes;       /* bound on the device bytes in use during the last
+                               numeric factorization: the sum of each of the
+                               handle's arenas' high-water marks */
 } hssmf_stats;
 
 /* Fill *o with defaults: rel_tol 1e-6, leaf_size 64, min_sep_hss INT32_MAX
  * (pure multifrontal), d0 128, dd 128, p 10, d_max 4096, seed 0, FP64,
  * iterative refinement, restart 30, tol 1e-10, max_it 50, resident ID
  * kernel (the stepwise one where it does not apply), sweeps launched one by
- * one (no graph), autotuned GEMM tiles, abs_tol 0. */
+ * one (no graph), autotuned GEMM tiles, abs_tol 0, update matrices expanded
+ * densely. */
 int hssmf_default_opts(hssmf_opts* o);
 
 /* Symbolic analysis, upload and numeric factorization (Sec. 3.2, Sec. 4).
@@ -285,7 +299,8 @@ int hssmf_profile_read(int32_t kclass, double* ms, int64_t* launches, double* fl
 /* Intermediate results of one HSS front of the last numeric factorization,
  * for checking each stage of the method on its own (diagnostics; the
  * factorization must have been made with keep_stages = 1, except for
- * HSSMF_STAGE_UPDATE).  Rows are the front's local indices: the separator
+ * HSSMF_STAGE_UPDATE of a front whose update matrix was expanded densely:
+ * hss_update = DENSE, or a dense parent).  Rows are the front's local indices: the separator
  * in elimination order, then the update set in ascending new numbering.
  *  RANDOM        R (n x d), the random matrix at the final d (Sec. 2.2.1);
  *  SAMPLES_ROW   S^r = F R (n x d), SAMPLES_COL S^c = F^T R (Eq. FtimesR);

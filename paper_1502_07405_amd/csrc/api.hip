@@ -194,6 +194,7 @@ void numeric(Handle& h) {
   h.drop_graphs();   // the sweeps change with the factors
   h.narena.release();
   h.cur = &h.narena;
+  for (Arena* a : {&h.arena, &h.narena, &h.larena, &h.sarena}) a->reset_peak();
   double t0 = now_ms();
   try {
     numeric_factor(h);
@@ -238,6 +239,7 @@ void numeric(Handle& h) {
   h.stats.max_d = maxd;
   h.stats.growth_rounds = rounds;
   h.stats.factor_bytes = (int64_t)(h.arena.used() + h.narena.used());
+  h.stats.peak_bytes = (int64_t)(h.arena.peak() + h.narena.peak() + h.larena.peak() + h.sarena.peak());
 }
 
 }  // namespace
@@ -520,6 +522,7 @@ int hssmf_default_opts(hssmf_opts* o) {
   o->tol = 1e-10;
   o->max_it = 50;
   o->id_kernel = HSSMF_ID_RESIDENT;
+  o->hss_update = HSSMF_UPDATE_DENSE;
   o->use_graph = 0;   // capture after every factorization costs more than replay saves
   return HSSMF_OK;
 }
@@ -533,7 +536,8 @@ bool opts_ok(const hssmf_opts* o) {
            o->restart < 1 || o->max_it < 0 || o->gemm_prec < 0 || o->gemm_prec > 2 || o->id_kernel < 0 ||
            o->id_kernel > 2 || o->use_graph < 0 || o->use_graph > 1 ||
            !(o->gemm_tile == 0 || o->gemm_tile == 64 || o->gemm_tile == 65 || o->gemm_tile == 128) ||
-           !(o->abs_tol >= 0.0) || o->keep_stages < 0 || o->keep_stages > 1);
+           !(o->abs_tol >= 0.0) || o->keep_stages < 0 || o->keep_stages > 1 || o->hss_update < 0 ||
+           o->hss_update > 1);
 }
 
 // a CSR matrix in host memory: the caller's arrays when they are host

@@ -51,6 +51,9 @@ class Arena {
   }
   void release();
   size_t used() const { return used_; }
+  // high-water mark of used() since the last reset_peak()
+  size_t peak() const { return peak_; }
+  void reset_peak() { peak_ = used_; }
   // scoped marks: everything allocated after mark() is reclaimed by reset()
   struct Mark {
     size_t chunk, off, used;
@@ -66,6 +69,7 @@ class Arena {
   std::vector<Chunk> chunks_;
   size_t off_ = 0;
   size_t used_ = 0;
+  size_t peak_ = 0;
 };
 
 // returns every released chunk held for reuse to the runtime

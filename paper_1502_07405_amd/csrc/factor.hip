@@ -266,6 +266,165 @@ void gen_random(Handle& h, HFront& F, int c0, int nc) {
   }
 }
 
+// A child whose update matrix U = F22 - Theta^* Phi is kept in low-rank
+// form, sampled for its parent (Sec. 4.4): U X = F22 X - Theta^* (Phi X)
+// and U^T X = F22^T X - Phi^T (Theta X) with X = R(map, cols), F22 X by
+// the HSS matrix-vector product of the q-subtree: up-sweep through the
+// interpolative generators (V^T X, level by level from the leaves), the
+// sibling couplings B12, B21, down-sweep through U from the top, the leaf
+// blocks D; F22^T X likewise with U and V exchanged, B transposed and D^T.
+// Every product is a batched FP64 GEMM over all jobs; the leaf terms go
+// straight into the parent's samples through the child-to-parent row map.
+struct LrJob {
+  HFront* F;        // the parent
+  HFront* C;        // the child in low-rank form
+  const int* map;   // child update index -> parent local row (device)
+  int64_t off;      // first sample column times F->n
+};
+
+void sample_lowrank(Handle& h, const std::vector<LrJob>& jobs, int nc) {
+  if (jobs.empty() || nc <= 0) return;
+  // per non-leaf node of each q-subtree: stacked children's up-sweep
+  // results (XS: V^T side, mc rows; XT: U^T side, mr rows) and down-sweep
+  // inputs (YS: mr rows; YT: mc rows)
+  struct Buf {
+    double *XS = nullptr, *YS = nullptr, *XT = nullptr, *YT = nullptr;
+  };
+  std::vector<std::vector<Buf>> bufs(jobs.size());
+  int maxh = 0;
+  for (size_t j = 0; j < jobs.size(); ++j) {
+    HFront& C = *jobs[j].C;
+    bufs[j].assign(C.nd.size(), Buf{});
+    for (int t = 0; t < (int)C.nd.size(); ++t) {
+      const HNode& nd = C.nd[t];
+      if (t == C.root || nd.lo < C.s || nd.leaf()) continue;
+      Buf& b = bufs[j][t];
+      b.XS = salloc(h, (int64_t)std::max(nd.mc, 1) * nc);
+      b.YT = salloc(h, (int64_t)std::max(nd.mc, 1) * nc);
+      b.XT = salloc(h, (int64_t)std::max(nd.mr, 1) * nc);
+      b.YS = salloc(h, (int64_t)std::max(nd.mr, 1) * nc);
+    }
+    maxh = std::max(maxh, C.nd[C.q].height);
+  }
+  auto in_q = [](const HFront& C, int t) { return t != C.root && C.nd[t].lo >= C.s; };
+  // offsets of a node's blocks in its parent's stacked buffers
+  auto offs = [](const HFront& C, int t, int& oc, int& orr) {
+    const HNode& p = C.nd[C.nd[t].parent];
+    const bool first = p.kid[0] == t;
+    oc = first ? 0 : C.nd[p.kid[0]].c;
+    orr = first ? 0 : C.nd[p.kid[0]].r;
+  };
+  // up-sweep
+  for (int hh = 0; hh < maxh; ++hh) {
+    std::vector<GemmDesc> g;
+    for (size_t j = 0; j < jobs.size(); ++j) {
+      const LrJob& jb = jobs[j];
+      HFront& F = *jb.F;
+      HFront& C = *jb.C;
+      for (int t = 0; t < (int)C.nd.size(); ++t) {
+        const HNode& nd = C.nd[t];
+        if (!in_q(C, t) || t == C.q || nd.height != hh) continue;
+        const Buf& pb = bufs[j][nd.parent];
+        const HNode& p = C.nd[nd.parent];
+        int oc, orr;
+        offs(C, t, oc, orr);
+        if (nd.leaf()) {
+          const int* bm = jb.map + (nd.lo - C.s);
+          const double* X = F.R + jb.off;
+          g.push_back(G(nd.Vd, nd.m(), 1, X, F.n, 0, pb.XS + oc, p.mc, nd.c, nc, nd.m(), 1.0, 0.0, bm));
+          g.push_back(G(nd.Ud, nd.m(), 1, X, F.n, 0, pb.XT + orr, p.mr, nd.r, nc, nd.m(), 1.0, 0.0, bm));
+        } else {
+          const Buf& b = bufs[j][t];
+          g.push_back(G(nd.Vd, nd.mc, 1, b.XS, nd.mc, 0, pb.XS + oc, p.mc, nd.c, nc, nd.mc, 1.0, 0.0));
+          g.push_back(G(nd.Ud, nd.mr, 1, b.XT, nd.mr, 0, pb.XT + orr, p.mr, nd.r, nc, nd.mr, 1.0, 0.0));
+        }
+      }
+    }
+    run_gemm(h, g);
+  }
+  // sibling couplings at every non-leaf node
+  {
+    std::vector<GemmDesc> g;
+    for (size_t j = 0; j < jobs.size(); ++j) {
+      HFront& C = *jobs[j].C;
+      for (int t = 0; t < (int)C.nd.size(); ++t) {
+        const HNode& nd = C.nd[t];
+        if (!in_q(C, t) || nd.leaf()) continue;
+        const Buf& b = bufs[j][t];
+        const HNode& a = C.nd[nd.kid[0]];
+        const HNode& e = C.nd[nd.kid[1]];
+        const int l12 = std::max(a.r, 1), l21 = std::max(e.r, 1);
+        g.push_back(G(nd.B12, l12, 0, b.XS + a.c, nd.mc, 0, b.YS, nd.mr, a.r, nc, e.c, 1.0, 0.0));
+        g.push_back(G(nd.B21, l21, 0, b.XS, nd.mc, 0, b.YS + a.r, nd.mr, e.r, nc, a.c, 1.0, 0.0));
+        g.push_back(G(nd.B21, l21, 1, b.XT + a.r, nd.mr, 0, b.YT, nd.mc, a.c, nc, e.r, 1.0, 0.0));
+        g.push_back(G(nd.B12, l12, 1, b.XT, nd.mr, 0, b.YT + a.c, nd.mc, e.c, nc, a.r, 1.0, 0.0));
+      }
+    }
+    run_gemm(h, g);
+  }
+  // down-sweep through the non-leaf nodes below q, parents first
+  for (int hh = maxh - 1; hh >= 1; --hh) {
+    std::vector<GemmDesc> g;
+    for (size_t j = 0; j < jobs.size(); ++j) {
+      HFront& C = *jobs[j].C;
+      for (int t = 0; t < (int)C.nd.size(); ++t) {
+        const HNode& nd = C.nd[t];
+        if (!in_q(C, t) || t == C.q || nd.leaf() || nd.height != hh) continue;
+        const Buf& b = bufs[j][t];
+        const Buf& pb = bufs[j][nd.parent];
+        const HNode& p = C.nd[nd.parent];
+        int oc, orr;
+        offs(C, t, oc, orr);
+        g.push_back(G(nd.Ud, nd.mr, 0, pb.YS + orr, p.mr, 0, b.YS, nd.mr, nd.mr, nc, nd.r, 1.0, 1.0));
+        g.push_back(G(nd.Vd, nd.mc, 0, pb.YT + oc, p.mc, 0, b.YT, nd.mc, nd.mc, nc, nd.c, 1.0, 1.0));
+      }
+    }
+    run_gemm(h, g);
+  }
+  // leaves: D X (D^T X), then U Y (V Y), into the parent's samples
+  for (int part = 0; part < 2; ++part) {
+    std::vector<GemmDesc> g;
+    for (size_t j = 0; j < jobs.size(); ++j) {
+      const LrJob& jb = jobs[j];
+      HFront& F = *jb.F;
+      HFront& C = *jb.C;
+      for (int t = 0; t < (int)C.nd.size(); ++t) {
+        const HNode& nd = C.nd[t];
+        if (!in_q(C, t) || !nd.leaf()) continue;
+        const int* rm = jb.map + (nd.lo - C.s);
+        const int m = nd.m();
+        if (part == 0) {
+          g.push_back(G(nd.D, m, 0, F.R + jb.off, F.n, 0, F.Sr + jb.off, F.n, m, nc, m, 1.0, 1.0, rm, rm));
+          g.push_back(G(nd.D, m, 1, F.R + jb.off, F.n, 0, F.Sc + jb.off, F.n, m, nc, m, 1.0, 1.0, rm, rm));
+        } else if (t != C.q) {
+          const Buf& pb = bufs[j][nd.parent];
+          const HNode& p = C.nd[nd.parent];
+          int oc, orr;
+          offs(C, t, oc, orr);
+          g.push_back(G(nd.Ud, m, 0, pb.YS + orr, p.mr, 0, F.Sr + jb.off, F.n, m, nc, nd.r, 1.0, 1.0, nullptr, rm));
+          g.push_back(G(nd.Vd, m, 0, pb.YT + oc, p.mc, 0, F.Sc + jb.off, F.n, m, nc, nd.c, 1.0, 1.0, nullptr, rm));
+        }
+      }
+    }
+    run_gemm(h, g);
+  }
+  // the low-rank Schur term
+  std::vector<GemmDesc> g1, g2;
+  for (const LrJob& jb : jobs) {
+    HFront& F = *jb.F;
+    HFront& C = *jb.C;
+    if (C.mk == 0) continue;
+    double* T1 = salloc(h, (int64_t)C.mk * nc);
+    double* T2 = salloc(h, (int64_t)C.mk * nc);
+    g1.push_back(G(C.Phi, C.mk, 0, F.R + jb.off, F.n, 0, T1, C.mk, C.mk, nc, C.u, 1.0, 0.0, jb.map));
+    g1.push_back(G(C.ThT, C.mk, 0, F.R + jb.off, F.n, 0, T2, C.mk, C.mk, nc, C.u, 1.0, 0.0, jb.map));
+    g2.push_back(G(C.ThT, C.mk, 1, T1, C.mk, 0, F.Sr + jb.off, F.n, C.u, nc, C.mk, -1.0, 1.0, nullptr, jb.map));
+    g2.push_back(G(C.Phi, C.mk, 1, T2, C.mk, 0, F.Sc + jb.off, F.n, C.u, nc, C.mk, -1.0, 1.0, nullptr, jb.map));
+  }
+  run_gemm(h, g1);
+  run_gemm(h, g2);
+}
+
 // columns [c0, c0+nc) of S^r = F R and S^c = F^T R (Eq. FtimesR): the
 // original entries by a sparse product, each child's update matrix by one
 // GEMM whose B rows and C rows go through the child-to-parent map
@@ -282,6 +441,7 @@ void sample(Handle& h, const std::vector<HFront*>& fs, const std::vector<int>& c
   launch_spmm(h.stager.put_vec(sp, h.st), (int)sp.size(), maxr, nc, h.st);
   for (int slot = 0; slot < 2; ++slot) {
     std::vector<GemmDesc> g;
+    std::vector<LrJob> lr;
     for (size_t i = 0; i < fs.size(); ++i) {
       HFront& F = *fs[i];
       const FrontPlan& fp = h.P.fr[F.f];
@@ -292,7 +452,9 @@ void sample(Handle& h, const std::vector<HFront*>& fs, const std::vector<int>& c
       if (u == 0) continue;
       const int* map = h.fr[F.f].d_kidmap[slot];
       const int64_t off = (int64_t)c0[i] * F.n;
-      if (h.o.gemm_prec == HSSMF_PREC_FP64) {
+      if (K.hidx >= 0 && h.hf[K.hidx].lowrank) {
+        lr.push_back({&F, &h.hf[K.hidx], map, off});
+      } else if (h.o.gemm_prec == HSSMF_PREC_FP64) {
         g.push_back(G(K.U, K.ldu, 0, F.R + off, F.n, 0, F.Sr + off, F.n, u, nc, u, 1.0, 1.0, map, map));
         g.push_back(G(K.U, K.ldu, 1, F.R + off, F.n, 0, F.Sc + off, F.n, u, nc, u, 1.0, 1.0, map, map));
       } else {
@@ -304,6 +466,7 @@ void sample(Handle& h, const std::vector<HFront*>& fs, const std::vector<int>& c
       }
     }
     run_gemm(h, g, h.gt());
+    sample_lowrank(h, lr, nc);
   }
 }
 
@@ -404,6 +567,7 @@ FrontOpDev* front_ops(Handle& h, const std::vector<HFront*>& fs) {
       int c = fp.kids[k];
       if (h.P.fr[c].u == 0) continue;
       o.U[o.nkids] = h.fr[c].U;
+      o.hk[o.nkids] = h.fr[c].hidx >= 0 && h.hf[h.fr[c].hidx].lowrank ? h.hf[h.fr[c].hidx].kdev : nullptr;
       o.ldu[o.nkids] = h.fr[c].ldu;
       o.inv[o.nkids] = h.fr[F->f].d_inv[k];
       o.nkids++;
@@ -450,6 +614,8 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
       }
       F->Dk = nullptr; F->ipivk = nullptr; F->mk = 0;
       F->Vbark = F->ThT = F->Phi = F->Upd = nullptr;
+      F->lowrank = false;
+      F->kdev = nullptr;
       F->kR = F->kSr = F->kSc = F->kTh = F->kPhi = nullptr;
       F->kd = 0;
       F->UpdLP = nullptr;
@@ -1070,6 +1236,51 @@ void ulv_level(Handle& h, std::vector<HFront*>& fs, const int* iota) {
   blocked_lu(h, lu);
 }
 
+// Device table of a front's update matrix in low-rank form (the q-subtree
+// in preorder, the leaf of every update row, Theta^T and Phi) for its
+// parent's entry extraction (Sec. 4.5)
+void build_kid_table(Handle& h, HFront& F) {
+  std::vector<int> order, tix(F.nd.size(), -1), stack{F.q};
+  while (!stack.empty()) {
+    const int t = stack.back();
+    stack.pop_back();
+    tix[t] = (int)order.size();
+    order.push_back(t);
+    const HNode& nd = F.nd[t];
+    if (!nd.leaf()) {
+      stack.push_back(nd.kid[1]);
+      stack.push_back(nd.kid[0]);
+    }
+  }
+  std::vector<HssKidNode> tab(order.size());
+  std::vector<int> leaf_of(F.u, -1);
+  for (size_t i = 0; i < order.size(); ++i) {
+    const HNode& nd = F.nd[order[i]];
+    HssKidNode& k = tab[i];
+    k.lo = nd.lo - F.s;
+    k.m = nd.m();
+    k.r = nd.r;
+    k.parent = order[i] == F.q ? -1 : tix[nd.parent];
+    k.depth = k.parent < 0 ? 0 : tab[k.parent].depth + 1;   // parents precede children in preorder
+    k.kid0 = nd.leaf() ? -1 : tix[nd.kid[0]];
+    k.D = nd.leaf() ? nd.D : nullptr;
+    k.Ubig = nd.Ubig;
+    k.T12 = nd.T12;
+    k.T21 = nd.T21;
+    if (nd.leaf())
+      for (int r = 0; r < nd.m(); ++r) leaf_of[k.lo + r] = (int)i;
+  }
+  HssKidDev kd{};
+  kd.u = F.u;
+  kd.mk = F.mk;
+  kd.nnode = (int)tab.size();
+  kd.leaf_of = upload(h, leaf_of);
+  kd.nodes = upload(h, tab);
+  kd.ThT = F.ThT;
+  kd.Phi = F.Phi;
+  F.kdev = upload(h, std::vector<HssKidDev>{kd});
+}
+
 // nested bases U^big, V^big (Eq. nestedUV) of every non-root node, the
 // low-rank Schur product and the dense update matrix of each front
 void schur_level(Handle& h, std::vector<HFront*>& fs) {
@@ -1078,6 +1289,11 @@ void schur_level(Handle& h, std::vector<HFront*>& fs) {
   for (HFront* F : fs)
     if (F->q >= 0) { wu.push_back(F); maxh = std::max(maxh, F->nd[F->root].height); }
   if (wu.empty()) return;
+  // fronts whose update matrix an HSS parent takes in low-rank form
+  for (HFront* F : wu) {
+    const int par = h.P.fr[F->f].parent;
+    F->lowrank = h.o.hss_update == HSSMF_UPDATE_LOWRANK && par >= 0 && h.P.fr[par].hss;
+  }
   for (int hh = 0; hh < maxh; ++hh) {
     std::vector<InterpDesc> ip;
     std::vector<GemmDesc> g;
@@ -1124,8 +1340,8 @@ void schur_level(Handle& h, std::vector<HFront*>& fs) {
     g1.push_back(G(F.Vbark, mk, 0, rt.B21, q.r, 1, T1[i], mk, mk, q.r, k.c, 1.0, 0.0));
     T3[i] = salloc(h, (int64_t)std::max(k.r, 1) * u);   // B_kq Vbig_q^T : r_k x u
     g1.push_back(G(rt.B12, k.r, 0, q.Vbig, u, 1, T3[i], std::max(k.r, 1), k.r, u, q.c, 1.0, 0.0));
-    F.ThT = salloc(h, (int64_t)mk * u);
-    F.Phi = salloc(h, (int64_t)mk * u);
+    F.ThT = F.lowrank ? dalloc(h, (int64_t)mk * u) : salloc(h, (int64_t)mk * u);
+    F.Phi = F.lowrank ? dalloc(h, (int64_t)mk * u) : salloc(h, (int64_t)mk * u);
     g2.push_back(G(T1[i], mk, 0, q.Ubig, u, 1, F.ThT, mk, mk, u, q.r, 1.0, 0.0));
     g2.push_back(G(k.Ud, mk, 0, T3[i], std::max(k.r, 1), 0, F.Phi, mk, mk, u, k.r, 1.0, 0.0));
   }
@@ -1145,14 +1361,39 @@ void schur_level(Handle& h, std::vector<HFront*>& fs) {
       HIP_CHECK(hipMemcpyAsync(F->kTh, F->ThT, nb, hipMemcpyDeviceToDevice, h.st));
       HIP_CHECK(hipMemcpyAsync(F->kPhi, F->Phi, nb, hipMemcpyDeviceToDevice, h.st));
     }
-  // dense update matrix: expand F22 of the q-subtree, subtract Theta^* Phi
+  // B12 Vbig_b^T and B21 Vbig_a^T of every non-leaf node of the q-subtrees:
+  // the off-diagonal blocks of F22 are Ubig_a times them.  Kept with the
+  // factors for a front in low-rank form (entry extraction by its parent),
+  // temporaries for the dense expansion otherwise.
+  std::vector<GemmDesc> e1;
+  for (HFront* F : wu)
+    for (int t = 0; t < (int)F->nd.size(); ++t) {
+      HNode& nd = F->nd[t];
+      if (nd.leaf() || nd.lo < F->s) continue;
+      HNode& a = F->nd[nd.kid[0]];
+      HNode& b = F->nd[nd.kid[1]];
+      const int64_t na = (int64_t)std::max(a.r, 1) * b.m(), nb = (int64_t)std::max(b.r, 1) * a.m();
+      nd.T12 = F->lowrank ? dalloc(h, na) : salloc(h, na);
+      nd.T21 = F->lowrank ? dalloc(h, nb) : salloc(h, nb);
+      e1.push_back(G(nd.B12, a.r, 0, b.Vbig, b.m(), 1, nd.T12, std::max(a.r, 1), a.r, b.m(), b.c, 1.0, 0.0));
+      e1.push_back(G(nd.B21, b.r, 0, a.Vbig, a.m(), 1, nd.T21, std::max(b.r, 1), b.r, a.m(), a.c, 1.0, 0.0));
+    }
+  run_gemm(h, e1, h.gs());
+  // dense update matrix (a dense parent, the dense option, or kept for
+  // inspection): expand F22 of the q-subtree, subtract Theta^* Phi
+  std::vector<HFront*> ex;
   for (HFront* F : wu) {
-    F->Upd = dalloc(h, (int64_t)F->u * F->u);
-    h.fr[F->f].U = F->Upd;
+    F->Upd = nullptr;
+    h.fr[F->f].U = nullptr;
     h.fr[F->f].ldu = F->u;
+    if (!F->lowrank || h.o.keep_stages) ex.push_back(F);
+  }
+  for (HFront* F : ex) {
+    F->Upd = dalloc(h, (int64_t)F->u * F->u);
+    if (!F->lowrank) h.fr[F->f].U = F->Upd;
   }
   std::vector<CopyDesc> cp;
-  for (HFront* F : wu)
+  for (HFront* F : ex)
     for (int t = 0; t < (int)F->nd.size(); ++t) {
       HNode& nd = F->nd[t];
       if (!nd.leaf() || nd.lo < F->s) continue;
@@ -1160,31 +1401,27 @@ void schur_level(Handle& h, std::vector<HFront*>& fs) {
       cp.push_back(Cp(nd.D, nd.m(), nullptr, F->Upd + o + (int64_t)o * F->u, F->u, nd.m(), nd.m()));
     }
   run_copy(h, cp);
-  std::vector<GemmDesc> e1, e2;
-  std::vector<std::pair<double*, int>> tmp;
-  for (HFront* F : wu)
+  std::vector<GemmDesc> e2;
+  for (HFront* F : ex)
     for (int t = 0; t < (int)F->nd.size(); ++t) {
       HNode& nd = F->nd[t];
       if (nd.leaf() || nd.lo < F->s) continue;
       HNode& a = F->nd[nd.kid[0]];
       HNode& b = F->nd[nd.kid[1]];
-      // block (a, b) = Ubig_a B12 Vbig_b^T ; block (b, a) = Ubig_b B21 Vbig_a^T
-      double* ta = salloc(h, (int64_t)std::max(a.r, 1) * b.m());
-      double* tb = salloc(h, (int64_t)std::max(b.r, 1) * a.m());
-      e1.push_back(G(nd.B12, a.r, 0, b.Vbig, b.m(), 1, ta, std::max(a.r, 1), a.r, b.m(), b.c, 1.0, 0.0));
-      e1.push_back(G(nd.B21, b.r, 0, a.Vbig, a.m(), 1, tb, std::max(b.r, 1), b.r, a.m(), a.c, 1.0, 0.0));
+      // block (a, b) = Ubig_a (B12 Vbig_b^T) ; block (b, a) = Ubig_b (B21 Vbig_a^T)
       const int oa = a.lo - F->s, ob = b.lo - F->s;
-      e2.push_back(G(a.Ubig, a.m(), 0, ta, std::max(a.r, 1), 0, F->Upd + oa + (int64_t)ob * F->u, F->u, a.m(),
+      e2.push_back(G(a.Ubig, a.m(), 0, nd.T12, std::max(a.r, 1), 0, F->Upd + oa + (int64_t)ob * F->u, F->u, a.m(),
                      b.m(), a.r, 1.0, 0.0));
-      e2.push_back(G(b.Ubig, b.m(), 0, tb, std::max(b.r, 1), 0, F->Upd + ob + (int64_t)oa * F->u, F->u, b.m(),
+      e2.push_back(G(b.Ubig, b.m(), 0, nd.T21, std::max(b.r, 1), 0, F->Upd + ob + (int64_t)oa * F->u, F->u, b.m(),
                      a.m(), b.r, 1.0, 0.0));
     }
-  run_gemm(h, e1, h.gs());
   run_gemm(h, e2, h.gs());
-  std::vector<GemmDesc> s;
+  std::vector<GemmDesc> sg;
+  for (HFront* F : ex)
+    sg.push_back(G(F->ThT, F->mk, 1, F->Phi, F->mk, 0, F->Upd, F->u, F->u, F->u, F->mk, -1.0, 1.0));
+  run_gemm(h, sg, h.gs());
   for (HFront* F : wu)
-    s.push_back(G(F->ThT, F->mk, 1, F->Phi, F->mk, 0, F->Upd, F->u, F->u, F->u, F->mk, -1.0, 1.0));
-  run_gemm(h, s, h.gs());
+    if (F->lowrank) build_kid_table(h, *F);
 }
 
 }  // namespace
@@ -1219,7 +1456,7 @@ static void debug_fronts(Handle& h, std::vector<HFront*>& fs) {
     if (F->q >= 0)
       std::fprintf(stderr, " mk %d |Th| %.6e |Phi| %.6e |U| %.6e |Dk| %.6e", F->mk,
                    dev_fro(h, F->ThT, (int64_t)F->mk * F->u), dev_fro(h, F->Phi, (int64_t)F->mk * F->u),
-                   dev_fro(h, F->Upd, (int64_t)F->u * F->u), dev_fro(h, F->Dk, (int64_t)F->mk * F->mk));
+                   F->Upd ? dev_fro(h, F->Upd, (int64_t)F->u * F->u) : -1.0, dev_fro(h, F->Dk, (int64_t)F->mk * F->mk));
     std::fprintf(stderr, "\n");
   }
 }
@@ -1298,7 +1535,7 @@ void numeric_factor(Handle& h) {
         for (HFront* F : fs)
           for (int c : P.fr[F->f].kids) {
             const int u = P.fr[c].u;
-            if (u == 0) continue;
+            if (u == 0 || !h.fr[c].U) continue;   // a child in low-rank form has no dense copy
             void* lp = h.cur->alloc((size_t)u * u * (bf ? 2 : 4));
             h.fr[c].Ulp = lp;
             if (bf) launch_copy_bf16(h, h.fr[c].U, h.fr[c].ldu, lp, u);

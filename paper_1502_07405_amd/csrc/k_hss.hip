@@ -212,6 +212,39 @@ void launch_round_lp(double* x, void* lp, int64_t n, int to_bf16, hipStream_t s)
 // ---------------------------------------------------------- extraction ---
 // F_i(I, J) = A_i(I, J) + sum over children of U_child(inv(I), inv(J))
 // (the element access that Alg. 1 needs for D and B, Sec. 4.5)
+// entry (a, b) of a child's update matrix F22 - Theta^* Phi in low-rank
+// form: F22 from a leaf block or from Ubig of the lowest common ancestor's
+// row-side child times B Vbig^T of the column side, minus row a of Theta^*
+// times column b of Phi
+__device__ double hss_kid_entry(const HssKidDev& K, int a, int b) {
+  const HssKidNode* N = K.nodes;
+  int x = K.leaf_of[a], y = K.leaf_of[b];
+  double v;
+  if (x == y) {
+    const HssKidNode& L = N[x];
+    v = L.D[(a - L.lo) + (int64_t)(b - L.lo) * L.m];
+  } else {
+    while (N[x].depth > N[y].depth) x = N[x].parent;
+    while (N[y].depth > N[x].depth) y = N[y].parent;
+    while (N[x].parent != N[y].parent) {
+      x = N[x].parent;
+      y = N[y].parent;
+    }
+    const HssKidNode& P = N[N[x].parent];
+    const HssKidNode& X = N[x];
+    const HssKidNode& Y = N[y];
+    const double* T = (x == P.kid0 ? P.T12 : P.T21) + (int64_t)(b - Y.lo) * (X.r > 1 ? X.r : 1);
+    const double* U = X.Ubig + (a - X.lo);
+    v = 0.0;
+    for (int l = 0; l < X.r; ++l) v += U[(int64_t)l * X.m] * T[l];
+  }
+  const double* th = K.ThT + (int64_t)a * K.mk;
+  const double* ph = K.Phi + (int64_t)b * K.mk;
+  double t = 0.0;
+  for (int l = 0; l < K.mk; ++l) t += th[l] * ph[l];
+  return v - t;
+}
+
 __global__ void extract_kernel(const ExtractDesc* __restrict__ descs, const FrontOpDev* __restrict__ fops) {
   const ExtractDesc d = descs[blockIdx.y];
   const FrontOpDev& f = fops[d.fop];
@@ -229,7 +262,7 @@ __global__ void extract_kernel(const ExtractDesc* __restrict__ descs, const Fron
     }
     for (int k = 0; k < f.nkids; ++k) {
       int a = f.inv[k][i], b = f.inv[k][j];
-      if (a >= 0 && b >= 0) v += f.U[k][a + (int64_t)b * f.ldu[k]];
+      if (a >= 0 && b >= 0) v += f.hk[k] ? hss_kid_entry(*f.hk[k], a, b) : f.U[k][a + (int64_t)b * f.ldu[k]];
     }
     d.dst[r + (int64_t)c * d.ldd] = v;
   }

@@ -173,10 +173,34 @@ inline int64_t copy_tiles(const CopyDesc& c) {
 }
 
 // what element extraction needs to know about a front F_i = A_i (+) U_kids
+// A child's update matrix U = F22 - Theta^* Phi kept in low-rank form
+// (Sec. 4.4), for entry extraction (Sec. 4.5): an entry of F22 is read from
+// a leaf block D when both indices fall in one leaf, else it is row a of
+// Ubig of the row side's child x of their lowest common ancestor p times
+// column b of T (B12 Vbig^T or B21 Vbig^T of p, r_x x m_y, ld max(r_x, 1)).
+struct HssKidNode {
+  int lo, m;            // rows [lo, lo + m) of the update set
+  int parent, depth;    // table index of the parent (-1 at the top), depth below the top
+  int r;                // row rank
+  int kid0;             // table index of the first child (-1 at a leaf)
+  const double* D;      // leaf: m x m
+  const double* Ubig;   // m x r
+  const double* T12;    // non-leaf: B12 Vbig_{kid1}^T
+  const double* T21;    // non-leaf: B21 Vbig_{kid0}^T
+};
+struct HssKidDev {
+  int u, mk, nnode;
+  const int* leaf_of;   // u: table index of the leaf holding each row
+  const HssKidNode* nodes;
+  const double* ThT;    // Theta^T, mk x u
+  const double* Phi;    // mk x u
+};
+
 struct FrontOpDev {
   SpFront A;
   const double* val;
   const double* U[2];
+  const HssKidDev* hk[2];   // a child in low-rank form (U null), else null
   const int* inv[2];   // front-local index -> child-local index or -1
   int ldu[2];
   int nkids, n;

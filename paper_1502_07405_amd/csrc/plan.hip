@@ -76,6 +76,7 @@ void* Arena::alloc(size_t bytes, size_t align) {
   char* r = chunks_.back().p + off_;
   off_ += need;
   used_ += need;
+  peak_ = std::max(peak_, used_);
   return r;
 }
 

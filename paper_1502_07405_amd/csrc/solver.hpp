@@ -67,6 +67,9 @@ struct HNode {
   double *Dbar = nullptr, *Vbar = nullptr;
   double *Ud = nullptr, *Vd = nullptr;    // dense interpolative generators
   double *Ubig = nullptr, *Vbig = nullptr;
+  // non-leaf nodes of an update subtree kept in low-rank form: B12 Vbig_b^T
+  // (r_a x m_b) and B21 Vbig_a^T (r_b x m_a), for entry extraction
+  double *T12 = nullptr, *T21 = nullptr;
   // solve buffers (fixed addresses, so the solve launches are built once)
   double *bbar = nullptr, *ctop = nullptr, *cbot = nullptr, *w = nullptr, *wab = nullptr;
   double *xin = nullptr, *xbar = nullptr, *gt = nullptr, *gbar = nullptr, *lbar = nullptr, *hv = nullptr;
@@ -94,6 +97,10 @@ struct HFront {
   int mk = 0;
   double *Vbark = nullptr, *ThT = nullptr, *Phi = nullptr;
   double* Upd = nullptr;     // dense update matrix (u x u)
+  // the update matrix reaches the (HSS) parent in low-rank form: the
+  // q-subtree generators with Theta^* and Phi, kept until the parent is done
+  bool lowrank = false;
+  struct HssKidDev* kdev = nullptr;   // device table for entry extraction
   // copies kept for inspection when opts.keep_stages is set: R, S^r, S^c at
   // the final d (n x kd each), Theta^T and Phi (mk x u each)
   double *kR = nullptr, *kSr = nullptr, *kSc = nullptr, *kTh = nullptr, *kPhi = nullptr;

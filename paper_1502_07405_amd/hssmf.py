@@ -53,7 +53,7 @@ class Opts(ctypes.Structure):
                 ("restart", ctypes.c_int32), ("tol", ctypes.c_double), ("max_it", ctypes.c_int32),
                 ("id_kernel", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("gemm_tile", ctypes.c_int32), ("abs_tol", ctypes.c_double),
-                ("keep_stages", ctypes.c_int32)]
+                ("keep_stages", ctypes.c_int32), ("hss_update", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -70,7 +70,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("nfront", ctypes.c_int32), ("n_hss_fronts", ctypes.c_int32),
                 ("max_rank", ctypes.c_int32), ("max_d", ctypes.c_int32), ("growth_rounds", ctypes.c_int32),
                 ("factor_bytes", ctypes.c_int64), ("t_plan_ms", ctypes.c_double),
-                ("t_factor_ms", ctypes.c_double), ("flops_factor", ctypes.c_double)]
+                ("t_factor_ms", ctypes.c_double), ("flops_factor", ctypes.c_double),
+                ("peak_bytes", ctypes.c_int64)]
 
 
 _lib = None
@@ -154,6 +155,8 @@ def default_opts(**kw):
             v = OUTER[v]
         if k == "id_kernel" and isinstance(v, str):
             v = {"stepwise": 0, "cooperative": 1, "resident": 2}[v]
+        if k == "hss_update" and isinstance(v, str):
+            v = {"lowrank": 0, "dense": 1}[v]
         if not hasattr(o, k):
             raise KeyError(k)
         setattr(o, k, v)

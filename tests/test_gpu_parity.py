@@ -81,20 +81,24 @@ def _oracle_case(case):
     return _ORACLE[case]
 
 
-@pytest.mark.parametrize("idk", ["stepwise", "cooperative", "resident"])
+@pytest.mark.parametrize("idk,upd", [("stepwise", "lowrank"), ("cooperative", "lowrank"), ("resident", "lowrank"),
+                                     ("resident", "dense")])
 @pytest.mark.parametrize("case", sorted(HSS_CASES))
-def test_hss_multifrontal_matches_oracle(case, idk):
+def test_hss_multifrontal_matches_oracle(case, idk, upd):
     """Every ID kernel (one launch per pivot step, cooperative, resident)
-    against the oracle: equal ranks per HSS front, M^-1 b to 1e-9."""
+    and both forms of an HSS child's update matrix (low rank: sampled by an
+    HSS matrix-vector product minus Theta^*(Phi X), entries from the
+    generators; dense: expanded once) against the oracle: equal ranks per
+    HSS front, M^-1 b to 1e-9."""
     kw = HSS_CASES[case][1]
     A, o, ofac = _oracle_case(case)
-    fac = H.Factorization(A, o, id_kernel=idk, **kw)
+    fac = H.Factorization(A, o, id_kernel=idk, hss_update=upd, **kw)
     assert fac.hss_ranks() == _orc_ranks(ofac)
     b = np.random.default_rng(4).standard_normal(A.n)
     for tr in (False, True):
         y = fac.apply(_t(b), trans=tr).cpu().numpy()
         yo = mf.apply_inverse(ofac, b, trans=tr)
-        assert np.linalg.norm(y - yo) <= 1e-9 * np.linalg.norm(yo), (case, idk, tr)
+        assert np.linalg.norm(y - yo) <= 1e-9 * np.linalg.norm(yo), (case, idk, upd, tr)
     fac.close()
 
 

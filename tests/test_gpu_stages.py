@@ -9,7 +9,10 @@ Per HSS front (hssmf_front_data with keep_stages = 1):
 - the ranks and final sample counts;
 - the low-rank Schur product Theta^* Phi and the update matrix
   F22 - Theta^* Phi handed to the parent;
-and M^{-1} v for v = default_rng(7).
+and M^{-1} v for v = default_rng(7).  Both forms of an HSS child's update
+matrix are run: low rank (the parent samples it by an HSS matrix-vector
+product of F22 minus Theta^*(Phi X), in FP64 in either mode, and reads its
+entries from the generators) and the dense expansion.
 
 Bounds.  FP64: the same ranks as the oracle, samples to 1e-12 (rounding
 only), Schur factors, update and M^{-1} v to 1e-9.  Mixed: the samples
@@ -57,16 +60,16 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_stage_errors_against_the_oracle(case, prec):
+@pytest.mark.parametrize("prec,upd", [("fp64", "lowrank"), ("fp32", "lowrank"), ("fp64", "dense"), ("fp32", "dense")])
+def test_stage_errors_against_the_oracle(case, prec, upd):
     A, o, ofac, rec = case
-    fac = H.Factorization(A, o, keep_stages=1, gemm_prec=prec, **KW)
+    fac = H.Factorization(A, o, keep_stages=1, gemm_prec=prec, hss_update=upd, **KW)
     gr = {r[0]: r for r in fac.hss_ranks()}
     orr = {r[0]: r for r in mf.hss_ranks(ofac)}
     assert sorted(gr) == sorted(orr) == sorted(rec)
     lim_s = 1e-12 if prec == "fp64" else 1e-5
     lim_x = 1e-9 if prec == "fp64" else 1e-3
-    print(f"\n[{prec}] front  rank gpu/orc   d gpu/orc   dS^r      dS^c      d(Theta*Phi)  dU")
+    print(f"\n[{prec} {upd}] front  rank gpu/orc   d gpu/orc   dS^r      dS^c      d(Theta*Phi)  dU")
     for f in sorted(rec):
         r = rec[f]
         Sr = fac.front_data(f, "samples_row")
@@ -89,6 +92,6 @@ def test_stage_errors_against_the_oracle(case, prec):
     v = np.random.default_rng(7).standard_normal(A.n)
     y = fac.apply(torch.tensor(v, device=DEV)).cpu().numpy()
     ey = _rel(y, mf.apply_inverse(ofac, v))
-    print(f"[{prec}] ||dM^-1 v|| / ||M^-1 v|| = {ey:.2e}")
+    print(f"[{prec} {upd}] ||dM^-1 v|| / ||M^-1 v|| = {ey:.2e}")
     assert ey <= lim_x
     fac.close()
