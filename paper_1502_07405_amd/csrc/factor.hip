@@ -66,7 +66,7 @@ void run_extract(Handle& h, const std::vector<ExtractDesc>& v, const FrontOpDev*
   for (auto& c : v)
     if (c.m > 0 && c.n > 0) { w.push_back(c); mx = std::max<int64_t>(mx, (int64_t)c.m * c.n); }
   if (w.empty()) return;
-  launch_extract(h.stager.put_vec(w, h.st), (int)w.size(), fops, mx, h.st);
+  launch_extract(h.stager.put_vec(w, h.st), (int)w.size(), fops, mx, h.o.hss_update == HSSMF_UPDATE_LOWRANK, h.st);
 }
 
 void run_interp(Handle& h, const std::vector<InterpDesc>& v) {
@@ -1254,6 +1254,7 @@ void build_kid_table(Handle& h, HFront& F) {
   }
   std::vector<HssKidNode> tab(order.size());
   std::vector<int> leaf_of(F.u, -1);
+  std::vector<CopyDesc> ut_copies;
   for (size_t i = 0; i < order.size(); ++i) {
     const HNode& nd = F.nd[order[i]];
     HssKidNode& k = tab[i];
@@ -1264,12 +1265,18 @@ void build_kid_table(Handle& h, HFront& F) {
     k.depth = k.parent < 0 ? 0 : tab[k.parent].depth + 1;   // parents precede children in preorder
     k.kid0 = nd.leaf() ? -1 : tix[nd.kid[0]];
     k.D = nd.leaf() ? nd.D : nullptr;
-    k.Ubig = nd.Ubig;
+    k.UT = nullptr;
+    if (order[i] != F.q && nd.r > 0) {
+      double* ut = dalloc(h, (int64_t)nd.r * nd.m());
+      ut_copies.push_back(Cp(nd.Ubig, nd.m(), nullptr, ut, nd.r, nd.r, nd.m(), 0, 1.0, nullptr, 1));
+      k.UT = ut;
+    }
     k.T12 = nd.T12;
     k.T21 = nd.T21;
     if (nd.leaf())
       for (int r = 0; r < nd.m(); ++r) leaf_of[k.lo + r] = (int)i;
   }
+  run_copy(h, ut_copies);
   HssKidDev kd{};
   kd.u = F.u;
   kd.mk = F.mk;

@@ -213,16 +213,17 @@ void launch_round_lp(double* x, void* lp, int64_t n, int to_bf16, hipStream_t s)
 // F_i(I, J) = A_i(I, J) + sum over children of U_child(inv(I), inv(J))
 // (the element access that Alg. 1 needs for D and B, Sec. 4.5)
 // entry (a, b) of a child's update matrix F22 - Theta^* Phi in low-rank
-// form: F22 from a leaf block or from Ubig of the lowest common ancestor's
-// row-side child times B Vbig^T of the column side, minus row a of Theta^*
-// times column b of Phi
-__device__ double hss_kid_entry(const HssKidDev& K, int a, int b) {
+// form, by one wavefront: F22 from a leaf block or from Ubig of the lowest
+// common ancestor's row-side child times B Vbig^T of the column side, minus
+// row a of Theta^* times column b of Phi; the dot products are split over
+// the lanes and summed by a butterfly (the same value in every lane)
+__device__ double hss_kid_entry(const HssKidDev& K, int a, int b, int lane) {
   const HssKidNode* N = K.nodes;
   int x = K.leaf_of[a], y = K.leaf_of[b];
-  double v;
+  double v = 0.0;
   if (x == y) {
     const HssKidNode& L = N[x];
-    v = L.D[(a - L.lo) + (int64_t)(b - L.lo) * L.m];
+    if (lane == 0) v = L.D[(a - L.lo) + (int64_t)(b - L.lo) * L.m];
   } else {
     while (N[x].depth > N[y].depth) x = N[x].parent;
     while (N[y].depth > N[x].depth) y = N[y].parent;
@@ -233,16 +234,16 @@ __device__ double hss_kid_entry(const HssKidDev& K, int a, int b) {
     const HssKidNode& P = N[N[x].parent];
     const HssKidNode& X = N[x];
     const HssKidNode& Y = N[y];
-    const double* T = (x == P.kid0 ? P.T12 : P.T21) + (int64_t)(b - Y.lo) * (X.r > 1 ? X.r : 1);
-    const double* U = X.Ubig + (a - X.lo);
-    v = 0.0;
-    for (int l = 0; l < X.r; ++l) v += U[(int64_t)l * X.m] * T[l];
+    const int ld = X.r > 1 ? X.r : 1;
+    const double* T = (x == P.kid0 ? P.T12 : P.T21) + (int64_t)(b - Y.lo) * ld;
+    const double* U = X.UT + (int64_t)(a - X.lo) * ld;
+    for (int l = lane; l < X.r; l += 64) v += U[l] * T[l];
   }
   const double* th = K.ThT + (int64_t)a * K.mk;
   const double* ph = K.Phi + (int64_t)b * K.mk;
-  double t = 0.0;
-  for (int l = 0; l < K.mk; ++l) t += th[l] * ph[l];
-  return v - t;
+  for (int l = lane; l < K.mk; l += 64) v -= th[l] * ph[l];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
 }
 
 __global__ void extract_kernel(const ExtractDesc* __restrict__ descs, const FrontOpDev* __restrict__ fops) {
@@ -261,18 +262,53 @@ __global__ void extract_kernel(const ExtractDesc* __restrict__ descs, const Fron
       if (cm < j) lo = mid + 1; else hi = mid - 1;
     }
     for (int k = 0; k < f.nkids; ++k) {
+      if (f.hk[k]) continue;   // low-rank children: the second pass
       int a = f.inv[k][i], b = f.inv[k][j];
-      if (a >= 0 && b >= 0) v += f.hk[k] ? hss_kid_entry(*f.hk[k], a, b) : f.U[k][a + (int64_t)b * f.ldu[k]];
+      if (a >= 0 && b >= 0) v += f.U[k][a + (int64_t)b * f.ldu[k]];
     }
     d.dst[r + (int64_t)c * d.ldd] = v;
   }
 }
 
-void launch_extract(const ExtractDesc* d, int nd, const FrontOpDev* fops, int64_t max_elems, hipStream_t s) {
+// the low-rank children's entries, added to what extract_kernel wrote: one
+// wavefront per entry
+__global__ __launch_bounds__(256) void extract_lowrank_kernel(const ExtractDesc* __restrict__ descs,
+                                                              const FrontOpDev* __restrict__ fops) {
+  const ExtractDesc d = descs[blockIdx.y];
+  const FrontOpDev& f = fops[d.fop];
+  bool any = false;
+  for (int k = 0; k < f.nkids; ++k) any = any || f.hk[k] != nullptr;
+  if (!any) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t total = (int64_t)d.m * d.n;
+  for (int64_t e = blockIdx.x * 4 + w; e < total; e += (int64_t)gridDim.x * 4) {
+    const int r = (int)(e % d.m), c = (int)(e / d.m);
+    const int i = d.I[r], j = d.J[c];
+    double v = 0.0;
+    bool hit = false;
+    for (int k = 0; k < f.nkids; ++k) {
+      if (!f.hk[k]) continue;
+      const int a = f.inv[k][i], b = f.inv[k][j];
+      if (a >= 0 && b >= 0) {
+        v += hss_kid_entry(*f.hk[k], a, b, lane);
+        hit = true;
+      }
+    }
+    if (hit && lane == 0) d.dst[r + (int64_t)c * d.ldd] += v;
+  }
+}
+
+void launch_extract(const ExtractDesc* d, int nd, const FrontOpDev* fops, int64_t max_elems, bool lowrank,
+                    hipStream_t s) {
   if (nd <= 0 || max_elems <= 0) return;
   int64_t blocks = (max_elems + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(extract_kernel, dim3((unsigned)blocks, nd), dim3(256), 0, s, d, fops);
+  if (lowrank) {
+    int64_t b2 = (max_elems + 3) / 4;
+    if (b2 > 4096) b2 = 4096;
+    hipLaunchKernelGGL(extract_lowrank_kernel, dim3((unsigned)b2, nd), dim3(256), 0, s, d, fops);
+  }
   HIP_CHECK(hipGetLastError());
 }
 

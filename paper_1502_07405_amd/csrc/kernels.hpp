@@ -178,13 +178,14 @@ inline int64_t copy_tiles(const CopyDesc& c) {
 // a leaf block D when both indices fall in one leaf, else it is row a of
 // Ubig of the row side's child x of their lowest common ancestor p times
 // column b of T (B12 Vbig^T or B21 Vbig^T of p, r_x x m_y, ld max(r_x, 1)).
+// Ubig is kept transposed so that row a is contiguous.
 struct HssKidNode {
   int lo, m;            // rows [lo, lo + m) of the update set
   int parent, depth;    // table index of the parent (-1 at the top), depth below the top
   int r;                // row rank
   int kid0;             // table index of the first child (-1 at a leaf)
   const double* D;      // leaf: m x m
-  const double* Ubig;   // m x r
+  const double* UT;     // Ubig^T, r x m (ld max(r, 1))
   const double* T12;    // non-leaf: B12 Vbig_{kid1}^T
   const double* T21;    // non-leaf: B21 Vbig_{kid0}^T
 };
@@ -226,7 +227,12 @@ void launch_rng(double* R, int ldr, const int* orig, int nrows, int c0, int nc, 
 void launch_spmm(const SpmmDesc* d, int nd, int max_rows, int max_cols, hipStream_t s);
 // max_tiles: largest copy_tiles() over the descriptors
 void launch_copy(const CopyBatch& d, int nd, int64_t max_tiles, int f32, hipStream_t s);
-void launch_extract(const ExtractDesc* d, int nd, const FrontOpDev* fops, int64_t max_elems, hipStream_t s);
+// entries of the fronts' operators: A_i and dense children's update
+// matrices in one pass (one thread per entry), then, when lowrank is set,
+// the low-rank children's entries added by a second pass (one wavefront per
+// entry)
+void launch_extract(const ExtractDesc* d, int nd, const FrontOpDev* fops, int64_t max_elems, bool lowrank,
+                    hipStream_t s);
 // dst (m x k, ld ldd) = Pi [I; E]: dst[perm[i], :] = row i of [I; E]
 struct InterpDesc {
   double* dst;

@@ -270,11 +270,13 @@ def _golden_ranks(name):
     return [tuple(int(v) for v in r) for r in rows]
 
 
-def test_poisson3d_64_full_size():
+@pytest.mark.parametrize("upd", ["dense", "lowrank"])
+def test_poisson3d_64_full_size(upd):
     """Full-size 64^3 FP64 HSS factor + iterative refinement, in the launch
     configuration the benchmark times, against the oracle's results stored by
     tests/golden/make_poisson3d_64.py: every HSS front's rank, final d and
-    growth count are equal; M^{-1} v for v = default_rng(7) agrees entry by
+    growth count are equal, with HSS children's update matrices expanded
+    densely or kept in low-rank form; M^{-1} v for v = default_rng(7) agrees entry by
     entry to 1e-9 relative (equal ranks leave reduction-order rounding only);
     with both sides refined to a relative residual of 1e-12 the solutions
     agree to 1e-8 (||x - x_orc|| / ||x|| <= 2 kappa(A) 1e-12, kappa =
@@ -283,7 +285,8 @@ def test_poisson3d_64_full_size():
     gold = _golden_ranks("poisson3d_64_hss_ranks.txt")
     vec = np.load(os.path.join(GOLD, "poisson3d_64_vectors.npz"))
     A, o, b = P.workload(**P.WORKLOADS["poisson3d_64"])
-    fac = H.Factorization(A, o, min_sep_hss=512, leaf_size=64, rel_tol=1e-6, d0=128, dd=128, p=10, tol=1e-12)
+    fac = H.Factorization(A, o, min_sep_hss=512, leaf_size=64, rel_tol=1e-6, d0=128, dd=128, p=10, tol=1e-12,
+                          hss_update=upd)
     assert fac.hss_ranks() == gold
     fac.refactor(A.val)
     assert fac.hss_ranks() == gold
