@@ -353,6 +353,40 @@ int hssmf_measure_peaks(void* stream, hssmf_peaks* out);
 #define HSSMF_NOALLOC_SCRATCH_BYTES (256u << 20)
 int hssmf_solve_noalloc(void* h, int32_t nrhs, const double* b, double* x, hssmf_info* info);
 
+/* Algebraic front end (host only; A in host memory, HSSMF_MEM_HOST; no GPU
+ * is used).
+ *
+ * Static scaling and column permutation for stability (Sec. 3.1: A is
+ * replaced by Dr A Dc Qc, computed as in MC64 of Duff and Koster): a
+ * permutation maximizing the product of the magnitudes of the matched
+ * entries, found by shortest augmenting paths on the costs
+ * log max_k |a_kj| - log |a_ij|, whose dual variables give the scalings.
+ * Outputs (caller-owned, n entries each): colperm[i] = the column of A
+ * placed at position i, so B(:, i) = A(:, colperm[i]); row_scale = Dr,
+ * col_scale = Dc (indexed by the columns of A).  The scaled, permuted
+ * matrix has |r_i a_{i,colperm[i]} c_{colperm[i]}| = 1 on the diagonal and
+ * every entry at most 1 in magnitude.  Errors: EINVAL (bad CSR or
+ * arguments), ESINGULAR (A is structurally singular: no perfect matching
+ * of its nonzero entries). */
+int hssmf_static_pivoting(const hssmf_csr* A, int32_t* colperm, double* row_scale, double* col_scale);
+
+/* Fill-reducing nested dissection of the graph of A + A^T (Sec. 3.1) with
+ * the separators ordered for HSS compression (Sec. 4.2).  A vertex set of
+ * more than leaf_size vertices is split at the middle level of a
+ * breadth-first level structure from a pseudo-peripheral vertex (the
+ * level's vertices without a neighbour beyond it join the near side); a
+ * disconnected set is split off one component at a time.  Each separator
+ * of more than sep_leaf vertices is ordered by recursive bisection of its
+ * graph enriched with length-two connections: the halves are the first
+ * ceil(m / 2) and the remaining vertices of a breadth-first order, down to
+ * sep_leaf vertices, which matches the count-halving HSS tree of a front
+ * with leaf size sep_leaf.  Outputs as hssmf_ordering, caller-owned: perm
+ * (n entries, perm[new] = old), sep_ptr (at least n + 1), parent (at least
+ * n), *nfront; fronts in postorder, at most two children each.  Errors:
+ * EINVAL. */
+int hssmf_nested_dissection(const hssmf_csr* A, int32_t leaf_size, int32_t sep_leaf, int32_t* perm,
+                            int32_t* sep_ptr, int32_t* parent, int32_t* nfront);
+
 void hssmf_destroy(void* h);
 
 const char* hssmf_strerror(int code);

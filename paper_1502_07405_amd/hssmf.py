@@ -22,7 +22,7 @@ EXPORTS = ["hssmf_default_opts", "hssmf_factor", "hssmf_refactor", "hssmf_apply"
            "hssmf_last_failed_front", "hssmf_destroy", "hssmf_strerror", "hssmf_profile_enable",
            "hssmf_profile_read", "hssmf_factor_batch", "hssmf_systems", "hssmf_measure_peaks",
            "hssmf_refactor_device", "hssmf_solve_batch", "hssmf_solve_noalloc",
-           "hssmf_front_data"]
+           "hssmf_front_data", "hssmf_static_pivoting", "hssmf_nested_dissection"]
 KCLASS = {"id": 0, "gemm64": 1, "gemmlp": 2, "lupanel": 3, "idres": 4}
 
 
@@ -111,6 +111,8 @@ def load():
         L.hssmf_measure_peaks.argtypes = [vp, ctypes.POINTER(Peaks)]
         L.hssmf_profile_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(ctypes.c_double)]
+        L.hssmf_static_pivoting.argtypes = [ctypes.POINTER(CSRArg), vp, vp, vp]
+        L.hssmf_nested_dissection.argtypes = [ctypes.POINTER(CSRArg), i32, i32, vp, vp, vp, ctypes.POINTER(i32)]
         _lib = L
     return _lib
 
@@ -183,6 +185,63 @@ def _args(A, ordering, keep):
     rp, ci, va, pe, sp, pa = arrs
     return (CSRArg(int(A.n), rp.ctypes.data, ci.ctypes.data, va.ctypes.data, MEM_HOST),
             OrderingArg(pe.ctypes.data, len(pa), sp.ctypes.data, pa.ctypes.data))
+
+
+def _host_csr(A, keep):
+    arrs = (np.ascontiguousarray(A.rowptr, dtype=np.int64), np.ascontiguousarray(A.colind, dtype=np.int32),
+            np.ascontiguousarray(A.val, dtype=np.float64))
+    keep.append(arrs)
+    rp, ci, va = arrs
+    return CSRArg(int(A.n), rp.ctypes.data, ci.ctypes.data, va.ctypes.data, MEM_HOST)
+
+
+def nested_dissection(A, leaf_size=64, sep_leaf=64):
+    """hssmf_nested_dissection: a fill-reducing ordering of the graph of
+    A + A^T with HSS-ordered separators, as an Ordering."""
+    from .problems import Ordering
+    keep = []
+    csr = _host_csr(A, keep)
+    n = int(A.n)
+    perm = np.empty(n, dtype=np.int32)
+    sep_ptr = np.empty(n + 1, dtype=np.int32)
+    parent = np.empty(n, dtype=np.int32)
+    nf = ctypes.c_int32()
+    rc = load().hssmf_nested_dissection(ctypes.byref(csr), int(leaf_size), int(sep_leaf), perm.ctypes.data,
+                                        sep_ptr.ctypes.data, parent.ctypes.data, ctypes.byref(nf))
+    if rc != HSSMF_OK:
+        raise HssmfError(rc, "hssmf_nested_dissection")
+    k = nf.value
+    return Ordering(perm, sep_ptr[:k + 1].copy(), parent[:k].copy(), [None] * k, None)
+
+
+def static_pivoting(A):
+    """hssmf_static_pivoting: (colperm, row_scale, col_scale) with
+    B(:, i) = Dr A Dc (:, colperm[i]) carrying the matched entries, of
+    magnitude 1, on its diagonal."""
+    keep = []
+    csr = _host_csr(A, keep)
+    n = int(A.n)
+    q = np.empty(n, dtype=np.int32)
+    r = np.empty(n, dtype=np.float64)
+    c = np.empty(n, dtype=np.float64)
+    rc = load().hssmf_static_pivoting(ctypes.byref(csr), q.ctypes.data, r.ctypes.data, c.ctypes.data)
+    if rc != HSSMF_OK:
+        raise HssmfError(rc, "hssmf_static_pivoting")
+    return q, r, c
+
+
+def apply_static_pivoting(A, colperm, row_scale, col_scale):
+    """The matrix B = Dr A Dc Q of static_pivoting's output as a CSR (host):
+    B[i, k] = r_i a[i, colperm[k]] c[colperm[k]].  A solution y of B y = Dr b
+    gives x[colperm[k]] = c[colperm[k]] y[k]."""
+    from .problems import CSR
+    S = A.to_scipy().tocoo()
+    pos = np.empty(int(A.n), dtype=np.int64)
+    pos[colperm] = np.arange(int(A.n))
+    import scipy.sparse as sp
+    B = sp.csr_matrix((S.data * row_scale[S.row] * col_scale[S.col], (S.row, pos[S.col])), shape=S.shape)
+    B.sort_indices()
+    return CSR(int(A.n), B.indptr.astype(np.int64), B.indices.astype(np.int32), B.data.astype(np.float64))
 
 
 class Factorization:

@@ -20,6 +20,10 @@ paper uses for regular grids (Sec. 6.1), made concrete as:
   bisection (longer side first, first part of size ``ceil(len / 2)``), so a
   run of consecutive indices is a compact patch of the face.  These patches
   play the role of the separator partitions of Sec. 4.2.
+
+For the algebraic front end, :func:`knn_mesh` gives an operator on a random
+unstructured point set (no grid, no geometric ordering) and
+:func:`permute_rows` scrambles its rows so that static pivoting is needed.
 """
 from __future__ import annotations
 
@@ -367,6 +371,40 @@ def workload(kind, n, leaf_side, rhs_seed=1, **_):
         raise ValueError(kind)
     b = np.random.default_rng(rhs_seed).standard_normal(A.n)
     return A, order, b
+
+
+def knn_mesh(npts, k=6, seed=0, wind=(0.6, -0.3), shift=1e-2):
+    """An unstructured-mesh operator for the algebraic front end: npts
+    points uniform in the unit square (``default_rng(seed)``), each joined
+    to its k nearest neighbours (edges symmetrized); a_ij = -1 - w.(x_j - x_i)
+    / |x_j - x_i| * 0.5 on every edge (a graph Laplacian with a skew
+    convection term along ``wind``), a_ii = degree + shift.  Diagonally
+    dominant, nonsymmetric, no geometric grid.  Returns (CSR, points)."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(seed)
+    pts = rng.uniform(0.0, 1.0, (npts, 2))
+    _, nb = cKDTree(pts).query(pts, k + 1)
+    rows = np.repeat(np.arange(npts), k)
+    cols = nb[:, 1:].ravel()
+    e = np.unique(np.concatenate([np.stack([rows, cols], 1), np.stack([cols, rows], 1)]), axis=0)
+    i, j = e[:, 0], e[:, 1]
+    d = pts[j] - pts[i]
+    skew = 0.5 * (d @ np.asarray(wind, dtype=np.float64)) / np.linalg.norm(d, axis=1)
+    off = -1.0 - skew
+    deg = np.bincount(i, minlength=npts).astype(np.float64)
+    rr = np.concatenate([i, np.arange(npts)])
+    cc = np.concatenate([j, np.arange(npts)])
+    vv = np.concatenate([off, deg + shift])
+    return _coo_to_csr(npts, rr, cc, vv), pts
+
+
+def permute_rows(A, seed):
+    """P A for a random row permutation P (``default_rng(seed)``): the
+    diagonal of the result is mostly zero."""
+    rng = np.random.default_rng(seed)
+    p = rng.permutation(A.n)
+    S = A.to_scipy()[p].tocoo()
+    return _coo_to_csr(A.n, S.row, S.col, S.data)
 
 
 def convdiff_batch(count=256, seed=2, side_lo=48, side_hi=160, wmax=20.0, leaf_side=8):
