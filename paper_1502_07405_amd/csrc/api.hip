@@ -196,9 +196,16 @@ void numeric(Handle& h) {
   h.cur = &h.narena;
   for (Arena* a : {&h.arena, &h.narena, &h.larena, &h.sarena}) a->reset_peak();
   double t0 = now_ms();
+  static const bool upload_census = std::getenv("HSSMF_UPLOAD_CENSUS") != nullptr;
+  const int64_t p0 = h.stager.n_put, q0 = h.stager.n_put_to;
   try {
     numeric_factor(h);
+    const int64_t p1 = h.stager.n_put, q1 = h.stager.n_put_to;
     build_solve_ops(h);
+    if (upload_census)
+      std::fprintf(stderr, "uploads: numeric factorization %lld ring + %lld direct, solve ops %lld ring + %lld direct\n",
+                   (long long)(p1 - p0), (long long)(q1 - q0), (long long)(h.stager.n_put - p1),
+                   (long long)(h.stager.n_put_to - q1));
     HIP_CHECK(hipStreamSynchronize(h.st));
   } catch (...) {
     // drain what was enqueued before giving the arenas back; the handle

@@ -132,6 +132,8 @@ class Stager {
   // device workspace for split-K partial products (stream ordered)
   double* ws = nullptr;
   size_t ws_elems = 0;
+  // host-to-device copies issued (diagnostics: HSSMF_UPLOAD_CENSUS=1)
+  int64_t n_put = 0, n_put_to = 0;
 
  private:
   char* host_ = nullptr;

@@ -129,6 +129,7 @@ void* Stager::put(const void* src, size_t bytes, hipStream_t s) {
   }
   std::memcpy(host_ + off_, src, bytes);
   HIP_CHECK(hipMemcpyAsync(dev_ + off_, host_ + off_, bytes, hipMemcpyHostToDevice, s));
+  ++n_put;
   void* r = dev_ + off_;
   off_ += need;
   return r;
@@ -147,6 +148,7 @@ void Stager::put_to(void* dst, const void* src, size_t bytes, hipStream_t s) {
   }
   std::memcpy(host_ + off_, src, bytes);
   HIP_CHECK(hipMemcpyAsync(dst, host_ + off_, bytes, hipMemcpyHostToDevice, s));
+  ++n_put_to;
   off_ += need;
 }
 
