@@ -15,6 +15,8 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <numeric>
 
 #include "solver.hpp"
 
@@ -736,32 +738,75 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
         HIP_CHECK(hipStreamSynchronize(h.st));
         census_t0 = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
       }
-      // the resident kernel where it applies: at most 640 samples, and a
-      // problem that needs several workgroups only with cooperative launches
-      // that can hold all of them; the stepwise kernel otherwise
-      int res_c = o.id_kernel == HSSMF_ID_RESIDENT ? id_res_candidates(maxd, maxm) : 0;
-      const int cap = res_c > 0 ? id_res_capacity(maxd, maxm) : 0;
-      for (size_t pi = 0; pi < q.size() && res_c > 0; ++pi)
-        if (q[pi].m > res_c && (q[pi].m + res_c - 1) / res_c > cap) res_c = 0;
-      if (!q.empty() && res_c > 0) {
-        // every pivot step of a problem in one launch, candidates resident
-        // in registers: problems of at most res_c candidates on one
-        // workgroup (ordinary launch), larger ones on several workgroups of
-        // a cooperative launch (all resident, bounded waits)
-        const int np = (int)q.size();
-        std::vector<int> single, multi;
-        for (int pi = 0; pi < np; ++pi) {
-          q[pi].P = std::max(1, (q[pi].m + res_c - 1) / res_c);
-          (q[pi].P > 1 ? multi : single).push_back(pi);
+      // the resident kernel where it applies (every problem at most 640
+      // samples; the stepwise kernel otherwise).  Two launch plans:
+      //  - all problems on the template of the pass's largest (d, m), in one
+      //    cooperative launch, when some problem spans several workgroups
+      //    and all workgroups of the pass fit at once;
+      //  - else each problem that fits one workgroup of the template its own
+      //    (d, m) selects in an ordinary launch of that template (one launch
+      //    per template, side by side on st and the auxiliary streams), then
+      //    the wider ones on the template of their largest (d, m), in
+      //    cooperative launches of at most its capacity, one after another.
+      // The results do not depend on the template or the plan.
+      const int np_all = (int)q.size();
+      bool resident = o.id_kernel == HSSMF_ID_RESIDENT && np_all > 0;
+      const int t_all = resident ? id_res_template(maxd, maxm) : -1;
+      resident = resident && t_all >= 0;
+      std::vector<int> tpl(np_all, -1), pall(np_all, 1);
+      std::vector<int> wide;   // problems wider than one workgroup of their own template
+      int cap_all = 0, tot_all = 0, t_wide = -1, cap_wide = 0;
+      bool any_all = false;
+      if (resident) {
+        const int c_all = id_res_template_candidates(t_all);
+        int wd = 0, wm = 0;
+        for (int pi = 0; pi < np_all; ++pi) {
+          pall[pi] = (q[pi].m + c_all - 1) / c_all;
+          tot_all += std::max(1, pall[pi]);
+          any_all |= pall[pi] > 1;
+          tpl[pi] = id_res_template(q[pi].d, q[pi].m);
+          REQUIRE(tpl[pi] >= 0, HSSMF_EDEVICE, "interpolative decomposition: no template for a problem");
+          if (q[pi].m > id_res_template_candidates(tpl[pi])) {
+            wide.push_back(pi);
+            wd = std::max(wd, q[pi].d);
+            wm = std::max(wm, q[pi].m);
+          }
+        }
+        if (any_all) cap_all = id_res_template_capacity(t_all);
+        if (!(any_all && tot_all <= cap_all) && !wide.empty()) {
+          t_wide = id_res_template(wd, wm);
+          cap_wide = id_res_template_capacity(t_wide);
+          const int c_wide = id_res_template_candidates(t_wide);
+          for (int pi : wide)
+            if ((q[pi].m + c_wide - 1) / c_wide > cap_wide) resident = false;
+        }
+      }
+      int res_c = resident ? 1 : 0;   // the pass ran on the resident kernel
+      if (resident) {
+        const int np = np_all;
+        const bool one = any_all && tot_all <= cap_all;
+        // workgroups per problem on the template it runs on
+        std::vector<bool> is_wide(np, false);
+        for (int pi : wide) is_wide[pi] = true;
+        if (one) {
+          for (int pi = 0; pi < np; ++pi) q[pi].P = std::max(1, pall[pi]);
+        } else {
+          const int c_wide = t_wide >= 0 ? id_res_template_candidates(t_wide) : 1;
+          for (int pi = 0; pi < np; ++pi)
+            q[pi].P = is_wide[pi] ? std::max(1, (q[pi].m + c_wide - 1) / c_wide) : 1;
         }
         int wgm = 0;
-        for (int pi : multi) wgm += q[pi].P;
-        double* slots = nullptr;
-        if (!multi.empty()) {
+        std::vector<int> coopp;   // problems with exchange records
+        for (int pi = 0; pi < np; ++pi)
+          if (q[pi].P > 1) {
+            coopp.push_back(pi);
+            wgm += q[pi].P;
+          }
+        if (!coopp.empty()) {
           derr = sialloc(h, 1);
-          slots = salloc(h, 6 * (int64_t)wgm);   // per problem 3 x P x (norm, index)
+          double* slots = salloc(h, 6 * (int64_t)wgm);   // per problem 3 x P x (norm, index)
           int o6 = 0;
-          for (int pi : multi) {
+          for (int pi : coopp) {
             q[pi].cand = salloc(h, 3 * (int64_t)q[pi].P * q[pi].d);
             q[pi].slots = slots + o6;
             o6 += 6 * q[pi].P;
@@ -772,31 +817,50 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
         }
         IDProb* dq = upload(h, q);
         std::vector<int2> wgs;
-        // one cooperative launch for everything when it all fits at once,
-        // else the single-workgroup problems in one ordinary launch and the
-        // wider ones in cooperative launches of at most cap workgroups
-        int total = wgm + (int)single.size();
-        if (!multi.empty() && total <= cap) {
+        if (one) {
           for (int pi = 0; pi < np; ++pi)
             for (int w = 0; w < q[pi].P; ++w) wgs.push_back(make_int2(pi, w));
-          launch_id_res(dq, upload(h, wgs), (int)wgs.size(), maxd, maxm, true, derr, h.st);
+          launch_id_res_template(t_all, dq, upload(h, wgs), (int)wgs.size(), true, derr, h.st);
         } else {
-          for (int pi : single) wgs.push_back(make_int2(pi, 0));
-          if (!wgs.empty()) launch_id_res(dq, upload(h, wgs), (int)wgs.size(), maxd, maxm, false, derr, h.st);
+          // one workgroup each, grouped by template
+          std::map<int, std::vector<int2>> single;
+          for (int pi = 0; pi < np; ++pi)
+            if (!is_wide[pi]) single[tpl[pi]].push_back(make_int2(pi, 0));
+          std::vector<std::pair<int, int2*>> launches;   // template, uploaded map
+          std::vector<int> counts;
+          for (auto& kv : single) {
+            launches.emplace_back(kv.first, upload(h, kv.second));
+            counts.push_back((int)kv.second.size());
+          }
+          const int nl = (int)launches.size();
+          const int naux = std::max(0, std::min(nl - 1, (int)Handle::kAux));
+          if (naux > 0) {
+            h.make_aux();
+            HIP_CHECK(hipEventRecord(h.ev_fork, h.st));
+            for (int a = 0; a < naux; ++a) HIP_CHECK(hipStreamWaitEvent(h.aux[a], h.ev_fork, 0));
+          }
+          for (int li = 0; li < nl; ++li) {
+            hipStream_t ls = li == 0 || naux == 0 ? h.st : h.aux[(li - 1) % naux];
+            launch_id_res_template(launches[li].first, dq, launches[li].second, counts[li], false, derr, ls);
+          }
+          for (int a = 0; a < naux; ++a) {
+            HIP_CHECK(hipEventRecord(h.ev_join[a], h.aux[a]));
+            HIP_CHECK(hipStreamWaitEvent(h.st, h.ev_join[a], 0));
+          }
+          // the wider problems: a launch lasts as long as its longest
+          // problem, so fill them in order of the most pivot steps a
+          // problem can take
+          std::stable_sort(wide.begin(), wide.end(), [&](int a, int b) {
+            return std::min(q[a].m, q[a].d) > std::min(q[b].m, q[b].d);
+          });
           wgs.clear();
           auto flush = [&]() {
             if (wgs.empty()) return;
-            launch_id_res(dq, upload(h, wgs), (int)wgs.size(), maxd, maxm, true, derr, h.st);
+            launch_id_res_template(t_wide, dq, upload(h, wgs), (int)wgs.size(), true, derr, h.st);
             wgs.clear();
           };
-          // launches run one after another, each as long as its longest
-          // problem: fill them in order of the most pivot steps a problem
-          // can take
-          std::stable_sort(multi.begin(), multi.end(), [&](int a, int b) {
-            return std::min(q[a].m, q[a].d) > std::min(q[b].m, q[b].d);
-          });
-          for (int pi : multi) {
-            if ((int)wgs.size() + q[pi].P > cap) flush();
+          for (int pi : wide) {
+            if ((int)wgs.size() + q[pi].P > cap_wide) flush();
             for (int w = 0; w < q[pi].P; ++w) wgs.push_back(make_int2(pi, w));
           }
           flush();

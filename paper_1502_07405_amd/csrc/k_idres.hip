@@ -512,15 +512,7 @@ const ResShape* res_shape(int max_d, int max_m) {
   return pick;
 }
 
-}  // namespace
-
-int id_res_candidates(int max_d, int max_m) {
-  const ResShape* s = res_shape(max_d, max_m);
-  return s ? kResWaves * (64 / s->lpc) * s->sl : 0;
-}
-
-int id_res_capacity(int max_d, int max_m) {
-  const ResShape* s = res_shape(max_d, max_m);
+int capacity_of(const ResShape* s) {
   if (!s) return 0;
   int dev = 0, cus = 0, coop = 0, nb = 0;
   HIP_CHECK(hipGetDevice(&dev));
@@ -531,16 +523,48 @@ int id_res_capacity(int max_d, int max_m) {
   return nb * cus;
 }
 
-void launch_id_res(const IDProb* p, const int2* wgmap, int total_wg, int max_d, int max_m, bool coop, int* err,
-                   hipStream_t s) {
+void launch_shape(const ResShape* sh, const IDProb* p, const int2* wgmap, int total_wg, bool coop, int* err,
+                  hipStream_t s) {
   if (total_wg <= 0) return;
-  const ResShape* sh = res_shape(max_d, max_m);
   REQUIRE(sh != nullptr, HSSMF_ERANK, "interpolative decomposition: more than 640 samples");
   void* args[] = {(void*)&p, (void*)&wgmap, (void*)&err};
   const int tok = prof::begin(4, s);   // timing hook (no-op when off)
   if (coop) HIP_CHECK(hipLaunchCooperativeKernel(sh->fn, dim3(total_wg), dim3(kResThreads), args, 0, s));
   else HIP_CHECK(hipLaunchKernel(sh->fn, dim3(total_wg), dim3(kResThreads), args, 0, s));
   prof::end(tok, s);
+}
+
+}  // namespace
+
+int id_res_candidates(int max_d, int max_m) {
+  const ResShape* s = res_shape(max_d, max_m);
+  return s ? kResWaves * (64 / s->lpc) * s->sl : 0;
+}
+
+int id_res_capacity(int max_d, int max_m) { return capacity_of(res_shape(max_d, max_m)); }
+
+void launch_id_res(const IDProb* p, const int2* wgmap, int total_wg, int max_d, int max_m, bool coop, int* err,
+                   hipStream_t s) {
+  launch_shape(res_shape(max_d, max_m), p, wgmap, total_wg, coop, err, s);
+}
+
+int id_res_template(int d, int m) {
+  // rows per lane for d samples, or more when the pivot order of m rows
+  // needs a larger template
+  const ResShape* s = res_shape(std::max(d, (m + 1) / 2), m);
+  return s ? (int)(s - kShapes) : -1;
+}
+
+int id_res_template_candidates(int tpl) {
+  const ResShape& s = kShapes[tpl];
+  return kResWaves * (64 / s.lpc) * s.sl;
+}
+
+int id_res_template_capacity(int tpl) { return capacity_of(&kShapes[tpl]); }
+
+void launch_id_res_template(int tpl, const IDProb* p, const int2* wgmap, int total_wg, bool coop, int* err,
+                            hipStream_t s) {
+  launch_shape(&kShapes[tpl], p, wgmap, total_wg, coop, err, s);
 }
 
 }  // namespace hssmf

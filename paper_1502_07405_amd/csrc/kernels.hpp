@@ -311,6 +311,17 @@ int id_res_candidates(int max_d, int max_m);
 int id_res_capacity(int max_d, int max_m);
 void launch_id_res(const IDProb* p, const int2* wgmap, int total_wg, int max_d, int max_m, bool coop, int* err,
                    hipStream_t s);
+// The same kernel with one template per problem: id_res_template(d, m) is
+// the template a problem of d samples and m rows takes on its own (-1: none
+// holds it), id_res_template_candidates / _capacity that template's
+// candidates per workgroup and cooperative capacity.  A problem's P then
+// follows from its own template, and every launch that covers it must use
+// that template.
+int id_res_template(int d, int m);
+int id_res_template_candidates(int tpl);
+int id_res_template_capacity(int tpl);
+void launch_id_res_template(int tpl, const IDProb* p, const int2* wgmap, int total_wg, bool coop, int* err,
+                            hipStream_t s);
 
 }  // namespace hssmf
 

@@ -254,6 +254,20 @@ struct Handle {
   // every numeric factorization; captured on a private stream
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   hipStream_t gst = nullptr;
+  // streams beside st for launches of one pass that may run side by side
+  // (default priority, created on first use), with the events that fork
+  // them from st and join them back
+  static constexpr int kAux = 3;
+  hipStream_t aux[kAux] = {};
+  hipEvent_t ev_fork = nullptr, ev_join[kAux] = {};
+  void make_aux() {
+    if (ev_fork) return;
+    for (int i = 0; i < kAux; ++i) {
+      HIP_CHECK(hipStreamCreateWithFlags(&aux[i], hipStreamNonBlocking));
+      HIP_CHECK(hipEventCreateWithFlags(&ev_join[i], hipEventDisableTiming));
+    }
+    HIP_CHECK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+  }
   void drop_graphs() {
     for (auto& g : gexec)
       if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
@@ -261,6 +275,11 @@ struct Handle {
   ~Handle() {
     drop_graphs();
     if (gst) (void)hipStreamDestroy(gst);
+    for (int i = 0; i < kAux; ++i) {
+      if (aux[i]) (void)hipStreamDestroy(aux[i]);
+      if (ev_join[i]) (void)hipEventDestroy(ev_join[i]);
+    }
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
   }
   hssmf_stats stats{};
   GemmType gt() const;
