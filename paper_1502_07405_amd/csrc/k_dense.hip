@@ -501,10 +501,21 @@ void launch_gemv(const GemvDesc* d, int nd, int gx, hipStream_t s) {
   HIP_CHECK(hipGetLastError());
 }
 
+// lane j's copy of a double, for every lane (j uniform): two scalar lane
+// reads, no trip through LDS
+__device__ __forceinline__ double lane_bcast(double v, int j) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), j);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), j);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // Triangular solves with the F11 factors, one workgroup per front, the
 // right-hand side staged in LDS.  Blocks of 64: the diagonal block is staged
-// in LDS with coalesced loads, one wavefront solves it with lane shuffles,
-// then all threads update the rest of the right-hand side.
+// in LDS with coalesced loads, one wavefront solves it (each new entry read
+// out of its lane into scalar registers for the others), then all threads
+// update the rest of the right-hand side.  Row interchanges are applied in
+// their sequential order, and only when a chunk of 256 holds any.
 template <int KIND, bool STAGE, int NT>
 __global__ __launch_bounds__(NT) void trsv_kernel(const TrsvDesc* __restrict__ descs) {
   extern __shared__ double xs[];   // s entries, then (STAGE) the 64 x 65 block
@@ -517,9 +528,13 @@ __global__ __launch_bounds__(NT) void trsv_kernel(const TrsvDesc* __restrict__ d
   __syncthreads();
   if (KIND == 0 && d.ipiv)
     for (int c0 = 0; c0 < s; c0 += 256) {
-      if (tid < 256 && c0 + tid < s) pv[tid] = d.ipiv[c0 + tid];
-      __syncthreads();
-      if (tid == 0)
+      bool sw = false;
+      if (tid < 256 && c0 + tid < s) {
+        const int p = d.ipiv[c0 + tid];
+        pv[tid] = p;
+        sw = p != c0 + tid;
+      }
+      if (__syncthreads_or(sw) && tid == 0)
         for (int i = c0; i < min(s, c0 + 256); ++i) {
           const int p = pv[i - c0];
           if (p != i) { double t = xs[i]; xs[i] = xs[p]; xs[p] = t; }
@@ -541,16 +556,16 @@ __global__ __launch_bounds__(NT) void trsv_kernel(const TrsvDesc* __restrict__ d
       if (r < bs && c < bs) Tb[r][c] = T(b0 + r, b0 + c);
     }
   };
-  // sum over the block's columns of T(i, b0 + j) x(b0 + j), sixteen loads in
-  // flight at a time, in column order
+  // sum over the block's columns of T(i, b0 + j) x(b0 + j), in column order,
+  // thirty-two loads in flight at a time
   auto row_dot = [&](int i, int b0, int bs) {
     double acc = 0.0;
-    for (int j0 = 0; j0 < bs; j0 += 16) {
-      double tv[16];
+    for (int j0 = 0; j0 < bs; j0 += 32) {
+      double tv[32];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) tv[u] = (j0 + u < bs) ? T(i, b0 + j0 + u) : 0.0;
+      for (int u = 0; u < 32; ++u) tv[u] = (j0 + u < bs) ? T(i, b0 + j0 + u) : 0.0;
 #pragma unroll
-      for (int u = 0; u < 16; ++u)
+      for (int u = 0; u < 32; ++u)
         if (j0 + u < bs) acc += tv[u] * xs[b0 + j0 + u];
     }
     return acc;
@@ -565,9 +580,10 @@ __global__ __launch_bounds__(NT) void trsv_kernel(const TrsvDesc* __restrict__ d
       if (tid < 64) {
         double v = (lane < bs) ? xs[b0 + lane] : 0.0;
         for (int j = 0; j < bs; ++j) {
+          const double t = (STAGE ? Tb[lane][j] : T(b0 + lane, b0 + j));
           if (!unit && lane == j) v /= STAGE ? Tb[j][j] : T(b0 + j, b0 + j);
-          double vj = __shfl(v, j);
-          if (lane > j && lane < bs) v -= (STAGE ? Tb[lane][j] : T(b0 + lane, b0 + j)) * vj;
+          const double vj = lane_bcast(v, j);
+          if (lane > j && lane < bs) v -= t * vj;
         }
         if (lane < bs) xs[b0 + lane] = v;
       }
@@ -583,9 +599,10 @@ __global__ __launch_bounds__(NT) void trsv_kernel(const TrsvDesc* __restrict__ d
       if (tid < 64) {
         double v = (lane < bs) ? xs[b0 + lane] : 0.0;
         for (int j = bs - 1; j >= 0; --j) {
+          const double t = (STAGE ? Tb[lane][j] : T(b0 + lane, b0 + j));
           if (!unit && lane == j) v /= STAGE ? Tb[j][j] : T(b0 + j, b0 + j);
-          double vj = __shfl(v, j);
-          if (lane < j) v -= (STAGE ? Tb[lane][j] : T(b0 + lane, b0 + j)) * vj;
+          const double vj = lane_bcast(v, j);
+          if (lane < j) v -= t * vj;
         }
         if (lane < bs) xs[b0 + lane] = v;
       }
@@ -598,9 +615,13 @@ __global__ __launch_bounds__(NT) void trsv_kernel(const TrsvDesc* __restrict__ d
     for (int c1 = s; c1 > 0; c1 -= 256) {
       const int c0 = max(0, c1 - 256);
       __syncthreads();
-      if (tid < 256 && c0 + tid < c1) pv[tid] = d.ipiv[c0 + tid];
-      __syncthreads();
-      if (tid == 0)
+      bool sw = false;
+      if (tid < 256 && c0 + tid < c1) {
+        const int p = d.ipiv[c0 + tid];
+        pv[tid] = p;
+        sw = p != c0 + tid;
+      }
+      if (__syncthreads_or(sw) && tid == 0)
         for (int i = c1 - 1; i >= c0; --i) {
           const int p = pv[i - c0];
           if (p != i) { double t = xs[i]; xs[i] = xs[p]; xs[p] = t; }
