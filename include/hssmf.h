@@ -115,10 +115,11 @@ typedef struct {
                           are captured once per factorization as a HIP graph
                           (on a private stream) and replayed on the handle's
                           stream; 0 (default): launched one by one */
-  int32_t gemm_tile;   /* FP64 matrix-core GEMM kernel: 0 = chosen per
+  int32_t gemm_tile;   /* matrix-core GEMM kernel: 0 = chosen per type and
                           shape class by the built-in autotuner (timed once
-                          per process); forced: 64 (64 x 64 tiles, k-tiles of
-                          16), 65 (64 x 64, k-tiles of 32), 128 (128 x 128);
+                          per process); forced: 64 (64 x 64 tiles; FP64 with
+                          k-tiles of 16), 65 (64 x 64, FP64 k-tiles of 32),
+                          128 (128 x 128); BF16 products always take 64 x 64;
                           the results do not depend on it */
   double abs_tol;      /* absolute HSS compression tolerance: the rank of an
                           ID stops at |R_{i+1,i+1}| <= max(rel_tol |R_11|,

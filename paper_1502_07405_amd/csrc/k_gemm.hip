@@ -13,6 +13,7 @@
 #include <map>
 #include <type_traits>
 #include <mutex>
+#include <tuple>
 
 #include "common.hpp"
 
@@ -451,6 +452,162 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(const GemmBatch batch) {
   store_c<TOut, TAcc, 8, 2>(g, r, c, out);
 }
 
+// 128 x 128 tiles for large FP32-input products: eight wavefronts (512
+// threads) each own a 64 x 32 block (4 x 2 MFMA blocks), k-tiles of 32 as in
+// gemm_lp_kernel, so each output accumulates over k in exactly the same
+// order and the two kernels give identical results.  Each thread loads 8
+// entries of A and of B per k-tile at fixed offsets from one row (or
+// column, or k) it owns, with addresses formed as it goes instead of held
+// per entry, which keeps the registers of both operands, the FP32 block
+// accumulators and the FP64 sums of the FP64-result forms within budget.
+template <class TIn, class TOut>
+__global__ __launch_bounds__(512) void gemm_lp_128_kernel(const GemmBatch batch) {
+  constexpr int BM = 128, BN = 128, TK = 32, NT = 512, PER = BM * TK / NT;   // 8
+  __shared__ float As[2][TK][BM + 1];
+  __shared__ float Bs[2][TK][BN + 1];
+  const GemmDesc g = batch_desc(batch, blockIdx.x);
+  const int64_t t = blockIdx.x - g.tile_base;
+  if (t >= (int64_t)g.tiles_m * g.tiles_n) return;
+  const int row0 = (int)(t % g.tiles_m) * BM;
+  const int col0 = (int)(t / g.tiles_m) * BN;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave & 1) * 64, wc = (wave >> 1) * 32;
+  const auto A = (gptr<const TIn>)g.A;
+  const auto B = (gptr<const TIn>)g.B;
+  const bool tA = g.transA, tB = g.transB;
+  // entry q of a k-tile: op(A)(ia + sa q, ka + ta q), op(B)(kb + tb q, jb + sb q)
+  const int ia = tA ? tid >> 5 : tid & 127, ka = tA ? tid & 31 : tid >> 7;
+  const int kb = tB ? tid >> 7 : tid & 31, jb = tB ? tid & 127 : tid >> 5;
+  // the fixed row of A (!tA, through the row map) and column of B (tB)
+  int64_t arow = 0, bcol = 0;
+  if (!tA) {
+    const int ic = min(row0 + ia, g.m - 1);
+    arow = g.amap ? ((gptr<const int>)g.amap)[ic] : ic;
+  }
+  if (tB) bcol = min(col0 + jb, g.n - 1);
+  TIn ra[PER], rb[PER];
+  unsigned aok = 0, bok = 0;
+  auto fetch = [&](int k0) {
+    aok = bok = 0;
+    int64_t ao[PER], bo[PER];
+    // B's k row through the map (!tB): one lookup per k-tile
+    int64_t bk = 0;
+    if (!tB) {
+      const int kc = min(k0 + kb, g.k - 1);
+      bk = g.bmap ? ((gptr<const int>)g.bmap)[kc] : kc;
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      if (tA) {
+        const int ig = row0 + ia + 16 * q, k = k0 + ka;
+        aok |= (unsigned)(ig < g.m && k < g.k) << q;
+        ao[q] = (int64_t)min(k, g.k - 1) + (int64_t)min(ig, g.m - 1) * g.lda;
+      } else {
+        const int k = k0 + ka + 4 * q;
+        aok |= (unsigned)(row0 + ia < g.m && k < g.k) << q;
+        ao[q] = arow + (int64_t)min(k, g.k - 1) * g.lda;
+      }
+      if (tB) {
+        const int k = k0 + kb + 4 * q;
+        bok |= (unsigned)(col0 + jb < g.n && k < g.k) << q;
+        bo[q] = bcol + (int64_t)min(k, g.k - 1) * g.ldb;
+      } else {
+        const int jg = col0 + jb + 16 * q, k = k0 + kb;
+        bok |= (unsigned)(jg < g.n && k < g.k) << q;
+        bo[q] = bk + (int64_t)min(jg, g.n - 1) * g.ldb;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) ra[q] = A[ao[q]];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) rb[q] = B[bo[q]];
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int i = tA ? ia + 16 * q : ia, kk = tA ? ka : ka + 4 * q;
+      As[buf][kk][i] = (aok >> q & 1u) ? (float)ra[q] : 0.0f;
+      const int j = tB ? jb : jb + 16 * q, kq = tB ? kb + 4 * q : kb;
+      Bs[buf][kq][j] = (bok >> q & 1u) ? (float)rb[q] : 0.0f;
+    }
+  };
+  flt4 acc[4][2];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = flt4{0, 0, 0, 0};
+  // FP64-result forms: each k-tile's FP32 sum is added into FP64 sums, as
+  // in gemm_lp_kernel
+  constexpr bool acc64 = sizeof(TOut) == 8;
+  double acc_d[4][2][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc_d[a][b][v] = 0.0;
+  int buf = 0;
+  if (g.k > 0) {
+    fetch(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int k0 = 0; k0 < g.k; k0 += TK) {
+    const bool more = k0 + TK < g.k;
+    if (more) fetch(k0 + TK);   // in flight while the matrix cores run
+#pragma unroll
+    for (int ks = 0; ks < TK; ks += 4) {
+      const int kk = ks + (lane >> 4);
+      float av[4], bv[2];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[buf][kk][wr + 16 * a + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[buf][kk][wc + 16 * b + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    if constexpr (acc64) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc_d[a][b][v] += (double)acc[a][b][v];
+          acc[a][b] = flt4{0, 0, 0, 0};
+        }
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  // FP32 16x16 result layout: lane l, slot v holds (row 4(l/16) + v, col
+  // l%16); two passes of 16 values keep the epilogue's registers in bounds
+  using TAcc = std::conditional_t<acc64, double, float>;
+#pragma unroll
+  for (int h2 = 0; h2 < 2; ++h2) {
+    int r[8], c[2];
+    TAcc out[8][2];
+#pragma unroll
+    for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = 2 * h2 + a2;
+        r[4 * a2 + v] = row0 + wr + 16 * a + 4 * (lane >> 4) + v;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          if constexpr (acc64) out[4 * a2 + v][b] = acc_d[a][b][v];
+          else out[4 * a2 + v][b] = acc[a][b][v];
+        }
+      }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) c[b] = col0 + wc + 16 * b + (lane & 15);
+    store_c<TOut, TAcc, 8, 2>(g, r, c, out);
+  }
+}
+
 // C(cmap(i), j) = alpha * sum_c P_c(i, j) + beta * C(cmap(i), j): the
 // fixed-order reduction of split-K partial products (no atomics)
 struct SplitRed {
@@ -494,7 +651,9 @@ void launch_tiles(const std::vector<GemmDesc>& d, int64_t tiles, GemmType type, 
   } else {
     b.descs = st.put_vec(d, s);
   }
-  dim3 grid((unsigned)tiles), blk(256);
+  // the 128 x 128 FP32-input kernel runs 512 threads, the others 256
+  const bool lp128 = tile == 128 && (type == GEMM_F32 || type == GEMM_F32_D || type == GEMM_D_F32);
+  dim3 grid((unsigned)tiles), blk(lp128 ? 512 : 256);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (prof::enabled()) prof::ext(type == GEMM_F64 ? 1 : 2, flops, &e0, &e1);   // timing hook
 #define HSSMF_GEMM_LAUNCH(K)                                                      \
@@ -506,9 +665,18 @@ void launch_tiles(const std::vector<GemmDesc>& d, int64_t tiles, GemmType type, 
       else if (tile == 65) { HSSMF_GEMM_LAUNCH(gemm_f64_kernel<32>) }
       else { HSSMF_GEMM_LAUNCH(gemm_f64_kernel<16>) }
       break;
-    case GEMM_F32: HSSMF_GEMM_LAUNCH((gemm_lp_kernel<float, float>)) break;
-    case GEMM_F32_D: HSSMF_GEMM_LAUNCH((gemm_lp_kernel<float, double>)) break;
-    case GEMM_D_F32: HSSMF_GEMM_LAUNCH((gemm_lp_kernel<double, double>)) break;
+    case GEMM_F32:
+      if (lp128) { HSSMF_GEMM_LAUNCH((gemm_lp_128_kernel<float, float>)) }
+      else { HSSMF_GEMM_LAUNCH((gemm_lp_kernel<float, float>)) }
+      break;
+    case GEMM_F32_D:
+      if (lp128) { HSSMF_GEMM_LAUNCH((gemm_lp_128_kernel<float, double>)) }
+      else { HSSMF_GEMM_LAUNCH((gemm_lp_kernel<float, double>)) }
+      break;
+    case GEMM_D_F32:
+      if (lp128) { HSSMF_GEMM_LAUNCH((gemm_lp_128_kernel<double, double>)) }
+      else { HSSMF_GEMM_LAUNCH((gemm_lp_kernel<double, double>)) }
+      break;
     case GEMM_BF16: HSSMF_GEMM_LAUNCH((gemm_lp_kernel<__bf16, float>)) break;
     case GEMM_BF16_D: HSSMF_GEMM_LAUNCH((gemm_lp_kernel<__bf16, double>)) break;
   }
@@ -529,23 +697,24 @@ int64_t set_tiles(std::vector<GemmDesc>& d, int T) {
   return t;
 }
 
-// Tile autotuner: the first time an FP64 batch of a given shape class (log2
-// of its largest k, log2 of its 64 x 64 tile count) is large enough to
-// matter, the three kernel variants (64 x 64 tiles with k-tiles of 16 or 32,
-// 128 x 128 tiles) are timed on the same operands with the products written
-// to the workspace, and the fastest is kept for that class for the rest of
-// the process.  The results do not depend on the choice.
+// Tile autotuner: the first time a batch of a given type and shape class
+// (log2 of its largest k, log2 of its 64 x 64 tile count) is large enough to
+// matter, the kernel variants of that type (FP64: 64 x 64 tiles with k-tiles
+// of 16 or 32, 128 x 128 tiles; FP32 inputs: 64 x 64 or 128 x 128 tiles)
+// are timed on the same operands with the products written to the
+// workspace, and the fastest is kept for that class for the rest of the
+// process.  The results do not depend on the choice.
 std::mutex g_tune_mu;
-std::map<std::pair<int, int>, int>& tune_table() {
-  static std::map<std::pair<int, int>, int> t;
+std::map<std::tuple<int, int, int>, int>& tune_table() {
+  static std::map<std::tuple<int, int, int>, int> t;
   return t;
 }
 
-int tuned_tile(const std::vector<GemmDesc>& d, int64_t tiles64, int64_t kmax, double flops, Stager& st,
-               hipStream_t s) {
+int tuned_tile(const std::vector<GemmDesc>& d, GemmType type, int64_t tiles64, int64_t kmax, double flops,
+               Stager& st, hipStream_t s) {
   if (flops < 2e8 || tiles64 < 16) return 64;
   auto lg = [](int64_t v) { int b = 0; while ((int64_t(1) << (b + 1)) <= v) ++b; return b; };
-  const std::pair<int, int> key{lg(std::max<int64_t>(kmax, 1)), lg(tiles64)};
+  const std::tuple<int, int, int> key{(int)type, lg(std::max<int64_t>(kmax, 1)), lg(tiles64)};
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = tune_table().find(key);
@@ -564,23 +733,27 @@ int tuned_tile(const std::vector<GemmDesc>& d, int64_t tiles64, int64_t kmax, do
       g.beta = 0.0;
       off += (int64_t)g.m * g.n;
     }
-    // variants: 64 x 64 with k-tiles of 16 (64), of 32 (65), 128 x 128 (128);
-    // two rounds, the second one timed
-    const int var[3] = {64, 65, 128};
+    // FP64 variants: 64 x 64 with k-tiles of 16 (64), of 32 (65), 128 x 128
+    // (128); FP32 inputs: 64 x 64 (64), 128 x 128 (128).  Two rounds, the
+    // second one timed
+    const bool f64 = type == GEMM_F64;
+    const int nv = f64 ? 3 : 2;
+    const int var64[3] = {64, 65, 128}, varlp[2] = {64, 128};
+    const int* var = f64 ? var64 : varlp;
     hipEvent_t ev[7];
     for (auto& e : ev) HIP_CHECK(hipEventCreate(&e));
     HIP_CHECK(hipEventRecord(ev[0], s));
     for (int rep = 0; rep < 2; ++rep)
-      for (int vi = 0; vi < 3; ++vi) {
+      for (int vi = 0; vi < nv; ++vi) {
         const int64_t nt = set_tiles(tr, var[vi]);
-        launch_tiles(tr, nt, GEMM_F64, st, s, 0.0, var[vi]);
-        HIP_CHECK(hipEventRecord(ev[1 + 3 * rep + vi], s));
+        launch_tiles(tr, nt, type, st, s, 0.0, var[vi]);
+        HIP_CHECK(hipEventRecord(ev[1 + nv * rep + vi], s));
       }
-    HIP_CHECK(hipEventSynchronize(ev[6]));
+    HIP_CHECK(hipEventSynchronize(ev[2 * nv]));
     float best = 0.0f;
-    for (int vi = 0; vi < 3; ++vi) {
+    for (int vi = 0; vi < nv; ++vi) {
       float ms = 0.0f;
-      HIP_CHECK(hipEventElapsedTime(&ms, ev[3 + vi], ev[4 + vi]));
+      HIP_CHECK(hipEventElapsedTime(&ms, ev[nv + vi], ev[nv + 1 + vi]));
       if (vi == 0 || ms < best) { best = ms; choice = var[vi]; }
     }
     for (auto& e : ev) (void)hipEventDestroy(e);
@@ -667,7 +840,10 @@ void gemm_batched(const std::vector<GemmDesc>& in, GemmType type, Stager& st, hi
   int tile = 64;
   if (type == GEMM_F64) {
     if (tile_pref == 64 || tile_pref == 65 || tile_pref == 128) tile = tile_pref;
-    else if (!split) tile = tuned_tile(d, tiles, kmax, flops, st, s);
+    else if (!split) tile = tuned_tile(d, type, tiles, kmax, flops, st, s);
+  } else if (type != GEMM_BF16 && type != GEMM_BF16_D) {
+    if (tile_pref == 64 || tile_pref == 65 || tile_pref == 128) tile = tile_pref == 65 ? 64 : tile_pref;
+    else if (!split) tile = tuned_tile(d, type, tiles, kmax, flops, st, s);
   }
   if (split) {
     std::vector<GemmDesc> parts;
