@@ -177,6 +177,12 @@ typedef struct {
   int64_t peak_bytes;       /* bound on the device bytes in use during the last
                                numeric factorization: the sum of each of the
                                handle's arenas' high-water marks */
+  int32_t trsv_multi_ops;   /* triangular-solve launches of the recorded
+                               preconditioner sweeps (both directions, both
+                               transposes) that run on several workgroups per
+                               system; the others, and every launch captured
+                               in a graph, take one workgroup per system */
+  int32_t pad0;
 } hssmf_stats;
 
 /* Fill *o with defaults: rel_tol 1e-6, leaf_size 64, min_sep_hss INT32_MAX

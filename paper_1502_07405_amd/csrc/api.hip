@@ -86,6 +86,11 @@ void setup(Handle& h, const hssmf_csr* A) {
   h.d_scal = h.arena.get<double>(1024);
   h.gm = gm_dev(h.arena.get<double>(kGmDevDoubles));
   h.gmpoll.init();
+  if (!h.werr_h) {
+    HIP_CHECK(hipHostMalloc((void**)&h.werr_h, sizeof(int), hipHostMallocMapped | hipHostMallocCoherent));
+    HIP_CHECK(hipHostGetDevicePointer((void**)&h.werr_d, h.werr_h, 0));
+    *h.werr_h = 0;
+  }
   h.d_part = h.arena.get<double>(kDotParts);
   h.d_info = h.arena.get<int>(2);
   h.fr.assign(P.nfront, FrontRT());
@@ -247,6 +252,11 @@ void numeric(Handle& h) {
   h.stats.growth_rounds = rounds;
   h.stats.factor_bytes = (int64_t)(h.arena.used() + h.narena.used());
   h.stats.peak_bytes = (int64_t)(h.arena.peak() + h.narena.peak() + h.larena.peak() + h.sarena.peak());
+  int multi = 0;
+  for (auto& a : h.sops)
+    for (auto& b : a)
+      for (const Op& o : b) multi += o.kind == OP_TRSV && o.ws != nullptr;
+  h.stats.trsv_multi_ops = multi;
 }
 
 }  // namespace
@@ -324,6 +334,15 @@ struct Ws {
 size_t outer_ws_doubles(const hssmf_opts& o, int64_t n) {
   const size_t nn = ((size_t)std::max<int64_t>(n, 1) + 31) & ~size_t(31);
   return nn * (size_t)(std::max(1, std::min(o.restart, kGmMaxRestart)) + 3);
+}
+
+// a bounded wait between workgroups of a device kernel that gave up during
+// the last solve (read once the stream has been synchronized)
+void check_waits(Handle& h) {
+  if (h.werr_h && __atomic_load_n(h.werr_h, __ATOMIC_ACQUIRE)) {
+    __atomic_store_n(h.werr_h, 0, __ATOMIC_RELEASE);
+    throw Error(HSSMF_EDEVICE, "triangular solve: a wait between workgroups gave up");
+  }
 }
 
 // restarted, left-preconditioned GMRES(m) (Sec. 4.6) with the modified
@@ -442,8 +461,10 @@ int outer(Handle& h, int trans, const double* b, double* x, hssmf_info* info, do
   if (info) { info->iterations = 0; info->rel_residual = 0; info->failed_front = -1; info->outer_switched = 0; }
   Ws ws(h, wsbase, wscap);
   const bool graph = wsbase == nullptr;   // capturing a graph allocates
-  return h.o.outer == HSSMF_OUTER_GMRES ? gmres(h, trans, b, x, info, ws, graph)
-                                        : refine(h, trans, b, x, info, ws, graph);
+  const int rc = h.o.outer == HSSMF_OUTER_GMRES ? gmres(h, trans, b, x, info, ws, graph)
+                                                : refine(h, trans, b, x, info, ws, graph);
+  check_waits(h);   // both end with the stream synchronized
+  return rc;
 }
 
 }  // namespace
@@ -718,6 +739,7 @@ int hssmf_apply(void* hv, int32_t trans, const double* x, double* y) {
     apply_inverse(*h, trans, x, y);
     HIP_CHECK(hipStreamSynchronize(h->st));
     h->stager.sync();
+    check_waits(*h);
   });
 }
 

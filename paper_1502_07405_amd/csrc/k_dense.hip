@@ -6,6 +6,8 @@
 // through each launch together.
 #include <type_traits>
 
+#include <cstdlib>
+
 #include "kernels.hpp"
 
 namespace hssmf {
@@ -510,6 +512,29 @@ __device__ __forceinline__ double lane_bcast(double v, int j) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// The row interchanges of rows [c0, c1) (their pivot indices staged in
+// pv[i - c0]) applied to v in order (FWD) or in reverse order, by wavefront
+// 0: each group of 64 indices is read once into registers and taken lane
+// by lane as scalars, and lane 0 makes the swaps in sequence.
+template <bool FWD>
+__device__ __forceinline__ void swap_rows(double* v, const int* pv, int c0, int c1, int lane) {
+  for (int g = 0; g < c1 - c0; g += 64) {
+    const int i0 = FWD ? c0 + g : max(c0, c1 - g - 64);
+    const int n = FWD ? min(64, c1 - i0) : c1 - g - i0;
+    const int pl = lane < n ? pv[i0 - c0 + lane] : i0 + lane;
+    for (int k = 0; k < n; ++k) {
+      const int u = FWD ? k : n - 1 - k;
+      const int p = __builtin_amdgcn_readlane(pl, u);
+      const int i = i0 + u;
+      if (p != i && lane == 0) {
+        const double t = v[i];
+        v[i] = v[p];
+        v[p] = t;
+      }
+    }
+  }
+}
+
 // Triangular solves with the F11 factors, one workgroup per front, the
 // right-hand side staged in LDS.  Blocks of 64: the diagonal block is staged
 // in LDS with coalesced loads, one wavefront solves it (each new entry read
@@ -534,11 +559,7 @@ __global__ __launch_bounds__(NT) void trsv_kernel(const TrsvDesc* __restrict__ d
         pv[tid] = p;
         sw = p != c0 + tid;
       }
-      if (__syncthreads_or(sw) && tid == 0)
-        for (int i = c0; i < min(s, c0 + 256); ++i) {
-          const int p = pv[i - c0];
-          if (p != i) { double t = xs[i]; xs[i] = xs[p]; xs[p] = t; }
-        }
+      if (__syncthreads_or(sw) && tid < 64) swap_rows<true>(xs, pv, c0, min(s, c0 + 256), lane);
       __syncthreads();
     }
   // logical matrix T: KIND 0: L (unit lower), 1: U (upper), 2: U^T (lower),
@@ -621,14 +642,244 @@ __global__ __launch_bounds__(NT) void trsv_kernel(const TrsvDesc* __restrict__ d
         pv[tid] = p;
         sw = p != c0 + tid;
       }
-      if (__syncthreads_or(sw) && tid == 0)
-        for (int i = c1 - 1; i >= c0; --i) {
-          const int p = pv[i - c0];
-          if (p != i) { double t = xs[i]; xs[i] = xs[p]; xs[p] = t; }
-        }
+      if (__syncthreads_or(sw) && tid < 64) swap_rows<false>(xs, pv, c0, c1, lane);
     }
   __syncthreads();
   for (int i = tid; i < s; i += NT) d.x[i] = xs[i];
+}
+
+// The same triangular solves with one workgroup per block of 64 entries
+// (the blocks the one-workgroup kernel steps through, in the same order).
+// The workgroup of block q subtracts every earlier block from its own as
+// each is published, in block order, then solves its block and publishes
+// its entries in x through agent-coherent stores and then its flag; each
+// entry takes exactly the operations of the one-workgroup kernel in the
+// same order, so both give identical results.  Workgroups take their
+// (system, block) from a ticket drawn when they start, blocks in order
+// across the systems, so a workgroup only ever waits for workgroups that
+// started before it: no co-residency is needed and an ordinary launch (also
+// inside a graph) is safe.  Flags hold the number of the launch that set
+// them (ws[0] counts launches; the last workgroup to finish advances it and
+// resets the ticket and finish counters), so no reset is needed between
+// launches; every wait is bounded and gives up once any workgroup has set
+// *err (host-visible memory, polled every 256 spins).
+constexpr unsigned kTrsvSpinLimit = 1u << 22;
+
+__device__ __forceinline__ void st_agent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_agent(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void trsv_multi_kernel(const TrsvDesc* __restrict__ descs, int nd, int maxnb,
+                                                         int* __restrict__ ws, int* __restrict__ err) {
+  constexpr int NT = 256;
+  constexpr bool trans = (KIND == 2 || KIND == 3 || KIND == 5);
+  constexpr bool lower = (KIND == 0 || KIND == 2 || KIND == 4);
+  constexpr bool unit = (KIND == 0 || KIND == 3);
+  extern __shared__ double sm[];
+  // LDS: this block's diagonal block and the block being subtracted (each
+  // staged ahead of the wait for the block it holds the columns of), the
+  // published block being applied, this block's entries, and (pivoted
+  // kinds) the whole vector for the sequential interchanges
+  double (*Td)[65] = reinterpret_cast<double (*)[65]>(sm);
+  double (*To)[65] = reinterpret_cast<double (*)[65]>(sm + 64 * 65);
+  double* xq = sm + 2 * 64 * 65;
+  double* own = xq + 64;
+  double* xall = own + 64;
+  __shared__ int pv[256];
+  __shared__ int sh_i;
+  const int tid = threadIdx.x, lane = tid & 63;
+  if (tid == 0) sh_i = __hip_atomic_fetch_add(ws + 2, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const int ticket = sh_i;
+  const int f = ticket % nd, t = ticket / nd;   // system, block
+  const TrsvDesc d = descs[f];
+  const int s = d.s;
+  const int64_t ld = d.ld;
+  const int nb = (s + 63) / 64;
+  int* flags = ws + 3 + (size_t)f * (maxnb + 1);   // [q]: block q published, [nb]: interchanges applied
+  const int target = __hip_atomic_load(ws, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+  auto T = [&](int i, int j) -> double {
+    return trans ? d.F[j + (int64_t)i * ld] : d.F[i + (int64_t)j * ld];
+  };
+  auto blk = [&](int q, int& b0, int& bs) {
+    if (lower) {
+      b0 = 64 * q;
+      bs = min(64, s - b0);
+    } else {
+      const int b1 = s - 64 * q;
+      b0 = max(0, b1 - 64);
+      bs = b1 - b0;
+    }
+  };
+  // D[r][c] = T(r0 + r, c0 + c), read along the stored columns
+  auto stage = [&](double (*D)[65], int r0, int rs, int c0, int cs) {
+    for (int e = tid; e < 64 * 64; e += NT) {
+      const int fast = e & 63, slow = e >> 6;
+      const int r = trans ? slow : fast, c = trans ? fast : slow;
+      if (r < rs && c < cs) D[r][c] = T(r0 + r, c0 + c);
+    }
+  };
+  // bounded wait (thread 0, agent-coherent polls) until *fl holds this
+  // launch's number, then one acquire fence
+  auto wait_flag = [&](const int* fl) {
+    if (tid == 0) {
+      unsigned spins = 0;
+      int ok = 1;
+      while (__hip_atomic_load(const_cast<int*>(fl), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != target) {
+        if (++spins > kTrsvSpinLimit ||
+            ((spins & 255) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))) {
+          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      sh_i = ok;
+    }
+    __syncthreads();
+    return sh_i != 0;
+  };
+  // every (agent-coherent) store of the workgroup complete, then the flag
+  auto publish = [&](int* fl) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(fl, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  bool alive = t < nb;
+  int b0 = 0, bs = 0;
+  if (alive) blk(t, b0, bs);
+  // interchanges before the solve (KIND 0): applied to the whole vector by
+  // the workgroup of block 0 (the first of its system), only when there are
+  // any
+  bool swaps = false;
+  if ((KIND == 0 || KIND == 3) && d.ipiv && alive) {
+    bool any = false;
+    for (int i = tid; i < s; i += NT) any |= d.ipiv[i] != i;
+    swaps = __syncthreads_or(any);
+  }
+  if (KIND == 0 && swaps) {
+    if (t == 0) {
+      for (int i = tid; i < s; i += NT) xall[i] = d.x[i];
+      for (int c0 = 0; c0 < s; c0 += 256) {
+        __syncthreads();
+        if (tid < 256 && c0 + tid < s) pv[tid] = d.ipiv[c0 + tid];
+        __syncthreads();
+        if (tid < 64) swap_rows<true>(xall, pv, c0, min(s, c0 + 256), lane);
+      }
+      __syncthreads();
+      for (int i = tid; i < s; i += NT) st_agent(d.x + i, xall[i]);
+      publish(flags + nb);
+    } else {
+      alive = wait_flag(flags + nb);
+    }
+  }
+  if (alive) {
+    // this block's right-hand side and diagonal block
+    if (tid < bs) own[tid] = (KIND == 0 && swaps) ? ld_agent(d.x + b0 + tid) : d.x[b0 + tid];
+    stage(Td, b0, bs, b0, bs);
+    // every earlier block, in order: its block in this block's rows is read
+    // before the wait for it
+    for (int q = 0; q < t; ++q) {
+      int c0, cs;
+      blk(q, c0, cs);
+      __syncthreads();   // To and xq may still be read by the previous step
+      stage(To, b0, bs, c0, cs);
+      if (!wait_flag(flags + q)) { alive = false; break; }
+      if (tid < cs) xq[tid] = ld_agent(d.x + c0 + tid);
+      __syncthreads();
+      if (tid < bs) {
+        double acc = 0.0;
+        if (cs == 64) {
+          double tv[64];
+#pragma unroll
+          for (int c = 0; c < 64; ++c) tv[c] = To[tid][c];
+#pragma unroll
+          for (int c = 0; c < 64; ++c) acc += tv[c] * xq[c];
+        } else {
+          for (int c = 0; c < cs; ++c) acc += To[tid][c] * xq[c];
+        }
+        own[tid] -= acc;
+      }
+    }
+  }
+  if (alive) {
+    // solve the block, publish it
+    __syncthreads();
+    if (tid < 64) {
+      double v = (lane < bs) ? own[lane] : 0.0;
+      if (bs == 64) {
+        // a whole block: the lane's row in registers, every step unrolled
+        double tr[64];
+#pragma unroll
+        for (int j = 0; j < 64; ++j) tr[j] = Td[lane][j];
+        const double dl = Td[lane][lane];
+        if (lower) {
+#pragma unroll
+          for (int j = 0; j < 64; ++j) {
+            if (!unit && lane == j) v /= dl;
+            const double vj = lane_bcast(v, j);
+            if (lane > j) v -= tr[j] * vj;
+          }
+        } else {
+#pragma unroll
+          for (int j = 63; j >= 0; --j) {
+            if (!unit && lane == j) v /= dl;
+            const double vj = lane_bcast(v, j);
+            if (lane < j) v -= tr[j] * vj;
+          }
+        }
+      } else if (lower) {
+        for (int j = 0; j < bs; ++j) {
+          const double tj = Td[lane][j];
+          if (!unit && lane == j) v /= Td[j][j];
+          const double vj = lane_bcast(v, j);
+          if (lane > j && lane < bs) v -= tj * vj;
+        }
+      } else {
+        for (int j = bs - 1; j >= 0; --j) {
+          const double tj = Td[lane][j];
+          if (!unit && lane == j) v /= Td[j][j];
+          const double vj = lane_bcast(v, j);
+          if (lane < j) v -= tj * vj;
+        }
+      }
+      if (lane < bs) st_agent(d.x + b0 + lane, v);
+    }
+    publish(flags + t);
+  }
+  // interchanges after the solve (KIND 3): by the workgroup of the last
+  // block, the last of its system, once every block is published
+  if (KIND == 3 && swaps && alive && t == nb - 1) {
+    for (int q = 0; q < nb - 1 && alive; ++q) alive = wait_flag(flags + q);
+    if (alive) {
+      for (int i = tid; i < s; i += NT) xall[i] = ld_agent(d.x + i);
+      for (int c1 = s; c1 > 0; c1 -= 256) {
+        const int c0 = max(0, c1 - 256);
+        __syncthreads();
+        if (tid < 256 && c0 + tid < c1) pv[tid] = d.ipiv[c0 + tid];
+        __syncthreads();
+        if (tid < 64) swap_rows<false>(xall, pv, c0, c1, lane);
+      }
+      __syncthreads();
+      for (int i = tid; i < s; i += NT) d.x[i] = xall[i];
+    }
+  }
+  // the last workgroup of the launch advances the launch count and resets
+  // the ticket and finish counters
+  __syncthreads();
+  if (tid == 0) {
+    const int done = __hip_atomic_fetch_add(ws + 1, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (done == (int)gridDim.x - 1) {
+      __hip_atomic_store(ws + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(ws + 2, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(ws, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
 }
 
 void launch_trsv(const TrsvDesc* d, int nd, int kind, int max_s, hipStream_t s) {
@@ -661,6 +912,40 @@ void launch_trsv(const TrsvDesc* d, int nd, int kind, int max_s, hipStream_t s) 
     default: HSSMF_TRSV(5) break;
   }
 #undef HSSMF_TRSV
+  HIP_CHECK(hipGetLastError());
+}
+
+size_t trsv_multi_lds(int kind, int max_s) {
+  size_t b = (size_t)(2 * 64 * 65 + 128) * sizeof(double);
+  if (kind == 0 || kind == 3) b += (size_t)max_s * sizeof(double);
+  return b;
+}
+
+// Systems of at least 256 entries.  Along the stored columns (L, U) the
+// one-workgroup kernel reads coalesced and many systems keep the chip busy
+// by themselves, so beyond 32 systems it stays; the transposed kinds read
+// across the stored columns there and always take the per-block kernel.
+bool trsv_multi_use(int nd, int kind, int max_s) {
+  // diagnostics: HSSMF_TRSV_ONE_WG=1 keeps every solve on one workgroup
+  static const bool one_wg = std::getenv("HSSMF_TRSV_ONE_WG") != nullptr;
+  const bool trans = kind == 2 || kind == 3 || kind == 5;
+  return !one_wg && nd > 0 && max_s >= 256 && (trans || nd <= 32) &&
+         trsv_multi_lds(kind, max_s) <= lds_budget(256 * sizeof(int) + 64);
+}
+
+void launch_trsv_multi(const TrsvDesc* d, int nd, int kind, int max_s, int* ws, int* err, hipStream_t s) {
+  if (nd <= 0) return;
+  const int maxnb = (max_s + 63) / 64;
+  const size_t lds = trsv_multi_lds(kind, max_s);
+  const dim3 grid((unsigned)(nd * maxnb)), blk(256);
+  switch (kind) {
+    case 0: hipLaunchKernelGGL(trsv_multi_kernel<0>, grid, blk, lds, s, d, nd, maxnb, ws, err); break;
+    case 1: hipLaunchKernelGGL(trsv_multi_kernel<1>, grid, blk, lds, s, d, nd, maxnb, ws, err); break;
+    case 2: hipLaunchKernelGGL(trsv_multi_kernel<2>, grid, blk, lds, s, d, nd, maxnb, ws, err); break;
+    case 3: hipLaunchKernelGGL(trsv_multi_kernel<3>, grid, blk, lds, s, d, nd, maxnb, ws, err); break;
+    case 4: hipLaunchKernelGGL(trsv_multi_kernel<4>, grid, blk, lds, s, d, nd, maxnb, ws, err); break;
+    default: hipLaunchKernelGGL(trsv_multi_kernel<5>, grid, blk, lds, s, d, nd, maxnb, ws, err); break;
+  }
   HIP_CHECK(hipGetLastError());
 }
 

@@ -121,6 +121,14 @@ void launch_gemv(const GemvDesc* d, int nd, int gx, hipStream_t s);
 // 2 = U^{-T}, 3 = P^T L^{-T} (unit, pivots last), 4 = L^{-1} (non-unit
 // lower), 5 = L^{-T} (non-unit lower, transposed)
 void launch_trsv(const TrsvDesc* d, int nd, int kind, int max_s, hipStream_t s);
+// The same solves with one workgroup per block of 64 entries of each system
+// (identical results; an ordinary launch of nd ceil(max_s / 64) workgroups,
+// also inside a graph).  trsv_multi_use: whether a batch takes it (systems of
+// at least 256 entries; at most 32 systems for the untransposed kinds).  ws holds 3 + nd (ceil(max_s / 64) + 1) ints, zero
+// before the first launch and kept between launches; *err != 0 after a
+// launch means a bounded wait gave up and the results are invalid.
+bool trsv_multi_use(int nd, int kind, int max_s);
+void launch_trsv_multi(const TrsvDesc* d, int nd, int kind, int max_s, int* ws, int* err, hipStream_t s);
 void launch_rhs_gather(const RhsDesc* d, int nd, int max_n, hipStream_t s);
 
 }  // namespace hssmf

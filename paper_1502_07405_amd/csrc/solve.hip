@@ -63,7 +63,15 @@ struct Rec {
     int64_t ms = 0;
     for (auto& t : v)
       if (t.s > 0) { w.push_back(t); ms = std::max<int64_t>(ms, t.s); }
-    if (!w.empty()) ops.push_back({OP_TRSV, upload(h, w), (int)w.size(), kind + 16 * ms});
+    if (w.empty()) return;
+    Op o{OP_TRSV, upload(h, w), (int)w.size(), kind + 16 * ms};
+    // long systems: one workgroup per block of 64 entries
+    if (trsv_multi_use((int)w.size(), kind, (int)ms)) {
+      const size_t nws = 3 + w.size() * (size_t)((ms + 63) / 64 + 1);
+      o.ws = h.cur->get<int>(nws);
+      HIP_CHECK(hipMemsetAsync(o.ws, 0, nws * sizeof(int), h.st));
+    }
+    ops.push_back(o);
   }
   void rhs(const std::vector<RhsDesc>& v, int mx) {
     if (!v.empty()) ops.push_back({OP_RHS, upload(h, v), (int)v.size(), mx});
@@ -456,7 +464,12 @@ void run_ops(Handle& h, const std::vector<Op>& ops) {
     switch (o.kind) {
       case OP_GEMV: launch_gemv((const GemvDesc*)o.d, o.n, (int)o.p0, h.st); break;
       case OP_COPY: launch_copy(device_batch<CopyDesc, 32>((const CopyDesc*)o.d), o.n, o.p0, 0, h.st); break;
-      case OP_TRSV: launch_trsv((const TrsvDesc*)o.d, o.n, (int)(o.p0 % 16), (int)(o.p0 / 16), h.st); break;
+      case OP_TRSV:
+        if (o.ws)
+          launch_trsv_multi((const TrsvDesc*)o.d, o.n, (int)(o.p0 % 16), (int)(o.p0 / 16), o.ws, h.werr_d, h.st);
+        else
+          launch_trsv((const TrsvDesc*)o.d, o.n, (int)(o.p0 % 16), (int)(o.p0 / 16), h.st);
+        break;
       case OP_RHS: launch_rhs_gather((const RhsDesc*)o.d, o.n, (int)o.p0, h.st); break;
     }
   }

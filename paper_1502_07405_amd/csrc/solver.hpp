@@ -115,6 +115,9 @@ struct Op {
   const void* d; // device descriptor array
   int n;         // descriptors
   int64_t p0;    // kernel parameter (max extent / trsv kind)
+  // triangular solves with one workgroup per block of 64 entries: their
+  // launch-count, ticket and flag words (nullptr: one workgroup per system)
+  int* ws = nullptr;
 };
 enum { OP_GEMV = 0, OP_COPY = 1, OP_TRSV = 2, OP_RHS = 3 };
 
@@ -219,6 +222,10 @@ struct Handle {
   Stager stager;
   IdPoll idpoll;
   GmPoll gmpoll;
+  // set by a device wait that gave up (mapped, host-coherent); checked once
+  // an entry point has synchronized its stream
+  int* werr_h = nullptr;
+  int* werr_d = nullptr;
   GmDev gm{};                  // GMRES state on the device
   std::vector<Op> sops[2][2];  // [trans][0 = forward, 1 = backward]
   // status of the last numeric factorization: HSSMF_OK when the factors and
@@ -280,6 +287,7 @@ struct Handle {
       if (ev_join[i]) (void)hipEventDestroy(ev_join[i]);
     }
     if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (werr_h) (void)hipHostFree(werr_h);
   }
   hssmf_stats stats{};
   GemmType gt() const;

@@ -71,7 +71,7 @@ class Stats(ctypes.Structure):
                 ("max_rank", ctypes.c_int32), ("max_d", ctypes.c_int32), ("growth_rounds", ctypes.c_int32),
                 ("factor_bytes", ctypes.c_int64), ("t_plan_ms", ctypes.c_double),
                 ("t_factor_ms", ctypes.c_double), ("flops_factor", ctypes.c_double),
-                ("peak_bytes", ctypes.c_int64)]
+                ("peak_bytes", ctypes.c_int64), ("trsv_multi_ops", ctypes.c_int32), ("pad0", ctypes.c_int32)]
 
 
 _lib = None
