@@ -134,7 +134,7 @@ MEASURED_KEY = {"id": "fp64_valu_TFLOPs", "gemm64": "fp64_mfma_TFLOPs", "gemmlp"
 # copy in the same run): profiles/id_res_hbm_traffic_poisson3d_64.md.  Valid
 # only for the kernel source those counters were taken on.  The bench divides
 # the total by its own launches per factorization.
-TRAFFIC = {"idres": (1.5822e10, "paper_1502_07405_amd/csrc/k_idres.hip", "24483633caefa2e3")}
+TRAFFIC = {"idres": (1.5700e10, "paper_1502_07405_amd/csrc/k_idres.hip", "fff91552dc661b6a")}
 
 
 def traffic_for(cls, launches_per_factorization):
@@ -180,6 +180,29 @@ def summarize(paths):
             for (name, cn), a in sorted(agg.items(), key=lambda kv: -sum(kv[1].values())):
                 tot = sum(a.values())
                 print(f"| {name} | {cn} | {len(a)} | {tot:.6g} | {tot / len(a):.6g} |")
+            # matrix-core runs: flops (MOPS x 512) over the dispatches' own
+            # durations, and MFMA busy cycles over one XCD's active cycles
+            # (GRBM_GUI_ACTIVE is summed over the 8 XCDs) times 1024 SIMDs
+            names = {cn for (_, cn) in agg}
+            if {"SQ_VALU_MFMA_BUSY_CYCLES", "GRBM_GUI_ACTIVE"} <= names:
+                dur = {}
+                for r in rows:
+                    dur[r["Dispatch_Id"]] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+                print(f"# {path}: matrix-core rates per kernel")
+                print("| kernel | dispatches | GFLOP / dispatch | mean us | TFLOP/s | MFMA busy |")
+                print("|---|---:|---:|---:|---:|---:|")
+                kern = sorted({name for (name, _) in agg})
+                for name in kern:
+                    busy = agg.get((name, "SQ_VALU_MFMA_BUSY_CYCLES"), {})
+                    gui = agg.get((name, "GRBM_GUI_ACTIVE"), {})
+                    mops = [agg.get((name, c), {}) for c in ("SQ_INSTS_VALU_MFMA_MOPS_F64", "SQ_INSTS_VALU_MFMA_MOPS_F32")]
+                    fl = 512.0 * sum(sum(m.values()) for m in mops)
+                    if fl <= 0 or not gui:
+                        continue
+                    ns = sum(dur[k] for k in gui)
+                    util = 8.0 * sum(busy.values()) / (sum(gui.values()) * 1024.0)
+                    print(f"| {name} | {len(gui)} | {fl / len(gui) / 1e9:.3f} | {ns / len(gui) / 1e3:.1f} | "
+                          f"{fl / ns / 1e3:.1f} | {100 * util:.1f}% |")
         else:
             for r in rows:
                 name = re.sub(r"\s+", " ", r["Kernel_Name"])[:110]
