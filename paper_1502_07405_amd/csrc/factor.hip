@@ -945,16 +945,23 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
         launch_id_finish(dq, np, maxm, h.st);
         }
       }
-      int herr = 0;
-      if (derr) HIP_CHECK(hipMemcpyAsync(&herr, derr, sizeof(int), hipMemcpyDeviceToHost, h.st));
+      // the pass's results: the wait flag, the stop steps and ranks, the
+      // pivot orders, read back through pinned memory with one
+      // synchronization
       std::vector<int> sh(4 * cand.size());
-      if (!sh.empty())
-        HIP_CHECK(hipMemcpyAsync(sh.data(), sbuf, sh.size() * sizeof(int), hipMemcpyDeviceToHost, h.st));
       std::vector<int> hbuf(off.back());
+      int* pin = h.pinned_ints(1 + sh.size() + hbuf.size());
+      pin[0] = 0;
+      if (derr) HIP_CHECK(hipMemcpyAsync(pin, derr, sizeof(int), hipMemcpyDeviceToHost, h.st));
+      if (!sh.empty())
+        HIP_CHECK(hipMemcpyAsync(pin + 1, sbuf, sh.size() * sizeof(int), hipMemcpyDeviceToHost, h.st));
       if (!hbuf.empty())
-        HIP_CHECK(hipMemcpyAsync(hbuf.data(), ibuf, hbuf.size() * sizeof(int), hipMemcpyDeviceToHost, h.st));
+        HIP_CHECK(hipMemcpyAsync(pin + 1 + sh.size(), ibuf, hbuf.size() * sizeof(int), hipMemcpyDeviceToHost, h.st));
       HIP_CHECK(hipStreamSynchronize(h.st));
       h.stager.sync();
+      const int herr = pin[0];
+      std::copy(pin + 1, pin + 1 + sh.size(), sh.begin());
+      std::copy(pin + 1 + sh.size(), pin + 1 + sh.size() + hbuf.size(), hbuf.begin());
       REQUIRE(herr == 0, HSSMF_EDEVICE, "interpolative decomposition: a workgroup barrier timed out");
       if (id_census && !cand.empty()) {
         const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count() - census_t0;

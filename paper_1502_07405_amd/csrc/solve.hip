@@ -65,11 +65,12 @@ struct Rec {
       if (t.s > 0) { w.push_back(t); ms = std::max<int64_t>(ms, t.s); }
     if (w.empty()) return;
     Op o{OP_TRSV, upload(h, w), (int)w.size(), kind + 16 * ms};
-    // long systems: one workgroup per block of 64 entries
+    // long systems: one workgroup per block of 64 entries; their launch,
+    // ticket and flag words travel zeroed in the blob (an offset until the
+    // blob is on the device, never 0: the descriptors precede them)
     if (trsv_multi_use((int)w.size(), kind, (int)ms)) {
       const size_t nws = 3 + w.size() * (size_t)((ms + 63) / 64 + 1);
-      o.ws = h.cur->get<int>(nws);
-      HIP_CHECK(hipMemsetAsync(o.ws, 0, nws * sizeof(int), h.st));
+      o.ws = reinterpret_cast<int*>(const_cast<void*>(upload(h, std::vector<int>(nws, 0))));
     }
     ops.push_back(o);
   }
@@ -456,7 +457,10 @@ void build_solve_ops(Handle& h) {
   HIP_CHECK(hipStreamSynchronize(h.st));  // the blob is pageable host memory
   for (int tr = 0; tr < 2; ++tr)
     for (int sw = 0; sw < 2; ++sw)
-      for (Op& o : h.sops[tr][sw]) o.d = dev + reinterpret_cast<size_t>(o.d);
+      for (Op& o : h.sops[tr][sw]) {
+        o.d = dev + reinterpret_cast<size_t>(o.d);
+        if (o.ws) o.ws = reinterpret_cast<int*>(dev + reinterpret_cast<size_t>(o.ws));
+      }
 }
 
 void run_ops(Handle& h, const std::vector<Op>& ops) {

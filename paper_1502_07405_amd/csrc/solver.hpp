@@ -226,6 +226,20 @@ struct Handle {
   // an entry point has synchronized its stream
   int* werr_h = nullptr;
   int* werr_d = nullptr;
+  // pinned host words for the results the host reads back after a pass
+  // (device-to-host copies into it stay asynchronous, so a pass's several
+  // read-backs cost one stream synchronization)
+  int* pin = nullptr;
+  size_t pin_cap = 0;
+  int* pinned_ints(size_t n) {
+    if (n > pin_cap) {
+      if (pin) HIP_CHECK(hipHostFree(pin));
+      pin = nullptr;
+      pin_cap = std::max<size_t>(n, 2 * pin_cap);
+      HIP_CHECK(hipHostMalloc((void**)&pin, pin_cap * sizeof(int), hipHostMallocDefault));
+    }
+    return pin;
+  }
   GmDev gm{};                  // GMRES state on the device
   std::vector<Op> sops[2][2];  // [trans][0 = forward, 1 = backward]
   // status of the last numeric factorization: HSSMF_OK when the factors and
@@ -288,6 +302,7 @@ struct Handle {
     }
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (werr_h) (void)hipHostFree(werr_h);
+    if (pin) (void)hipHostFree(pin);
   }
   hssmf_stats stats{};
   GemmType gt() const;
