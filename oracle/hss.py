@@ -135,11 +135,32 @@ class HSS:
 # randomized compression (Alg. 1) with adaptive rank (Sec. 2.2.1, Sec. 4.3)
 # ---------------------------------------------------------------------------
 
-def compress(op, nodes, root, rand, eps, d0, dd, p, d_max, atol=0.0):
+def power_samples(op, R, q):
+    """Samples of F and F^T with q steps of power iteration (Sec. 2.2, the
+    power-iteration variant the paper describes and leaves as an option):
+    S^r = (F F^T)^q F R and S^c = (F^T F)^q F^T R, with the matrices Alg. 1
+    then takes in place of R: R^r = F^T (F F^T)^(q-1) F R for the row side
+    (S^r = F R^r) and R^c = F (F^T F)^(q-1) F^T R for the column side
+    (S^c = F^T R^c).  q = 0 is the plain sampling, R^r = R^c = R.  No
+    reorthogonalization between the products (the paper names it as a
+    possible need, without making it part of the scheme)."""
+    Sr, Sc = op.sample(R)
+    Rr = Rc = R
+    for _ in range(q):
+        Rr = op.sample(Sr)[1]    # F^T applied to the current row samples
+        Rc = op.sample(Sc)[0]    # F applied to the current column samples
+        Sr = op.sample(Rr)[0]
+        Sc = op.sample(Rc)[1]
+    return Sr, Sc, Rr, Rc
+
+
+def compress(op, nodes, root, rand, eps, d0, dd, p, d_max, atol=0.0, power_q=0):
     """Alg. 1 applied to a matrix known through ``op``:
     op.sample(R) -> (F R, F^T R) for a block of random columns and
     op.extract(I, J) -> F[I][:, J].  ``rand(c0, nc)`` returns columns
-    [c0, c0+nc) of the random matrix R (n x nc).
+    [c0, c0+nc) of the random matrix R (n x nc).  With power_q > 0 the
+    samples come from ``power_samples``, and the row side of every node
+    takes R^r, the column side R^c, where plain sampling takes R for both.
 
     Bottom-up over the tree.  Reading of the paper's ID failure test (not
     stated there): a node succeeds iff its rank k satisfies k <= d - p or
@@ -155,8 +176,7 @@ def compress(op, nodes, root, rand, eps, d0, dd, p, d_max, atol=0.0):
     Rr_red = [None] * nn
     Rc_red = [None] * nn
     d = d0
-    R = rand(0, d)
-    Sr, Sc = op.sample(R)
+    Sr, Sc, Rr, Rc = power_samples(op, rand(0, d), power_q)
     rounds = 0
     # record of the work done, for the algorithmic operation counts only
     # (oracle.work): columns sampled per pass, and per ID attempt the node,
@@ -170,8 +190,7 @@ def compress(op, nodes, root, rand, eps, d0, dd, p, d_max, atol=0.0):
         g = gen[t]
         if nd.leaf:
             I = np.arange(nd.lo, nd.hi)
-            Rt = R[I][:, cols]
-            return Sr[I][:, cols] - g.D @ Rt, Sc[I][:, cols] - g.D.T @ Rt
+            return Sr[I][:, cols] - g.D @ Rr[I][:, cols], Sc[I][:, cols] - g.D.T @ Rc[I][:, cols]
         a, b = nd.children
         sr = np.vstack([Sr_red[a][:, cols] - g.B12 @ Rr_red[b][:, cols],
                         Sr_red[b][:, cols] - g.B21 @ Rr_red[a][:, cols]])
@@ -186,8 +205,8 @@ def compress(op, nodes, root, rand, eps, d0, dd, p, d_max, atol=0.0):
         g = gen[t]
         if nd.leaf:
             I = np.arange(nd.lo, nd.hi)
-            Rr_in = R[I][:, cols]
-            Rc_in = Rr_in
+            Rr_in = Rr[I][:, cols]
+            Rc_in = Rc[I][:, cols]
         else:
             a, b = nd.children
             Rr_in = np.vstack([Rr_red[a][:, cols], Rr_red[b][:, cols]])
@@ -236,10 +255,10 @@ def compress(op, nodes, root, rand, eps, d0, dd, p, d_max, atol=0.0):
             break
         if d + dd > d_max:
             raise RankError(f"HSS compression needs more than d_max={d_max} samples")
-        Rn = rand(d, dd)
-        Srn, Scn = op.sample(Rn)
+        Srn, Scn, Rrn, Rcn = power_samples(op, rand(d, dd), power_q)
         log["sampled"].append(dd)
-        R = np.hstack([R, Rn])
+        Rr = np.hstack([Rr, Rrn])
+        Rc = np.hstack([Rc, Rcn])
         Sr = np.hstack([Sr, Srn])
         Sc = np.hstack([Sc, Scn])
         newc = np.arange(d, d + dd)
@@ -666,12 +685,12 @@ class Front11Ops:
         return down_expand(self.H, self.k, self.B_qk.T @ self._vt(self.q, x, "U"), "V")
 
 
-def build_hss_front(op, s, u, leaf_size, rand, eps, d0, dd, p, d_max, atol=0.0):
+def build_hss_front(op, s, u, leaf_size, rand, eps, d0, dd, p, d_max, atol=0.0, power_q=0):
     """Compress a front of size s+u (Alg. 1), then ULV-factor its F11 part and
     form Theta^*, Phi.  Returns (H, ULV, k, q, Theta, Phi)."""
     nodes, k, q = hss_tree(s, u, leaf_size)
     root = len(nodes) - 1
-    H = compress(op, nodes, root, rand, eps, d0, dd, p, d_max, atol)
+    H = compress(op, nodes, root, rand, eps, d0, dd, p, d_max, atol, power_q)
     F = ulv_factor(H, k)
     Theta = Phi = None
     if q >= 0:

@@ -337,3 +337,48 @@ def test_ulv_equals_dense_solve(rng, s, u, leaf):
         assert np.allclose(ops.f12(x), Fd[:s, s:] @ x, atol=1e-11)
         assert np.allclose(ops.f12t(z), Fd[:s, s:].T @ z, atol=1e-11)
         assert np.allclose(ops.f21t(x), Fd[s:, :s].T @ x, atol=1e-11)
+
+
+@pytest.mark.parametrize("q", [1, 2])
+def test_power_iteration_keeps_exact_recovery(rng, q):
+    """Power iteration (samples of (F F^T)^q F and (F^T F)^q F^T, Sec. 2.2)
+    spans the same spaces as plain sampling when the off-diagonal blocks
+    have exact rank r: every node gets rank exactly r and the HSS form
+    reproduces the matrix."""
+    r = 3
+    src = _four_leaf_hss(rng, m=(9, 10, 8, 11), r=r)
+    A = H.hss_dense(src, 6)
+    hs = H.compress(DenseOp(A), src.nodes, 6, _rand_fn(A.shape[0]), 1e-10, 16, 8, 5, 1000, power_q=q)
+    for t in range(6):
+        assert hs.gen[t].r == r and hs.gen[t].c == r
+    assert np.linalg.norm(H.hss_dense(hs, 6) - A) <= 1e-9 * np.linalg.norm(A)
+
+
+@pytest.mark.parametrize("q,rank12,rank21", [(0, 4, 3), (1, 2, 1), (2, 1, 1)])
+def test_power_iteration_rank_follows_the_amplified_spectrum(q, rank12, rank21):
+    """The ID of the power-iterated samples sees the singular values of an
+    off-diagonal block raised to 2q + 1.  With zero diagonal blocks,
+    F = [0, A12; A21, 0]: F F^T and F^T F are block diagonal, so leaf 1's
+    row samples are (A12 A12^T)^q A12 times Gaussian rows and its column
+    samples (A21^T A21)^q A21^T times Gaussian rows, and leaf 2's the other
+    way round.  A12 = U diag(10^-2j) V^T and A21 = W diag(10^-3j) Z^T
+    (j = 0..7, orthonormal factors) differ, so a product taken with F where
+    F^T belongs (or the reverse) mixes the two spectra and changes a rank.
+    At eps = 1e-7 the eps-rank (|R_kk| <= eps |R_11|, Sec. 5.3) counts the
+    singular values whose (2q + 1)-th power exceeds 1e-7 times the largest,
+    every decision a decade or more from eps: 4, 2, 1 for A12 and 3, 1, 1
+    for A21 at q = 0, 1, 2."""
+    rg = np.random.default_rng(17)
+    m = 32
+    j = np.arange(8)
+    orth = lambda: np.linalg.qr(rg.standard_normal((m, 8)))[0]  # noqa: E731
+    A12 = orth() @ np.diag(10.0 ** (-2.0 * j)) @ orth().T
+    A21 = orth() @ np.diag(10.0 ** (-3.0 * j)) @ orth().T
+    A = np.zeros((2 * m, 2 * m))
+    A[:m, m:] = A12
+    A[m:, :m] = A21
+    nodes, k, qq = hss_tree(2 * m, 0, m)
+    root = len(nodes) - 1
+    hs = H.compress(DenseOp(A), nodes, root, _rand_fn(2 * m, 5), 1e-7, 24, 8, 4, 1000, power_q=q)
+    assert (hs.gen[0].r, hs.gen[0].c) == (rank12, rank21)
+    assert (hs.gen[1].r, hs.gen[1].c) == (rank21, rank12)
