@@ -131,6 +131,17 @@ typedef struct {
                           of O(n d + m_k u) per front); 0 (default): not */
   int32_t hss_update;  /* HSSMF_UPDATE_*: how an HSS front's update matrix
                           F22 - Theta^* Phi reaches an HSS parent */
+  int32_t power_q;     /* steps of power iteration in the sampling (Sec. 2.2,
+                          the variant the paper describes as an option):
+                          S^r = (F F^T)^q F R, S^c = (F^T F)^q F^T R, and
+                          Alg. 1 takes R^r = F^T (F F^T)^(q-1) F R on the row
+                          side, R^c = F (F^T F)^(q-1) F^T R on the column
+                          side.  The eps-rank rule then applies to the
+                          iterated samples, whose singular values are those
+                          of F raised to 2q + 1.  0 (default) = plain
+                          sampling; 1..4 need gemm_prec = FP64 (EINVAL
+                          otherwise); each step costs four more sampling
+                          passes */
 } hssmf_opts;
 
 /* hss_update: LOWRANK = kept as the HSS generators of F22 with Theta^* and
@@ -190,7 +201,7 @@ typedef struct {
  * iterative refinement, restart 30, tol 1e-10, max_it 50, resident ID
  * kernel (the stepwise one where it does not apply), sweeps launched one by
  * one (no graph), autotuned GEMM tiles, abs_tol 0, update matrices expanded
- * densely. */
+ * densely, plain sampling (power_q 0). */
 int hssmf_default_opts(hssmf_opts* o);
 
 /* Symbolic analysis, upload and numeric factorization (Sec. 3.2, Sec. 4).

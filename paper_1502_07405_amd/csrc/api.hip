@@ -551,6 +551,7 @@ int hssmf_default_opts(hssmf_opts* o) {
   o->max_it = 50;
   o->id_kernel = HSSMF_ID_RESIDENT;
   o->hss_update = HSSMF_UPDATE_DENSE;
+  o->power_q = 0;
   o->use_graph = 0;   // capture after every factorization costs more than replay saves
   return HSSMF_OK;
 }
@@ -565,7 +566,8 @@ bool opts_ok(const hssmf_opts* o) {
            o->id_kernel > 2 || o->use_graph < 0 || o->use_graph > 1 ||
            !(o->gemm_tile == 0 || o->gemm_tile == 64 || o->gemm_tile == 65 || o->gemm_tile == 128) ||
            !(o->abs_tol >= 0.0) || o->keep_stages < 0 || o->keep_stages > 1 || o->hss_update < 0 ||
-           o->hss_update > 1);
+           o->hss_update > 1 || o->power_q < 0 || o->power_q > 4 ||
+           (o->power_q > 0 && o->gemm_prec != HSSMF_PREC_FP64));
 }
 
 // a CSR matrix in host memory: the caller's arrays when they are host

@@ -253,6 +253,18 @@ void grow_samples(Handle& h, HFront& F, int dnew) {
     F.Rlp = lp;
   }
   F.R = R; F.Sr = Sr; F.Sc = Sc;
+  if (h.o.power_q > 0) {
+    // R^r and R^c of the power iteration, grown alike
+    double* Rr = lalloc(h, (int64_t)F.n * cap);
+    double* Rc = lalloc(h, (int64_t)F.n * cap);
+    if (F.Rr && F.d > 0) {
+      size_t bytes = sizeof(double) * (size_t)F.n * F.d;
+      HIP_CHECK(hipMemcpyAsync(Rr, F.Rr, bytes, hipMemcpyDeviceToDevice, h.st));
+      HIP_CHECK(hipMemcpyAsync(Rc, F.Rc, bytes, hipMemcpyDeviceToDevice, h.st));
+    }
+    F.Rr = Rr;
+    F.Rc = Rc;
+  }
   F.dcap = cap;
 }
 
@@ -472,6 +484,61 @@ void sample(Handle& h, const std::vector<HFront*>& fs, const std::vector<int>& c
   }
 }
 
+// Power iteration on columns [c0, c0+nc) (Sec. 2.2, the variant the paper
+// describes as an option), once sample() has formed S^r = F R and
+// S^c = F^T R there: q steps of R^r <- F^T S^r, R^c <- F S^c,
+// S^r <- F R^r, S^c <- F^T R^c.  Each product is a sample() pass with its
+// input and output arrays pointed elsewhere (every array n x columns, ld n);
+// the half of a pass that is not wanted goes to a scratch block.  Alg. 1
+// then takes R^r on the row side and R^c on the column side.
+void power_iterate(Handle& h, const std::vector<HFront*>& fs, const std::vector<int>& c0, int nc) {
+  const int q = h.o.power_q;
+  if (q <= 0 || fs.empty() || nc <= 0) return;
+  const size_t nf = fs.size();
+  std::vector<double*> R0(nf), Sr0(nf), Sc0(nf), junk(nf);
+  for (size_t i = 0; i < nf; ++i) {
+    R0[i] = fs[i]->R;
+    Sr0[i] = fs[i]->Sr;
+    Sc0[i] = fs[i]->Sc;
+    junk[i] = salloc(h, (int64_t)fs[i]->n * (c0[i] + nc));
+  }
+  // one pass: F in -> outr, F^T in -> outc
+  auto pass = [&](const std::vector<double*>& in, const std::vector<double*>& outr,
+                  const std::vector<double*>& outc) {
+    for (size_t i = 0; i < nf; ++i) {
+      fs[i]->R = in[i];
+      fs[i]->Sr = outr[i];
+      fs[i]->Sc = outc[i];
+    }
+    sample(h, fs, c0, nc);
+  };
+  std::vector<double*> Rr(nf), Rc(nf);
+  for (size_t i = 0; i < nf; ++i) {
+    Rr[i] = fs[i]->Rr;
+    Rc[i] = fs[i]->Rc;
+  }
+  try {
+    for (int it = 0; it < q; ++it) {
+      pass(Sr0, junk, Rr);   // R^r = F^T S^r
+      pass(Sc0, Rc, junk);   // R^c = F S^c
+      pass(Rr, Sr0, junk);   // S^r = F R^r
+      pass(Rc, junk, Sc0);   // S^c = F^T R^c
+    }
+  } catch (...) {
+    for (size_t i = 0; i < nf; ++i) {
+      fs[i]->R = R0[i];
+      fs[i]->Sr = Sr0[i];
+      fs[i]->Sc = Sc0[i];
+    }
+    throw;
+  }
+  for (size_t i = 0; i < nf; ++i) {
+    fs[i]->R = R0[i];
+    fs[i]->Sr = Sr0[i];
+    fs[i]->Sc = Sc0[i];
+  }
+}
+
 // unreduced node samples S^r_tau, S^c_tau on all current columns (Alg. 1:
 // leaf S - D R, non-leaf stacked reduced children samples minus B R)
 void node_samples(Handle& h, const std::vector<NRef>& nodes) {
@@ -487,8 +554,8 @@ void node_samples(Handle& h, const std::vector<NRef>& nodes) {
       const int m = nd.m();
       cp.push_back(Cp(F.Sr + nd.lo, F.n, nullptr, nd.Sr, m, m, d));
       cp.push_back(Cp(F.Sc + nd.lo, F.n, nullptr, nd.Sc, m, m, d));
-      g.push_back(G(nd.D, m, 0, F.R + nd.lo, F.n, 0, nd.Sr, m, m, d, m, -1.0, 1.0));
-      g.push_back(G(nd.D, m, 1, F.R + nd.lo, F.n, 0, nd.Sc, m, m, d, m, -1.0, 1.0));
+      g.push_back(G(nd.D, m, 0, F.rr() + nd.lo, F.n, 0, nd.Sr, m, m, d, m, -1.0, 1.0));
+      g.push_back(G(nd.D, m, 1, F.rc() + nd.lo, F.n, 0, nd.Sc, m, m, d, m, -1.0, 1.0));
     } else {
       HNode& a = F.nd[nd.kid[0]];
       HNode& b = F.nd[nd.kid[1]];
@@ -524,7 +591,8 @@ void reduce_nodes(Handle& h, const std::vector<NRef>& nodes) {
     const double *Rin_r, *Rin_c;
     int ld_r, ld_c;
     if (nd.leaf()) {
-      Rin_r = Rin_c = F.R + nd.lo;
+      Rin_r = F.rr() + nd.lo;
+      Rin_c = F.rc() + nd.lo;
       ld_r = ld_c = F.n;
     } else {
       HNode& a = F.nd[nd.kid[0]];
@@ -600,7 +668,7 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
       HFront* F = fs[fi];
       F->d = 0;
       F->dcap = 0;
-      F->R = F->Sr = F->Sc = nullptr;
+      F->R = F->Sr = F->Sc = F->Rr = F->Rc = nullptr;
       grow_samples(h, *F, dinit[fi]);
       F->d = dinit[fi];
       F->rounds = 0;
@@ -635,6 +703,7 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
       for (size_t fi = 0; fi < fs.size(); ++fi)
         if (dinit[fi] == wd) { grp.push_back(fs[fi]); gc0.push_back(0); }
       sample(h, grp, gc0, wd);
+      power_iterate(h, grp, gc0, wd);
     }
   }
   int maxh = 0;
@@ -1103,6 +1172,7 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
       F->refresh = true;
     }
     sample(h, grow, c0, o.dd);
+    power_iterate(h, grow, c0, o.dd);
   }
   if (o.keep_stages) {
     // the random matrix and the samples at the final d, for inspection

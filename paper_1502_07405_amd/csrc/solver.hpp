@@ -84,6 +84,11 @@ struct HFront {
   // sampling
   int d = 0, dcap = 0, rounds = 0;
   double *R = nullptr, *Sr = nullptr, *Sc = nullptr;
+  // power iteration: R^r (row side) and R^c (column side) of Alg. 1, n x
+  // dcap like R; nullptr for plain sampling, where both are R
+  double *Rr = nullptr, *Rc = nullptr;
+  const double* rr() const { return Rr ? Rr : R; }
+  const double* rc() const { return Rc ? Rc : R; }
   void* Rlp = nullptr;       // low-precision copy of R (mixed precision)
   int* orig = nullptr;       // original row ids of the front's indices
   bool finished = false, refresh = false;

@@ -53,7 +53,8 @@ class Opts(ctypes.Structure):
                 ("restart", ctypes.c_int32), ("tol", ctypes.c_double), ("max_it", ctypes.c_int32),
                 ("id_kernel", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("gemm_tile", ctypes.c_int32), ("abs_tol", ctypes.c_double),
-                ("keep_stages", ctypes.c_int32), ("hss_update", ctypes.c_int32)]
+                ("keep_stages", ctypes.c_int32), ("hss_update", ctypes.c_int32),
+                ("power_q", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
