@@ -87,3 +87,26 @@ def test_aggressive_tolerance_gmres_matches_the_oracle(case, eps):
     assert abs(info.iterations - its_o) <= 1
     assert np.linalg.norm(xh - xo) <= 1e-7 * np.linalg.norm(xo)
     fac.close()
+
+
+@pytest.mark.parametrize("case", sorted(NEXT_CASES))
+def test_aggressive_tolerance_with_power_iteration_matches_the_oracle(case):
+    """The same regime with one step of power iteration in the sampling
+    (power_q = 1, Sec. 2.2): ranks per HSS front equal the oracle's and
+    GMRES(30) takes the oracle's number of iterations within one."""
+    mk, kw = NEXT_CASES[case]
+    A, o = mk()
+    ofac = mf.factor(A, o, mf.Options(rel_tol=0.5, power_q=1, **kw))
+    S = A.to_scipy()
+    b = np.random.default_rng(50).standard_normal(A.n)
+    xo, its_o, _ = krylov.gmres(lambda v: S @ v, lambda r: mf.apply_inverse(ofac, r), b, 1e-12, restart=30,
+                                max_it=400)
+    fac = H.Factorization(A, o, rel_tol=0.5, power_q=1, outer="gmres", restart=30, tol=1e-12, max_it=400, **kw)
+    assert fac.hss_ranks() == [tuple(int(v) for v in r) for r in mf.hss_ranks(ofac)]
+    x, info = fac.solve(torch.tensor(b, device=DEV))
+    xh = x.cpu().numpy()
+    print(f"{case} eps 0.5 q 1: GMRES iterations gpu {info.iterations} oracle {its_o}")
+    assert np.linalg.norm(b - S @ xh) <= 1e-12 * np.linalg.norm(b)
+    assert abs(info.iterations - its_o) <= 1
+    assert np.linalg.norm(xh - xo) <= 1e-7 * np.linalg.norm(xo)
+    fac.close()
