@@ -156,16 +156,63 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(const LUFront* __restrict_
   }
 }
 
+// a double moved between lanes of a 16-lane row by a data-parallel
+// primitive (CTRL: quad permutation, half-row mirror or row rotation)
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  const long long u = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffll), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xf, 0xf, false);
+}
+
+// (v, i) <- the larger of (v, i) and (o, oi), ties to the lower index
+__device__ __forceinline__ void amax_pair(double& v, int& i, double o, int oi) {
+  const bool tk = (o > v) | ((o == v) & (oi < i));
+  v = tk ? o : v;
+  i = tk ? oi : i;
+}
+
+// (value, index) maximum over the wavefront, larger value first, ties to the
+// lower index, the same in every lane: inside each 16-lane row by quad
+// permutations, half-row mirror and rotation by 8, then over the four rows'
+// results read as scalars.  The maximum with that tie rule does not depend
+// on the order it is taken in.
+__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+  amax_pair(v, i, dpp_d<0xB1>(v), dpp_i<0xB1>(i));     // quad_perm [1,0,3,2]
+  amax_pair(v, i, dpp_d<0x4E>(v), dpp_i<0x4E>(i));     // quad_perm [2,3,0,1]
+  amax_pair(v, i, dpp_d<0x141>(v), dpp_i<0x141>(i));   // row_half_mirror
+  amax_pair(v, i, dpp_d<0x128>(v), dpp_i<0x128>(i));   // row_ror:8
+  double rv = __longlong_as_double(((long long)__builtin_amdgcn_readlane((int)(__double_as_longlong(v) >> 32), 0) << 32) |
+                                   (unsigned)__builtin_amdgcn_readlane((int)(__double_as_longlong(v) & 0xffffffffll), 0));
+  int ri = __builtin_amdgcn_readlane(i, 0);
+#pragma unroll
+  for (int r = 1; r < 4; ++r) {
+    const long long u = __double_as_longlong(v);
+    const double o = __longlong_as_double(((long long)__builtin_amdgcn_readlane((int)(u >> 32), 16 * r) << 32) |
+                                          (unsigned)__builtin_amdgcn_readlane((int)(u & 0xffffffffll), 16 * r));
+    amax_pair(rv, ri, o, __builtin_amdgcn_readlane(i, 16 * r));
+  }
+  v = rv;
+  i = ri;
+}
+
 // Panel of the F11 rows only, resident in LDS: rows [jb, s) x columns
 // [jb, jb+w) of each front (m1 = s - jb rows, column major with ld m1).
 // Same pivot rule and the same operations per element as lu_panel_kernel;
-// the F21 rows of the panel are done afterwards by lu_panel21_kernel.
+// the F21 rows of the panel are done afterwards by lu_panel21_kernel.  Two
+// workgroup barriers per column: the next column's pivot candidates are
+// found while the rows are updated, and every thread combines the
+// wavefronts' records itself.
 __global__ __launch_bounds__(256) void lu_panel11_kernel(const LUFront* __restrict__ fr, int jb, int nb, int* info) {
   extern __shared__ double P[];
   __shared__ double wv[4];
   __shared__ int wi[4];
-  __shared__ int pshared;
-  __shared__ double pval;
+  __shared__ double prow[32];
   const LUFront f = fr[blockIdx.x];
   if (jb >= f.s) return;
   const int w = min(nb, f.s - jb), m1 = f.s - jb;
@@ -187,48 +234,53 @@ __global__ __launch_bounds__(256) void lu_panel11_kernel(const LUFront* __restri
     }
   }
   __syncthreads();
+  // this thread's candidate for the first column's pivot: largest |value|
+  // in column 0 over its rows, ties to the lowest row
+  double best = -1.0;
+  int bi = 0;
+  for (int r = tid; r < m1; r += 256) {
+    const double a = fabs(P[r]);
+    if (a > best) { best = a; bi = r; }
+  }
   for (int c = 0; c < w; ++c) {
-    // pivot: largest |value| in column c over rows c.., ties to the lowest row
-    double best = -1.0;
-    int bi = c;
-    for (int r = c + tid; r < m1; r += 256) {
-      const double a = fabs(P[r + c * m1]);
-      if (a > best) { best = a; bi = r; }
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      const double o = __shfl_xor(best, off);
-      const int oi = __shfl_xor(bi, off);
-      if (o > best || (o == best && oi < bi)) { best = o; bi = oi; }
-    }
+    wave_argmax(best, bi);
     if (lane == 0) { wv[wave] = best; wi[wave] = bi; }
     __syncthreads();
+    best = wv[0];
+    bi = wi[0];
+#pragma unroll
+    for (int q = 1; q < 4; ++q) amax_pair(best, bi, wv[q], wi[q]);
+    const int p = bi;
     if (tid == 0) {
-      double b = wv[0];
-      int i = wi[0];
-      for (int q = 1; q < 4; ++q)
-        if (wv[q] > b || (wv[q] == b && wi[q] < i)) { b = wv[q]; i = wi[q]; }
-      pshared = i;
-      pval = b;
-      f.ipiv[jb + c] = jb + i;
-      if (b == 0.0) atomicCAS(info, 0, f.id + 1);
+      f.ipiv[jb + c] = jb + p;
+      if (best == 0.0) atomicCAS(info, 0, f.id + 1);
+    }
+    // the interchange inside the panel; the pivot row also goes to prow
+    if (tid < w) {
+      const double a = P[c + tid * m1];
+      const double b = P[p + tid * m1];
+      if (p != c) {
+        P[c + tid * m1] = b;
+        P[p + tid * m1] = a;
+      }
+      prow[tid] = (p != c) ? b : a;
     }
     __syncthreads();
-    const int p = pshared;
-    if (p != c && tid < w) {
-      const double t = P[c + tid * m1];
-      P[c + tid * m1] = P[p + tid * m1];
-      P[p + tid * m1] = t;
-    }
-    __syncthreads();
-    const double piv = P[c + c * m1];
+    const double piv = prow[c];
     const double rp = (piv != 0.0) ? 1.0 / piv : 0.0;
+    best = -1.0;
+    bi = c + 1;
     for (int r = c + 1 + tid; r < m1; r += 256) {
       const double l = P[r + c * m1] * rp;
       P[r + c * m1] = l;
-      for (int cc = c + 1; cc < w; ++cc) P[r + cc * m1] -= l * P[c + cc * m1];
+      for (int cc = c + 1; cc < w; ++cc) {
+        const double y = P[r + cc * m1] - l * prow[cc];
+        P[r + cc * m1] = y;
+        if (cc == c + 1 && fabs(y) > best) { best = fabs(y); bi = r; }
+      }
     }
-    __syncthreads();
   }
+  __syncthreads();
   for (int e = tid; e < m1 * w; e += 256) {
     const int r = e % m1, c = e / m1;
     F[(jb + r) + (int64_t)(jb + c) * ld] = P[e];
