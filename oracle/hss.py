@@ -25,6 +25,25 @@ class RankError(RuntimeError):
 # interpolative decomposition (Sec. 2.2, Eq. for ID; stopping rule Sec. 5.3)
 # ---------------------------------------------------------------------------
 
+def _householder_step(W, perm, j, p, nrm):
+    """Step j of a column-pivoted Householder QR of W in place: interchange
+    positions j and p (columns of W and entries of perm), then reduce column
+    j below row j with the reflector of its remaining norm nrm, applied to
+    columns j.. ."""
+    if p != j:
+        W[:, [j, p]] = W[:, [p, j]]
+        perm[[j, p]] = perm[[p, j]]
+    x = W[j:, j]
+    alpha = -np.copysign(nrm, x[0]) if x[0] != 0 else -nrm
+    v = x.copy()
+    v[0] -= alpha
+    vn = np.dot(v, v)
+    if vn > 0:
+        W[j:, j:] -= np.outer(v, (2.0 / vn) * (v @ W[j:, j:]))
+    W[j, j] = alpha
+    W[j + 1:, j] = 0.0
+
+
 def cpqr_eps(Y, eps, atol=0.0):
     """Householder QR with column pivoting of Y (d x m), stopped at the
     numerical rank.  At every step the pivot is the column whose remaining
@@ -53,30 +72,81 @@ def cpqr_eps(Y, eps, atol=0.0):
                 break
         elif nrm <= max(eps * first, atol):
             break
-        if p != j:
-            W[:, [j, p]] = W[:, [p, j]]
-            perm[[j, p]] = perm[[p, j]]
-        x = W[j:, j]
-        alpha = -np.copysign(nrm, x[0]) if x[0] != 0 else -nrm
-        v = x.copy()
-        v[0] -= alpha
-        vn = np.dot(v, v)
-        if vn > 0:
-            W[j:, j:] -= np.outer(v, (2.0 / vn) * (v @ W[j:, j:]))
-        W[j, j] = alpha
-        W[j + 1:, j] = 0.0
+        _householder_step(W, perm, j, p, nrm)
         k = j + 1
     return perm, W[:kmax], k
 
 
-def interp_decomp(Y, eps, atol=0.0):
+def qr_forced(Y, order):
+    """Householder QR of Y (d x m) whose pivots are the columns ``order``
+    (original indices), taken in that sequence, with the interchange
+    bookkeeping of cpqr_eps.  Returns (perm, W): Y[:, perm] = Q W with W
+    (d x m) upper triangular in its first k = len(order) columns; rows < k
+    of the other columns hold R12, rows >= k hold R22."""
+    W = np.array(Y, dtype=np.float64, copy=True)
+    m = W.shape[1]
+    perm = np.arange(m)
+    for j, c in enumerate(order):
+        p = int(np.flatnonzero(perm == c)[0])
+        nrm = np.sqrt(np.sum(W[j:, p] ** 2))
+        _householder_step(W, perm, j, p, nrm)
+    return perm, W
+
+
+SRRQR_MAX_SWAPS = 64
+
+
+def strong_rrqr(Y, perm, k, f, max_swaps=SRRQR_MAX_SWAPS):
+    """Strong rank-revealing QR with the rank k held fixed (Gu and
+    Eisenstat, SIAM J. Sci. Comput. 17 (1996), the algorithm for a given k),
+    started from the selection perm[:k] of a column-pivoted QR; Sec. 2.2 and
+    Sec. 7 name it as a replacement of that QR inside the ID.
+
+    With Y[:, perm] = Q [R11 R12; 0 R22], interchanging selected column i
+    with remaining column j multiplies |det R11| by sqrt(rho_ij), where
+    rho_ij = (R11^{-1} R12)_ij^2 + gamma_j^2 / omega_i^2, gamma_j the
+    2-norm of column j of R22 and 1/omega_i the 2-norm of row i of
+    R11^{-1}.  While the largest rho (ties: lowest i + k j) exceeds f^2,
+    column i leaves the selection, column j joins it as the last selected
+    column, and Y is factored again in that pivot order.  At the end every
+    |(R11^{-1} R12)_ij| <= f, unless max_swaps interchanges were made first.
+
+    Returns (perm, W, swaps) with W as from qr_forced."""
+    m = Y.shape[1]
+    order = [int(c) for c in perm[:k]]
+    swaps = 0
+    while True:
+        perm, W = qr_forced(Y, order)
+        if k == 0 or k == m:
+            return perm, W, swaps
+        R11 = W[:k, :k]
+        X = sla.solve_triangular(R11, W[:k, k:], lower=False)
+        Z = sla.solve_triangular(R11, np.eye(k), lower=False)
+        gam2 = np.sum(W[k:, k:] ** 2, axis=0)
+        rho = X ** 2 + np.outer(np.sum(Z ** 2, axis=1), gam2)
+        e = int(np.argmax(rho.ravel(order="F")))
+        i, j = e % k, e // k
+        if not rho[i, j] > f * f or swaps >= max_swaps:
+            return perm, W, swaps
+        order = [int(perm[t]) for t in range(k) if t != i] + [int(perm[k + j])]
+        swaps += 1
+
+
+def interp_decomp(Y, eps, atol=0.0, srrqr_f=0.0, stats=None):
     """[X, J] = ID(Y, eps): Y ~= Y[:, J] X with X = [I, R1^{-1} R2] Pi^{-1}
     (Sec. 2.2).  Returns (perm, E, k) where J = perm[:k] and
-    E = (R1^{-1} R2)^T, so that Y^T ~= Pi [I; E] Y[:, J]^T."""
+    E = (R1^{-1} R2)^T, so that Y^T ~= Pi [I; E] Y[:, J]^T.  The rank k comes
+    from cpqr_eps; with srrqr_f > 0 the selection is then improved by
+    strong_rrqr with f = srrqr_f (k unchanged), and stats["swaps"] (when a
+    dict is given) counts its interchanges."""
     perm, R, k = cpqr_eps(Y, eps, atol)
     m = Y.shape[1]
     if k == 0:
         return perm, np.zeros((m, 0)), 0
+    if srrqr_f > 0 and k < m:
+        perm, R, sw = strong_rrqr(Y, perm, k, srrqr_f)
+        if stats is not None:
+            stats["swaps"] = stats.get("swaps", 0) + sw
     X = sla.solve_triangular(R[:k, :k], R[:k, k:], lower=False)
     return perm, X.T.copy(), k
 
@@ -154,7 +224,7 @@ def power_samples(op, R, q):
     return Sr, Sc, Rr, Rc
 
 
-def compress(op, nodes, root, rand, eps, d0, dd, p, d_max, atol=0.0, power_q=0):
+def compress(op, nodes, root, rand, eps, d0, dd, p, d_max, atol=0.0, power_q=0, srrqr_f=0.0):
     """Alg. 1 applied to a matrix known through ``op``:
     op.sample(R) -> (F R, F^T R) for a block of random columns and
     op.extract(I, J) -> F[I][:, J].  ``rand(c0, nc)`` returns columns
@@ -182,6 +252,7 @@ def compress(op, nodes, root, rand, eps, d0, dd, p, d_max, atol=0.0, power_q=0):
     # (oracle.work): columns sampled per pass, and per ID attempt the node,
     # side, samples d, rows m and rank k
     log = dict(sampled=[d], ids=[], node_cols=[])
+    swaps = {}   # strong-RRQR interchanges over every ID attempt
 
     def node_samples(t, cols):
         """Unreduced S^r_tau, S^c_tau on columns ``cols`` (Alg. 1, leaf and
@@ -232,8 +303,8 @@ def compress(op, nodes, root, rand, eps, d0, dd, p, d_max, atol=0.0, power_q=0):
                 done[t] = True
                 continue
             sr, sc = node_samples(t, allc)
-            pu, Eu, kr = interp_decomp(sr.T, eps, atol)
-            pv, Ev, kc = interp_decomp(sc.T, eps, atol)
+            pu, Eu, kr = interp_decomp(sr.T, eps, atol, srrqr_f, swaps)
+            pv, Ev, kc = interp_decomp(sc.T, eps, atol, srrqr_f, swaps)
             log["ids"].append((t, d, sr.shape[0], kr, sc.shape[0], kc))
             ok_r = kr <= d - p or kr == sr.shape[0]
             ok_c = kc <= d - p or kc == sc.shape[0]
@@ -273,7 +344,7 @@ def compress(op, nodes, root, rand, eps, d0, dd, p, d_max, atol=0.0, power_q=0):
                 Sc_red[t] = np.hstack([Sc_red[t], a2])
                 Rr_red[t] = np.hstack([Rr_red[t], a3])
                 Rc_red[t] = np.hstack([Rc_red[t], a4])
-    return HSS(nodes, gen, root, dict(d=d, rounds=rounds, log=log))
+    return HSS(nodes, gen, root, dict(d=d, rounds=rounds, log=log, swaps=swaps.get("swaps", 0)))
 
 
 # ---------------------------------------------------------------------------
@@ -685,12 +756,12 @@ class Front11Ops:
         return down_expand(self.H, self.k, self.B_qk.T @ self._vt(self.q, x, "U"), "V")
 
 
-def build_hss_front(op, s, u, leaf_size, rand, eps, d0, dd, p, d_max, atol=0.0, power_q=0):
+def build_hss_front(op, s, u, leaf_size, rand, eps, d0, dd, p, d_max, atol=0.0, power_q=0, srrqr_f=0.0):
     """Compress a front of size s+u (Alg. 1), then ULV-factor its F11 part and
     form Theta^*, Phi.  Returns (H, ULV, k, q, Theta, Phi)."""
     nodes, k, q = hss_tree(s, u, leaf_size)
     root = len(nodes) - 1
-    H = compress(op, nodes, root, rand, eps, d0, dd, p, d_max, atol, power_q)
+    H = compress(op, nodes, root, rand, eps, d0, dd, p, d_max, atol, power_q, srrqr_f)
     F = ulv_factor(H, k)
     Theta = Phi = None
     if q >= 0:

@@ -32,6 +32,7 @@ class Options:
     seed: int = 0
     abs_tol: float = 0.0
     power_q: int = 0   # steps of power iteration in the sampling (0: plain sampling)
+    srrqr_f: float = 0.0   # strong-RRQR bound f inside the IDs (0: column-pivoted QR alone)
 
 
 class DenseUpdate:
@@ -167,7 +168,7 @@ def factor(A, ordering, opts, stop_after=None, record=None):
             d_init = max([opts.d0] + [hss_d[c] for c in f.children if c in hss_d])
             H, F, k, q, Theta, Phi = hs.build_hss_front(
                 op, f.s, f.u, opts.leaf_size, rand, opts.rel_tol, d_init, opts.dd, opts.p, opts.d_max,
-                opts.abs_tol, opts.power_q)
+                opts.abs_tol, opts.power_q, opts.srrqr_f)
             hss_d[f.id] = H.stats["d"]
             data = dict(H=H, ulv=F, k=k, q=q)
             if q >= 0:

@@ -354,6 +354,24 @@ def test_power_iteration_keeps_exact_recovery(rng, q):
     assert np.linalg.norm(H.hss_dense(hs, 6) - A) <= 1e-9 * np.linalg.norm(A)
 
 
+def test_compression_with_strong_rrqr_keeps_exact_recovery(rng):
+    """Alg. 1 with the strong RRQR (Gu and Eisenstat, rank held fixed)
+    inside every ID: on off-diagonal blocks of exact rank r every node keeps
+    rank r, the HSS form reproduces the matrix, every interpolation
+    coefficient is at most f, and with f close to 1 some ID interchanged
+    columns."""
+    r, f = 3, 1.01
+    src = _four_leaf_hss(rng, m=(9, 10, 8, 11), r=r)
+    A = H.hss_dense(src, 6)
+    hs = H.compress(DenseOp(A), src.nodes, 6, _rand_fn(A.shape[0]), 1e-10, 16, 8, 5, 1000, srrqr_f=f)
+    for t in range(6):
+        assert hs.gen[t].r == r and hs.gen[t].c == r
+        assert np.max(np.abs(hs.gen[t].UE)) <= f * (1 + 1e-9)
+        assert np.max(np.abs(hs.gen[t].VE)) <= f * (1 + 1e-9)
+    assert hs.stats["swaps"] > 0
+    assert np.linalg.norm(H.hss_dense(hs, 6) - A) <= 1e-9 * np.linalg.norm(A)
+
+
 @pytest.mark.parametrize("q,rank12,rank21", [(0, 4, 3), (1, 2, 1), (2, 1, 1)])
 def test_power_iteration_rank_follows_the_amplified_spectrum(q, rank12, rank21):
     """The ID of the power-iterated samples sees the singular values of an
