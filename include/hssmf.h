@@ -142,6 +142,21 @@ typedef struct {
                           sampling; 1..4 need gemm_prec = FP64 (EINVAL
                           otherwise); each step costs four more sampling
                           passes */
+  double srrqr_f;      /* strong rank-revealing QR inside every ID (Sec. 2.2
+                          and Sec. 7 name it as the replacement of the
+                          column-pivoted QR; Gu and Eisenstat's algorithm
+                          with the rank k held fixed): after the pivoted QR
+                          has fixed k, while some interchange of a selected
+                          column i and a remaining column j would multiply
+                          |det R11| by more than f, the largest such
+                          interchange is made (column i leaves, column j
+                          joins as the last selected one) and the QR is
+                          redone in that pivot order, at most 64 times per
+                          ID.  Afterwards every interpolation coefficient
+                          |(R11^{-1} R12)_ij| is at most f.  0 (default) =
+                          the pivoted QR alone; otherwise f > 1, which needs
+                          the resident ID kernel (EINVAL otherwise; a pass
+                          it cannot take fails with EINVAL) */
 } hssmf_opts;
 
 /* hss_update: LOWRANK = kept as the HSS generators of F22 with Theta^* and
@@ -193,7 +208,8 @@ typedef struct {
                                transposes) that run on several workgroups per
                                system; the others, and every launch captured
                                in a graph, take one workgroup per system */
-  int32_t pad0;
+  int32_t srrqr_swaps;      /* strong-RRQR interchanges made by the last
+                               numeric factorization (0 when srrqr_f is 0) */
 } hssmf_stats;
 
 /* Fill *o with defaults: rel_tol 1e-6, leaf_size 64, min_sep_hss INT32_MAX
@@ -201,7 +217,7 @@ typedef struct {
  * iterative refinement, restart 30, tol 1e-10, max_it 50, resident ID
  * kernel (the stepwise one where it does not apply), sweeps launched one by
  * one (no graph), autotuned GEMM tiles, abs_tol 0, update matrices expanded
- * densely, plain sampling (power_q 0). */
+ * densely, plain sampling (power_q 0), no strong RRQR (srrqr_f 0). */
 int hssmf_default_opts(hssmf_opts* o);
 
 /* Symbolic analysis, upload and numeric factorization (Sec. 3.2, Sec. 4).

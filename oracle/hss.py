@@ -252,7 +252,7 @@ def compress(op, nodes, root, rand, eps, d0, dd, p, d_max, atol=0.0, power_q=0, 
     # (oracle.work): columns sampled per pass, and per ID attempt the node,
     # side, samples d, rows m and rank k
     log = dict(sampled=[d], ids=[], node_cols=[])
-    swaps = {}   # strong-RRQR interchanges over every ID attempt
+    swaps = {}   # strong-RRQR interchanges of the IDs kept (nodes that succeeded)
 
     def node_samples(t, cols):
         """Unreduced S^r_tau, S^c_tau on columns ``cols`` (Alg. 1, leaf and
@@ -303,13 +303,15 @@ def compress(op, nodes, root, rand, eps, d0, dd, p, d_max, atol=0.0, power_q=0, 
                 done[t] = True
                 continue
             sr, sc = node_samples(t, allc)
-            pu, Eu, kr = interp_decomp(sr.T, eps, atol, srrqr_f, swaps)
-            pv, Ev, kc = interp_decomp(sc.T, eps, atol, srrqr_f, swaps)
+            sw_node = {}
+            pu, Eu, kr = interp_decomp(sr.T, eps, atol, srrqr_f, sw_node)
+            pv, Ev, kc = interp_decomp(sc.T, eps, atol, srrqr_f, sw_node)
             log["ids"].append((t, d, sr.shape[0], kr, sc.shape[0], kc))
             ok_r = kr <= d - p or kr == sr.shape[0]
             ok_c = kc <= d - p or kc == sc.shape[0]
             if not (ok_r and ok_c):
                 continue
+            swaps["swaps"] = swaps.get("swaps", 0) + sw_node.get("swaps", 0)
             g.Uperm, g.UE, g.Vperm, g.VE = pu, Eu, pv, Ev
             if nd.leaf:
                 base_r = base_c = np.arange(nd.lo, nd.hi)

@@ -241,12 +241,14 @@ void numeric(Handle& h) {
   h.cur = &h.arena;
   h.factor_status = HSSMF_OK;
   // statistics
-  int maxr = 0, maxd = 0, rounds = 0;
+  int maxr = 0, maxd = 0, rounds = 0, swaps = 0;
   for (auto& F : h.hf) {
     for (auto& nd : F.nd) maxr = std::max(maxr, std::max(nd.r, nd.c));
     maxd = std::max(maxd, F.d);
     rounds += F.rounds;
+    swaps += F.swaps;
   }
+  h.stats.srrqr_swaps = swaps;
   h.stats.max_rank = maxr;
   h.stats.max_d = maxd;
   h.stats.growth_rounds = rounds;
@@ -552,6 +554,7 @@ int hssmf_default_opts(hssmf_opts* o) {
   o->id_kernel = HSSMF_ID_RESIDENT;
   o->hss_update = HSSMF_UPDATE_DENSE;
   o->power_q = 0;
+  o->srrqr_f = 0.0;
   o->use_graph = 0;   // capture after every factorization costs more than replay saves
   return HSSMF_OK;
 }
@@ -567,7 +570,9 @@ bool opts_ok(const hssmf_opts* o) {
            !(o->gemm_tile == 0 || o->gemm_tile == 64 || o->gemm_tile == 65 || o->gemm_tile == 128) ||
            !(o->abs_tol >= 0.0) || o->keep_stages < 0 || o->keep_stages > 1 || o->hss_update < 0 ||
            o->hss_update > 1 || o->power_q < 0 || o->power_q > 4 ||
-           (o->power_q > 0 && o->gemm_prec != HSSMF_PREC_FP64));
+           (o->power_q > 0 && o->gemm_prec != HSSMF_PREC_FP64) ||
+           !(o->srrqr_f == 0.0 || (o->srrqr_f > 1.0 && o->srrqr_f <= 1e300)) ||
+           (o->srrqr_f > 0.0 && o->id_kernel != HSSMF_ID_RESIDENT));
 }
 
 // a CSR matrix in host memory: the caller's arrays when they are host

@@ -222,6 +222,9 @@ struct NRef {
   HNode& n() const { return F->nd[t]; }
 };
 
+// interchanges per ID at most in the strong rank-revealing QR
+constexpr int kSrrqrMaxSwaps = 64;
+
 double* dalloc(Handle& h, int64_t n) { return h.cur->get<double>((size_t)std::max<int64_t>(n, 1)); }
 int* ialloc(Handle& h, int64_t n) { return h.cur->get<int>((size_t)std::max<int64_t>(n, 1)); }
 // temporaries: every launch that uses them is ordered on the one stream
@@ -672,6 +675,7 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
       grow_samples(h, *F, dinit[fi]);
       F->d = dinit[fi];
       F->rounds = 0;
+      F->swaps = 0;
       F->finished = false;
       F->refresh = false;
       // every numeric pass starts from the structure only: buffers of an
@@ -807,8 +811,10 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
         HIP_CHECK(hipStreamSynchronize(h.st));
         census_t0 = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
       }
-      // the resident kernel where it applies (every problem at most 640
-      // samples; the stepwise kernel otherwise).  Two launch plans:
+      // The resident kernel's launch plan for the problems qv, ending with
+      // the R1 / R2 gathers; false, with nothing launched and qv unchanged,
+      // where it does not apply (a problem above 640 samples, or wider than
+      // one cooperative launch holds).  Two launch plans:
       //  - all problems on the template of the pass's largest (d, m), in one
       //    cooperative launch, when some problem spans several workgroups
       //    and all workgroups of the pass fit at once;
@@ -818,27 +824,27 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
       //    the wider ones on the template of their largest (d, m), in
       //    cooperative launches of at most its capacity, one after another.
       // The results do not depend on the template or the plan.
-      const int np_all = (int)q.size();
-      bool resident = o.id_kernel == HSSMF_ID_RESIDENT && np_all > 0;
-      const int t_all = resident ? id_res_template(maxd, maxm) : -1;
-      resident = resident && t_all >= 0;
-      std::vector<int> tpl(np_all, -1), pall(np_all, 1);
-      std::vector<int> wide;   // problems wider than one workgroup of their own template
-      int cap_all = 0, tot_all = 0, t_wide = -1, cap_wide = 0;
-      bool any_all = false;
-      if (resident) {
+      auto run_resident = [&](std::vector<IDProb>& qv, int maxd_v, int maxm_v, int*& derr_v) -> bool {
+        const int np_all = (int)qv.size();
+        if (np_all == 0) return false;
+        const int t_all = id_res_template(maxd_v, maxm_v);
+        if (t_all < 0) return false;
+        std::vector<int> tpl(np_all, -1), pall(np_all, 1);
+        std::vector<int> wide;   // problems wider than one workgroup of their own template
+        int cap_all = 0, tot_all = 0, t_wide = -1, cap_wide = 0;
+        bool any_all = false;
         const int c_all = id_res_template_candidates(t_all);
         int wd = 0, wm = 0;
         for (int pi = 0; pi < np_all; ++pi) {
-          pall[pi] = (q[pi].m + c_all - 1) / c_all;
+          pall[pi] = (qv[pi].m + c_all - 1) / c_all;
           tot_all += std::max(1, pall[pi]);
           any_all |= pall[pi] > 1;
-          tpl[pi] = id_res_template(q[pi].d, q[pi].m);
+          tpl[pi] = id_res_template(qv[pi].d, qv[pi].m);
           REQUIRE(tpl[pi] >= 0, HSSMF_EDEVICE, "interpolative decomposition: no template for a problem");
-          if (q[pi].m > id_res_template_candidates(tpl[pi])) {
+          if (qv[pi].m > id_res_template_candidates(tpl[pi])) {
             wide.push_back(pi);
-            wd = std::max(wd, q[pi].d);
-            wm = std::max(wm, q[pi].m);
+            wd = std::max(wd, qv[pi].d);
+            wm = std::max(wm, qv[pi].m);
           }
         }
         if (any_all) cap_all = id_res_template_capacity(t_all);
@@ -847,49 +853,46 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
           cap_wide = id_res_template_capacity(t_wide);
           const int c_wide = id_res_template_candidates(t_wide);
           for (int pi : wide)
-            if ((q[pi].m + c_wide - 1) / c_wide > cap_wide) resident = false;
+            if ((qv[pi].m + c_wide - 1) / c_wide > cap_wide) return false;
         }
-      }
-      int res_c = resident ? 1 : 0;   // the pass ran on the resident kernel
-      if (resident) {
         const int np = np_all;
         const bool one = any_all && tot_all <= cap_all;
         // workgroups per problem on the template it runs on
         std::vector<bool> is_wide(np, false);
         for (int pi : wide) is_wide[pi] = true;
         if (one) {
-          for (int pi = 0; pi < np; ++pi) q[pi].P = std::max(1, pall[pi]);
+          for (int pi = 0; pi < np; ++pi) qv[pi].P = std::max(1, pall[pi]);
         } else {
           const int c_wide = t_wide >= 0 ? id_res_template_candidates(t_wide) : 1;
           for (int pi = 0; pi < np; ++pi)
-            q[pi].P = is_wide[pi] ? std::max(1, (q[pi].m + c_wide - 1) / c_wide) : 1;
+            qv[pi].P = is_wide[pi] ? std::max(1, (qv[pi].m + c_wide - 1) / c_wide) : 1;
         }
         int wgm = 0;
         std::vector<int> coopp;   // problems with exchange records
         for (int pi = 0; pi < np; ++pi)
-          if (q[pi].P > 1) {
+          if (qv[pi].P > 1) {
             coopp.push_back(pi);
-            wgm += q[pi].P;
+            wgm += qv[pi].P;
           }
         if (!coopp.empty()) {
-          derr = sialloc(h, 1);
+          derr_v = sialloc(h, 1);
           double* slots = salloc(h, 6 * (int64_t)wgm);   // per problem 3 x P x (norm, index)
           int o6 = 0;
           for (int pi : coopp) {
-            q[pi].cand = salloc(h, 3 * (int64_t)q[pi].P * q[pi].d);
-            q[pi].slots = slots + o6;
-            o6 += 6 * q[pi].P;
+            qv[pi].cand = salloc(h, 3 * (int64_t)qv[pi].P * qv[pi].d);
+            qv[pi].slots = slots + o6;
+            o6 += 6 * qv[pi].P;
           }
           // every exchange record starts empty
           launch_fill(slots, 6 * (int64_t)wgm, std::numeric_limits<double>::quiet_NaN(), h.st);
-          HIP_CHECK(hipMemsetAsync(derr, 0, sizeof(int), h.st));
+          HIP_CHECK(hipMemsetAsync(derr_v, 0, sizeof(int), h.st));
         }
-        IDProb* dq = upload(h, q);
+        IDProb* dq = upload(h, qv);
         std::vector<int2> wgs;
         if (one) {
           for (int pi = 0; pi < np; ++pi)
-            for (int w = 0; w < q[pi].P; ++w) wgs.push_back(make_int2(pi, w));
-          launch_id_res_template(t_all, dq, upload(h, wgs), (int)wgs.size(), true, derr, h.st);
+            for (int w = 0; w < qv[pi].P; ++w) wgs.push_back(make_int2(pi, w));
+          launch_id_res_template(t_all, dq, upload(h, wgs), (int)wgs.size(), true, derr_v, h.st);
         } else {
           // one workgroup each, grouped by template
           std::map<int, std::vector<int2>> single;
@@ -910,7 +913,7 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
           }
           for (int li = 0; li < nl; ++li) {
             hipStream_t ls = li == 0 || naux == 0 ? h.st : h.aux[(li - 1) % naux];
-            launch_id_res_template(launches[li].first, dq, launches[li].second, counts[li], false, derr, ls);
+            launch_id_res_template(launches[li].first, dq, launches[li].second, counts[li], false, derr_v, ls);
           }
           for (int a = 0; a < naux; ++a) {
             HIP_CHECK(hipEventRecord(h.ev_join[a], h.aux[a]));
@@ -920,22 +923,27 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
           // problem, so fill them in order of the most pivot steps a
           // problem can take
           std::stable_sort(wide.begin(), wide.end(), [&](int a, int b) {
-            return std::min(q[a].m, q[a].d) > std::min(q[b].m, q[b].d);
+            return std::min(qv[a].m, qv[a].d) > std::min(qv[b].m, qv[b].d);
           });
           wgs.clear();
           auto flush = [&]() {
             if (wgs.empty()) return;
-            launch_id_res_template(t_wide, dq, upload(h, wgs), (int)wgs.size(), true, derr, h.st);
+            launch_id_res_template(t_wide, dq, upload(h, wgs), (int)wgs.size(), true, derr_v, h.st);
             wgs.clear();
           };
           for (int pi : wide) {
-            if ((int)wgs.size() + q[pi].P > cap_wide) flush();
-            for (int w = 0; w < q[pi].P; ++w) wgs.push_back(make_int2(pi, w));
+            if ((int)wgs.size() + qv[pi].P > cap_wide) flush();
+            for (int w = 0; w < qv[pi].P; ++w) wgs.push_back(make_int2(pi, w));
           }
           flush();
         }
+        launch_id_finish(dq, np, maxm_v, h.st);
+        return true;
+      };
+      const bool resident = o.id_kernel == HSSMF_ID_RESIDENT && run_resident(q, maxd, maxm, derr);
+      const int res_c = resident ? 1 : 0;   // the pass ran on the resident kernel
+      if (resident) {
         census_steps = -1;
-        launch_id_finish(dq, np, maxm, h.st);
       } else if (!q.empty()) {
         const int np = (int)q.size();
         int maxp = 0;
@@ -1032,6 +1040,121 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
       std::copy(pin + 1, pin + 1 + sh.size(), sh.begin());
       std::copy(pin + 1 + sh.size(), pin + 1 + sh.size() + hbuf.size(), hbuf.begin());
       REQUIRE(herr == 0, HSSMF_EDEVICE, "interpolative decomposition: a workgroup barrier timed out");
+      // Strong rank-revealing QR (Gu and Eisenstat, the rank k held fixed)
+      // on both IDs of every node that succeeded.  Per round, for each ID
+      // still open: one solve R1 [X | Z] = [R2 | I] and the interchange test
+      // (largest rho_ij = X_ij^2 + gamma_j^2 |Z_i|^2); an ID whose rho
+      // exceeds f^2, with fewer than kSrrqrMaxSwaps interchanges made, moves
+      // its selected column i out and its remaining column j in as the last
+      // selected one and is factored again in that pivot order (the
+      // resident kernel with a forced order).  The R1 / R2 gathers are
+      // redone for every problem at the end, since the test's solves
+      // overwrite R2.
+      if (o.srrqr_f > 0.0 && !q.empty()) {
+        REQUIRE(resident, HSSMF_EINVAL, "strong RRQR: an ID pass that the resident kernel cannot take");
+        const double f2 = o.srrqr_f * o.srrqr_f;
+        auto rank_of = [&](int pi) { return sh[4 * (pi / 2) + 1 + 2 * (pi % 2)]; };
+        auto host_perm = [&](int pi) {
+          const int i = pi / 2;
+          return hbuf.data() + off[i] + (pi % 2 ? cand[i].n().mr : 0);
+        };
+        std::vector<int> live, nsw(q.size(), 0);
+        for (size_t i = 0; i < cand.size(); ++i) {
+          HFront& F = *cand[i].F;
+          HNode& nd = cand[i].n();
+          const int r = sh[4 * i + 1], c = sh[4 * i + 3];
+          if (!((r <= F.d - o.p || r == nd.mr) && (c <= F.d - o.p || c == nd.mc))) continue;
+          for (int sd = 0; sd < 2; ++sd) {
+            const int pi = 2 * (int)i + sd;
+            if (rank_of(pi) > 0 && rank_of(pi) < q[pi].m) live.push_back(pi);
+          }
+        }
+        IDProb* dq_all = live.empty() ? nullptr : upload(h, q);
+        const bool tested = !live.empty();
+        while (!live.empty()) {
+          const int nl = (int)live.size();
+          int mk = 0, mm = 0;
+          std::vector<TriProb> tp;
+          for (int pi : live) {
+            const int k = rank_of(pi);
+            mk = std::max(mk, k);
+            mm = std::max(mm, q[pi].m);
+            tp.push_back({q[pi].R1, k, k, q[pi].W2, k, q[pi].m});
+          }
+          int* didx = upload(h, live);
+          launch_srrqr_eye(dq_all, didx, nl, mk, h.st);
+          tri_solve_upper_batched(h, tp);
+          double* drho = salloc(h, nl);
+          int* de = sialloc(h, nl);
+          launch_srrqr_test(dq_all, didx, nl, mm, drho, de, h.st);
+          int* tpin = h.pinned_ints(3 * nl);
+          HIP_CHECK(hipMemcpyAsync(tpin, drho, nl * sizeof(double), hipMemcpyDeviceToHost, h.st));
+          HIP_CHECK(hipMemcpyAsync(tpin + 2 * nl, de, nl * sizeof(int), hipMemcpyDeviceToHost, h.st));
+          HIP_CHECK(hipStreamSynchronize(h.st));
+          h.stager.sync();
+          std::vector<double> rho(nl);
+          std::vector<int> ev(tpin + 2 * nl, tpin + 3 * nl);
+          std::memcpy(rho.data(), tpin, nl * sizeof(double));
+          std::vector<int> redo, forder, foff;
+          for (int x = 0; x < nl; ++x) {
+            const int pi = live[x];
+            const int k = rank_of(pi), m = q[pi].m;
+            if (!(rho[x] > f2) || nsw[pi] >= kSrrqrMaxSwaps) continue;
+            REQUIRE(ev[x] >= 0 && ev[x] < k * (m - k), HSSMF_EDEVICE, "strong RRQR: interchange test out of range");
+            const int ii = ev[x] % k, jj = ev[x] / k;
+            const int* pp = host_perm(pi);
+            foff.push_back((int)forder.size());
+            for (int t = 0; t < k; ++t)
+              if (t != ii) forder.push_back(pp[t]);
+            forder.push_back(pp[k + jj]);
+            ++nsw[pi];
+            ++cand[pi / 2].F->swaps;
+            redo.push_back(pi);
+          }
+          if (redo.empty()) break;
+          int* dorder = upload(h, forder);
+          std::vector<IDProb> qs;
+          int md = 0, mm2 = 0;
+          for (size_t x = 0; x < redo.size(); ++x) {
+            IDProb pr = q[redo[x]];
+            pr.force = dorder + foff[x];
+            pr.kf = rank_of(redo[x]);
+            pr.cand = nullptr;
+            pr.slots = nullptr;
+            md = std::max(md, pr.d);
+            mm2 = std::max(mm2, pr.m);
+            qs.push_back(pr);
+          }
+          int* derr2 = nullptr;
+          REQUIRE(run_resident(qs, md, mm2, derr2), HSSMF_EINVAL,
+                  "strong RRQR: a re-factorization that the resident kernel cannot take");
+          // the wait flag, the ranks and the new pivot orders
+          size_t tot = 1 + redo.size();
+          for (int pi : redo) tot += q[pi].m;
+          int* rpin = h.pinned_ints(tot);
+          rpin[0] = 0;
+          if (derr2) HIP_CHECK(hipMemcpyAsync(rpin, derr2, sizeof(int), hipMemcpyDeviceToHost, h.st));
+          size_t at = 1 + redo.size();
+          for (size_t x = 0; x < redo.size(); ++x) {
+            const IDProb& pr = q[redo[x]];
+            HIP_CHECK(hipMemcpyAsync(rpin + 1 + x, pr.state + 1, sizeof(int), hipMemcpyDeviceToHost, h.st));
+            HIP_CHECK(hipMemcpyAsync(rpin + at, pr.perm, pr.m * sizeof(int), hipMemcpyDeviceToHost, h.st));
+            at += pr.m;
+          }
+          HIP_CHECK(hipStreamSynchronize(h.st));
+          h.stager.sync();
+          REQUIRE(rpin[0] == 0, HSSMF_EDEVICE, "strong RRQR: a workgroup barrier timed out");
+          at = 1 + redo.size();
+          for (size_t x = 0; x < redo.size(); ++x) {
+            const int pi = redo[x];
+            REQUIRE(rpin[1 + x] == rank_of(pi), HSSMF_EDEVICE, "strong RRQR: a forced re-factorization stopped early");
+            std::copy(rpin + at, rpin + at + q[pi].m, host_perm(pi));
+            at += q[pi].m;
+          }
+          live.swap(redo);
+        }
+        if (tested) launch_id_finish(dq_all, (int)q.size(), maxm, h.st);
+      }
       if (id_census && !cand.empty()) {
         const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count() - census_t0;
         int mlo = 1 << 30, mhi = 0, dlo = 1 << 30, dhi = 0, kmx = 0, fails = 0;

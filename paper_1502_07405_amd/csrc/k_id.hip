@@ -532,6 +532,87 @@ __global__ void id_r2_kernel(const IDProb* __restrict__ probs) {
   }
 }
 
+// the k x k identity into columns [m-k, m) of W2 (k x m, ld k), for the
+// strong-RRQR test's solve with R1
+__global__ void srrqr_eye_kernel(const IDProb* __restrict__ probs, const int* __restrict__ idx) {
+  const IDProb q = probs[idx[blockIdx.y]];
+  const int k = q.state[1];
+  const int64_t kk = (int64_t)k * k;
+  double* Z = q.W2 + (int64_t)(q.m - k) * k;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < kk; e += (int64_t)gridDim.x * blockDim.x)
+    Z[e] = (e % k == e / k) ? 1.0 : 0.0;
+}
+
+// Per problem (one workgroup): gamma_j^2 over the remaining columns and the
+// squared row norms of Z = R1^{-1} into LDS, then the largest
+// rho = X_ij^2 + gamma_j^2 |Z_i|^2 over e = i + k j, ties to the lowest e
+__global__ __launch_bounds__(256) void srrqr_test_kernel(const IDProb* __restrict__ probs, const int* __restrict__ idx,
+                                                         double* __restrict__ rho_out, int* __restrict__ e_out) {
+  extern __shared__ double sm[];
+  __shared__ double wv[4];
+  __shared__ int wi[4];
+  const IDProb q = probs[idx[blockIdx.x]];
+  const int k = q.state[1], m = q.m, d = q.d, nr = m - k;
+  const int tid = threadIdx.x;
+  double* gam2 = sm;        // nr
+  double* zr2 = sm + nr;    // k
+  for (int j = tid; j < nr; j += 256) {
+    const double* c = q.W + (int64_t)q.perm[k + j] * d;
+    double ss = 0.0;
+    for (int i = k; i < d; ++i) ss += c[i] * c[i];
+    gam2[j] = ss;
+  }
+  const double* X = q.W2;
+  const double* Z = q.W2 + (int64_t)nr * k;
+  for (int i = tid; i < k; i += 256) {
+    double ss = 0.0;
+    for (int l = i; l < k; ++l) ss += Z[i + (int64_t)l * k] * Z[i + (int64_t)l * k];
+    zr2[i] = ss;
+  }
+  __syncthreads();
+  double bv = -1.0;
+  int bi = 0x7fffffff;
+  const int64_t tot = (int64_t)k * nr;
+  for (int64_t e = tid; e < tot; e += 256) {
+    const int i = (int)(e % k), j = (int)(e / k);
+    const double x = X[e];
+    const double v = x * x + gam2[j] * zr2[i];
+    if (v > bv) { bv = v; bi = (int)e; }   // each thread's e ascend: the first of equals stays
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(bv, off);
+    const int oi = __shfl_xor(bi, off);
+    if (o > bv || (o == bv && oi < bi)) { bv = o; bi = oi; }
+  }
+  const int lane = tid & 63, wave = tid >> 6;
+  if (lane == 0) { wv[wave] = bv; wi[wave] = bi; }
+  __syncthreads();
+  if (tid == 0) {
+    bv = wv[0];
+    bi = wi[0];
+    for (int w = 1; w < 4; ++w)
+      if (wv[w] > bv || (wv[w] == bv && wi[w] < bi)) { bv = wv[w]; bi = wi[w]; }
+    rho_out[blockIdx.x] = bv;
+    e_out[blockIdx.x] = bi;
+  }
+}
+
+void launch_srrqr_eye(const IDProb* p, const int* idx, int n, int max_k, hipStream_t s) {
+  if (n <= 0 || max_k <= 0) return;
+  int64_t bx = ((int64_t)max_k * max_k + 255) / 256;
+  if (bx > 256) bx = 256;
+  hipLaunchKernelGGL(srrqr_eye_kernel, dim3((unsigned)bx, n), dim3(256), 0, s, p, idx);
+  HIP_CHECK(hipGetLastError());
+}
+
+void launch_srrqr_test(const IDProb* p, const int* idx, int n, int max_m, double* rho, int* e, hipStream_t s) {
+  if (n <= 0) return;
+  const size_t lds = (size_t)std::max(max_m, 1) * sizeof(double);
+  REQUIRE(lds <= 64 * 1024, HSSMF_EINVAL, "strong RRQR: more than 8192 rows in one ID");
+  hipLaunchKernelGGL(srrqr_test_kernel, dim3(n), dim3(256), lds, s, p, idx, rho, e);
+  HIP_CHECK(hipGetLastError());
+}
+
 void launch_id_init(const IDProb* p, int np, int total_wg, int max_d, hipStream_t s) {
   if (np <= 0 || total_wg <= 0) return;
   (void)max_d;

@@ -28,7 +28,10 @@
 // records of that step are filled, and takes the pivot column from the
 // winner's published copy.  Columns never move: perm / ipos record the interchanges a swapping
 // QR would make, and the factored columns are written back to W (d x m) at
-// the end for the R1 / R2 gathers.
+// the end for the R1 / R2 gathers.  A problem may instead bring a pivot
+// order to follow (the re-factorizations of the strong rank-revealing QR):
+// then only that step's candidate competes, and the steps end with the
+// order.
 #include "kernels.hpp"
 
 namespace hssmf {
@@ -126,6 +129,7 @@ __global__ __launch_bounds__(kResThreads) void id_res_kernel(const IDProb* __res
   __shared__ WRec wrec[2][NW];
   __shared__ int lperm[kMaxM], lipos[kMaxM];  // pivot order (workgroup 0 of a problem)
   __shared__ double lalpha[kV];               // R diagonal, written out at the end
+  __shared__ int lforce[kV];                  // a forced pivot order
   __shared__ double gbest, gx0;
   __shared__ int gidx, gok;
 
@@ -145,6 +149,9 @@ __global__ __launch_bounds__(kResThreads) void id_res_kernel(const IDProb* __res
   double* __restrict__ first_out = qr.first;
   const int m = qr.m, d = qr.d, P = qr.P, lds = qr.lds;
   const double eps = qr.eps, atol = qr.atol;
+  const int* __restrict__ force = qr.force;
+  const bool forced = force != nullptr;
+  const int kf = forced ? qr.kf : 0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane / LPC, e = lane % LPC;   // lane group, row offset in it
   const int kmax = min(m, d);
@@ -154,6 +161,8 @@ __global__ __launch_bounds__(kResThreads) void id_res_kernel(const IDProb* __res
   const int dc = (d + LPC * RB - 1) / (LPC * RB);   // chunks holding rows < d
   // candidate of slot s in this lane's group: jw + s G + g
 
+  if (forced)
+    for (int j = tid; j < kf; j += kResThreads) lforce[j] = force[j];
   // stage the workgroup's candidates: rows j0.. of S (m x d, ld lds), 64
   // samples at a time, read coalesced along the candidates and turned
   // around in LDS
@@ -217,13 +226,16 @@ __global__ __launch_bounds__(kResThreads) void id_res_kernel(const IDProb* __res
   for (;; ++t) {
     const int par = t & 1;
     const int tc = t / (LPC * RB);            // the chunk holding row t
-    // this wavefront's best active candidate (inactive slots never win)
+    // this wavefront's best active candidate (inactive slots never win;
+    // with a forced order only the step's candidate may)
+    const int ft = (forced && t < kf) ? lforce[t] : -1;
     double bv = -1.0;
     int bi = 0x7fffffff;
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
-      const bool on = (act >> s) & 1u;
-      amax(bv, bi, on ? nv[s] : -1.0, on ? jw + s * G + g : 0x7fffffff);
+      const int j = jw + s * G + g;
+      const bool on = ((act >> s) & 1u) && (ft < 0 || j == ft);
+      amax(bv, bi, on ? nv[s] : -1.0, on ? j : 0x7fffffff);
     }
 #pragma unroll
     for (int off = LPC; off < 64; off <<= 1) {
@@ -381,7 +393,7 @@ __global__ __launch_bounds__(kResThreads) void id_res_kernel(const IDProb* __res
       }
     }
     if (t == 0) first = best;
-    const bool stop = (t >= kmax) || (t == 0 ? best <= atol : best <= fmax(eps * first, atol));
+    const bool stop = (t >= kmax) || (forced ? t >= kf : t == 0 ? best <= atol : best <= fmax(eps * first, atol));
     if (stop) break;
     const double alpha = (x0 >= 0.0) ? -best : best;
     const double v0 = x0 - alpha;   // row t of the reflector
@@ -454,7 +466,7 @@ __global__ __launch_bounds__(kResThreads) void id_res_kernel(const IDProb* __res
     }
     for (int j = tid; j < t; j += kResThreads) alpha_out[j] = lalpha[j];
     if (tid == 0) {
-      first_out[0] = first;
+      if (!forced) first_out[0] = first;
       state[1] = failed ? 0 : t;
       state[0] = 1;
     }

@@ -279,8 +279,9 @@ struct IDProb {
   unsigned char* active;
   double* cand;         // per step buffer x P x d: each workgroup's best candidate column (layout per kernel)
   int* hdone;           // null, or a flag in mapped host memory that the stop step sets (stepwise path)
+  const int* force;     // null, or (resident kernel) the pivot order to take: kf candidates
   int m, d, lds, P;     // P workgroups of kIDCols candidates each
-  int wg0, pad;         // first workgroup of this problem in the launch grid
+  int wg0, kf;          // first workgroup of this problem in the launch grid; length of force
   double eps;           // relative stopping tolerance (Sec. 5.3)
   double atol;          // absolute stopping tolerance (0: the relative rule alone)
 };
@@ -290,6 +291,17 @@ void launch_id_init(const IDProb* p, int np, int total_wg, int max_d, hipStream_
 // wgmap[w] = (problem, workgroup within the problem) of grid workgroup w
 void launch_id_step(const IDProb* p, const int2* wgmap, int total_wg, int t, int max_d, hipStream_t s);
 void launch_id_finish(const IDProb* p, int np, int max_m, hipStream_t s);
+// Strong-RRQR interchange test of the problems idx[0..n) (Gu and Eisenstat,
+// rank k = state[1] fixed), after launch_id_finish and before any solve:
+//  - launch_srrqr_eye writes the k x k identity into columns [m-k, m) of
+//    W2 (k x m, ld k; columns [0, m-k) hold R2), so that one upper
+//    triangular solve with R1 leaves X = R1^{-1} R2 and Z = R1^{-1} there;
+//  - launch_srrqr_test then finds, per problem, the largest
+//    rho_ij = X_ij^2 + gamma_j^2 sum_l Z_il^2 over e = i + k j (ties to the
+//    lowest e), gamma_j the 2-norm of rows k.. of remaining column j in W:
+//    rho[x] and e[x] for problem idx[x].  max_m bounds every problem's m.
+void launch_srrqr_eye(const IDProb* p, const int* idx, int n, int max_k, hipStream_t s);
+void launch_srrqr_test(const IDProb* p, const int* idx, int n, int max_m, double* rho, int* e, hipStream_t s);
 
 // Copy (HBM GB/s), FP64 FMA loop and FP64 matrix-core loop (TFLOP/s) rates.
 void measure_peaks(hipStream_t s, double* hbm_gbps, double* valu_tflops, double* mfma_tflops);
@@ -314,7 +326,11 @@ void launch_id_coop(const IDProb* p, const int2* wgmap, int total_wg, int max_d,
 // workgroups), with that problem's slots (3 x P x 2 doubles, all NaN) and
 // cand (3 x P x d) set and *err zero; *err != 0
 // afterwards means a wait gave up and the results are invalid.  Every
-// launch of one pass must take the same (max_d, max_m).
+// launch of one pass must take the same (max_d, max_m).  A problem with
+// force set takes the candidates force[0..kf) as its pivots, in that order
+// (kf <= min(m, d), distinct), and stops after them: its rank is kf, and
+// its pivot order, R diagonal and W are those of a Householder QR in that
+// order with the same interchange bookkeeping.
 int id_res_candidates(int max_d, int max_m);
 int id_res_capacity(int max_d, int max_m);
 void launch_id_res(const IDProb* p, const int2* wgmap, int total_wg, int max_d, int max_m, bool coop, int* err,

@@ -82,7 +82,7 @@ struct HFront {
   std::vector<HNode> nd;
   int root = -1, k = -1, q = -1, maxh = 0;
   // sampling
-  int d = 0, dcap = 0, rounds = 0;
+  int d = 0, dcap = 0, rounds = 0, swaps = 0;   // swaps: strong-RRQR interchanges
   double *R = nullptr, *Sr = nullptr, *Sc = nullptr;
   // power iteration: R^r (row side) and R^c (column side) of Alg. 1, n x
   // dcap like R; nullptr for plain sampling, where both are R

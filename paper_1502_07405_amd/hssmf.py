@@ -54,7 +54,7 @@ class Opts(ctypes.Structure):
                 ("id_kernel", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("gemm_tile", ctypes.c_int32), ("abs_tol", ctypes.c_double),
                 ("keep_stages", ctypes.c_int32), ("hss_update", ctypes.c_int32),
-                ("power_q", ctypes.c_int32)]
+                ("power_q", ctypes.c_int32), ("srrqr_f", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -72,7 +72,7 @@ class Stats(ctypes.Structure):
                 ("max_rank", ctypes.c_int32), ("max_d", ctypes.c_int32), ("growth_rounds", ctypes.c_int32),
                 ("factor_bytes", ctypes.c_int64), ("t_plan_ms", ctypes.c_double),
                 ("t_factor_ms", ctypes.c_double), ("flops_factor", ctypes.c_double),
-                ("peak_bytes", ctypes.c_int64), ("trsv_multi_ops", ctypes.c_int32), ("pad0", ctypes.c_int32)]
+                ("peak_bytes", ctypes.c_int64), ("trsv_multi_ops", ctypes.c_int32), ("srrqr_swaps", ctypes.c_int32)]
 
 
 _lib = None

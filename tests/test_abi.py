@@ -40,6 +40,7 @@ def test_default_options_and_strerror(lib):
     assert o.leaf_size == 64 and o.d0 == 128 and o.dd == 128 and o.p == 10 and o.restart == 30
     assert o.tol == 1e-10 and o.rel_tol == 1e-6 and o.min_sep_hss == 2 ** 31 - 1
     assert o.id_kernel == 2 and o.use_graph == 0 and o.hss_update == 1 and o.power_q == 0
+    assert o.srrqr_f == 0.0
     assert H.strerror(0) == "ok" and H.strerror(H.HSSMF_ERANK) == "HSS rank exceeds d_max"
 
 
@@ -119,6 +120,12 @@ def test_rejects_bad_options(lib, small):
     # power iteration: at most 4 steps, and only with FP64 products
     for kw in (dict(power_q=-1), dict(power_q=5), dict(power_q=1, gemm_prec="fp32"),
                dict(power_q=2, gemm_prec="bf16")):
+        opts = H.default_opts(**kw)
+        assert _call_factor(A.rowptr, A.colind, A.val, o.perm, o.sep_ptr, o.parent, A.n, opts) == H.HSSMF_EINVAL, kw
+    # strong RRQR: 0 (off) or f > 1 (finite), and only on the resident ID kernel
+    for kw in (dict(srrqr_f=-1.0), dict(srrqr_f=0.5), dict(srrqr_f=1.0), dict(srrqr_f=float("nan")),
+               dict(srrqr_f=float("inf")), dict(srrqr_f=2.0, id_kernel="stepwise"),
+               dict(srrqr_f=2.0, id_kernel="cooperative")):
         opts = H.default_opts(**kw)
         assert _call_factor(A.rowptr, A.colind, A.val, o.perm, o.sep_ptr, o.parent, A.n, opts) == H.HSSMF_EINVAL, kw
 
