@@ -134,7 +134,7 @@ MEASURED_KEY = {"id": "fp64_valu_TFLOPs", "gemm64": "fp64_mfma_TFLOPs", "gemmlp"
 # copy in the same run): profiles/id_res_hbm_traffic_poisson3d_64.md.  Valid
 # only for the kernel source those counters were taken on.  The bench divides
 # the total by its own launches per factorization.
-TRAFFIC = {"idres": (1.5700e10, "paper_1502_07405_amd/csrc/k_idres.hip", "fff91552dc661b6a")}
+TRAFFIC = {"idres": (1.5704e10, "paper_1502_07405_amd/csrc/k_idres.hip", "9ffc09f92baebe7f")}
 
 
 def traffic_for(cls, launches_per_factorization):

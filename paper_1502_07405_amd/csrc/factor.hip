@@ -827,6 +827,10 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
       auto run_resident = [&](std::vector<IDProb>& qv, int maxd_v, int maxm_v, int*& derr_v) -> bool {
         const int np_all = (int)qv.size();
         if (np_all == 0) return false;
+        // forced pivot orders: every problem of the call or none
+        const bool forced = qv[0].force != nullptr;
+        for (const IDProb& pr : qv)
+          REQUIRE((pr.force != nullptr) == forced, HSSMF_EDEVICE, "interpolative decomposition: mixed forced orders");
         const int t_all = id_res_template(maxd_v, maxm_v);
         if (t_all < 0) return false;
         std::vector<int> tpl(np_all, -1), pall(np_all, 1);
@@ -892,7 +896,7 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
         if (one) {
           for (int pi = 0; pi < np; ++pi)
             for (int w = 0; w < qv[pi].P; ++w) wgs.push_back(make_int2(pi, w));
-          launch_id_res_template(t_all, dq, upload(h, wgs), (int)wgs.size(), true, derr_v, h.st);
+          launch_id_res_template(t_all, dq, upload(h, wgs), (int)wgs.size(), true, derr_v, h.st, forced);
         } else {
           // one workgroup each, grouped by template
           std::map<int, std::vector<int2>> single;
@@ -913,7 +917,7 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
           }
           for (int li = 0; li < nl; ++li) {
             hipStream_t ls = li == 0 || naux == 0 ? h.st : h.aux[(li - 1) % naux];
-            launch_id_res_template(launches[li].first, dq, launches[li].second, counts[li], false, derr_v, ls);
+            launch_id_res_template(launches[li].first, dq, launches[li].second, counts[li], false, derr_v, ls, forced);
           }
           for (int a = 0; a < naux; ++a) {
             HIP_CHECK(hipEventRecord(h.ev_join[a], h.aux[a]));
@@ -928,7 +932,7 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
           wgs.clear();
           auto flush = [&]() {
             if (wgs.empty()) return;
-            launch_id_res_template(t_wide, dq, upload(h, wgs), (int)wgs.size(), true, derr_v, h.st);
+            launch_id_res_template(t_wide, dq, upload(h, wgs), (int)wgs.size(), true, derr_v, h.st, forced);
             wgs.clear();
           };
           for (int pi : wide) {

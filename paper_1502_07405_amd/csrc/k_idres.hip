@@ -108,8 +108,8 @@ __device__ __forceinline__ void wargmax(double& v, int& i) {
 }  // namespace
 
 // LPC lanes per candidate, RL rows per lane (d <= LPC RL), SL candidates per
-// lane group
-template <int LPC, int RL, int SL>
+// lane group; FORCED: every problem of the launch follows its forced order
+template <int LPC, int RL, int SL, bool FORCED>
 __global__ __launch_bounds__(kResThreads) void id_res_kernel(const IDProb* __restrict__ probs,
                                                              const int2* __restrict__ wgmap, int* err) {
   constexpr int G = 64 / LPC;                 // lane groups per wavefront
@@ -149,9 +149,9 @@ __global__ __launch_bounds__(kResThreads) void id_res_kernel(const IDProb* __res
   double* __restrict__ first_out = qr.first;
   const int m = qr.m, d = qr.d, P = qr.P, lds = qr.lds;
   const double eps = qr.eps, atol = qr.atol;
-  const int* __restrict__ force = qr.force;
-  const bool forced = force != nullptr;
-  const int kf = forced ? qr.kf : 0;
+  constexpr bool forced = FORCED;
+  const int* __restrict__ force = FORCED ? qr.force : nullptr;
+  const int kf = FORCED ? qr.kf : 0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane / LPC, e = lane % LPC;   // lane group, row offset in it
   const int kmax = min(m, d);
@@ -227,15 +227,18 @@ __global__ __launch_bounds__(kResThreads) void id_res_kernel(const IDProb* __res
     const int par = t & 1;
     const int tc = t / (LPC * RB);            // the chunk holding row t
     // this wavefront's best active candidate (inactive slots never win;
-    // with a forced order only the step's candidate may)
-    const int ft = (forced && t < kf) ? lforce[t] : -1;
+    // with a forced order only the slot holding the step's candidate may)
+    unsigned sel = act;
+    if (forced && t < kf) {
+      const int qf = lforce[t] - jw;
+      sel = (qf >= 0 && qf < CW && qf % G == g) ? (act & (1u << (qf / G))) : 0u;
+    }
     double bv = -1.0;
     int bi = 0x7fffffff;
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
-      const int j = jw + s * G + g;
-      const bool on = ((act >> s) & 1u) && (ft < 0 || j == ft);
-      amax(bv, bi, on ? nv[s] : -1.0, on ? j : 0x7fffffff);
+      const bool on = (sel >> s) & 1u;
+      amax(bv, bi, on ? nv[s] : -1.0, on ? jw + s * G + g : 0x7fffffff);
     }
 #pragma unroll
     for (int off = LPC; off < 64; off <<= 1) {
@@ -496,14 +499,20 @@ namespace {
 // time), or the most if none does (fewest workgroups per problem).
 struct ResShape {
   int lpc, rl, sl;
-  const void* fn;
+  const void* fn;    // pivots by the largest remaining norm
+  const void* fnf;   // pivots in a forced order
 };
 const ResShape kShapes[] = {
-    {16, 8, 2, (const void*)id_res_kernel<16, 8, 2>},   {16, 8, 4, (const void*)id_res_kernel<16, 8, 4>},
-    {16, 8, 8, (const void*)id_res_kernel<16, 8, 8>},   {16, 16, 2, (const void*)id_res_kernel<16, 16, 2>},
-    {16, 16, 4, (const void*)id_res_kernel<16, 16, 4>}, {16, 16, 5, (const void*)id_res_kernel<16, 16, 5>},
-    {16, 24, 2, (const void*)id_res_kernel<16, 24, 2>}, {16, 24, 3, (const void*)id_res_kernel<16, 24, 3>},
-    {16, 32, 2, (const void*)id_res_kernel<16, 32, 2>}, {16, 40, 2, (const void*)id_res_kernel<16, 40, 2>},
+    {16, 8, 2, (const void*)id_res_kernel<16, 8, 2, false>, (const void*)id_res_kernel<16, 8, 2, true>},
+    {16, 8, 4, (const void*)id_res_kernel<16, 8, 4, false>, (const void*)id_res_kernel<16, 8, 4, true>},
+    {16, 8, 8, (const void*)id_res_kernel<16, 8, 8, false>, (const void*)id_res_kernel<16, 8, 8, true>},
+    {16, 16, 2, (const void*)id_res_kernel<16, 16, 2, false>, (const void*)id_res_kernel<16, 16, 2, true>},
+    {16, 16, 4, (const void*)id_res_kernel<16, 16, 4, false>, (const void*)id_res_kernel<16, 16, 4, true>},
+    {16, 16, 5, (const void*)id_res_kernel<16, 16, 5, false>, (const void*)id_res_kernel<16, 16, 5, true>},
+    {16, 24, 2, (const void*)id_res_kernel<16, 24, 2, false>, (const void*)id_res_kernel<16, 24, 2, true>},
+    {16, 24, 3, (const void*)id_res_kernel<16, 24, 3, false>, (const void*)id_res_kernel<16, 24, 3, true>},
+    {16, 32, 2, (const void*)id_res_kernel<16, 32, 2, false>, (const void*)id_res_kernel<16, 32, 2, true>},
+    {16, 40, 2, (const void*)id_res_kernel<16, 40, 2, false>, (const void*)id_res_kernel<16, 40, 2, true>},
 };
 
 const ResShape* res_shape(int max_d, int max_m) {
@@ -532,17 +541,20 @@ int capacity_of(const ResShape* s) {
   if (!coop) return 0;
   HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, s->fn, kResThreads, 0));
-  return nb * cus;
+  int nbf = 0;
+  HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nbf, s->fnf, kResThreads, 0));
+  return std::min(nb, nbf) * cus;
 }
 
 void launch_shape(const ResShape* sh, const IDProb* p, const int2* wgmap, int total_wg, bool coop, int* err,
-                  hipStream_t s) {
+                  hipStream_t s, bool forced) {
   if (total_wg <= 0) return;
   REQUIRE(sh != nullptr, HSSMF_ERANK, "interpolative decomposition: more than 640 samples");
   void* args[] = {(void*)&p, (void*)&wgmap, (void*)&err};
+  const void* fn = forced ? sh->fnf : sh->fn;
   const int tok = prof::begin(4, s);   // timing hook (no-op when off)
-  if (coop) HIP_CHECK(hipLaunchCooperativeKernel(sh->fn, dim3(total_wg), dim3(kResThreads), args, 0, s));
-  else HIP_CHECK(hipLaunchKernel(sh->fn, dim3(total_wg), dim3(kResThreads), args, 0, s));
+  if (coop) HIP_CHECK(hipLaunchCooperativeKernel(fn, dim3(total_wg), dim3(kResThreads), args, 0, s));
+  else HIP_CHECK(hipLaunchKernel(fn, dim3(total_wg), dim3(kResThreads), args, 0, s));
   prof::end(tok, s);
 }
 
@@ -557,7 +569,7 @@ int id_res_capacity(int max_d, int max_m) { return capacity_of(res_shape(max_d, 
 
 void launch_id_res(const IDProb* p, const int2* wgmap, int total_wg, int max_d, int max_m, bool coop, int* err,
                    hipStream_t s) {
-  launch_shape(res_shape(max_d, max_m), p, wgmap, total_wg, coop, err, s);
+  launch_shape(res_shape(max_d, max_m), p, wgmap, total_wg, coop, err, s, false);
 }
 
 int id_res_template(int d, int m) {
@@ -575,8 +587,8 @@ int id_res_template_candidates(int tpl) {
 int id_res_template_capacity(int tpl) { return capacity_of(&kShapes[tpl]); }
 
 void launch_id_res_template(int tpl, const IDProb* p, const int2* wgmap, int total_wg, bool coop, int* err,
-                            hipStream_t s) {
-  launch_shape(&kShapes[tpl], p, wgmap, total_wg, coop, err, s);
+                            hipStream_t s, bool forced) {
+  launch_shape(&kShapes[tpl], p, wgmap, total_wg, coop, err, s, forced);
 }
 
 }  // namespace hssmf

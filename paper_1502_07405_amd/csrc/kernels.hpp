@@ -326,8 +326,9 @@ void launch_id_coop(const IDProb* p, const int2* wgmap, int total_wg, int max_d,
 // workgroups), with that problem's slots (3 x P x 2 doubles, all NaN) and
 // cand (3 x P x d) set and *err zero; *err != 0
 // afterwards means a wait gave up and the results are invalid.  Every
-// launch of one pass must take the same (max_d, max_m).  A problem with
-// force set takes the candidates force[0..kf) as its pivots, in that order
+// launch of one pass must take the same (max_d, max_m).  A launch with
+// forced = true (its own instantiations; every problem it covers has force
+// set) takes the candidates force[0..kf) as each problem's pivots, in that order
 // (kf <= min(m, d), distinct), and stops after them: its rank is kf, and
 // its pivot order, R diagonal and W are those of a Householder QR in that
 // order with the same interchange bookkeeping.
@@ -345,7 +346,7 @@ int id_res_template(int d, int m);
 int id_res_template_candidates(int tpl);
 int id_res_template_capacity(int tpl);
 void launch_id_res_template(int tpl, const IDProb* p, const int2* wgmap, int total_wg, bool coop, int* err,
-                            hipStream_t s);
+                            hipStream_t s, bool forced = false);
 
 }  // namespace hssmf
 
