@@ -1051,9 +1051,11 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
       // exceeds f^2, with fewer than kSrrqrMaxSwaps interchanges made, moves
       // its selected column i out and its remaining column j in as the last
       // selected one and is factored again in that pivot order (the
-      // resident kernel with a forced order).  The R1 / R2 gathers are
-      // redone for every problem at the end, since the test's solves
-      // overwrite R2.
+      // resident kernel with a forced order), then tested again.  An ID
+      // leaves the rounds right after a test, whose solve has left
+      // X = R1^{-1} R2 of its final pivot order in W2: the E step below
+      // only copies it (x_ready).
+      std::vector<char> x_ready(q.size(), 0);
       if (o.srrqr_f > 0.0 && !q.empty()) {
         REQUIRE(resident, HSSMF_EINVAL, "strong RRQR: an ID pass that the resident kernel cannot take");
         const double f2 = o.srrqr_f * o.srrqr_f;
@@ -1074,7 +1076,7 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
           }
         }
         IDProb* dq_all = live.empty() ? nullptr : upload(h, q);
-        const bool tested = !live.empty();
+        for (int pi : live) x_ready[pi] = 1;
         while (!live.empty()) {
           const int nl = (int)live.size();
           int mk = 0, mm = 0;
@@ -1157,7 +1159,6 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
           }
           live.swap(redo);
         }
-        if (tested) launch_id_finish(dq_all, (int)q.size(), maxm, h.st);
       }
       if (id_census && !cand.empty()) {
         const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count() - census_t0;
@@ -1231,7 +1232,8 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
       }
       {
         // E = (R1^{-1} R2)^T for the successful IDs: batched blocked
-        // triangular solve (64-row diagonal blocks + GEMM updates)
+        // triangular solve (64-row diagonal blocks + GEMM updates), except
+        // where the strong RRQR's last test already solved for X
         std::vector<TriProb> tp;
         std::vector<CopyDesc> tc;
         for (size_t i = 0; i < cand.size(); ++i) {
@@ -1241,7 +1243,7 @@ void compress_level(Handle& h, std::vector<HFront*>& fs, const FrontOpDev* fops,
             const IDProb& pr = q[2 * i + sd];
             const int k = sd ? nd.c : nd.r, nrest = pr.m - k;
             if (k == 0 || nrest == 0) continue;
-            tp.push_back({pr.R1, k, k, pr.W2, k, nrest});
+            if (!x_ready[2 * i + sd]) tp.push_back({pr.R1, k, k, pr.W2, k, nrest});
             tc.push_back(Cp(pr.W2, k, nullptr, sd ? nd.Ec : nd.Er, nrest, nrest, k, 0, 1.0, nullptr, 1));
           }
         }
