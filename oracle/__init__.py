@@ -14,6 +14,7 @@ symbolic   fronts, update index sets and per-front HSS trees from an ordering
 dense      dense fronts: extend-add and partial LU (Sec. 3)
 hss        ID, randomized HSS compression (Alg. 1), HSS matvec / extraction,
            ULV-like factorization and solves (Sec. 2)
+complexeq  complex systems through their real-equivalent form (Helmholtz)
 mf         multifrontal factorization with dense and HSS fronts (Sec. 3, 4)
 krylov     iterative refinement and GMRES(30) (Sec. 4.6, Sec. 6.1)
 adjoint    transpose solve based gradients

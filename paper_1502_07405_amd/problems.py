@@ -174,6 +174,114 @@ def convdiff_paper(n, ndim=2, nu=1e-4):
     return _stencil(dims, 2 * ndim * nu + h * sum(np.abs(va) for va in v), coeff)
 
 
+@dataclass
+class ZCSR:
+    """A complex sparse matrix: CSR pattern as in CSR, val complex128."""
+    n: int
+    rowptr: np.ndarray
+    colind: np.ndarray
+    val: np.ndarray
+
+    def to_scipy(self):
+        import scipy.sparse as sp
+        return sp.csr_matrix((self.val, self.colind, self.rowptr), shape=(self.n, self.n))
+
+
+def helmholtz(n, ndim=2, freq=10.0, ppw=15.0, npml=8, vmin=1500.0, vmax=2500.0):
+    """The paper's H2D / H3D problems (Sec. 6.1): (-Lap - omega^2 / v(x)^2) u
+    = s on an n^ndim grid, omega = 2 pi freq, h = vmin / (freq ppw) (ppw
+    points per wavelength at the slowest velocity), npml layers of
+    perfectly matched layer on every side, homogeneous Dirichlet beyond.
+
+    Stretched coordinates s_a = 1 + i sigma_a / omega, sigma_a = sigma0
+    (xi / L)^2 at depth xi into a layer of width L = npml h, sigma0 =
+    3 vmax ln(10^6) / (2 L); the conservative form -div(D grad u) -
+    (omega / v)^2 S u with S = prod_a s_a and D_aa = S / s_a^2 gives a
+    complex symmetric matrix.  Stencil: 9 points in 2D, 27 in 3D.  The
+    Laplacian is w_1 L_faces + w_2 L_edges (+ w_3 L_corners in 3D), each L_c
+    the consistent second difference over the neighbours of its class
+    (sum over offsets d of (u(x + h d) - u(x)) divided by h^2 |class| times
+    the d d^T trace factor), with the neighbour pair's coefficient
+    d^T D d / d^T d taken at the pair's midpoint; the mass term spreads
+    (omega / v)^2 S over the same neighbours with weights m_c (centre m_0).
+    Velocity v = vmin + (vmax - vmin) times the depth fraction, plus a
+    smooth Gaussian anomaly of 10% at the centre."""
+    dims = (n,) * ndim
+    N = n ** ndim
+    omega = 2.0 * np.pi * freq
+    h = vmin / (freq * ppw)
+    L = npml * h
+    sigma0 = 3.0 * vmax * np.log(1e6) / (2.0 * L) if npml > 0 else 0.0
+    idx = np.arange(N)
+    coords = []
+    rem = idx.copy()
+    for _ in dims:
+        coords.append(rem % n)
+        rem = rem // n
+    stride = np.array([n ** a for a in range(ndim)])
+
+    def stretch(xa):
+        # xa: grid coordinate (may be half-integer); depth into the layers
+        if npml == 0:
+            return np.ones(np.shape(xa), dtype=np.complex128)
+        lo = (npml - 1) - xa
+        hi = xa - (n - npml)
+        xi = np.maximum(np.maximum(lo, hi), 0.0) * h
+        sig = sigma0 * (xi / L) ** 2
+        return 1.0 + 1j * sig / omega
+
+    def fields(xs):
+        s = [stretch(xa) for xa in xs]
+        S = np.prod(s, axis=0)
+        D = [S / sa ** 2 for sa in s]
+        depth = xs[-1] / max(n - 1, 1)
+        r2 = sum(((xa / max(n - 1, 1)) - 0.5) ** 2 for xa in xs)
+        v = vmin + (vmax - vmin) * depth + 0.1 * vmin * np.exp(-r2 / 0.02)
+        return D, S * (omega / v) ** 2
+
+    offs = [np.array(d) for d in np.ndindex(*(3,) * ndim)]
+    offs = [d - 1 for d in offs if np.any(d != 1)]
+    if ndim == 2:
+        lap_w = {1: 0.6, 2: 0.4}
+        mass_w = {0: 0.6, 1: 0.08, 2: 0.02}
+    else:
+        lap_w = {1: 0.6, 2: 0.3, 3: 0.1}
+        mass_w = {0: 0.5, 1: 0.05, 2: 0.01, 3: 0.0025}
+    # trace factor: sum over a class's offsets of d d^T = t_c I
+    tr = {c: sum(int(np.sum(d != 0) == c) * (np.abs(d) > 0) for d in offs)[0] for c in lap_w}
+    rows, cols, vals = [], [], []
+    centre = np.zeros(N, dtype=np.complex128)
+    D0, K0 = fields([c.astype(np.float64) for c in coords])
+    centre -= mass_w[0] * K0
+    for d in offs:
+        c = int(np.sum(d != 0))
+        ok = np.ones(N, dtype=bool)
+        for a in range(ndim):
+            ok &= (coords[a] + d[a] >= 0) & (coords[a] + d[a] < n)
+        mid = [coords[a][ok] + 0.5 * d[a] for a in range(ndim)]
+        Dm, Km = fields(mid)
+        ddd = sum(Dm[a] * d[a] * d[a] for a in range(ndim)) / float(d @ d)
+        lap = -lap_w[c] / (tr[c] * h * h) * 2.0 * ddd
+        mass = -mass_w[c] * Km
+        off = lap + mass
+        src = idx[ok]
+        rows.append(src)
+        cols.append(src + int(d @ stride))
+        vals.append(off)
+        np.add.at(centre, src, -lap)
+    rows.append(idx)
+    cols.append(idx)
+    vals.append(centre)
+    r = np.concatenate(rows)
+    cc = np.concatenate(cols)
+    vv = np.concatenate(vals)
+    order = np.lexsort((cc, r))
+    r, cc, vv = r[order], cc[order], vv[order]
+    rowptr = np.zeros(N + 1, dtype=np.int64)
+    np.add.at(rowptr, r + 1, 1)
+    return ZCSR(N, np.cumsum(rowptr), cc.astype(np.int32), vv.astype(np.complex128))
+
+
 def smoothed_log_kappa(n, seed=3, sigma=0.5):
     """log(kappa) iid N(0, sigma^2) from ``default_rng(seed)``, then a 3x3x3 box
     mean over the in-domain neighbours.  Returns (kappa, rng) so that the caller
