@@ -252,6 +252,34 @@ int hssmf_systems(void* h, int64_t* off, int32_t cap);
  * matrix given to hssmf_factor; val has rowptr[n] entries, host memory). */
 int hssmf_refactor(void* h, const double* val);
 
+/* A complex sparse system (the Helmholtz problems of Sec. 6.1 use complex
+ * arithmetic), factored through its real-equivalent form.  A->val holds
+ * 2 rowptr[n] doubles, the (real, imaginary) pair of each stored entry in
+ * CSR order; A->mem as for hssmf_factor (values and pattern are read during
+ * the call only).  The ordering is the complex system's (perm, separator
+ * tree over its n unknowns).  The library forms the real system of 2n
+ * unknowns in which complex unknown j becomes unknowns 2j (real part) and
+ * 2j + 1 (imaginary part) and entry a + ib becomes the block [a -b; b a]:
+ * 4 rowptr[n] stored entries, the ordering expanded alike (every front
+ * keeps its unknowns' pairs together, separator sizes double), and factors
+ * it as hssmf_factor does (every option applies; leaf_size, min_sep_hss
+ * and the ranks count real unknowns).  The handle then behaves as one of
+ * 2n real unknowns: a complex vector stored as interleaved (real,
+ * imaginary) doubles is exactly that real system's vector, so
+ * hssmf_solve and hssmf_apply take and return complex vectors in that
+ * storage.  The real form's transpose is the real form of the conjugate
+ * transpose: hssmf_solve_transpose and hssmf_apply with trans = 1 solve
+ * with A^H.  Errors
+ * as hssmf_factor; EINVAL also for n above INT32_MAX / 2.  Products cost
+ * about twice the real flops that complex kernels would need. */
+int hssmf_factor_z(const hssmf_csr* A, const hssmf_ordering* ord, const hssmf_opts* opts, void* stream,
+                   void** out);
+
+/* New complex values for a handle from hssmf_factor_z (same pattern; val:
+ * 2 rowptr[n] doubles, (real, imaginary) pairs, host memory).  EINVAL for
+ * a handle from hssmf_factor or hssmf_factor_batch. */
+int hssmf_refactor_z(void* h, const double* val);
+
 /* hssmf_refactor with the new values already in device memory: val_dev has
  * rowptr[n] entries in the CSR order given to hssmf_factor, is read on the
  * handle's stream (copied into the handle there) and stays owned by the

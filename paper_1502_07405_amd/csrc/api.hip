@@ -583,7 +583,8 @@ struct HostCSR {
   std::vector<int32_t> ci;
   std::vector<double> v;
 };
-int to_host(const hssmf_csr* A, HostCSR& out) {
+// per: values per stored entry (1 real, 2 for a complex (re, im) pair)
+int to_host(const hssmf_csr* A, HostCSR& out, int per = 1) {
   out.a = *A;
   out.a.mem = HSSMF_MEM_HOST;
   if (A->mem == HSSMF_MEM_HOST) return HSSMF_OK;
@@ -595,7 +596,7 @@ int to_host(const hssmf_csr* A, HostCSR& out) {
     REQUIRE(out.rp[0] >= 0 && nnz >= 0, HSSMF_EINVAL, "device CSR: bad rowptr");
     REQUIRE(nnz == 0 || (A->colind && A->val), HSSMF_EINVAL, "device CSR: null arrays");
     out.ci.resize((size_t)out.rp[A->n]);
-    out.v.resize((size_t)out.rp[A->n]);
+    out.v.resize((size_t)out.rp[A->n] * per);
     if (!out.ci.empty()) {
       HIP_CHECK(hipMemcpy(out.ci.data(), A->colind, sizeof(int32_t) * out.ci.size(), hipMemcpyDeviceToHost));
       HIP_CHECK(hipMemcpy(out.v.data(), A->val, sizeof(double) * out.v.size(), hipMemcpyDeviceToHost));
@@ -710,6 +711,99 @@ int hssmf_factor_batch(int32_t nsys, const hssmf_csr* A, const hssmf_ordering* o
   hssmf_csr ca{(int32_t)n, rowptr.data(), col.data(), val.data(), HSSMF_MEM_HOST};
   hssmf_ordering co{perm.data(), (int32_t)nf, sep.data(), par.data()};
   return factor_impl(&ca, &co, opts, stream, out, off);
+}
+
+int hssmf_factor_z(const hssmf_csr* A, const hssmf_ordering* ord, const hssmf_opts* opts, void* stream,
+                   void** out) {
+  if (!out || !A || !ord || !opts) return HSSMF_EINVAL;
+  *out = nullptr;
+  if (!opts_ok(opts)) return HSSMF_EINVAL;
+  HostCSR hc;
+  int rc = to_host(A, hc, 2);
+  if (rc != HSSMF_OK) return rc;
+  const hssmf_csr& a = hc.a;
+  if (a.n < 0 || a.n > INT32_MAX / 2 || !a.rowptr || ord->nfront < 0 || !ord->sep_ptr || !ord->parent ||
+      (a.n > 0 && (!a.colind || !a.val || !ord->perm)))
+    return HSSMF_EINVAL;
+  const int64_t base = a.rowptr[0];
+  const int64_t nnz = a.rowptr[a.n] - base;
+  if (base < 0 || nnz < 0) return HSSMF_EINVAL;
+  for (int i = 0; i < a.n; ++i)
+    if (a.rowptr[i + 1] < a.rowptr[i]) return HSSMF_EINVAL;
+  // the real-equivalent form: unknown j becomes 2j (real part) and 2j + 1
+  // (imaginary part); entry alpha + i beta becomes [alpha -beta; beta alpha]
+  const int n2 = 2 * a.n;
+  std::vector<int64_t> rp(n2 + 1, 0), zrow(a.n + 1);
+  std::vector<int32_t> ci(4 * nnz);
+  std::vector<double> v(4 * nnz);
+  for (int i = 0; i < a.n; ++i) {
+    const int64_t e0 = a.rowptr[i] - base, len = a.rowptr[i + 1] - a.rowptr[i];
+    zrow[i] = e0;
+    rp[2 * i + 1] = rp[2 * i] + 2 * len;
+    rp[2 * i + 2] = rp[2 * i + 1] + 2 * len;
+    for (int64_t t = 0; t < len; ++t) {
+      const int j = a.colind[base + e0 + t];
+      if (j < 0 || j >= a.n) return HSSMF_EINVAL;
+      const double re = a.val[2 * (base + e0 + t)], im = a.val[2 * (base + e0 + t) + 1];
+      const int64_t r0 = rp[2 * i] + 2 * t, r1 = rp[2 * i + 1] + 2 * t;
+      ci[r0] = 2 * j;
+      ci[r0 + 1] = 2 * j + 1;
+      v[r0] = re;
+      v[r0 + 1] = -im;
+      ci[r1] = 2 * j;
+      ci[r1 + 1] = 2 * j + 1;
+      v[r1] = im;
+      v[r1 + 1] = re;
+    }
+  }
+  zrow[a.n] = nnz;
+  std::vector<int32_t> perm(n2), sep(ord->nfront + 1), par(ord->parent, ord->parent + ord->nfront);
+  for (int k = 0; k < a.n; ++k) {
+    const int p = ord->perm[k];
+    if (p < 0 || p >= a.n) return HSSMF_EINVAL;
+    perm[2 * k] = 2 * p;
+    perm[2 * k + 1] = 2 * p + 1;
+  }
+  for (int f = 0; f <= ord->nfront; ++f) {
+    if (ord->sep_ptr[f] < 0 || ord->sep_ptr[f] > a.n) return HSSMF_EINVAL;
+    sep[f] = 2 * ord->sep_ptr[f];
+  }
+  hssmf_csr ca{n2, rp.data(), ci.data(), v.data(), HSSMF_MEM_HOST};
+  hssmf_ordering co{perm.data(), ord->nfront, sep.data(), par.data()};
+  rc = factor_impl(&ca, &co, opts, stream, out, {0, (int64_t)n2});
+  if (rc == HSSMF_OK) {
+    Handle* h = static_cast<Handle*>(*out);
+    h->zexp = true;
+    h->zrow = std::move(zrow);
+  }
+  return rc;
+}
+
+int hssmf_refactor_z(void* hv, const double* val) {
+  Handle* h = static_cast<Handle*>(hv);
+  if (!h || !val || !h->zexp) return HSSMF_EINVAL;
+  return guard_impl(h, [&]() {
+    const int n = (int)h->zrow.size() - 1;
+    std::vector<double> v((size_t)h->P.nnz);
+    int64_t r = 0;
+    for (int i = 0; i < n; ++i) {
+      const int64_t e0 = h->zrow[i], len = h->zrow[i + 1] - e0;
+      for (int64_t t = 0; t < len; ++t) {   // the real part's row
+        v[r + 2 * t] = val[2 * (e0 + t)];
+        v[r + 2 * t + 1] = -val[2 * (e0 + t) + 1];
+      }
+      r += 2 * len;
+      for (int64_t t = 0; t < len; ++t) {   // the imaginary part's row
+        v[r + 2 * t] = val[2 * (e0 + t) + 1];
+        v[r + 2 * t + 1] = val[2 * (e0 + t)];
+      }
+      r += 2 * len;
+    }
+    REQUIRE(r == h->P.nnz, HSSMF_EDEVICE, "complex refactorization: pattern size mismatch");
+    HIP_CHECK(hipMemcpyAsync(h->d_val, v.data(), sizeof(double) * v.size(), hipMemcpyHostToDevice, h->st));
+    HIP_CHECK(hipStreamSynchronize(h->st));
+    numeric(*h);
+  });
 }
 
 int hssmf_systems(void* hv, int64_t* off, int32_t cap) {

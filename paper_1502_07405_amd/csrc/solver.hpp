@@ -274,6 +274,10 @@ struct Handle {
   // independent systems factored together (hssmf_factor_batch): unknowns
   // [sys_off[s], sys_off[s+1]) belong to system s; one system otherwise
   std::vector<int64_t> sys_off;
+  // a complex system factored through its real-equivalent form
+  // (hssmf_factor_z): the complex CSR's row pointers, base 0
+  bool zexp = false;
+  std::vector<int64_t> zrow;
   int64_t* d_sys_off = nullptr;
   double* d_seg = nullptr;     // per-system sums of squares
   // preconditioner sweeps captured as HIP graphs ([trans]), rebuilt after

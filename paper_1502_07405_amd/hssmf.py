@@ -22,7 +22,8 @@ EXPORTS = ["hssmf_default_opts", "hssmf_factor", "hssmf_refactor", "hssmf_apply"
            "hssmf_last_failed_front", "hssmf_destroy", "hssmf_strerror", "hssmf_profile_enable",
            "hssmf_profile_read", "hssmf_factor_batch", "hssmf_systems", "hssmf_measure_peaks",
            "hssmf_refactor_device", "hssmf_solve_batch", "hssmf_solve_noalloc",
-           "hssmf_front_data", "hssmf_static_pivoting", "hssmf_nested_dissection"]
+           "hssmf_front_data", "hssmf_static_pivoting", "hssmf_nested_dissection", "hssmf_factor_z",
+           "hssmf_refactor_z"]
 KCLASS = {"id": 0, "gemm64": 1, "gemmlp": 2, "lupanel": 3, "idres": 4}
 
 
@@ -90,6 +91,9 @@ def load():
         L.hssmf_factor.argtypes = [ctypes.POINTER(CSRArg), ctypes.POINTER(OrderingArg), ctypes.POINTER(Opts), vp,
                                    ctypes.POINTER(vp)]
         L.hssmf_refactor.argtypes = [vp, vp]
+        L.hssmf_factor_z.argtypes = [ctypes.POINTER(CSRArg), ctypes.POINTER(OrderingArg), ctypes.POINTER(Opts), vp,
+                                     ctypes.POINTER(vp)]
+        L.hssmf_refactor_z.argtypes = [vp, vp]
         L.hssmf_refactor_device.argtypes = [vp, vp]
         L.hssmf_apply.argtypes = [vp, i32, vp, vp]
         L.hssmf_solve.argtypes = [vp, i32, vp, vp, ctypes.POINTER(Info)]
@@ -394,6 +398,83 @@ class Factorization:
             self.close()
         except Exception:
             pass
+
+
+class ZFactorization(Factorization):
+    """hssmf_factor_z: a complex system (problems.ZCSR, complex128 values)
+    factored through its real-equivalent form.  Vectors are complex128 CUDA
+    tensors or numpy arrays of n entries; they cross the boundary as their
+    interleaved (real, imaginary) doubles, which is the real form's
+    vector of 2n entries."""
+
+    def __init__(self, A, ordering, opts=None, stream=None, **kw):
+        import torch
+        self._torch = torch
+        self.lib = load()
+        self.nz = int(A.n)
+        self.n = 2 * self.nz
+        self.nnz = 4 * int(A.rowptr[-1])
+        self._keep = []
+        zval = np.ascontiguousarray(A.val, dtype=np.complex128).view(np.float64)
+        arrs = (np.ascontiguousarray(A.rowptr, dtype=np.int64), np.ascontiguousarray(A.colind, dtype=np.int32),
+                zval, np.ascontiguousarray(ordering.perm, dtype=np.int32),
+                np.ascontiguousarray(ordering.sep_ptr, dtype=np.int32),
+                np.ascontiguousarray(ordering.parent, dtype=np.int32))
+        self._keep.append(arrs)
+        rp, ci, va, pe, sp, pa = arrs
+        csr = CSRArg(self.nz, rp.ctypes.data, ci.ctypes.data, va.ctypes.data, MEM_HOST)
+        ordg = OrderingArg(pe.ctypes.data, len(pa), sp.ctypes.data, pa.ctypes.data)
+        self.opts = opts if opts is not None else default_opts(**kw)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self._stream = stream
+        h = ctypes.c_void_p()
+        rc = self.lib.hssmf_factor_z(ctypes.byref(csr), ctypes.byref(ordg), ctypes.byref(self.opts),
+                                     ctypes.c_void_p(stream), ctypes.byref(h))
+        if rc != HSSMF_OK:
+            raise HssmfError(rc, "hssmf_factor_z", self.lib.hssmf_last_failed_front(None))
+        self.h = h
+        self.offsets = [0, self.n]
+        self._vals_host = None
+        self._vals_dev = None
+
+    def refactor(self, val):
+        v = np.ascontiguousarray(val, dtype=np.complex128).view(np.float64)
+        assert v.size == self.nnz // 2
+        self._check(self.lib.hssmf_refactor_z(self.h, v.ctypes.data), "hssmf_refactor_z")
+
+    def _as_real(self, z):
+        """One complex right-hand side as the real form's vector (a view of
+        its interleaved doubles)."""
+        torch = self._torch
+        if isinstance(z, torch.Tensor):
+            if not (z.dtype == torch.complex128 and z.dim() == 1 and z.shape[0] == self.nz):
+                raise ValueError(f"expected a complex128 vector of {self.nz} entries")
+            return torch.view_as_real(z.contiguous()).reshape(self.n)
+        z = np.ascontiguousarray(z, dtype=np.complex128)
+        if z.shape != (self.nz,):
+            raise ValueError(f"expected a vector of {self.nz} entries")
+        return z.view(np.float64)
+
+    def _as_complex(self, x):
+        torch = self._torch
+        if isinstance(x, torch.Tensor):
+            return torch.view_as_complex(x.contiguous().view(self.nz, 2))
+        return np.ascontiguousarray(x).view(np.complex128)
+
+    def apply(self, z, trans=False):
+        return self._as_complex(Factorization.apply(self, self._as_real(z), trans))
+
+    def solve(self, b, allow_noconv=False):
+        x, info = Factorization.solve(self, self._as_real(b), allow_noconv)
+        return self._as_complex(x), info
+
+    def solve_transpose(self, g, allow_noconv=False):
+        x, info = Factorization.solve_transpose(self, self._as_real(g), allow_noconv)
+        return self._as_complex(x), info
+
+    def adjoint(self, x, g):
+        raise NotImplementedError("hssmf_adjoint is defined for real systems")
 
 
 class BatchFactorization(Factorization):

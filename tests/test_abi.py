@@ -169,3 +169,35 @@ def test_solve_family_rejects_bad_arguments(lib):
     for fn in (lib.hssmf_solve, lib.hssmf_solve_transpose):
         assert fn(None, 1, p, p, None) == H.HSSMF_EINVAL
     assert lib.hssmf_solve_batch(None, None, None, None) == H.HSSMF_EINVAL
+
+
+def test_complex_factor_rejects_bad_input(lib):
+    """hssmf_factor_z refuses malformed complex input on the host, before any
+    device work, and hssmf_refactor_z a null handle."""
+    A = P.helmholtz(6, 2, npml=1)
+    o = P.geometric_nd((6, 6), 2)
+    keep = []
+
+    def call(rowptr, colind, zval, perm, n=A.n, opts=None):
+        arrs = (np.ascontiguousarray(rowptr, dtype=np.int64), np.ascontiguousarray(colind, dtype=np.int32),
+                np.ascontiguousarray(zval, dtype=np.complex128).view(np.float64),
+                np.ascontiguousarray(perm, dtype=np.int32), np.ascontiguousarray(o.sep_ptr, dtype=np.int32),
+                np.ascontiguousarray(o.parent, dtype=np.int32))
+        keep.append(arrs)
+        rp, ci, va, pe, sp, pa = arrs
+        csr = H.CSRArg(n, rp.ctypes.data, ci.ctypes.data, va.ctypes.data, H.MEM_HOST)
+        ordg = H.OrderingArg(pe.ctypes.data, len(pa), sp.ctypes.data, pa.ctypes.data)
+        h = ctypes.c_void_p()
+        return lib.hssmf_factor_z(ctypes.byref(csr), ctypes.byref(ordg), ctypes.byref(opts or H.default_opts()),
+                                  None, ctypes.byref(h))
+
+    bad_col = A.colind.copy()
+    bad_col[3] = A.n
+    assert call(A.rowptr, bad_col, A.val, o.perm) == H.HSSMF_EINVAL
+    bad_perm = o.perm.copy()
+    bad_perm[0] = -1
+    assert call(A.rowptr, A.colind, A.val, bad_perm) == H.HSSMF_EINVAL
+    assert call(A.rowptr, A.colind, A.val, o.perm, n=-1) == H.HSSMF_EINVAL
+    assert call(A.rowptr, A.colind, A.val, o.perm, opts=H.default_opts(srrqr_f=0.5)) == H.HSSMF_EINVAL
+    assert lib.hssmf_factor_z(None, None, None, None, None) == H.HSSMF_EINVAL
+    assert lib.hssmf_refactor_z(None, None) == H.HSSMF_EINVAL
