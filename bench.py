@@ -150,6 +150,124 @@ def traffic_for(cls, launches_per_factorization):
     return nbytes / launches_per_factorization
 
 
+# Workloads of the rows beyond the hot path, each timed with --workload NAME
+# (one JSON line like the headline's, for that workload): the paper's C3D in
+# the aggressive-tolerance regime with GMRES(30) (Sec. 6.1), power-iteration
+# sampling and the strong rank-revealing QR (Sec. 2.2), and the complex H3D
+# (Sec. 6.1) through the real-equivalent form.  All FP64 products.
+NEXT_WORKLOADS = {
+    "convdiff3d_24_eps0.5": dict(
+        kind="convdiff", n=24, ndim=3, leaf=4,
+        opts=dict(min_sep_hss=256, leaf_size=64, d0=64, dd=64, p=10, rel_tol=0.5, outer="gmres", restart=30,
+                  tol=1e-12, max_it=400)),
+    "poisson3d_24_power1": dict(
+        kind="poisson", n=24, ndim=3, leaf=4,
+        opts=dict(min_sep_hss=200, leaf_size=48, rel_tol=1e-6, d0=64, dd=64, p=8, power_q=1, tol=1e-10)),
+    "poisson3d_24_srrqr1.2": dict(
+        kind="poisson", n=24, ndim=3, leaf=4,
+        opts=dict(min_sep_hss=200, leaf_size=48, rel_tol=1e-9, d0=128, dd=64, p=8, srrqr_f=1.2, tol=1e-10)),
+    "helmholtz3d_24": dict(
+        kind="helmholtz", n=24, ndim=3, leaf=4, npml=4,
+        opts=dict(min_sep_hss=512, leaf_size=64, rel_tol=1e-4, d0=128, dd=128, p=10, outer="gmres", tol=1e-10,
+                  max_it=300)),
+}
+
+
+def run_workload(name, args):
+    """Factor + solve steps on one of NEXT_WORKLOADS: W untimed steps, K timed
+    steps (hssmf_refactor_device, or hssmf_refactor_z with host values for the
+    complex system, then the solve), K more with the kernel timing hooks for
+    the dominant class's roofline, and the oracle on the same workload (its
+    whole factorization and one application of M^-1) as the CPU baseline."""
+    import torch
+    from paper_1502_07405_amd import hssmf as H
+    from paper_1502_07405_amd import problems as P
+    from oracle import mf
+    w = NEXT_WORKLOADS[name]
+    dims = (w["n"],) * w["ndim"]
+    order = P.geometric_nd(dims, w["leaf"])
+    cplx = w["kind"] == "helmholtz"
+    if w["kind"] == "convdiff":
+        A = P.convdiff_paper(w["n"], w["ndim"])
+    elif w["kind"] == "poisson":
+        A = P.poisson3d(w["n"])
+    else:
+        A = P.helmholtz(w["n"], w["ndim"], npml=w["npml"])
+    rg = np.random.default_rng(1)
+    b = rg.standard_normal(A.n) + (1j * rg.standard_normal(A.n) if cplx else 0.0)
+    dev = torch.device("cuda:0")
+    bt = torch.tensor(b, device=dev)
+    opts = w["opts"]
+    fac = (H.ZFactorization if cplx else H.Factorization)(A, order, **opts)
+    vals = A.val if cplx else torch.tensor(A.val, device=dev)
+
+    def steps(k):
+        infos = []
+        for _ in range(k):
+            fac.refactor(vals)
+            x, info = fac.solve(bt)
+            infos.append((info.iterations, info.rel_residual))
+        return x, infos
+
+    steps(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, infos = steps(args.steps)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    H.profile_enable(True)
+    for k in KCLASSES:
+        H.profile_read(k)
+    t0 = time.perf_counter()
+    steps(args.steps)
+    torch.cuda.synchronize()
+    sec_hooked = (time.perf_counter() - t0) / args.steps
+    prof = {k: H.profile_read(k) for k in KCLASSES}
+    H.profile_enable(False)
+    st = fac.stats()
+    fac.close()
+    S = A.to_scipy()
+    xr = x.cpu().numpy()
+    relres = float(np.linalg.norm(b - S @ xr) / np.linalg.norm(b))
+    dom = max(prof, key=lambda k: prof[k][0])
+    ms, launches, flops = prof[dom]
+    avg_ms = ms / max(launches, 1)
+    achieved = (flops / launches) / (avg_ms * 1e-3) / 1e12 if launches and avg_ms > 0 else 0.0
+    bound, peak = BOUND[dom]
+    if peak is None:
+        peak = FP64_PEAK_TFLOPS
+    roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": None, "kernel": KERNEL_NAME[dom], "avg_launch_ms": avg_ms, "launches": launches,
+            "time_share": ms / (sec_hooked * 1e3 * args.steps)}
+    # the oracle on the same workload: its whole factorization and one
+    # application of M^-1 (the complex system on the oracle's own real form)
+    from threadpoolctl import threadpool_info
+    cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    oo = {k: v for k, v in opts.items() if k in ("min_sep_hss", "leaf_size", "rel_tol", "d0", "dd", "p", "power_q",
+                                                 "srrqr_f")}
+    if cplx:
+        from oracle import complexeq as CE
+        Ao, ordo, bo = CE.real_form(A), CE.real_ordering(order), CE.to_real(b)
+    else:
+        Ao, ordo, bo = A, order, b
+    t0 = time.perf_counter()
+    ofac = mf.factor(Ao, ordo, mf.Options(**oo))
+    mf.apply_inverse(ofac, bo)
+    tcpu = time.perf_counter() - t0
+    line = {"metric": f"factor+solve sec, {name}", "value": sec, "unit": "s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": False, "scaling": "strong",
+            "vs_baseline": None, "dtype": "c128 as f64 pairs" if cplx else "f64", "data": "synthetic",
+            "config": {"workload": name, "n": int(A.n), **{k: v for k, v in opts.items()}},
+            "roofline": roof,
+            "cpu_baseline": {"value": tcpu, "unit": "s", "cores": int(cores), "kind": "oracle",
+                             "sample": "whole oracle factorization and one application of M^-1 (no outer solve)"},
+            "extra": {"iterations": infos[-1][0], "rel_residual": relres, "max_rank": st["max_rank"],
+                      "growth_rounds": st["growth_rounds"], "srrqr_swaps": st["srrqr_swaps"],
+                      "step_s_with_timing_hooks": sec_hooked,
+                      "kernel_ms_per_step": {k: prof[k][0] / args.steps for k in KCLASSES}}}
+    print(json.dumps(line), flush=True)
+
+
 def progress(msg):
     """One line on stderr per finished phase (the JSON line is the only stdout)."""
     print(f"bench.py: {msg}", file=sys.stderr, flush=True)
@@ -229,6 +347,8 @@ def main():
     ap.add_argument("--summarize", nargs="+", metavar="CSV",
                     help="print per-kernel totals of rocprofv3 CSV output (counter_collection or kernel_trace "
                          "files) and exit; no GPU is used")
+    ap.add_argument("--workload", choices=sorted(NEXT_WORKLOADS),
+                    help="time one workload beyond the 64^3 headline instead (one JSON line)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="program for the HBM counter runs: a 256 MiB device copy (calibration), then one "
                          "factorization, one refactorization and one solve of the headline workload; prints no JSON")
@@ -239,6 +359,9 @@ def main():
     if args.gpus != 1:
         print(f"bench.py: this solver path runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
+    if args.workload:
+        run_workload(args.workload, args)
+        return
     import torch
     from paper_1502_07405_amd import hssmf as H
     from paper_1502_07405_amd import problems as P
