@@ -48,3 +48,18 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+@pytest.mark.parametrize("name", sorted(bench.NEXT_WORKLOADS))
+def test_workload_options_are_valid_on_both_sides(name):
+    """Each --workload entry: its options make a valid hssmf_opts (the
+    library's own check runs in hssmf_factor; here the binding accepts every
+    key) and the oracle's Options accept the keys the CPU baseline passes."""
+    from oracle import mf
+    from paper_1502_07405_amd import hssmf as H
+    w = bench.NEXT_WORKLOADS[name]
+    o = H.default_opts(**w["opts"])
+    assert o.rel_tol == w["opts"]["rel_tol"]
+    keys = ("min_sep_hss", "leaf_size", "rel_tol", "d0", "dd", "p", "power_q", "srrqr_f")
+    mf.Options(**{k: v for k, v in w["opts"].items() if k in keys})
+    assert w["kind"] in ("convdiff", "poisson", "helmholtz")
