@@ -175,8 +175,8 @@ NEXT_WORKLOADS = {
 
 def run_workload(name, args):
     """Factor + solve steps on one of NEXT_WORKLOADS: W untimed steps, K timed
-    steps (hssmf_refactor_device, or hssmf_refactor_z with host values for the
-    complex system, then the solve), K more with the kernel timing hooks for
+    steps (hssmf_refactor_device, or hssmf_refactor_z_device for the complex
+    system, from values resident on the device, then the solve), K more with the kernel timing hooks for
     the dominant class's roofline, and the oracle on the same workload (its
     whole factorization and one application of M^-1) as the CPU baseline."""
     import torch
@@ -199,7 +199,7 @@ def run_workload(name, args):
     bt = torch.tensor(b, device=dev)
     opts = w["opts"]
     fac = (H.ZFactorization if cplx else H.Factorization)(A, order, **opts)
-    vals = A.val if cplx else torch.tensor(A.val, device=dev)
+    vals = torch.tensor(A.val, device=dev)   # resident before any timing (complex128 for the complex system)
 
     def steps(k):
         infos = []

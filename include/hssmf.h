@@ -280,6 +280,12 @@ int hssmf_factor_z(const hssmf_csr* A, const hssmf_ordering* ord, const hssmf_op
  * a handle from hssmf_factor or hssmf_factor_batch. */
 int hssmf_refactor_z(void* h, const double* val);
 
+/* hssmf_refactor_z with the complex values already in device memory (2
+ * rowptr[n] doubles, (real, imaginary) pairs in CSR order), read on the
+ * handle's stream; a kernel forms the real-equivalent values in place of
+ * the host.  The caller keeps ownership.  EINVAL as hssmf_refactor_z. */
+int hssmf_refactor_z_device(void* h, const double* val_dev);
+
 /* hssmf_refactor with the new values already in device memory: val_dev has
  * rowptr[n] entries in the CSR order given to hssmf_factor, is read on the
  * handle's stream (copied into the handle there) and stays owned by the

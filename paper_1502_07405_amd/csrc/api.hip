@@ -775,8 +775,27 @@ int hssmf_factor_z(const hssmf_csr* A, const hssmf_ordering* ord, const hssmf_op
     Handle* h = static_cast<Handle*>(*out);
     h->zexp = true;
     h->zrow = std::move(zrow);
+    rc = guard_impl(h, [&]() {
+      h->d_zrow = h->arena.get<int64_t>(h->zrow.size());
+      HIP_CHECK(hipMemcpyAsync(h->d_zrow, h->zrow.data(), sizeof(int64_t) * h->zrow.size(), hipMemcpyHostToDevice,
+                               h->st));
+      HIP_CHECK(hipStreamSynchronize(h->st));
+    });
+    if (rc != HSSMF_OK) {
+      hssmf_destroy(h);
+      *out = nullptr;
+    }
   }
   return rc;
+}
+
+int hssmf_refactor_z_device(void* hv, const double* val_dev) {
+  Handle* h = static_cast<Handle*>(hv);
+  if (!h || !val_dev || !h->zexp || !h->d_zrow) return HSSMF_EINVAL;
+  return guard_impl(h, [&]() {
+    launch_zexpand(h->d_val, val_dev, h->d_zrow, (int)h->zrow.size() - 1, h->st);
+    numeric(*h);
+  });
 }
 
 int hssmf_refactor_z(void* hv, const double* val) {

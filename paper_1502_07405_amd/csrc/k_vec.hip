@@ -89,6 +89,32 @@ void launch_gather(double* y, const double* x, const int* map, int n, hipStream_
   HIP_CHECK(hipGetLastError());
 }
 
+// complex values (re, im pairs, complex CSR order) into the real-equivalent
+// matrix's values: row i's entries a + ib give [a, -b] in row 2i and [b, a]
+// in row 2i + 1, each row of the real form holding two values per complex
+// entry; one thread per complex row
+__global__ void zexpand_kernel(double* __restrict__ out, const double* __restrict__ z,
+                               const int64_t* __restrict__ zrow, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t e0 = zrow[i], len = zrow[i + 1] - e0;
+  double* r0 = out + 4 * e0;        // row 2i
+  double* r1 = r0 + 2 * len;        // row 2i + 1
+  for (int64_t t = 0; t < len; ++t) {
+    const double re = z[2 * (e0 + t)], im = z[2 * (e0 + t) + 1];
+    r0[2 * t] = re;
+    r0[2 * t + 1] = -im;
+    r1[2 * t] = im;
+    r1[2 * t + 1] = re;
+  }
+}
+
+void launch_zexpand(double* out, const double* z, const int64_t* zrow, int n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(zexpand_kernel, dim3((n + 255) / 256), dim3(256), 0, s, out, z, zrow, n);
+  HIP_CHECK(hipGetLastError());
+}
+
 // ------------------------------------------------------------- GMRES ------
 
 GmDev gm_dev(double* base) {

@@ -278,6 +278,7 @@ struct Handle {
   // (hssmf_factor_z): the complex CSR's row pointers, base 0
   bool zexp = false;
   std::vector<int64_t> zrow;
+  int64_t* d_zrow = nullptr;   // the same on the device (arena)
   int64_t* d_sys_off = nullptr;
   double* d_seg = nullptr;     // per-system sums of squares
   // preconditioner sweeps captured as HIP graphs ([trans]), rebuilt after

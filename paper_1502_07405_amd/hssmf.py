@@ -23,7 +23,7 @@ EXPORTS = ["hssmf_default_opts", "hssmf_factor", "hssmf_refactor", "hssmf_apply"
            "hssmf_profile_read", "hssmf_factor_batch", "hssmf_systems", "hssmf_measure_peaks",
            "hssmf_refactor_device", "hssmf_solve_batch", "hssmf_solve_noalloc",
            "hssmf_front_data", "hssmf_static_pivoting", "hssmf_nested_dissection", "hssmf_factor_z",
-           "hssmf_refactor_z"]
+           "hssmf_refactor_z", "hssmf_refactor_z_device"]
 KCLASS = {"id": 0, "gemm64": 1, "gemmlp": 2, "lupanel": 3, "idres": 4}
 
 
@@ -94,6 +94,7 @@ def load():
         L.hssmf_factor_z.argtypes = [ctypes.POINTER(CSRArg), ctypes.POINTER(OrderingArg), ctypes.POINTER(Opts), vp,
                                      ctypes.POINTER(vp)]
         L.hssmf_refactor_z.argtypes = [vp, vp]
+        L.hssmf_refactor_z_device.argtypes = [vp, vp]
         L.hssmf_refactor_device.argtypes = [vp, vp]
         L.hssmf_apply.argtypes = [vp, i32, vp, vp]
         L.hssmf_solve.argtypes = [vp, i32, vp, vp, ctypes.POINTER(Info)]
@@ -439,6 +440,14 @@ class ZFactorization(Factorization):
         self._vals_dev = None
 
     def refactor(self, val):
+        """New complex values: a complex128 CUDA tensor (read in place,
+        hssmf_refactor_z_device) or host values (hssmf_refactor_z)."""
+        torch = self._torch
+        if isinstance(val, torch.Tensor) and val.is_cuda:
+            if not (val.dtype == torch.complex128 and val.is_contiguous() and val.numel() == self.nnz // 4):
+                raise ValueError(f"expected a contiguous complex128 tensor of {self.nnz // 4} values")
+            self._check(self.lib.hssmf_refactor_z_device(self.h, val.data_ptr()), "hssmf_refactor_z_device")
+            return
         v = np.ascontiguousarray(val, dtype=np.complex128).view(np.float64)
         assert v.size == self.nnz // 2
         self._check(self.lib.hssmf_refactor_z(self.h, v.ctypes.data), "hssmf_refactor_z")

@@ -201,3 +201,4 @@ def test_complex_factor_rejects_bad_input(lib):
     assert call(A.rowptr, A.colind, A.val, o.perm, opts=H.default_opts(srrqr_f=0.5)) == H.HSSMF_EINVAL
     assert lib.hssmf_factor_z(None, None, None, None, None) == H.HSSMF_EINVAL
     assert lib.hssmf_refactor_z(None, None) == H.HSSMF_EINVAL
+    assert lib.hssmf_refactor_z_device(None, None) == H.HSSMF_EINVAL

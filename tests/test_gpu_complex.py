@@ -67,8 +67,9 @@ def test_complex_system_matches_the_oracle(case, upd):
 
 def test_complex_refactor_equals_a_fresh_factorization():
     """New complex values on the same pattern (another frequency at the same
-    spacing): hssmf_refactor_z gives the factorization hssmf_factor_z gives
-    for them, bit for bit."""
+    spacing): hssmf_refactor_z, and hssmf_refactor_z_device from values in
+    device memory, give the factorization hssmf_factor_z gives for them, bit
+    for bit."""
     mk, kw = CASES["h2d48"]
     A, o = mk()
     B = P.helmholtz(48, 2, freq=12.0, ppw=12.5, npml=8)
@@ -77,8 +78,12 @@ def test_complex_refactor_equals_a_fresh_factorization():
     f1 = H.ZFactorization(A, o, **kw)
     f1.refactor(B.val)
     y1 = f1.apply(s).cpu().numpy()
+    f1.refactor(torch.tensor(A.val, device=DEV))   # back to A's values, from the device
+    f1.refactor(torch.tensor(B.val, device=DEV))
+    y1d = f1.apply(s).cpu().numpy()
     f1.close()
     f2 = H.ZFactorization(B, o, **kw)
     y2 = f2.apply(s).cpu().numpy()
     f2.close()
     assert np.array_equal(y1, y2)
+    assert np.array_equal(y1d, y2)
