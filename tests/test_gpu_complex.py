@@ -87,3 +87,22 @@ def test_complex_refactor_equals_a_fresh_factorization():
     f2.close()
     assert np.array_equal(y1, y2)
     assert np.array_equal(y1d, y2)
+
+
+def test_complex_system_with_power_iteration_and_strong_rrqr():
+    """Every option applies to the real-equivalent form: power iteration
+    (q = 1) and the strong RRQR (f = 1.2) together on H2D 48^2, against the
+    oracle with the same options (ranks and interchange counts equal,
+    M^-1 s to the HSS parity tolerance)."""
+    mk, kw = CASES["h2d48"]
+    A, o = mk()
+    kw = dict(kw, power_q=1, srrqr_f=1.2)
+    ofac = mf.factor(CE.real_form(A), CE.real_ordering(o), mf.Options(**kw))
+    fac = H.ZFactorization(A, o, **kw)
+    assert fac.hss_ranks() == [tuple(int(v) for v in r) for r in mf.hss_ranks(ofac)]
+    assert fac.stats()["srrqr_swaps"] == sum(fa.data["H"].stats["swaps"] for fa in ofac.factors if fa.kind == "hss")
+    s = np.random.default_rng(8).standard_normal(A.n) + 1j * np.random.default_rng(9).standard_normal(A.n)
+    y = fac.apply(torch.tensor(s, device=DEV)).cpu().numpy()
+    yo = CE.to_complex(mf.apply_inverse(ofac, CE.to_real(s)))
+    assert np.linalg.norm(y - yo) <= 1e-9 * np.linalg.norm(yo)
+    fac.close()
